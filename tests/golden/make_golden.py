@@ -1,0 +1,45 @@
+"""Write the oracle's expected eigenvalues for the seeded workloads to tests/golden/*.json.
+
+Calls only ``oracle/`` (the FP64 dense definition, route D) and ``workloads/`` (inputs). The
+paper prints no worked example for this path, so every stored value here is the oracle's.
+
+    python tests/golden/make_golden.py small      # 5 x 20 x 100, seeds 0-4, both spins (seconds)
+    python tests/golden/make_golden.py davidson   # 20 x 200 x 700, seed 0, both spins (minutes)
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import pprpa_oracle as O  # noqa: E402
+from workloads import gen  # noqa: E402
+
+
+def run(name, nocc, nvir, naux, seeds, mults, nroot):
+    out = dict(
+        source="oracle/pprpa_oracle.py, dense build + route D (Cholesky of M - 2 mu W, eigh)",
+        inputs=f"workloads/gen.py: orbital_energies(seed, {nocc}, {nvir}), lpq_full(seed, {nocc + nvir}, {naux})",
+        units="Hartree", nocc=nocc, nvir=nvir, naux=naux, nroot=nroot, roots={})
+    for seed in seeds:
+        eps = gen.orbital_energies(seed, nocc, nvir)
+        L = gen.lpq_full(seed, nocc + nvir, naux)
+        for mult in mults:
+            t = time.time()
+            om = O.solve(eps, L, nocc, mult, nroot)
+            out["roots"][f"{seed}/{mult}"] = [float(x) for x in om]
+            print(name, seed, mult, f"{time.time() - t:.1f}s", om[:3], flush=True)
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["small"]
+    if "small" in which:
+        run("small_direct", 5, 20, 100, (0, 1, 2, 3, 4), ("singlet", "triplet"), 5)
+    if "davidson" in which:
+        run("davidson_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10)

@@ -1,0 +1,239 @@
+"""Pins for the FP64 oracle: each checks it against something other than itself.
+
+P1  L = 0: closed form Omega = e_a + e_b (pp), e_i + e_j (hh).
+P2  B = 0 (L_vo = 0): pp roots = eigvalsh(A), hh roots = -eigvalsh(C) (LAPACK), E_c = 0.
+P3  sum rule of Eq. correlation_energy: sum(pp) + sum(hh) = Tr A - Tr C; root counts.
+P4  normalisation of Eq. xy_norm: Z^T W Z = diag(+-1).
+P5  the spin-orbital build (general elements with a<b, i<j) has the spectrum
+    singlet U 3 x triplet.
+P6  second order: with A/C interactions off and L_vo scaled by lam,
+    E_c(singlet) + 3 E_c(triplet) -> lam^2 * closed-shell RI-MP2 (section "Total Energy":
+    ppRPA correlation is exact to second order).
+P7  two electrons: with no occupied orbitals the singlet and triplet A spectra together are
+    the spectrum of the two-electron CI Hamiltonian (Slater-Condon).
+P8  the factorised sigma equals the dense M z; route D equals route G.
+Plus mutation checks: plausible mistakes planted in a copy of the oracle fail a pin.
+"""
+import numpy as np
+import pytest
+
+from oracle import pprpa_oracle as O
+from workloads import gen
+
+
+def make_sp(seed, nocc, nvir, naux, scale=None):
+    eps = gen.orbital_energies(seed, nocc, nvir)
+    L = gen.lpq_full(seed, nocc + nvir, naux)
+    if scale is not None:
+        L = L * scale
+    return eps, L, O.active_space(eps, L, nocc)
+
+
+def full_spectrum(sp, mult, route="D"):
+    A, B, C = O.build_matrices(sp, mult)
+    M = O.pprpa_matrix(A, B, C)
+    if route == "D":
+        Om, Z, sg = O.solve_definite(M, A.shape[0], O.midgap(sp))
+    else:
+        Om, Z, sg = O.solve_general(M, A.shape[0])
+    return A, B, C, M, Om, Z, sg
+
+
+MULTS = ["singlet", "triplet"]
+SIZES = [(1, 2, 5), (2, 3, 7), (3, 5, 11), (4, 9, 30)]
+
+
+@pytest.mark.parametrize("mult", MULTS)
+@pytest.mark.parametrize("route", ["D", "G"])
+@pytest.mark.parametrize("nocc,nvir,naux", SIZES)
+def test_p1_zero_interaction(mult, route, nocc, nvir, naux):
+    eps, L, sp = make_sp(1, nocc, nvir, naux, scale=0.0)
+    A, B, C, M, Om, Z, sg = full_spectrum(sp, mult, route)
+    k = 0 if mult == "singlet" else 1
+    eo, ev = eps[:nocc], eps[nocc:]
+    pp = np.sort([ev[a] + ev[b] for a in range(nvir) for b in range(a + k, nvir)])
+    hh = np.sort([eo[i] + eo[j] for i in range(nocc) for j in range(i + k, nocc)])
+    assert np.allclose(np.sort(Om[sg > 0]), pp, atol=1e-13)
+    assert np.allclose(np.sort(Om[sg < 0]), hh, atol=1e-13)
+
+
+@pytest.mark.parametrize("mult", MULTS)
+@pytest.mark.parametrize("nocc,nvir,naux", SIZES)
+def test_p2_no_coupling(mult, nocc, nvir, naux):
+    eps, L, sp = make_sp(2, nocc, nvir, naux)
+    sp["Lov"] = np.zeros_like(sp["Lov"])
+    A, B, C, M, Om, Z, sg = full_spectrum(sp, mult)
+    assert np.all(B == 0.0)
+    assert np.allclose(np.sort(Om[sg > 0]), np.linalg.eigvalsh(A), atol=1e-12)
+    assert np.allclose(np.sort(Om[sg < 0]), np.sort(-np.linalg.eigvalsh(C)), atol=1e-12)
+    ec1, ec2 = O.correlation_energy(Om[sg > 0], Om[sg < 0], A, C)
+    assert abs(ec1) < 1e-12 and abs(ec2) < 1e-12
+
+
+@pytest.mark.parametrize("mult", MULTS)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p3_p4_sum_rule_counts_normalisation(mult, seed):
+    eps, L, sp = make_sp(seed, 4, 9, 30)
+    A, B, C, M, Om, Z, sg = full_spectrum(sp, mult)
+    nvv, noo = A.shape[0], C.shape[0]
+    assert int(np.sum(sg > 0)) == nvv and int(np.sum(sg < 0)) == noo
+    ec1, ec2 = O.correlation_energy(Om[sg > 0], Om[sg < 0], A, C)
+    assert abs(ec1 - ec2) < 1e-12
+    assert ec1 < 0.0  # correlation lowers the energy
+    w = O.metric(nvv, noo)
+    G = Z.T @ (w[:, None] * Z)
+    assert np.allclose(G, np.diag(sg), atol=1e-10)
+    # eigen-relation itself
+    assert np.allclose(M @ Z, (w[:, None] * Z) * Om[None, :], atol=1e-11)
+
+
+@pytest.mark.parametrize("nocc,nvir,naux", [(1, 2, 5), (2, 3, 6), (2, 4, 9), (3, 3, 8)])
+def test_p5_spin_orbital_equals_singlet_plus_3_triplet(nocc, nvir, naux):
+    eps, L, sp = make_sp(3, nocc, nvir, naux)
+    Mso, nvv_so = O.spin_orbital_matrix(sp)
+    Om_so, _, sg_so = O.solve_general(Mso, nvv_so)
+    parts_pp, parts_hh = [], []
+    for mult, mult_count in (("singlet", 1), ("triplet", 3)):
+        _, _, _, _, Om, _, sg = full_spectrum(sp, mult, "G")
+        parts_pp += list(Om[sg > 0]) * mult_count
+        parts_hh += list(Om[sg < 0]) * mult_count
+    assert np.allclose(np.sort(Om_so[sg_so > 0]), np.sort(parts_pp), atol=1e-12)
+    assert np.allclose(np.sort(Om_so[sg_so < 0]), np.sort(parts_hh), atol=1e-12)
+
+
+def _ec_total(sp):
+    tot = 0.0
+    for mult, g in (("singlet", 1), ("triplet", 3)):
+        A, B, C, M, Om, Z, sg = full_spectrum(sp, mult)
+        tot += g * O.correlation_energy(Om[sg > 0], Om[sg < 0], A, C)[0]
+    return tot
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_p6_mp2_limit(seed):
+    eps, L, sp = make_sp(seed, 3, 6, 20)
+    emp2 = O.rimp2_energy(sp)
+    lam = 1e-2
+    sp2 = dict(sp)
+    sp2["Lvv"] = np.zeros_like(sp["Lvv"])
+    sp2["Loo"] = np.zeros_like(sp["Loo"])
+    sp2["Lov"] = sp["Lov"] * np.sqrt(lam)  # integrals (ak|bl) scale by lam
+    ec = _ec_total(sp2)
+    assert emp2 < 0
+    assert abs(ec / lam ** 2 - emp2) < 1e-5 * abs(emp2)  # measured 7e-7 and 1.3e-6
+
+
+@pytest.mark.parametrize("nvir,naux", [(1, 4), (3, 8), (5, 12)])
+def test_p7_two_electron_ci(nvir, naux):
+    eps, L, sp = make_sp(4, 0, nvir, naux)
+    As, _, _ = O.build_matrices(sp, "singlet")
+    At, _, _ = O.build_matrices(sp, "triplet")
+    spec = np.sort(np.concatenate([np.linalg.eigvalsh(As), np.linalg.eigvalsh(At)]))
+    ci = O.two_electron_ci(sp["ev"], sp["Lvv"])
+    # the CI over |a alpha b beta> holds the singlets and the M_s = 0 triplets once each
+    assert np.allclose(spec, ci, atol=1e-13)
+
+
+@pytest.mark.parametrize("mult", MULTS)
+@pytest.mark.parametrize("nocc,nvir,naux", SIZES + [(5, 20, 100)])
+def test_p8_factorised_sigma_and_routes(mult, nocc, nvir, naux):
+    eps, L, sp = make_sp(5, nocc, nvir, naux)
+    A, B, C = O.build_matrices(sp, mult)
+    M = O.pprpa_matrix(A, B, C)
+    z = gen.random_vectors(9, 3, M.shape[0]).T
+    s_dense = O.sigma_dense(M, z)
+    s_fact = O.sigma_factorised(sp, mult, z)
+    assert np.allclose(s_fact, s_dense, atol=1e-13 * max(1.0, np.abs(s_dense).max()))
+    rows = np.unique(np.r_[0, M.shape[0] - 1, M.shape[0] // 2, A.shape[0] - 1])
+    assert np.allclose(O.sigma_rows(sp, mult, rows, z[:, 0]), s_dense[rows, 0], atol=1e-13)
+    OmD, _, sgD = O.solve_definite(M, A.shape[0], O.midgap(sp))
+    OmG, _, sgG = O.solve_general(M, A.shape[0])
+    assert np.array_equal(sgD, sgG)
+    assert np.allclose(OmD, OmG, atol=1e-11)
+
+
+def test_subset_route_matches_full():
+    eps, L, sp = make_sp(0, 5, 20, 100)
+    A, B, C = O.build_matrices(sp, "singlet")
+    M = O.pprpa_matrix(A, B, C)
+    Om, Z, sg = O.solve_definite(M, A.shape[0], O.midgap(sp))
+    Om5, Z5, sg5 = O.solve_definite(M, A.shape[0], O.midgap(sp), nroot=5)
+    assert np.all(sg5 > 0)
+    assert np.allclose(Om5, Om[sg > 0][:5], atol=1e-12)
+
+
+def test_active_window_equals_oracle_on_sliced_input():
+    nocc, nvir, naux = 6, 12, 40
+    eps = gen.orbital_energies(0, nocc, nvir)
+    L = gen.lpq_full(0, nocc + nvir, naux)
+    a = O.solve(eps, L, nocc, "triplet", 4, nocc_act=3, nvir_act=7)
+    La = gen.lpq_active(0, nocc, nvir, naux, 3, 7)
+    b = O.solve(eps, La, nocc, "triplet", 4, nocc_act=3, nvir_act=7, lpq_is_active=True)
+    assert np.array_equal(a, b)
+    idx = gen.active_indices(nocc, nvir, 3, 7)
+    c = O.solve(np.r_[eps[idx]], La, 3, "triplet", 4)
+    assert np.allclose(a, c, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------------------
+# Mutation checks: a planted mistake in the oracle must fail at least one pin.
+# ----------------------------------------------------------------------------------------
+
+def test_mutation_wrong_b_convention_fails_p6(monkeypatch):
+    """Reading B as (ab|kl) (from L_vv and L_oo) instead of (ak|bl) breaks the MP2 limit."""
+    eps, L, sp = make_sp(0, 3, 6, 20)
+    emp2 = O.rimp2_energy(sp)
+    lam = 1e-2
+    sp2 = dict(sp)
+    sp2["Lvv"] = np.zeros_like(sp["Lvv"])
+    sp2["Loo"] = np.zeros_like(sp["Loo"])
+    sp2["Lov"] = sp["Lov"] * np.sqrt(lam)
+    good = O.build_matrices
+
+    def wrong(spx, mult):
+        A, B, C = good(spx, mult)
+        sign = 1.0 if mult == "singlet" else -1.0
+        va, vb = O.pairs(spx["ev"].size, mult)
+        oi, oj = O.pairs(spx["eo"].size, mult)
+        Lv = sp["Lvv"] * np.sqrt(lam)
+        Lo = sp["Loo"] * np.sqrt(lam)
+        ab_kl = np.einsum("Pab,Pkl->abkl", Lv, Lo)
+        Bw = (ab_kl[va, vb][:, oi, oj] + sign * ab_kl[va, vb][:, oj, oi])
+        Bw *= np.outer(O.pair_norm(va, vb, mult), O.pair_norm(oi, oj, mult))
+        return A, Bw, C
+
+    monkeypatch.setattr(O, "build_matrices", wrong)
+    ec = _ec_total(sp2)
+    assert abs(ec / lam ** 2 - emp2) > 1e-2 * abs(emp2)
+
+
+def test_mutation_dropped_singlet_norm_fails_p5(monkeypatch):
+    eps, L, sp = make_sp(3, 2, 3, 6)
+    Mso, nvv_so = O.spin_orbital_matrix(sp)
+    Om_so, _, sg_so = O.solve_general(Mso, nvv_so)
+    monkeypatch.setattr(O, "pair_norm", lambda p, q, mult: np.ones(p.size))
+    parts = []
+    for mult, g in (("singlet", 1), ("triplet", 3)):
+        _, _, _, _, Om, _, sg = full_spectrum(sp, mult, "G")
+        parts += list(Om[sg > 0]) * g
+    assert not np.allclose(np.sort(Om_so[sg_so > 0]), np.sort(parts), atol=1e-6)
+
+
+def test_mutation_exchange_sign_fails_p7(monkeypatch):
+    """Using (ab|cd) (chemists' order) in A instead of (ac|bd) breaks the 2-electron CI pin."""
+    eps, L, sp = make_sp(4, 0, 3, 8)
+    ci = O.two_electron_ci(sp["ev"], sp["Lvv"])
+    orig = O.pair_integrals
+
+    def chem(L_rc, rp, rq, cp, cq, sign, chunk=256):
+        if rp.size == 0 or cp.size == 0:
+            return np.zeros((rp.size, cp.size))
+        g = np.einsum("Ppq,Prs->pqrs", L_rc, L_rc)  # (pq|rs) used as <pq|rs>
+        return g[rp, rq][:, cp, cq] + sign * g[rp, rq][:, cq, cp]
+
+    monkeypatch.setattr(O, "pair_integrals", chem)
+    As, _, _ = O.build_matrices(sp, "singlet")
+    At, _, _ = O.build_matrices(sp, "triplet")
+    monkeypatch.setattr(O, "pair_integrals", orig)
+    spec = np.sort(np.concatenate([np.linalg.eigvalsh(As), np.linalg.eigvalsh(At)]))
+    assert not np.allclose(spec, ci, atol=1e-6)
