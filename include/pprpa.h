@@ -1,0 +1,147 @@
+/*
+ * pprpa.h -- C ABI of the MI355X (gfx950) particle-particle RPA library (libpprpa.so).
+ *
+ * The library solves the ppRPA generalised eigenproblem of arXiv 2512.12515,
+ * section "ppRPA Equation", Eq. eigen_equation:
+ *
+ *     [[A, B], [B^T, C]] [X; Y] = Omega diag(I, -I) [X; Y]
+ *
+ * for a closed-shell reference in its spin-adapted singlet or triplet form (same section),
+ * with the physicists' integrals <pq|rs> = (pr|qs) (defined beside Eq. dyson) from
+ * density-fitted MO-basis three-centre integrals, (pq|rs) = sum_P L^P_pq L^P_rs
+ * (section "Implementation Details"), optionally in a canonical active window.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Orbitals are in physical order: occupied 0..nocc-1 then virtual nocc..nmo-1, each block
+ *    in ascending energy. Energies in Hartree.
+ *  - Active window: the highest nocc_act occupied and the lowest nvir_act virtual orbitals
+ *    (<= 0 means all of them). Below, no/nv are the active counts.
+ *  - Packed pair vectors: z = [x; y], x over virtual pairs (a, b), y over occupied pairs
+ *    (i, j), each in upper-triangle row-major order with the first index outer:
+ *    singlet a <= b (n_pp = nv(nv+1)/2), triplet a < b (n_pp = nv(nv-1)/2); the same for y.
+ *    n = n_pp + n_hh. Blocks of k vectors are row-major [k][n] (vector-contiguous), FP64.
+ *  - Returned eigenvectors are normalised to x^T x - y^T y = +1 (Eq. xy_norm, pp roots) and
+ *    signed so that their largest-magnitude component is positive.
+ *  - All functions are synchronous with respect to the caller: device work is ordered on
+ *    the context's stream, which is synchronised before results are returned.
+ *  - No exception crosses the ABI. Every function returns a pprpa_status; on failure
+ *    pprpa_last_error() gives a message for the calling thread.
+ *  - "host or device" pointers: the on_device flag says which; device pointers must be
+ *    memory of the context's device (e.g. a torch tensor's data_ptr()).
+ */
+#ifndef PPRPA_H
+#define PPRPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PPRPA_OK = 0,
+  PPRPA_EINVAL = 1,       /* invalid or inconsistent argument (sizes, window, NaN/Inf input) */
+  PPRPA_ENOMEM = 2,       /* device allocation failed or exceeded a budget */
+  PPRPA_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
+  PPRPA_ENOCONV = 4,      /* Davidson did not converge in max_iter; outputs hold the last iterate */
+  PPRPA_ENONDEF = 5,      /* (projected) pencil M - 2 mu W not positive definite */
+  PPRPA_EUNSUPPORTED = 6, /* valid but unsupported combination */
+  PPRPA_EBUSY = 7         /* the context is in use by another thread */
+} pprpa_status;
+
+typedef enum { PPRPA_SINGLET = 0, PPRPA_TRIPLET = 1 } pprpa_mult;
+
+/* Arithmetic of the sigma contractions (the Davidson linear algebra is FP64 always).
+ * FP64: FP64 MFMA. FP32: L and the unpacked vectors rounded to FP32, FP32 MFMA, FP32
+ * accumulation. BF16X3 / BF16X6: each FP32 operand split into bf16 hi+mid+lo, products
+ * hh+hm+mh (X3) or hh+hm+mh+mm+hl+lh (X6) on BF16 MFMA, FP32 accumulation. The diagonal
+ * (e_a+e_b) x term is always applied in FP64. */
+typedef enum { PPRPA_FP64 = 0, PPRPA_FP32 = 1, PPRPA_BF16X6 = 2, PPRPA_BF16X3 = 3 } pprpa_prec;
+
+typedef struct pprpa_ctx pprpa_ctx; /* opaque; owns every device allocation it makes */
+
+typedef struct {
+  int32_t nmo;          /* number of MO (full space)                                        */
+  int32_t nocc;         /* occupied count (full space); 0 <= nocc <= nmo                    */
+  int32_t naux;         /* auxiliary (density-fitting) count, > 0                           */
+  int32_t nocc_act;     /* active occupied (<= 0: all)                                      */
+  int32_t nvir_act;     /* active virtual  (<= 0: all)                                      */
+  const double* eps;    /* [nmo] orbital energies (host or device, see on_device)            */
+  const double* Lpq;    /* [naux][nmo][nmo] row-major, symmetric in (p,q); or, when
+                           lpq_is_active, [naux][nact][nact] over the active orbitals in
+                           physical order (nact = no + nv). FP64. Host or device.           */
+  int32_t lpq_is_active;
+  int32_t on_device;    /* 1: eps and Lpq are device pointers                               */
+  int32_t mult;         /* pprpa_mult                                                        */
+  int32_t prec;         /* pprpa_prec                                                        */
+  int32_t dense;        /* 1: also build the dense matrix M on the device (small systems)   */
+  int32_t max_block;    /* largest k passed to pprpa_matvec / Davidson block (<= 0: 32)     */
+  void* stream;         /* hipStream_t to order work on, or NULL (library-owned stream)     */
+} pprpa_build_args;
+
+/* Stage the problem on the current device: slice the active window, reorder L into the
+ * sigma kernels' padded layout in the chosen precision, tabulate pair energies, and (dense=1)
+ * build M. Copies everything it needs: no caller pointer is retained after return.
+ * Errors: EINVAL (sizes, window outside the spaces, non-finite eps/L, nv or no = 0 with no
+ * pairs), ENOMEM, EDEVICE. On error *out is set to NULL. */
+pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
+
+/* Packed dimensions of the context: n_pp (virtual pairs) and n_hh (occupied pairs). */
+pprpa_status pprpa_dims(const pprpa_ctx* ctx, int64_t* n_pp, int64_t* n_hh);
+
+/* sigma = M z for k packed vectors (the density-fitted product of the method: the A, B, B^T
+ * and C blocks of Eq. eigen_equation applied without forming M).
+ * z, sigma: [k][n] FP64, host or device (on_device). 1 <= k <= max_block.
+ * Errors: EINVAL, EDEVICE, EBUSY. */
+pprpa_status pprpa_matvec(pprpa_ctx* ctx, int32_t k, const double* z, double* sigma,
+                          int32_t on_device);
+
+/* The dense ppRPA matrix M = [[A, B], [B^T, C]] (requires dense=1 at build): [n][n] row-major
+ * FP64, host or device. Errors: EUNSUPPORTED (no dense build), EINVAL, EDEVICE. */
+pprpa_status pprpa_dense_matrix(pprpa_ctx* ctx, double* M, int32_t on_device);
+
+typedef struct {
+  int32_t nroot;        /* number of lowest pp roots wanted (>= 1)                          */
+  int32_t block;        /* max correction vectors added per iteration (<= 0: nroot)         */
+  int32_t max_iter;     /* iteration cap (<= 0: 100)                                        */
+  int32_t max_subspace; /* subspace size that triggers a restart (<= 0: automatic)          */
+  double tol;           /* converged when ||M z - Omega W z||_2 <= tol for every root       */
+  const double* guess;  /* optional [nguess][n] FP64 host start vectors, or NULL             */
+  int32_t nguess;
+  int32_t direct;       /* 1: dense direct diagonalisation (requires dense=1 at build)     */
+  void (*log)(void* user, const char* json_line); /* optional per-iteration log            */
+  void* user;
+} pprpa_davidson_args;
+
+typedef struct {
+  int32_t iters;        /* Davidson iterations done                                        */
+  int32_t n_sigma;      /* single-vector sigma products computed                           */
+  int32_t n_conv;       /* roots with residual <= tol                                      */
+  int32_t subspace;     /* final subspace size                                             */
+  double max_resid;     /* largest residual norm of the returned roots                     */
+  double t_sigma_s;     /* seconds in sigma launches (device events)                       */
+  double t_total_s;     /* seconds for the whole call (host clock)                         */
+} pprpa_report;
+
+/* Lowest nroot two-electron-addition (pp) roots Omega of Eq. eigen_equation, ascending,
+ * by the block Davidson method (direct=0) or by dense diagonalisation (direct=1).
+ * omega: [nroot] host. vecs: [nroot][n] host or NULL. resid: [nroot] host or NULL.
+ * rep: host or NULL. Returns ENOCONV (outputs filled with the last iterate) when max_iter is
+ * reached, ENONDEF if the projected pencil is not definite, EUNSUPPORTED for direct without
+ * a dense build, EINVAL for nroot > n_pp. */
+pprpa_status pprpa_davidson(pprpa_ctx* ctx, const pprpa_davidson_args* args, double* omega,
+                            double* vecs, double* resid, pprpa_report* rep);
+
+/* Release the context and all its device memory. NULL-safe. */
+void pprpa_free(pprpa_ctx* ctx);
+
+const char* pprpa_strerror(pprpa_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* pprpa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPRPA_H */

@@ -1,0 +1,241 @@
+"""ctypes binding of libpprpa.so (argument marshalling only; every step runs in the library).
+
+The names mirror the C ABI in include/pprpa.h: ``pprpa_build``, ``pprpa_matvec``,
+``pprpa_dense_matrix``, ``pprpa_davidson``, ``pprpa_free``. ``PpRPA`` wraps one context.
+
+Host arrays are NumPy float64; device arrays are torch tensors (float64, contiguous, on the
+context's GPU), passed by pointer. torch is used for nothing else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpprpa.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONDEF, EUNSUPPORTED, EBUSY = range(8)
+STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOCONV", "ENONDEF", "EUNSUPPORTED", "EBUSY"]
+MULT = {"singlet": 0, "triplet": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2, "bf16x3": 3}
+
+
+class PpRPAError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {msg}")
+
+
+class BuildArgs(C.Structure):
+    _fields_ = [("nmo", C.c_int32), ("nocc", C.c_int32), ("naux", C.c_int32),
+                ("nocc_act", C.c_int32), ("nvir_act", C.c_int32),
+                ("eps", C.c_void_p), ("Lpq", C.c_void_p),
+                ("lpq_is_active", C.c_int32), ("on_device", C.c_int32),
+                ("mult", C.c_int32), ("prec", C.c_int32), ("dense", C.c_int32),
+                ("max_block", C.c_int32), ("stream", C.c_void_p)]
+
+
+LOGFN = C.CFUNCTYPE(None, C.c_void_p, C.c_char_p)
+
+
+class DavidsonArgs(C.Structure):
+    _fields_ = [("nroot", C.c_int32), ("block", C.c_int32), ("max_iter", C.c_int32),
+                ("max_subspace", C.c_int32), ("tol", C.c_double), ("guess", C.c_void_p),
+                ("nguess", C.c_int32), ("direct", C.c_int32), ("log", LOGFN),
+                ("user", C.c_void_p)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_sigma", C.c_int32), ("n_conv", C.c_int32),
+                ("subspace", C.c_int32), ("max_resid", C.c_double), ("t_sigma_s", C.c_double),
+                ("t_total_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+EXPORTS = ["pprpa_build", "pprpa_dims", "pprpa_matvec", "pprpa_dense_matrix", "pprpa_davidson",
+           "pprpa_free", "pprpa_strerror", "pprpa_last_error"]
+
+
+def lib():
+    """Load libpprpa.so (raises if it has not been built: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 / libhsa-runtime64.so.1.
+    # Loading torch first makes the dynamic linker resolve this library's dependencies to those
+    # already-loaded copies (same SONAME), so torch tensors and this library share a runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_12515_amd.build`"
+                          " (there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    L.pprpa_build.argtypes = [C.POINTER(BuildArgs), C.POINTER(C.c_void_p)]
+    L.pprpa_build.restype = C.c_int
+    L.pprpa_dims.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.pprpa_dims.restype = C.c_int
+    L.pprpa_matvec.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]
+    L.pprpa_matvec.restype = C.c_int
+    L.pprpa_dense_matrix.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+    L.pprpa_dense_matrix.restype = C.c_int
+    L.pprpa_davidson.argtypes = [C.c_void_p, C.POINTER(DavidsonArgs), C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.POINTER(Report)]
+    L.pprpa_davidson.restype = C.c_int
+    L.pprpa_free.argtypes = [C.c_void_p]
+    L.pprpa_free.restype = None
+    L.pprpa_strerror.argtypes = [C.c_int]
+    L.pprpa_strerror.restype = C.c_char_p
+    L.pprpa_last_error.argtypes = []
+    L.pprpa_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != OK:
+        raise PpRPAError(status, lib().pprpa_last_error().decode())
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, on_device):
+    if on_device:
+        import torch  # noqa: F401  (only for tensors the caller handed in)
+        assert x.dtype.itemsize == 8 and x.is_contiguous(), "device arrays must be contiguous float64"
+        return C.c_void_p(x.data_ptr())
+    assert x.dtype == np.float64 and x.flags["C_CONTIGUOUS"], "host arrays must be C-contiguous float64"
+    return C.c_void_p(x.ctypes.data)
+
+
+class PpRPA:
+    """One staged ppRPA problem (a library context).
+
+    eps: [nmo] orbital energies; Lpq: [naux, nmo, nmo] (or the active block with
+    lpq_is_active). Both NumPy (host) or both torch CUDA tensors (device)."""
+
+    def __init__(self, eps, Lpq, nocc, mult="singlet", prec="fp64", nocc_act=0, nvir_act=0,
+                 lpq_is_active=False, dense=False, max_block=32, stream=None):
+        on_dev = _is_torch(Lpq) and Lpq.is_cuda
+        if not on_dev:
+            eps = np.ascontiguousarray(eps, dtype=np.float64)
+            Lpq = np.ascontiguousarray(Lpq, dtype=np.float64)
+        a = BuildArgs()
+        a.nmo = int(eps.shape[0])
+        a.nocc = int(nocc)
+        a.naux = int(Lpq.shape[0])
+        a.nocc_act = int(nocc_act or 0)
+        a.nvir_act = int(nvir_act or 0)
+        a.eps = _ptr(eps, on_dev).value
+        a.Lpq = _ptr(Lpq, on_dev).value
+        a.lpq_is_active = int(bool(lpq_is_active))
+        a.on_device = int(on_dev)
+        a.mult = MULT[mult]
+        a.prec = PREC[prec]
+        a.dense = int(bool(dense))
+        a.max_block = int(max_block)
+        a.stream = stream
+        h = C.c_void_p()
+        _check(lib().pprpa_build(C.byref(a), C.byref(h)))
+        self._h = h
+        npp, nhh = C.c_int64(), C.c_int64()
+        _check(lib().pprpa_dims(h, C.byref(npp), C.byref(nhh)))
+        self.n_pp, self.n_hh = npp.value, nhh.value
+        self.n = self.n_pp + self.n_hh
+        self.mult, self.prec = mult, prec
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pprpa_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- sigma = M z ---------------------------------------------------------------------
+    def matvec(self, z, out=None):
+        """z: [k, n] (or [n]) NumPy or torch CUDA float64; returns sigma of the same kind."""
+        on_dev = _is_torch(z) and z.is_cuda
+        one = z.ndim == 1
+        if on_dev:
+            z2 = z.reshape(1, -1) if one else z
+            z2 = z2.contiguous()
+            s = out if out is not None else z2.new_empty(z2.shape)
+        else:
+            z2 = np.ascontiguousarray(np.atleast_2d(z), dtype=np.float64)
+            s = np.empty_like(z2)
+        assert z2.shape[1] == self.n, f"vectors must have length n={self.n}"
+        _check(lib().pprpa_matvec(self._h, int(z2.shape[0]), _ptr(z2, on_dev), _ptr(s, on_dev),
+                                  int(on_dev)))
+        return s.reshape(-1) if one else s
+
+    def dense_matrix(self):
+        M = np.empty((self.n, self.n))
+        _check(lib().pprpa_dense_matrix(self._h, _ptr(M, False), 0))
+        return M
+
+    # -- eigensolvers ------------------------------------------------------------------------
+    def davidson(self, nroot, block=0, tol=1e-6, max_iter=0, max_subspace=0, guess=None,
+                 direct=False, vectors=False, log=None, raise_noconv=True):
+        a = DavidsonArgs()
+        a.nroot = int(nroot)
+        a.block = int(block)
+        a.max_iter = int(max_iter)
+        a.max_subspace = int(max_subspace)
+        a.tol = float(tol)
+        g = None
+        if guess is not None:
+            g = np.ascontiguousarray(np.atleast_2d(guess), dtype=np.float64)
+            a.guess = g.ctypes.data
+            a.nguess = g.shape[0]
+        a.direct = int(bool(direct))
+        lines = []
+        cb = LOGFN((lambda u, s: (lines.append(s.decode()), log and log(s.decode()))) if True else 0)
+        a.log = cb
+        omega = np.empty(nroot)
+        resid = np.empty(nroot)
+        vecs = np.empty((nroot, self.n)) if vectors else None
+        rep = Report()
+        st = lib().pprpa_davidson(self._h, C.byref(a), omega.ctypes.data,
+                                  vecs.ctypes.data if vectors else None, resid.ctypes.data,
+                                  C.byref(rep))
+        msg = lib().pprpa_last_error().decode()
+        if st not in (OK, ENOCONV) or (st == ENOCONV and raise_noconv):
+            raise PpRPAError(st, msg)
+        return dict(omega=omega, vecs=vecs, resid=resid, report=rep.as_dict(), status=st,
+                    log=lines, message=msg)
+
+
+# Plain-function forms with the C names (thin wrappers over PpRPA).
+def pprpa_build(eps, Lpq, nocc, **kw):
+    return PpRPA(eps, Lpq, nocc, **kw)
+
+
+def pprpa_matvec(ctx, z):
+    return ctx.matvec(z)
+
+
+def pprpa_davidson(ctx, nroot, **kw):
+    return ctx.davidson(nroot, **kw)
+
+
+def pprpa_free(ctx):
+    ctx.close()

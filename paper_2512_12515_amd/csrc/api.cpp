@@ -1,0 +1,398 @@
+// C ABI of libpprpa: argument checks, ownership, staging, sigma and dense entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "ctx.h"
+
+namespace pprpa {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+static pprpa_status einval(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return PPRPA_EINVAL;
+}
+
+pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    *p = nullptr;
+    return PPRPA_ENOMEM;
+  }
+  c->allocs.push_back(*p);
+  return PPRPA_OK;
+}
+
+// Aux-index splits of a sigma launch: enough workgroups to fill 256 CUs several times over.
+int nsplit_for(const pprpa_ctx* c, int k) {
+  const int target = 1536;
+  const int per = std::max(1, c->plan.nitems * k);
+  int ns = (target + per - 1) / per;
+  ns = std::min(ns, std::min(c->g.naux, 64));
+  return std::max(1, ns);
+}
+
+pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
+  const int64_t n = c->g.n;
+  for (int k0 = 0; k0 < k; k0 += c->kcap) {
+    const int kk = std::min(c->kcap, k - k0);
+    const double* z = dz + (int64_t)k0 * n;
+    double* s = ds + (int64_t)k0 * n;
+    const int ns = nsplit_for(c, kk);
+    PPRPA_HIP(launch_unpack(c->g, c->st, z, kk, c->ptab, c->ZT, c->zplane, c->stream));
+    SigmaLaunch la;
+    la.L = c->L;
+    la.ZT = c->ZT;
+    la.Sp = c->Sp;
+    la.k = kk;
+    la.nsplit = ns;
+    la.npan_v = c->plan.npan_v;
+    la.npan_o = 0;
+    la.plane = c->plane;
+    la.zplane = c->zplane;
+    la.nprod = c->nprod;
+    PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
+    PPRPA_HIP(launch_epilogue(c->g, c->st, z, kk, c->Sp, ns, c->ptab, c->epair, s, c->stream));
+  }
+  return PPRPA_OK;
+}
+
+}  // namespace pprpa
+
+using namespace pprpa;
+
+namespace {
+
+struct Busy {
+  std::atomic<int>& b;
+  bool ok;
+  explicit Busy(std::atomic<int>& x) : b(x) {
+    int e = 0;
+    ok = b.compare_exchange_strong(e, 1);
+  }
+  ~Busy() {
+    if (ok) b.store(0);
+  }
+};
+
+void destroy(pprpa_ctx* c) {
+  if (!c) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->dws.base) (void)hipFree(c->dws.base);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->e0) (void)hipEventDestroy(c->e0);
+  if (c->e1) (void)hipEventDestroy(c->e1);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  if (cur != c->device) (void)hipSetDevice(cur);
+  delete c;
+}
+
+pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
+  // ---- sizes and window ----------------------------------------------------------------
+  const int nmo = a->nmo, nocc = a->nocc, naux = a->naux;
+  const int nvir = nmo - nocc;
+  if (a->nocc_act > nocc) return einval("nocc_act=%d exceeds nocc=%d", a->nocc_act, nocc);
+  if (a->nvir_act > nvir) return einval("nvir_act=%d exceeds nvir=%d", a->nvir_act, nvir);
+  const int no = a->nocc_act > 0 ? a->nocc_act : nocc;
+  const int nv = a->nvir_act > 0 ? a->nvir_act : nvir;
+  const int mult = a->mult;
+  if (nv <= 0) return einval("no virtual orbitals in the window");
+  if (nv > 16000 || no > 16000) return einval("window too large (nv=%d, no=%d)", nv, no);
+  Geometry& g = c->g;
+  g.nv = nv;
+  g.no = no;
+  g.naux = naux;
+  g.mult = mult;
+  g.nvp = round_up(nv, TILE);
+  g.nop = round_up(no, TILE);
+  g.nmop = g.nvp + g.nop;
+  g.nvt = g.nvp / TILE;
+  g.nct = g.nmop / TILE;
+  const int k = mult == PPRPA_SINGLET ? 0 : 1;
+  g.nvv = (int64_t)nv * (nv + 1) / 2 - (int64_t)k * nv;
+  g.noo = (int64_t)no * (no + 1) / 2 - (int64_t)k * no;
+  g.n = g.nvv + g.noo;
+  if (g.nvv <= 0) return einval("no particle pairs (nv=%d, triplet)", nv);
+  c->prec = a->prec;
+  c->st = a->prec == PPRPA_FP64 ? Store::F64 : (a->prec == PPRPA_FP32 ? Store::F32 : Store::BF16);
+  c->nprod = a->prec == PPRPA_BF16X3 ? 3 : 6;
+  c->kcap = a->max_block > 0 ? std::min(a->max_block, 64) : 32;
+
+  // ---- energies (host copy; validated) -------------------------------------------------
+  std::vector<double> eps(nmo);
+  if (a->on_device) {
+    PPRPA_HIP(hipMemcpy(eps.data(), a->eps, nmo * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(eps.data(), a->eps, nmo * sizeof(double));
+  }
+  for (int i = 0; i < nmo; ++i)
+    if (!std::isfinite(eps[i])) return einval("eps[%d] is not finite", i);
+  c->eo_h.assign(eps.begin() + (nocc - no), eps.begin() + nocc);
+  c->ev_h.assign(eps.begin() + nocc, eps.begin() + nocc + nv);
+  c->mu2 = no > 0 ? c->eo_h.back() + c->ev_h.front() : 2.0 * (c->ev_h.front() - 1.0);
+
+  // ---- stream, events, pinned status buffer --------------------------------------------
+  PPRPA_HIP(hipGetDevice(&c->device));
+  if (a->stream) {
+    c->stream = (hipStream_t)a->stream;
+  } else {
+    PPRPA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  PPRPA_HIP(hipEventCreate(&c->e0));
+  PPRPA_HIP(hipEventCreate(&c->e1));
+  c->pinned_elems = 4096;
+  PPRPA_HIP(hipHostMalloc((void**)&c->pinned, c->pinned_elems * sizeof(double), hipHostMallocDefault));
+  PPRPA_HIP(prepare_kernels());
+
+  // ---- pair table and pair energies ----------------------------------------------------
+  c->ptab_h.resize(g.n);
+  {
+    int64_t e = 0;
+    for (int p = 0; p < nv; ++p)
+      for (int q = p + k; q < nv; ++q) c->ptab_h[e++] = (p << 16) | q;
+    for (int p = 0; p < no; ++p)
+      for (int q = p + k; q < no; ++q) c->ptab_h[e++] = (p << 16) | q;
+  }
+  PPRPA_TRY(dalloc(c, g.n * sizeof(int), (void**)&c->ptab));
+  PPRPA_TRY(dalloc(c, nv * sizeof(double), (void**)&c->ev));
+  PPRPA_TRY(dalloc(c, std::max(no, 1) * sizeof(double), (void**)&c->eo));
+  PPRPA_TRY(dalloc(c, g.n * sizeof(double), (void**)&c->epair));
+  PPRPA_HIP(hipMemcpyAsync(c->ptab, c->ptab_h.data(), g.n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  PPRPA_HIP(hipMemcpyAsync(c->ev, c->ev_h.data(), nv * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (no > 0)
+    PPRPA_HIP(hipMemcpyAsync(c->eo, c->eo_h.data(), no * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  PPRPA_HIP(launch_epair(g, c->ptab, c->ev, c->eo, c->epair, c->stream));
+
+  // ---- stage L ---------------------------------------------------------------------------
+  const int nin = a->lpq_is_active ? no + nv : nmo;
+  std::vector<int> src(g.nmop, -1);
+  for (int r = 0; r < nv; ++r) src[r] = a->lpq_is_active ? no + r : nocc + r;
+  for (int r = 0; r < no; ++r) src[g.nvp + r] = a->lpq_is_active ? r : nocc - no + r;
+  int* d_src = nullptr;
+  int* d_bad = nullptr;
+  PPRPA_TRY(dalloc(c, g.nmop * sizeof(int), (void**)&d_src));
+  PPRPA_TRY(dalloc(c, sizeof(int), (void**)&d_bad));
+  PPRPA_HIP(hipMemcpyAsync(d_src, src.data(), g.nmop * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  PPRPA_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
+  c->plane = (size_t)naux * g.nmop * g.nmop;
+  const size_t esz = c->st == Store::F64 ? 8 : (c->st == Store::F32 ? 4 : 2);
+  const size_t nplanes = c->st == Store::BF16 ? 3 : 1;
+  PPRPA_TRY(dalloc(c, c->plane * esz * nplanes, &c->L));
+  auto stage = [&](Store st, void* dst, size_t plane) -> pprpa_status {
+    if (a->on_device) {
+      for (int p0 = 0; p0 < naux; p0 += 65535) {
+        const int np = std::min(65535, naux - p0);
+        PPRPA_HIP(launch_stage_L(g, st, a->Lpq + (size_t)p0 * nin * nin, nin, p0, np, d_src, dst,
+                                 plane, d_bad, c->stream));
+      }
+      return PPRPA_OK;
+    }
+    const size_t per = (size_t)nin * nin;
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(65535, (size_t(256) << 20) / (per * 8)));
+    double* tmp = nullptr;
+    PPRPA_HIP(hipMalloc((void**)&tmp, (size_t)chunk * per * sizeof(double)));
+    pprpa_status rc = PPRPA_OK;
+    for (int p0 = 0; p0 < naux && rc == PPRPA_OK; p0 += chunk) {
+      const int np = std::min(chunk, naux - p0);
+      hipError_t e = hipMemcpyAsync(tmp, a->Lpq + (size_t)p0 * per, (size_t)np * per * sizeof(double),
+                                    hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = launch_stage_L(g, st, tmp, nin, p0, np, d_src, dst, plane, d_bad, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) {
+        set_error("staging L: %s", hipGetErrorString(e));
+        rc = PPRPA_EDEVICE;
+      }
+    }
+    (void)hipFree(tmp);
+    return rc;
+  };
+  PPRPA_TRY(stage(c->st, c->L, c->plane));
+  if (a->dense) {
+    if (c->st == Store::F64) {
+      c->L64 = (double*)c->L;
+    } else {
+      PPRPA_TRY(dalloc(c, c->plane * sizeof(double), (void**)&c->L64));
+      PPRPA_TRY(stage(Store::F64, c->L64, c->plane));
+    }
+  }
+  int bad = 0;
+  PPRPA_HIP(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  if (bad) return einval("Lpq contains non-finite values");
+
+  // ---- sigma plan and workspaces ---------------------------------------------------------
+  int RT = 16;
+  c->plan.variant = sigma_variant(g, c->st, &RT);
+  c->plan.RT = RT;
+  std::vector<int> items;
+  make_sigma_items(g, RT, items, c->plan.npan_v);
+  c->plan.nitems = (int)items.size();
+  PPRPA_TRY(dalloc(c, items.size() * sizeof(int), (void**)&c->plan.d_items));
+  PPRPA_HIP(hipMemcpyAsync(c->plan.d_items, items.data(), items.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+  size_t sp_max = 0;
+  for (int kk = 1; kk <= c->kcap; ++kk)
+    sp_max = std::max(sp_max, (size_t)nsplit_for(c, kk) * kk);
+  const size_t zz = (size_t)g.nmop * g.nmop;
+  c->zplane = (size_t)c->kcap * zz;
+  PPRPA_TRY(dalloc(c, c->zplane * esz * nplanes, &c->ZT));
+  PPRPA_HIP(hipMemsetAsync(c->ZT, 0, c->zplane * esz * nplanes, c->stream));
+  const size_t spsz = c->st == Store::F64 ? 8 : 4;
+  PPRPA_TRY(dalloc(c, sp_max * zz * spsz, &c->Sp));
+  PPRPA_TRY(dalloc(c, (size_t)c->kcap * g.n * sizeof(double), (void**)&c->zbuf));
+  PPRPA_TRY(dalloc(c, (size_t)c->kcap * g.n * sizeof(double), (void**)&c->sbuf));
+
+  // ---- dense matrix ------------------------------------------------------------------------
+  if (a->dense) {
+    if (g.n > 46000) return einval("dense build needs n <= 46000 (n=%lld)", (long long)g.n);
+    PPRPA_TRY(dalloc(c, (size_t)g.n * g.n * sizeof(double), (void**)&c->M));
+    PPRPA_HIP(launch_dense_build(g, c->L64, c->ptab, c->epair, c->M, c->stream));
+  }
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  return PPRPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pprpa_strerror(pprpa_status s) {
+  switch (s) {
+    case PPRPA_OK: return "ok";
+    case PPRPA_EINVAL: return "invalid argument";
+    case PPRPA_ENOMEM: return "out of device memory";
+    case PPRPA_EDEVICE: return "device error";
+    case PPRPA_ENOCONV: return "not converged";
+    case PPRPA_ENONDEF: return "pencil not definite";
+    case PPRPA_EUNSUPPORTED: return "unsupported";
+    case PPRPA_EBUSY: return "context busy";
+  }
+  return "unknown status";
+}
+
+const char* pprpa_last_error(void) { return pprpa::g_err.c_str(); }
+
+pprpa_status pprpa_build(const pprpa_build_args* a, pprpa_ctx** out) {
+  g_err.clear();
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (!a) return einval("args is NULL");
+  if (a->nmo <= 0 || a->naux <= 0) return einval("nmo=%d and naux=%d must be positive", a->nmo, a->naux);
+  if (a->nocc < 0 || a->nocc > a->nmo) return einval("nocc=%d outside [0, nmo=%d]", a->nocc, a->nmo);
+  if (!a->eps || !a->Lpq) return einval("eps and Lpq must not be NULL");
+  if (a->mult != PPRPA_SINGLET && a->mult != PPRPA_TRIPLET) return einval("mult=%d", a->mult);
+  if (a->prec < PPRPA_FP64 || a->prec > PPRPA_BF16X3) return einval("prec=%d", a->prec);
+  pprpa_ctx* c = new (std::nothrow) pprpa_ctx();
+  if (!c) return einval("host allocation failed");
+  pprpa_status s = build_impl(a, c);
+  if (s != PPRPA_OK) {
+    std::string keep = g_err;
+    destroy(c);
+    g_err = keep;
+    return s;
+  }
+  *out = c;
+  return PPRPA_OK;
+}
+
+pprpa_status pprpa_dims(const pprpa_ctx* c, int64_t* n_pp, int64_t* n_hh) {
+  if (!c) return einval("ctx is NULL");
+  if (n_pp) *n_pp = c->g.nvv;
+  if (n_hh) *n_hh = c->g.noo;
+  return PPRPA_OK;
+}
+
+pprpa_status pprpa_matvec(pprpa_ctx* c, int32_t k, const double* z, double* sigma,
+                          int32_t on_device) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  if (k <= 0) return einval("k=%d must be positive", k);
+  if (!z || !sigma) return einval("z and sigma must not be NULL");
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  const int64_t n = c->g.n;
+  if (on_device) {
+    PPRPA_TRY(sigma_device(c, k, z, sigma));
+  } else {
+    for (int k0 = 0; k0 < k; k0 += c->kcap) {
+      const int kk = std::min(c->kcap, k - k0);
+      PPRPA_HIP(hipMemcpyAsync(c->zbuf, z + (size_t)k0 * n, (size_t)kk * n * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+      PPRPA_TRY(sigma_device(c, kk, c->zbuf, c->sbuf));
+      PPRPA_HIP(hipMemcpyAsync(sigma + (size_t)k0 * n, c->sbuf, (size_t)kk * n * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+      PPRPA_HIP(hipStreamSynchronize(c->stream));
+    }
+  }
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  return PPRPA_OK;
+}
+
+pprpa_status pprpa_dense_matrix(pprpa_ctx* c, double* M, int32_t on_device) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  if (!M) return einval("M is NULL");
+  if (!c->M) {
+    set_error("context was built without dense=1");
+    return PPRPA_EUNSUPPORTED;
+  }
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  const size_t bytes = (size_t)c->g.n * c->g.n * sizeof(double);
+  PPRPA_HIP(hipMemcpyAsync(M, c->M, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  return PPRPA_OK;
+}
+
+pprpa_status pprpa_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
+                            double* vecs, double* resid, pprpa_report* rep) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  if (!a || !omega) return einval("args and omega must not be NULL");
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  return run_davidson(c, a, omega, vecs, resid, rep);
+}
+
+void pprpa_free(pprpa_ctx* c) { destroy(c); }
+
+}  // extern "C"

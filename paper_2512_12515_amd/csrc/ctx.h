@@ -1,0 +1,55 @@
+// The context behind the opaque pprpa_ctx handle.
+#pragma once
+
+#include "internal.h"
+
+struct pprpa_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  pprpa::Geometry g;
+  int prec = PPRPA_FP64;
+  pprpa::Store st = pprpa::Store::F64;
+  int nprod = 6;      // BF16 products (3 or 6)
+  double mu2 = 0.0;   // 2 mu = e_HOMO + e_LUMO of the active window
+  int kcap = 32;      // largest sigma block
+  int nsplit_max = 1;
+
+  void* L = nullptr;  // staged integrals [naux][nmop][nmop] (3 planes for BF16)
+  size_t plane = 0;   // elements per plane
+  double* L64 = nullptr;  // FP64 staged integrals for the dense build (may alias L)
+  int* ptab = nullptr;    // packed pair -> (p << 16 | q)
+  double* ev = nullptr;   // active virtual energies
+  double* eo = nullptr;   // active occupied energies
+  double* epair = nullptr;  // +(e_a+e_b) / -(e_i+e_j) per packed pair
+  void* ZT = nullptr;       // unpacked vectors [kcap][nmop][nmop] (3 planes for BF16)
+  size_t zplane = 0;
+  void* Sp = nullptr;       // sigma partial sums
+  double* zbuf = nullptr;   // [kcap][n] staging of host vectors
+  double* sbuf = nullptr;
+  double* M = nullptr;      // dense matrix [n][n] (dense builds)
+  pprpa::SigmaPlan plan;
+
+  std::vector<double> ev_h, eo_h;
+  std::vector<int> ptab_h;
+  std::atomic<int> busy{0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double* pinned = nullptr;  // small pinned host buffer for per-iteration status
+  size_t pinned_elems = 0;
+  std::vector<void*> allocs;
+
+  // Davidson workspace (grown on demand, reused across calls)
+  struct {
+    size_t bytes = 0;
+    void* base = nullptr;
+  } dws;
+};
+
+namespace pprpa {
+// sigma = M z for k vectors already on the device ([k][n] each), on the context's stream.
+pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds);
+int nsplit_for(const pprpa_ctx* c, int k);
+pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p);
+pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
+                          double* vecs, double* resid, pprpa_report* rep);
+}  // namespace pprpa

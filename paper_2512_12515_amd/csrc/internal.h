@@ -1,0 +1,141 @@
+// Internal declarations shared by the host side (api.cpp, davidson.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pprpa.h"
+
+namespace pprpa {
+
+void set_error(const char* fmt, ...);
+
+#define PPRPA_HIP(expr)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      ::pprpa::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,    \
+                         __LINE__);                                                          \
+      return PPRPA_EDEVICE;                                                                  \
+    }                                                                                        \
+  } while (0)
+
+#define PPRPA_TRY(expr)                   \
+  do {                                    \
+    pprpa_status s_ = (expr);             \
+    if (s_ != PPRPA_OK) return s_;        \
+  } while (0)
+
+// Tiles of the sigma kernels are 16 x 16 (one MFMA output tile).
+constexpr int TILE = 16;
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Geometry of the padded orbital layout used by the sigma kernels: virtual block first
+// (rows/cols [0, nvp)), then the occupied block ([nvp, nvp + nop)); each block padded with
+// zeros to a multiple of 16.
+struct Geometry {
+  int nv = 0, no = 0, naux = 0;
+  int nvp = 0, nop = 0, nmop = 0;
+  int nvt = 0, nct = 0;  // tiles in the virtual block; tiles in total
+  int mult = 0;          // 0 singlet, 1 triplet
+  int64_t nvv = 0, noo = 0, n = 0;
+};
+
+// Sigma precision and storage type.
+enum class Store { F64, F32, BF16 };
+
+// Arguments of one sigma launch.
+struct SigmaLaunch {
+  const void* L;     // staged integrals
+  const void* ZT;    // unpacked transposed vectors [kcap][nmop][nmop]
+  void* Sp;          // partial sums [nsplit][k][nmop][nmop]
+  int k;             // vectors in the block
+  int nsplit;        // aux-index splits
+  int npan_v, npan_o;
+  size_t plane;      // elements per bf16 plane of L (BF16 only)
+  size_t zplane;     // elements per bf16 plane of ZT (BF16 only)
+  int nprod;         // 3 or 6 (BF16 only)
+};
+
+// Sigma launch plan (kernel variant and its work-item table), fixed per context.
+struct SigmaPlan {
+  int variant = 0;
+  int RT = 16;
+  int nitems = 0;
+  int npan_v = 0;
+  int* d_items = nullptr;
+};
+void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v);
+int sigma_variant(const Geometry& g, Store st, int* RT);
+
+// --- kernel launchers (k_sigma.hip) -------------------------------------------------------
+hipError_t launch_stage_L(const Geometry& g, Store st, const double* Lin, int nin, int p0, int np,
+                          const int* d_src, void* Lout, size_t plane, int* d_bad,
+                          hipStream_t s);
+hipError_t launch_unpack(const Geometry& g, Store st, const double* z, int k, const int* d_ptab,
+                         void* ZT, size_t zplane, hipStream_t s);
+hipError_t launch_sigma(const Geometry& g, Store st, const SigmaPlan& plan, const SigmaLaunch& a,
+                        hipStream_t s);
+hipError_t launch_epilogue(const Geometry& g, Store st, const double* z, int k, const void* Sp,
+                           int nsplit, const int* d_ptab, const double* d_epair, double* sigma,
+                           hipStream_t s);
+hipError_t launch_check_finite(const double* x, size_t n, int* d_bad, hipStream_t s);
+
+// --- dense (k_dense.hip) -------------------------------------------------------------------
+hipError_t launch_dense_build(const Geometry& g, const double* L64, const int* d_ptab,
+                              const double* d_epair, double* M, hipStream_t s);
+hipError_t launch_epair(const Geometry& g, const int* d_ptab, const double* d_ev,
+                        const double* d_eo, double* d_epair, hipStream_t s);
+hipError_t launch_set_units(double* V, int64_t ld, const int64_t* idx, int r, hipStream_t s);
+hipError_t launch_metric_matrix(double* W, int64_t n, int64_t nvv, hipStream_t s);
+hipError_t launch_transpose(const double* in, int ldi, int m, int r, double* out, int64_t ldo,
+                            hipStream_t s);
+
+// --- FP64 linear algebra (k_linalg.hip) ----------------------------------------------------
+// C[i][j] (ldc) = sum_t A[i][t] * w(t) * B[j][t], i < ma, j < mb; w(t) = -1 for t >= nsplit_w
+// when signed != 0. A: [ma][n] (lda), B: [mb][n] (ldb). Uses partial buffer `part` of
+// nchunk * ma * mb doubles.
+hipError_t launch_dots(const double* A, int64_t lda, int ma, const double* B, int64_t ldb, int mb,
+                       int64_t n, int64_t nsign, int signed_w, double* C, int ldc, double* part,
+                       int nchunk, hipStream_t s);
+// Y[j][t] (ldy) = beta * Y[j][t] + alpha * sum_i Cm[i][j] X[i][t], i < m, j < r.
+// Cm: [m][ldcm] device.
+hipError_t launch_combine(const double* X, int64_t ldx, int m, const double* Cm, int ldcm, int r,
+                          int64_t n, double alpha, double beta, double* Y, int64_t ldy,
+                          hipStream_t s);
+// Residual + norms + preconditioner for r roots.
+hipError_t launch_residual(const double* Z, const double* SZ, int64_t ld, int r, int64_t n,
+                           int64_t nvv, const double* d_omega, double* R, double* part_norm,
+                           int nchunk, hipStream_t s);
+hipError_t launch_reduce_norms(const double* part, int nchunk, int r, double* out, hipStream_t s);
+hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nsel, int64_t n,
+                          int64_t nvv, const double* d_diag, const double* d_omega, double* T,
+                          int64_t ldt, hipStream_t s);
+// Pencil solve on one workgroup: K = Ms - 2 mu Ws = R R^T, G = R^-1 Ws R^-T = U diag(theta) U^T,
+// Omega = 2 mu + 1/theta; returns the nroot lowest pp roots and coefficient columns
+// Cout[m][nroot] with c^T Ws c = +1. work: 4*m*m doubles. info: [0] status (0 ok, 1 not
+// definite, 2 fewer than nroot pp roots, 3 no convergence), [1] number of pp roots.
+// Columns nroot..nret-1 of Cout hold the next Ritz vectors (kept on restart).
+hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
+                         int nret, double* omega, double* Cout, int ldc, double* work, int* info,
+                         hipStream_t s);
+hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
+hipError_t prepare_kernels();
+// Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.
+hipError_t launch_small_orth(const double* C, int ldc, int m, int r, double* Q, int ldq,
+                             int* rank, hipStream_t s);
+// Ms_new = Q^T Ms Q (r x r), one workgroup.
+hipError_t launch_small_congruence(const double* Ms, int ldm, int m, const double* Q, int ldq,
+                                   int r, double* out, int ldo, double* work, hipStream_t s);
+// Orthonormal basis of block T (b x n) against itself (symmetric orthonormalisation from its
+// Gram matrix with eigenvalue cut). Produces Tmat (b x b, rows = combos) and count kept.
+hipError_t launch_gram_orth(const double* G, int ldg, int b, double cut, double* Tm, int ldt,
+                            int* kept, double* work, hipStream_t s);
+hipError_t launch_scale_sign(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
+
+}  // namespace pprpa

@@ -1,0 +1,689 @@
+// FP64 linear algebra of the Davidson solver and of the direct path, on the GPU.
+//
+//  * tall-skinny products over the long pair dimension (HBM-bound, VALU FP64):
+//      dots     C = A diag(w) B^T       (subspace matrices V^T M V, V^T W V, projections)
+//      combine  Y = beta Y + alpha C^T X (Ritz vectors, projections, basis rotations)
+//      residual r = sigma(z) - Omega W z and its 2-norm; Davidson diagonal preconditioner
+//  * one-workgroup dense solvers for the small projected problems:
+//      pencil   the definite generalised eigenproblem M c = Omega W c via
+//               M - 2 mu W = R R^T (Cholesky), G = R^-1 W R^-T, G = U diag(theta) U^T (cyclic
+//               Jacobi, round-robin parallel ordering), Omega = 2 mu + 1/theta; pp roots have
+//               theta > 0 (c^T W c = +1 after scaling by 1/sqrt(theta))
+//      gram_orth / small_orth / congruence for the basis bookkeeping.
+#include "internal.h"
+
+namespace pprpa {
+namespace {
+
+constexpr int NT = 256;  // threads per block of the streaming kernels
+
+// ------------------------------------------------------------------------------------------
+// dots: part[chunk][i][j] = sum_{t in chunk} A[i][t] w(t) B[j][t]
+// ------------------------------------------------------------------------------------------
+constexpr int DOT_TT = 32;
+constexpr int DOT_NQ = 64;  // max pairs per thread => ma*mb <= 16384
+
+__global__ __launch_bounds__(NT) void k_dots(const double* __restrict__ A, int64_t lda, int ma,
+                                             const double* __restrict__ B, int64_t ldb, int mb,
+                                             int64_t n, int64_t nsign, int signed_w,
+                                             double* __restrict__ part) {
+  extern __shared__ double sh[];
+  double* sA = sh;                       // [ma][DOT_TT]
+  double* sB = sh + (size_t)ma * DOT_TT;  // [mb][DOT_TT]
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * chunk;
+  const int64_t t1 = t0 + chunk < n ? t0 + chunk : n;
+  const int npair = ma * mb;
+  double acc[DOT_NQ];
+#pragma unroll
+  for (int q = 0; q < DOT_NQ; ++q) acc[q] = 0.0;
+  for (int64_t tb = t0; tb < t1; tb += DOT_TT) {
+    const int tt = (int)((t1 - tb) < DOT_TT ? (t1 - tb) : DOT_TT);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ma * DOT_TT; e += NT) {
+      const int i = e / DOT_TT, t = e % DOT_TT;
+      sA[e] = t < tt ? A[i * lda + tb + t] : 0.0;
+    }
+    for (int e = threadIdx.x; e < mb * DOT_TT; e += NT) {
+      const int j = e / DOT_TT, t = e % DOT_TT;
+      double v = t < tt ? B[j * ldb + tb + t] : 0.0;
+      if (signed_w && tb + t >= nsign) v = -v;
+      sB[e] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < DOT_NQ; ++q) {
+      const int p = threadIdx.x + q * NT;
+      if (p < npair) {
+        const int i = p / mb, j = p % mb;
+        const double* a = sA + i * DOT_TT;
+        const double* b = sB + j * DOT_TT;
+        double s = 0.0;
+#pragma unroll 8
+        for (int t = 0; t < DOT_TT; ++t) s += a[t] * b[t];
+        acc[q] += s;
+      }
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * npair;
+#pragma unroll
+  for (int q = 0; q < DOT_NQ; ++q) {
+    const int p = threadIdx.x + q * NT;
+    if (p < npair) out[p] = acc[q];
+  }
+}
+
+__global__ void k_dots_reduce(const double* __restrict__ part, int nchunk, int ma, int mb,
+                              double* __restrict__ C, int ldc) {
+  const int p = blockIdx.x * NT + threadIdx.x;
+  if (p >= ma * mb) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * ma * mb + p];
+  C[(p / mb) * ldc + (p % mb)] = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// combine: Y[j][t] = beta Y[j][t] + alpha sum_i Cm[i][j] X[i][t]
+// ------------------------------------------------------------------------------------------
+template <int RMAX>
+__global__ __launch_bounds__(NT) void k_combine(const double* __restrict__ X, int64_t ldx, int m,
+                                                const double* __restrict__ Cm, int ldcm, int r,
+                                                int64_t n, double alpha, double beta,
+                                                double* __restrict__ Y, int64_t ldy) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= n) return;
+  double acc[RMAX];
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) acc[j] = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double x = X[i * ldx + t];
+    const double* c = Cm + (size_t)i * ldcm;
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j)
+      if (j < r) acc[j] += c[j] * x;
+  }
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    if (j < r) {
+      double* y = Y + j * ldy + t;
+      *y = (beta == 0.0 ? 0.0 : beta * *y) + alpha * acc[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// residuals: R[j][t] = SZ[j][t] - omega_j w(t) Z[j][t]; partial squared norms per chunk
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_residual(const double* __restrict__ Z,
+                                                 const double* __restrict__ SZ, int64_t ld,
+                                                 int64_t n, int64_t nvv,
+                                                 const double* __restrict__ omega,
+                                                 double* __restrict__ R, double* __restrict__ part) {
+  __shared__ double red[NT];
+  const int j = blockIdx.y;
+  const double om = omega[j];
+  double s = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) {
+    const double w = t < nvv ? 1.0 : -1.0;
+    const double r = SZ[j * ld + t] - om * w * Z[j * ld + t];
+    R[j * ld + t] = r;
+    s += r * r;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_reduce_norms(const double* __restrict__ part, int nchunk, int r,
+                               double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= r) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)j * nchunk + c];
+  out[j] = sqrt(s);
+}
+
+struct SelList {
+  int idx[64];
+};
+
+// Davidson correction t = r / (omega w - D), |den| floored at 1e-6 (D = diagonal pair energies
+// with the sign of the metric block: +(e_a+e_b) for x, -(e_i+e_j) for y).
+__global__ __launch_bounds__(NT) void k_precond(const double* __restrict__ R, int64_t ld,
+                                                SelList sel, int64_t n, int64_t nvv,
+                                                const double* __restrict__ diag,
+                                                const double* __restrict__ omega,
+                                                double* __restrict__ T, int64_t ldt) {
+  const int jj = blockIdx.y;
+  const int j = sel.idx[jj];
+  const double om = omega[j];
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) {
+    const double w = t < nvv ? 1.0 : -1.0;
+    double den = om * w - diag[t];
+    if (fabs(den) < 1e-6) den = den < 0.0 ? -1e-6 : 1e-6;
+    T[jj * ldt + t] = R[j * ld + t] / den;
+  }
+}
+
+// Make the largest-magnitude component of each row positive (ties: lowest index).
+__global__ __launch_bounds__(NT) void k_scale_sign(double* __restrict__ V, int64_t ld, int64_t n) {
+  __shared__ double bv[NT];
+  __shared__ int64_t bi[NT];
+  double* v = V + blockIdx.x * ld;
+  double best = -1.0;
+  int64_t besti = 0;
+  for (int64_t t = threadIdx.x; t < n; t += NT) {
+    const double a = fabs(v[t]);
+    if (a > best) {
+      best = a;
+      besti = t;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = besti;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const double o = bv[threadIdx.x + h];
+      const int64_t oi = bi[threadIdx.x + h];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const double sgn = v[bi[0]] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
+  if (sgn < 0.0)
+    for (int64_t t = threadIdx.x; t < n; t += NT) v[t] = -v[t];
+}
+
+// Scale each row to unit 2-norm (rows of zero norm are left as they are).
+__global__ __launch_bounds__(NT) void k_normalize_rows(double* __restrict__ V, int64_t ld, int64_t n) {
+  __shared__ double red[NT];
+  double* v = V + blockIdx.x * ld;
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += NT) s += v[t] * v[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  if (nrm > 0.0) {
+    const double inv = 1.0 / nrm;
+    for (int64_t t = threadIdx.x; t < n; t += NT) v[t] *= inv;
+  }
+}
+
+__global__ void k_fill(double* __restrict__ p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// One-workgroup dense kernels (1024 threads). Matrices live in global memory (L2-resident).
+// ------------------------------------------------------------------------------------------
+constexpr int WG = 1024;
+constexpr int JMAX = 512;  // largest matrix order handled by the Jacobi solver
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = WG / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Cyclic Jacobi on the symmetric m x m matrix G (ld), accumulating eigenvectors into U (ld).
+// Round-robin ordering: m (padded to even) - 1 rounds of m/2 disjoint rotations per sweep.
+// On return G's diagonal holds the eigenvalues and U's columns the eigenvectors.
+__device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, double* cs,
+                           double* sn) {
+  const int me = m + (m & 1);
+  const int half = me / 2;
+  for (int e = threadIdx.x; e < m * m; e += WG) U[(e / m) * ld + (e % m)] = (e / m == e % m);
+  __syncthreads();
+  if (m < 2) return 0;
+  __shared__ int nrot;
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) nrot = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < me - 1; ++rnd) {
+      // rotation parameters for each pair of this round
+      for (int pi = threadIdx.x; pi < half; pi += WG) {
+        int p, q;
+        if (pi == 0) {
+          p = 0;
+          q = rnd % (me - 1) + 1;
+        } else {
+          p = (rnd + pi) % (me - 1) + 1;
+          q = (rnd - pi + me - 1) % (me - 1) + 1;
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < m) {
+          const double apq = G[p * ld + q];
+          const double app = G[p * ld + p], aqq = G[q * ld + q];
+          // rotate unless |apq| is negligible against the diagonal (relative 1e-17)
+          if (fabs(apq) > 1e-17 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > 1e-300) {
+            atomicAdd(&nrot, 1);
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        cs[pi] = c;
+        sn[pi] = s;
+        red[2 * pi] = (double)p;
+        red[2 * pi + 1] = (double)q;
+      }
+      __syncthreads();
+      // G <- J^T G J on all 2x2 blocks (pair a, pair b)
+      for (int e = threadIdx.x; e < half * half; e += WG) {
+        const int pa = e / half, pb = e % half;
+        const int p = (int)red[2 * pa], q = (int)red[2 * pa + 1];
+        const int r = (int)red[2 * pb], s = (int)red[2 * pb + 1];
+        if (q >= m || s >= m) {
+          // pairs with the padding index: rotate only the real row/column
+          if (q >= m && s >= m) {
+          } else if (q >= m) {
+            // row p only (c=1,s=0 for pair a); columns rotate by pair b
+            const double c2 = cs[pb], s2 = sn[pb];
+            const double x0 = G[p * ld + r], x1 = G[p * ld + s];
+            G[p * ld + r] = c2 * x0 - s2 * x1;
+            G[p * ld + s] = s2 * x0 + c2 * x1;
+          } else {
+            const double c1 = cs[pa], s1 = sn[pa];
+            const double x0 = G[p * ld + r], x1 = G[q * ld + r];
+            G[p * ld + r] = c1 * x0 - s1 * x1;
+            G[q * ld + r] = s1 * x0 + c1 * x1;
+          }
+          continue;
+        }
+        const double c1 = cs[pa], s1 = sn[pa], c2 = cs[pb], s2 = sn[pb];
+        const double apr = G[p * ld + r], aps = G[p * ld + s];
+        const double aqr = G[q * ld + r], aqs = G[q * ld + s];
+        const double x0r = c1 * apr - s1 * aqr, x0s = c1 * aps - s1 * aqs;
+        const double x1r = s1 * apr + c1 * aqr, x1s = s1 * aps + c1 * aqs;
+        G[p * ld + r] = c2 * x0r - s2 * x0s;
+        G[p * ld + s] = s2 * x0r + c2 * x0s;
+        G[q * ld + r] = c2 * x1r - s2 * x1s;
+        G[q * ld + s] = s2 * x1r + c2 * x1s;
+      }
+      // U <- U J
+      for (int e = threadIdx.x; e < m * half; e += WG) {
+        const int i = e / half, pb = e % half;
+        const int r = (int)red[2 * pb], s = (int)red[2 * pb + 1];
+        if (s >= m) continue;
+        const double c2 = cs[pb], s2 = sn[pb];
+        const double u0 = U[i * ld + r], u1 = U[i * ld + s];
+        U[i * ld + r] = c2 * u0 - s2 * u1;
+        U[i * ld + s] = s2 * u0 + c2 * u1;
+      }
+      __syncthreads();
+    }
+    if (nrot == 0) break;
+    __syncthreads();
+  }
+  return sweep >= 60 ? 1 : 0;
+}
+
+// Pencil: see launch_pencil. work holds 4 m x m matrices (ld = m): K/R, Rinv, G, U.
+__global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
+                                               const double* __restrict__ Ws, int ldm, int m,
+                                               double mu2, int nroot, int nret,
+                                               double* __restrict__ omega, double* __restrict__ Cout,
+                                               int ldc, double* __restrict__ work,
+                                               int* __restrict__ info) {
+  __shared__ double red[WG];
+  __shared__ double cs[JMAX / 2 + 1], sn[JMAX / 2 + 1];
+  __shared__ int flag;
+  __shared__ int rank_of[JMAX];
+  double* K = work;
+  double* Ri = work + (size_t)m * m;
+  double* G = work + 2 * (size_t)m * m;
+  double* U = work + 3 * (size_t)m * m;
+  if (threadIdx.x == 0) flag = 0;
+  // K = sym(Ms) - mu2 sym(Ws), from the upper triangles
+  for (int e = threadIdx.x; e < m * m; e += WG) {
+    const int i = e / m, j = e % m;
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    K[e] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
+    Ri[e] = 0.0;
+  }
+  __syncthreads();
+  // Cholesky K = R R^T (lower, in place)
+  for (int j = 0; j < m; ++j) {
+    const double d = K[j * m + j];
+    if (!(d > 0.0)) {
+      if (threadIdx.x == 0) flag = 1;
+      __syncthreads();
+      break;
+    }
+    const double rjj = sqrt(d);
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < m; i += WG) K[i * m + j] /= rjj;
+    if (threadIdx.x == 0) K[j * m + j] = rjj;
+    __syncthreads();
+    const int nt = m - j - 1;
+    for (int e = threadIdx.x; e < nt * nt; e += WG) {
+      const int i = j + 1 + e / nt, k = j + 1 + e % nt;
+      if (k <= i) K[i * m + k] -= K[i * m + j] * K[k * m + j];
+    }
+    __syncthreads();
+  }
+  if (flag) {
+    if (threadIdx.x == 0) {
+      info[0] = 1;
+      info[1] = 0;
+    }
+    return;
+  }
+  // Ri = R^-1 (lower): column c by forward substitution, one thread per column
+  for (int c = threadIdx.x; c < m; c += WG) {
+    for (int i = c; i < m; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= K[i * m + k] * Ri[k * m + c];
+      Ri[i * m + c] = s / K[i * m + i];
+    }
+  }
+  __syncthreads();
+  // G = Ri Wsym Ri^T: first U = Ri Wsym (U used as scratch)
+  for (int e = threadIdx.x; e < m * m; e += WG) {
+    const int i = e / m, j = e % m;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) {
+      const int a = k < j ? k : j, b = k < j ? j : k;
+      s += Ri[i * m + k] * Ws[a * ldm + b];
+    }
+    U[e] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += WG) {
+    const int i = e / m, j = e % m;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int k = 0; k <= j; ++k) s += U[i * m + k] * Ri[j * m + k];
+    G[i * m + j] = s;
+    G[j * m + i] = s;
+  }
+  __syncthreads();
+  const int nconv = jacobi_eigh(G, m, m, U, red, cs, sn);
+  // rank positive theta in descending order
+  for (int i = threadIdx.x; i < m; i += WG) {
+    const double ti = G[i * m + i];
+    int rk = -1;
+    if (ti > 0.0) {
+      rk = 0;
+      for (int j = 0; j < m; ++j) {
+        const double tj = G[j * m + j];
+        if (tj > ti || (tj == ti && j < i)) rk += (tj > 0.0);
+      }
+    }
+    rank_of[i] = rk;
+  }
+  __syncthreads();
+  int npos = 0;
+  for (int i = threadIdx.x; i < m; i += WG) npos += (G[i * m + i] > 0.0);
+  npos = (int)block_sum((double)npos, red);
+  // outputs: columns j < nret: c_j = Ri^T u / sqrt(theta)
+  for (int i = threadIdx.x; i < m; i += WG) {
+    const int rk = rank_of[i];
+    if (rk >= 0 && rk < nret) {
+      const double th = G[i * m + i];
+      if (rk < nroot) omega[rk] = mu2 + 1.0 / th;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * nret; e += WG) {
+    const int row = e / nret, rk = e % nret;
+    if (rk >= npos) {
+      Cout[row * ldc + rk] = 0.0;
+      continue;
+    }
+    int col = -1;
+    for (int i = 0; i < m; ++i)
+      if (rank_of[i] == rk) col = i;
+    const double th = G[col * m + col];
+    double s = 0.0;
+    for (int k = row; k < m; ++k) s += Ri[k * m + row] * U[k * m + col];
+    Cout[row * ldc + rk] = s / sqrt(th);
+  }
+  if (threadIdx.x == 0) {
+    info[0] = nconv ? 3 : (npos < nroot ? 2 : 0);
+    info[1] = npos;
+  }
+}
+
+// Q = orth(C[:, :r]) by modified Gram-Schmidt, twice; columns with relative norm below 1e-10
+// are dropped. Q: [m][ldq]; rank written to rank[0].
+__global__ __launch_bounds__(WG) void k_small_orth(const double* __restrict__ C, int ldc, int m,
+                                                   int r, double* __restrict__ Q, int ldq,
+                                                   int* __restrict__ rank) {
+  __shared__ double red[WG];
+  int kept = 0;
+  for (int j = 0; j < r; ++j) {
+    // copy column j into column kept
+    for (int i = threadIdx.x; i < m; i += WG) Q[i * ldq + kept] = C[i * ldc + j];
+    __syncthreads();
+    double n0 = 0.0;
+    for (int i = threadIdx.x; i < m; i += WG) n0 += Q[i * ldq + kept] * Q[i * ldq + kept];
+    n0 = sqrt(block_sum(n0, red));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int k = 0; k < kept; ++k) {
+        double d = 0.0;
+        for (int i = threadIdx.x; i < m; i += WG) d += Q[i * ldq + k] * Q[i * ldq + kept];
+        d = block_sum(d, red);
+        for (int i = threadIdx.x; i < m; i += WG) Q[i * ldq + kept] -= d * Q[i * ldq + k];
+        __syncthreads();
+      }
+    }
+    double nn = 0.0;
+    for (int i = threadIdx.x; i < m; i += WG) nn += Q[i * ldq + kept] * Q[i * ldq + kept];
+    nn = sqrt(block_sum(nn, red));
+    if (nn > 1e-10 * n0 && nn > 1e-300) {
+      for (int i = threadIdx.x; i < m; i += WG) Q[i * ldq + kept] /= nn;
+      __syncthreads();
+      ++kept;
+    }
+  }
+  if (threadIdx.x == 0) rank[0] = kept;
+}
+
+// out = Q^T sym(A) Q, A upper-stored (ld lda), Q [m][ldq] r columns; work m*r.
+__global__ __launch_bounds__(WG) void k_congruence(const double* __restrict__ A, int lda, int m,
+                                                   const double* __restrict__ Q, int ldq, int r,
+                                                   double* __restrict__ out, int ldo,
+                                                   double* __restrict__ work) {
+  for (int e = threadIdx.x; e < m * r; e += WG) {
+    const int i = e / r, j = e % r;
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const int a = i < k ? i : k, b = i < k ? k : i;
+      s += A[a * lda + b] * Q[k * ldq + j];
+    }
+    work[e] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * r; e += WG) {
+    const int i = e / r, j = e % r;
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += Q[k * ldq + i] * work[k * r + j];
+    out[i * ldo + j] = s;
+  }
+}
+
+// Symmetric orthonormalisation of a block from its Gram matrix G (b x b): G = U diag(l) U^T;
+// keep l_j > cut * l_max (descending order); Tm[i][jj] = U[i][j] / sqrt(l_j).
+__global__ __launch_bounds__(WG) void k_gram_orth(const double* __restrict__ Gin, int ldg, int b,
+                                                  double cut, double* __restrict__ Tm, int ldt,
+                                                  int* __restrict__ kept,
+                                                  double* __restrict__ work) {
+  __shared__ double red[WG];
+  __shared__ double cs[JMAX / 2 + 1], sn[JMAX / 2 + 1];
+  __shared__ int rank_of[JMAX];
+  double* G = work;
+  double* U = work + (size_t)b * b;
+  for (int e = threadIdx.x; e < b * b; e += WG) {
+    const int i = e / b, j = e % b;
+    G[e] = 0.5 * (Gin[i * ldg + j] + Gin[j * ldg + i]);
+  }
+  __syncthreads();
+  jacobi_eigh(G, b, b, U, red, cs, sn);
+  double lmax = 0.0;
+  for (int i = 0; i < b; ++i) lmax = fmax(lmax, G[i * b + i]);
+  for (int i = threadIdx.x; i < b; i += WG) {
+    const double li = G[i * b + i];
+    int rk = -1;
+    if (li > cut * lmax && li > 1e-280) {
+      rk = 0;
+      for (int j = 0; j < b; ++j) {
+        const double lj = G[j * b + j];
+        if (lj > li || (lj == li && j < i)) rk += (lj > cut * lmax && lj > 1e-280);
+      }
+    }
+    rank_of[i] = rk;
+  }
+  __syncthreads();
+  int nk = 0;
+  for (int i = 0; i < b; ++i) nk += rank_of[i] >= 0;
+  for (int e = threadIdx.x; e < b * b; e += WG) {
+    const int row = e / b, i = e % b;
+    const int rk = rank_of[i];
+    if (rk >= 0) Tm[row * ldt + rk] = U[row * b + i] / sqrt(G[i * b + i]);
+  }
+  if (threadIdx.x == 0) kept[0] = nk;
+}
+
+}  // namespace
+
+// ==========================================================================================
+// Launchers
+// ==========================================================================================
+hipError_t launch_dots(const double* A, int64_t lda, int ma, const double* B, int64_t ldb, int mb,
+                       int64_t n, int64_t nsign, int signed_w, double* C, int ldc, double* part,
+                       int nchunk, hipStream_t s) {
+  if (ma * mb > DOT_NQ * NT) return hipErrorInvalidValue;
+  const size_t shm = (size_t)(ma + mb) * DOT_TT * sizeof(double);
+  hipLaunchKernelGGL(k_dots, dim3(nchunk), dim3(NT), shm, s, A, lda, ma, B, ldb, mb, n, nsign,
+                     signed_w, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_reduce, dim3((ma * mb + NT - 1) / NT), dim3(NT), 0, s, part, nchunk,
+                     ma, mb, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const double* X, int64_t ldx, int m, const double* Cm, int ldcm, int r,
+                          int64_t n, double alpha, double beta, double* Y, int64_t ldy,
+                          hipStream_t s) {
+  if (r <= 0 || n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + NT - 1) / NT));
+  if (r <= 8)
+    hipLaunchKernelGGL(k_combine<8>, grid, dim3(NT), 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy);
+  else if (r <= 16)
+    hipLaunchKernelGGL(k_combine<16>, grid, dim3(NT), 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy);
+  else if (r <= 32)
+    hipLaunchKernelGGL(k_combine<32>, grid, dim3(NT), 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy);
+  else if (r <= 64)
+    hipLaunchKernelGGL(k_combine<64>, grid, dim3(NT), 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const double* Z, const double* SZ, int64_t ld, int r, int64_t n,
+                           int64_t nvv, const double* d_omega, double* R, double* part_norm,
+                           int nchunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(nchunk, r), dim3(NT), 0, s, Z, SZ, ld, n, nvv, d_omega, R,
+                     part_norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norms(const double* part, int nchunk, int r, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_norms, dim3((r + 63) / 64), dim3(64), 0, s, part, nchunk, r, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nsel, int64_t n,
+                          int64_t nvv, const double* d_diag, const double* d_omega, double* T,
+                          int64_t ldt, hipStream_t s) {
+  if (nsel <= 0) return hipSuccess;
+  if (nsel > 64) return hipErrorInvalidValue;
+  SelList sl;
+  for (int i = 0; i < 64; ++i) sl.idx[i] = i < nsel ? h_sel[i] : 0;
+  const int nb = (int)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_precond, dim3(nb, nsel), dim3(NT), 0, s, R, ld, sl, n, nvv, d_diag,
+                     d_omega, T, ldt);
+  return hipGetLastError();
+}
+
+hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
+                         int nret, double* omega, double* Cout, int ldc, double* work, int* info,
+                         hipStream_t s) {
+  if (m > JMAX || nret > WG) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pencil, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret, omega,
+                     Cout, ldc, work, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_orth(const double* C, int ldc, int m, int r, double* Q, int ldq,
+                             int* rank, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_orth, dim3(1), dim3(WG), 0, s, C, ldc, m, r, Q, ldq, rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_congruence(const double* Ms, int ldm, int m, const double* Q, int ldq,
+                                   int r, double* out, int ldo, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_congruence, dim3(1), dim3(WG), 0, s, Ms, ldm, m, Q, ldq, r, out, ldo, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_orth(const double* G, int ldg, int b, double cut, double* Tm, int ldt,
+                            int* kept, double* work, hipStream_t s) {
+  if (b > JMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gram_orth, dim3(1), dim3(WG), 0, s, G, ldg, b, cut, Tm, ldt, kept, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_sign(double* V, int64_t ld, int r, int64_t n, hipStream_t s) {
+  if (r <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_sign, dim3(r), dim3(NT), 0, s, V, ld, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s) {
+  if (r <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize_rows, dim3(r), dim3(NT), 0, s, V, ld, n);
+  return hipGetLastError();
+}
+
+hipError_t prepare_kernels() {
+  return hipFuncSetAttribute((const void*)k_dots, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             96 * 1024);
+}
+
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = (int)std::min<size_t>((n + NT - 1) / NT, 4096);
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NT), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace pprpa

@@ -1,0 +1,84 @@
+"""The C-ABI library: exports and argument checks that return before touching a GPU (CPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2512_12515_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "pprpa.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:pprpa_status|void|const char\*)\s+(pprpa_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["pprpa_build", "pprpa_matvec", "pprpa_davidson", "pprpa_dims", "pprpa_free",
+              "pprpa_dense_matrix", "pprpa_strerror", "pprpa_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_strerror():
+    L = B.lib()
+    assert L.pprpa_strerror(0) == b"ok"
+    assert L.pprpa_strerror(4) == b"not converged"
+
+
+def _args(**over):
+    eps = np.linspace(-1, 1, 6)
+    L = np.zeros((3, 6, 6))
+    a = B.BuildArgs()
+    a.nmo, a.nocc, a.naux = 6, 2, 3
+    a.eps = eps.ctypes.data
+    a.Lpq = L.ctypes.data
+    a.mult, a.prec = 0, 0
+    for k, v in over.items():
+        setattr(a, k, v)
+    return a, eps, L
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(nocc=7), "nocc"),
+    (dict(nocc=-1), "nocc"),
+    (dict(naux=0), "naux"),
+    (dict(mult=2), "mult"),
+    (dict(prec=9), "prec"),
+    (dict(nocc_act=3), "nocc_act"),
+    (dict(nvir_act=5), "nvir_act"),
+    (dict(nocc=6), "virtual"),
+])
+def test_build_rejects_invalid_arguments(over, msg):
+    a, eps, L = _args(**over)
+    h = C.c_void_p(1234)
+    st = B.lib().pprpa_build(C.byref(a), C.byref(h))
+    assert st == B.EINVAL
+    assert h.value is None
+    assert msg in B.lib().pprpa_last_error().decode()
+
+
+def test_build_rejects_non_finite_energies():
+    a, eps, L = _args()
+    eps[3] = np.nan
+    h = C.c_void_p()
+    assert B.lib().pprpa_build(C.byref(a), C.byref(h)) == B.EINVAL
+    assert "not finite" in B.lib().pprpa_last_error().decode()
+
+
+def test_null_arguments():
+    L = B.lib()
+    assert L.pprpa_build(None, None) == B.EINVAL
+    L.pprpa_free(None)  # NULL-safe
+    assert L.pprpa_matvec(None, 1, None, None, 0) == B.EINVAL
+    d = B.DavidsonArgs()
+    assert L.pprpa_davidson(None, C.byref(d), None, None, None, None) == B.EINVAL
