@@ -134,6 +134,19 @@ typedef struct {
 pprpa_status pprpa_davidson(pprpa_ctx* ctx, const pprpa_davidson_args* args, double* omega,
                             double* vecs, double* resid, pprpa_report* rep);
 
+/* Timing of the sigma contraction kernel (the fused sandwich kernel only, without the unpack
+ * and epilogue kernels), measured with HIP events recorded on the context's stream around
+ * every launch since the last reset. flops and bytes are algorithmic counts: per vector
+ * 4 naux (nv + no) (nv^2 + no^2) flops; per launch the staged integrals once plus the packed
+ * input and output vectors. */
+typedef struct {
+  int64_t launches;
+  double seconds;
+  double flops;
+  double bytes;
+} pprpa_kernel_stats;
+pprpa_status pprpa_sigma_stats(pprpa_ctx* ctx, pprpa_kernel_stats* out, int32_t reset);
+
 /* Release the context and all its device memory. NULL-safe. */
 void pprpa_free(pprpa_ctx* ctx);
 

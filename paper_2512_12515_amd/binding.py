@@ -57,9 +57,17 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 EXPORTS = ["pprpa_build", "pprpa_dims", "pprpa_matvec", "pprpa_dense_matrix", "pprpa_davidson",
-           "pprpa_free", "pprpa_strerror", "pprpa_last_error"]
+           "pprpa_free", "pprpa_strerror", "pprpa_last_error", "pprpa_sigma_stats"]
 
 
 def lib():
@@ -89,6 +97,8 @@ def lib():
     L.pprpa_davidson.argtypes = [C.c_void_p, C.POINTER(DavidsonArgs), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.POINTER(Report)]
     L.pprpa_davidson.restype = C.c_int
+    L.pprpa_sigma_stats.argtypes = [C.c_void_p, C.POINTER(KernelStats), C.c_int32]
+    L.pprpa_sigma_stats.restype = C.c_int
     L.pprpa_free.argtypes = [C.c_void_p]
     L.pprpa_free.restype = None
     L.pprpa_strerror.argtypes = [C.c_int]
@@ -186,6 +196,12 @@ class PpRPA:
         _check(lib().pprpa_matvec(self._h, int(z2.shape[0]), _ptr(z2, on_dev), _ptr(s, on_dev),
                                   int(on_dev)))
         return s.reshape(-1) if one else s
+
+    def sigma_stats(self, reset=False):
+        """Event-timed launches of the sigma contraction kernel since the last reset."""
+        st = KernelStats()
+        _check(lib().pprpa_sigma_stats(self._h, C.byref(st), int(bool(reset))))
+        return st.as_dict()
 
     def dense_matrix(self):
         M = np.empty((self.n, self.n))

@@ -54,6 +54,31 @@ int nsplit_for(const pprpa_ctx* c, int k) {
   return std::max(1, ns);
 }
 
+static pprpa_status get_event(pprpa_ctx* c, hipEvent_t* e) {
+  if (!c->pool.empty()) {
+    *e = c->pool.back();
+    c->pool.pop_back();
+    return PPRPA_OK;
+  }
+  PPRPA_HIP(hipEventCreate(e));
+  return PPRPA_OK;
+}
+
+pprpa_status harvest_timing(pprpa_ctx* c) {
+  for (auto& t : c->pend) {
+    float ms = 0.f;
+    PPRPA_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+    c->stats.launches += 1;
+    c->stats.seconds += ms * 1e-3;
+    c->stats.flops += t.flops;
+    c->stats.bytes += t.bytes;
+    c->pool.push_back(t.a);
+    c->pool.push_back(t.b);
+  }
+  c->pend.clear();
+  return PPRPA_OK;
+}
+
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
   const int64_t n = c->g.n;
   for (int k0 = 0; k0 < k; k0 += c->kcap) {
@@ -73,7 +98,19 @@ pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
     la.plane = c->plane;
     la.zplane = c->zplane;
     la.nprod = c->nprod;
+    pprpa_ctx::Timed tm;
+    PPRPA_TRY(get_event(c, &tm.a));
+    PPRPA_TRY(get_event(c, &tm.b));
+    const Geometry& g = c->g;
+    const double nmo = g.nv + g.no;
+    tm.flops = 4.0 * g.naux * nmo * ((double)g.nv * g.nv + (double)g.no * g.no) * kk;
+    const double esz = c->st == Store::F64 ? 8.0 : (c->st == Store::F32 ? 4.0 : 2.0 * (c->nprod == 3 ? 2 : 3));
+    tm.bytes = (double)g.naux * ((double)g.nv * g.nv + (double)g.nv * g.no + (double)g.no * g.no) * esz +
+               2.0 * kk * (double)n * 8.0;
+    PPRPA_HIP(hipEventRecord(tm.a, c->stream));
     PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
+    PPRPA_HIP(hipEventRecord(tm.b, c->stream));
+    c->pend.push_back(tm);
     PPRPA_HIP(launch_epilogue(c->g, c->st, z, kk, c->Sp, ns, c->ptab, c->epair, s, c->stream));
   }
   return PPRPA_OK;
@@ -105,6 +142,11 @@ void destroy(pprpa_ctx* c) {
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->dws.base) (void)hipFree(c->dws.base);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& t : c->pend) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->e0) (void)hipEventDestroy(c->e0);
   if (c->e1) (void)hipEventDestroy(c->e1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -355,6 +397,22 @@ pprpa_status pprpa_matvec(pprpa_ctx* c, int32_t k, const double* z, double* sigm
     }
   }
   PPRPA_HIP(hipStreamSynchronize(c->stream));
+  return harvest_timing(c);
+}
+
+pprpa_status pprpa_sigma_stats(pprpa_ctx* c, pprpa_kernel_stats* out, int32_t reset) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  PPRPA_TRY(harvest_timing(c));
+  if (out) *out = c->stats;
+  if (reset) c->stats = pprpa_kernel_stats{};
   return PPRPA_OK;
 }
 
@@ -390,7 +448,9 @@ pprpa_status pprpa_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* 
     return PPRPA_EBUSY;
   }
   PPRPA_HIP(hipSetDevice(c->device));
-  return run_davidson(c, a, omega, vecs, resid, rep);
+  pprpa_status st = run_davidson(c, a, omega, vecs, resid, rep);
+  if (hipStreamSynchronize(c->stream) == hipSuccess) (void)harvest_timing(c);
+  return st;
 }
 
 void pprpa_free(pprpa_ctx* c) { destroy(c); }

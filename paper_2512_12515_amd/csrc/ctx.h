@@ -38,6 +38,15 @@ struct pprpa_ctx {
   size_t pinned_elems = 0;
   std::vector<void*> allocs;
 
+  // per-launch timing of the sandwich kernel (events harvested after stream synchronisation)
+  struct Timed {
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Timed> pend;
+  std::vector<hipEvent_t> pool;
+  pprpa_kernel_stats stats{};
+
   // Davidson workspace (grown on demand, reused across calls)
   struct {
     size_t bytes = 0;
@@ -50,6 +59,8 @@ namespace pprpa {
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds);
 int nsplit_for(const pprpa_ctx* c, int k);
 pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p);
+// Fold completed launch timings into c->stats (call after synchronising the stream).
+pprpa_status harvest_timing(pprpa_ctx* c);
 pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
                           double* vecs, double* resid, pprpa_report* rep);
 }  // namespace pprpa

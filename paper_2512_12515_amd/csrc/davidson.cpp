@@ -295,6 +295,7 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
       t_sigma += ms * 1e-3;
       sigma_pending = false;
     }
+    PPRPA_TRY(harvest_timing(c));
     const int* info = (const int*)(hp + 128);
     const int npos = info[1];
     if (info[0] == 1) {
