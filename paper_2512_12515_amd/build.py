@@ -16,7 +16,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Wno-unused-function", "-Wno-unused-result",
          # packed FP32 instructions are avoided on this hardware: the compiler must not emit them
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # keep per-thread staging arrays in registers (not promoted into LDS)
+         "-mllvm", "-disable-promote-alloca-to-lds"]
 
 
 def _compile(src, objdir):

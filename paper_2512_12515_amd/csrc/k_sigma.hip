@@ -38,6 +38,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct AccT;
 template <> struct AccT<double> { using V = d4; };
@@ -126,22 +127,22 @@ __global__ void k_check_finite(const double* __restrict__ x, size_t n, int* __re
 }
 
 // ------------------------------------------------------------------------------------------
-// Unpack packed vectors into ZT[k][nmop][nmop] = Zh^T (only the two diagonal blocks written).
+// Unpack packed vectors into UT[k][nmop][nmop] = U^T (only the two diagonal blocks written; the
+// off-diagonal blocks stay zero from allocation).
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ double unpacked_value(const double* __restrict__ zk, int nb, int mult,
                                                  int c, int d) {
-  // Zh[c][d] for one diagonal block of size nb; zk points at the block's packed entries.
-  if (c >= nb || d >= nb) return 0.0;
-  const int p = c < d ? c : d, q = c < d ? d : c;
+  // U[c][d], the upper triangle of the unpacked block (Zh = U + s U^T): x_cd for c < d; on the
+  // diagonal half of Zh[c][c] = sqrt2 x_cc (singlet), 0 (triplet); 0 below the diagonal.
+  if (c >= nb || d >= nb || c > d) return 0.0;
   if (mult == 0) {
-    const int64_t idx = (int64_t)p * nb - (int64_t)p * (p - 1) / 2 + (q - p);
+    const int64_t idx = (int64_t)c * nb - (int64_t)c * (c - 1) / 2 + (d - c);
     const double v = zk[idx];
-    return p == q ? v * 1.4142135623730951 : v;
+    return c == d ? v * 0.70710678118654752440 : v;
   }
-  if (p == q) return 0.0;
-  const int64_t idx = (int64_t)p * (nb - 1) - (int64_t)p * (p - 1) / 2 + (q - p - 1);
-  const double v = zk[idx];
-  return c < d ? v : -v;
+  if (c == d) return 0.0;
+  const int64_t idx = (int64_t)c * (nb - 1) - (int64_t)c * (c - 1) / 2 + (d - c - 1);
+  return zk[idx];
 }
 
 template <typename T>
@@ -211,32 +212,57 @@ struct SandParams {
   int npan_v;
 };
 
-// Copy a rows x cols tile (cols a multiple of 16 elements, 16-byte aligned rows) into LDS.
+// c tiles of the chunk a contraction-1 step on d tile dt touches, rounded out to groups of 4
+// (columns outside the valid range hold exact zeros in U^T: c > d, or the other block).
+__device__ __forceinline__ void c_range(int dt, int cc0, int cc1, int nvt, int* g0, int* g1) {
+  const int blo = dt < nvt ? 0 : nvt;            // first c tile of d's block
+  const int lo = max(cc0, blo);                   // lowest c tile used
+  const int hi = min(cc1, dt + 1);                // one past the highest (c <= d)
+  *g0 = cc0 + ((lo - cc0) & ~3);
+  *g1 = min(cc1, cc0 + ((hi - cc0 + 3) & ~3));
+}
+
+template <typename T, int CT, int RT>
+struct SandCfg {
+  // LDS tiles are packed row-major (row stride = staged width) because direct global->LDS loads
+  // write each wave's 64 x 16 bytes contiguously.
+  static constexpr int S1 = TILE * CT * TILE + TILE * 4 * TILE;  // contraction-1 stage
+  static constexpr int S2 = TILE * RT * TILE;                    // contraction-2 stage
+  static constexpr int BUF = S1 > S2 ? S1 : S2;                  // elements per LDS buffer
+  static constexpr int VEC = 16 / sizeof(T);                     // elements per lane per load
+  static constexpr int CHUNK = 1024 / sizeof(T);                 // elements per wave load
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Issue this wave's share of the direct global->LDS loads of a rows x cols tile (packed in LDS at
+// dst, row stride cols). Each wave load moves 64 lanes x 16 bytes into 1 KiB of contiguous LDS.
 template <typename T>
-__device__ __forceinline__ void stage_tile(T* __restrict__ dst, int ldd, const T* __restrict__ src,
-                                           int64_t lds, int rows, int cols) {
-  constexpr int VEC = 16 / sizeof(T);
-  const int nvr = cols / VEC;
-  const int total = rows * nvr;
-  for (int v = threadIdx.x; v < total; v += 256) {
-    const int r = v / nvr, c = (v - r * nvr) * VEC;
-    const uint4 x = *reinterpret_cast<const uint4*>(src + r * lds + c);
-    *reinterpret_cast<uint4*>(dst + r * ldd + c) = x;
+__device__ __forceinline__ void dma_tile(const T* __restrict__ src, int64_t ld, int cols,
+                                         T* dst, int w, int lane) {
+  constexpr int VEC = 16 / sizeof(T), CHUNK = 1024 / sizeof(T);
+  const int nchunk = TILE * cols / CHUNK;
+  for (int j = w; j < nchunk; j += 4) {
+    const int e = j * CHUNK + lane * VEC;
+    const int row = e / cols, col = e - row * cols;
+    __builtin_amdgcn_global_load_lds((const void*)(src + row * ld + col), (lds_ptr_t)(dst + j * CHUNK),
+                                     16, 0, 0);
   }
 }
 
-template <typename T, int CC, int RT>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 2)))
-void k_sandwich(const T* __restrict__ L, const T* __restrict__ ZT, T* __restrict__ Sp,
+// Q = sum_P L^P U L^P for one vector, a panel of up to 4 column tiles of one diagonal block and a
+// range of up to RT row tiles of that block (U: upper triangle of the unpacked vector; the sigma
+// block is Q + s Q^T, formed in the epilogue). Every wave of a panel does the same work. Each
+// stage is staged by direct global->LDS loads into one buffer; two workgroups per CU overlap one
+// another's staging with their MFMA work.
+template <typename T, int CT, int RT, int OCC>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(OCC, OCC)))
+void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict__ Qp,
                 SandParams a) {
   using V = typename AccT<T>::V;
-  constexpr int PAD = 16 / sizeof(T);
-  constexpr int WA = CC * TILE + PAD;
-  constexpr int WB = 4 * TILE + PAD;
-  constexpr int WL = RT * TILE + PAD;
-  __shared__ __attribute__((aligned(16))) T sA[TILE * WA];
-  __shared__ __attribute__((aligned(16))) T sB[TILE * WB];
-  __shared__ __attribute__((aligned(16))) T sL[TILE * WL];
+  using Cfg = SandCfg<T, CT, RT>;
+  static_assert(CT % 4 == 0 && RT % 4 == 0, "tile groups of 4");
+  __shared__ __attribute__((aligned(1024))) T buf[Cfg::BUF];
 
   const int g = blockIdx.x;
   const int u = (g & 7) * a.per_xcd + (g >> 3);
@@ -245,7 +271,7 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ ZT, T* __restrict
   const int kv = (u / a.nitems) % a.k;
   const int sp = u / (a.nitems * a.k);
   const int pn = item >> 16;
-  const int R0 = item & 0xFFFF;  // first row tile (local to the block)
+  const int R0 = item & 0xFFFF;  // first row tile of the range (local to the block)
 
   const bool vblk = pn < a.npan_v;
   const int t0 = vblk ? 4 * pn : 4 * (pn - a.npan_v);
@@ -254,13 +280,17 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ ZT, T* __restrict
   const int npt = min(4, bnt - t0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int mytile = t0 + w;
   const bool active = w < npt;
-  const int rend = min(t0 + npt, R0 + RT);            // row tiles [R0, rend) staged
-  const int nrt = active ? max(0, min(mytile + 1, R0 + RT) - R0) : 0;
+  const int wc = min(w, npt - 1);  // idle waves of a short panel repeat the last column
+  const int rend = min(bnt, R0 + RT);
+  const int nrt = rend - R0;
+  const int col0 = brow0 + t0 * TILE;
+  const int ncol = npt * TILE;
+  const int row0 = brow0 + R0 * TILE;
+  const int wl = nrt * TILE;  // row stride of a staged L^P row tile (contraction 2)
   const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
   const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
-  const T* __restrict__ Z = ZT + (int64_t)kv * a.zstride;
+  const T* __restrict__ Z = UT + (int64_t)kv * a.zstride;
 
   V S[RT];
 #pragma unroll
@@ -268,61 +298,66 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ ZT, T* __restrict
 
   for (int P = P0; P < P1; ++P) {
     const T* __restrict__ Lp = L + (int64_t)P * a.zstride;
-    for (int cc0 = 0; cc0 < a.nct; cc0 += CC) {
-      const int cc1 = min(cc0 + CC, a.nct);
-      V Tacc[CC];
+    for (int cc0 = 0; cc0 < a.nct; cc0 += CT) {
+      const int cc1 = min(cc0 + CT, a.nct);
+      V Tacc[CT];
 #pragma unroll
-      for (int i = 0; i < CC; ++i) Tacc[i] = V{0, 0, 0, 0};
-
-      // contraction 1: T[c][cols] = sum_d Zh[c][d] L^P[d][cols], d in the block of c
-      for (int part = 0; part < 2; ++part) {
-        const int cb0 = part == 0 ? cc0 : max(cc0, a.nvt);
-        const int cb1 = part == 0 ? min(cc1, a.nvt) : cc1;
-        if (cb0 >= cb1) continue;
-        const int dbase = part == 0 ? 0 : a.nvp;
-        const int dlen = part == 0 ? a.nvp : a.nop;
-        const int ncol = (cb1 - cb0) * TILE;
-        for (int d0 = 0; d0 < dlen; d0 += TILE) {
-          __syncthreads();
-          stage_tile(sA, WA, Z + (int64_t)(dbase + d0) * a.nmop + cb0 * TILE, a.nmop, TILE, ncol);
-          stage_tile(sB, WB, Lp + (int64_t)(dbase + d0) * a.nmop + brow0 + t0 * TILE, a.nmop, TILE,
-                     npt * TILE);
-          __syncthreads();
-          if (active) {
-            T b[4];
+      for (int i = 0; i < CT; ++i) Tacc[i] = V{0, 0, 0, 0};
+      // contraction 1: T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], d tiles of c's block
+      const int dlo = cc0;
+      for (int dt = dlo; dt < a.nct; ++dt) {
+        if (dt < a.nvt && cc0 >= a.nvt) continue;
+        if (dt >= a.nvt && cc1 <= a.nvt) break;
+        int g0, g1;
+        c_range(dt, cc0, cc1, a.nvt, &g0, &g1);
+        if (g0 >= g1) continue;
+        const int wa = (g1 - g0) * TILE;
+        __syncthreads();
+        dma_tile(Z + (int64_t)(dt * TILE) * a.nmop + g0 * TILE, a.nmop, wa, buf, w, lane);
+        dma_tile(Lp + (int64_t)(dt * TILE) * a.nmop + col0, a.nmop, ncol, buf + TILE * CT * TILE, w,
+                 lane);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const T* sA = buf;
+        const T* sB = buf + TILE * CT * TILE;
+        T bv[4];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) b[ks] = sB[(4 * ks + lk) * WB + w * TILE + li];
+        for (int ks = 0; ks < 4; ++ks) bv[ks] = sB[(4 * ks + lk) * ncol + wc * TILE + li];
 #pragma unroll
-            for (int i = 0; i < CC; ++i) {
-              const int cb = cc0 + i;
-              if (cb >= cb0 && cb < cb1) {
+        for (int grp = 0; grp < CT / 4; ++grp) {
+          const int cg = cc0 + 4 * grp;
+          if (cg >= g0 && cg < g1) {
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                  const T av = sA[(4 * ks + lk) * WA + (cb - cb0) * TILE + li];
-                  Tacc[i] = mfma(av, b[ks], Tacc[i]);
-                }
-              }
+            for (int ks = 0; ks < 4; ++ks) {
+              T av[4];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) av[j] = sA[(4 * ks + lk) * wa + (cg - g0 + j) * TILE + li];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) Tacc[4 * grp + j] = mfma(av[j], bv[ks], Tacc[4 * grp + j]);
             }
           }
         }
       }
-
-      // contraction 2: S[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers
+      // contraction 2: Q[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers
 #pragma unroll
-      for (int i = 0; i < CC; ++i) {
-        const int cb = cc0 + i;
-        if (cb < cc1) {
+      for (int i = 0; i < CT; ++i) {
+        if (cc0 + i < cc1) {
           __syncthreads();
-          stage_tile(sL, WL, Lp + (int64_t)(cb * TILE) * a.nmop + brow0 + R0 * TILE, a.nmop, TILE,
-                     (rend - R0) * TILE);
+          dma_tile(Lp + (int64_t)((cc0 + i) * TILE) * a.nmop + row0, a.nmop, wl, buf, w, lane);
+          __builtin_amdgcn_s_waitcnt(0);
           __syncthreads();
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            if (rt < nrt) {
+          for (int grp = 0; grp < RT / 4; ++grp) {
+            if (4 * grp < nrt) {
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) {
-                const T av = sL[acc_row<T>(lk, ks) * WL + rt * TILE + li];
-                S[rt] = mfma(av, Tacc[i][ks], S[rt]);
+                T av[4];
+                // row tiles at or beyond nrt read other data of the buffer (in bounds); their
+                // results are never stored
+#pragma unroll
+                for (int j = 0; j < 4; ++j) av[j] = buf[acc_row<T>(lk, ks) * wl + (4 * grp + j) * TILE + li];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) S[4 * grp + j] = mfma(av[j], Tacc[i][ks], S[4 * grp + j]);
               }
             }
           }
@@ -332,21 +367,21 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ ZT, T* __restrict
   }
 
   if (active) {
-    T* __restrict__ out = Sp + ((int64_t)sp * a.k + kv) * a.zstride;
-    const int col = brow0 + mytile * TILE + li;
+    T* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.zstride;
+    const int col = col0 + w * TILE + li;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       if (rt < nrt) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          out[(int64_t)(brow0 + (R0 + rt) * TILE + acc_row<T>(lk, j)) * a.nmop + col] = S[rt][j];
+          out[(int64_t)(row0 + rt * TILE + acc_row<T>(lk, j)) * a.nmop + col] = S[rt][j];
       }
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// Epilogue: sigma = E z + N * sum_splits S (upper triangle), FP64.
+// Epilogue: sigma = E z + N * (Q + s Q^T), Q summed over the aux splits in a fixed order, FP64.
 // ------------------------------------------------------------------------------------------
 template <typename T>
 __global__ void k_epilogue(const double* __restrict__ z, int64_t n, int64_t nvv, int nvp,
@@ -359,9 +394,15 @@ __global__ void k_epilogue(const double* __restrict__ z, int64_t n, int64_t nvv,
   const int pq = ptab[e];
   const int p = pq >> 16, q = pq & 0xFFFF;
   const int off = e < nvv ? 0 : nvp;
-  const int64_t si = ((int64_t)kv * nmop + off + p) * nmop + off + q;
-  double s = 0.0;
-  for (int t = 0; t < nsplit; ++t) s += (double)Sp[t * split_stride + si];
+  // S[p][q] = Q[p][q] + s Q[q][p]
+  const int64_t spq = ((int64_t)kv * nmop + off + p) * nmop + off + q;
+  const int64_t sqp = ((int64_t)kv * nmop + off + q) * nmop + off + p;
+  double a = 0.0, b = 0.0;
+  for (int t = 0; t < nsplit; ++t) {
+    a += (double)Sp[t * split_stride + spq];
+    b += (double)Sp[t * split_stride + sqp];
+  }
+  const double s = mult == 0 ? a + b : a - b;
   const double nrm = (mult == 0 && p == q) ? 0.70710678118654752440 : 1.0;
   sigma[(int64_t)kv * n + e] = epair[e] * z[(int64_t)kv * n + e] + nrm * s;
 }
@@ -437,23 +478,23 @@ void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& n
     const bool v = pn < npan_v;
     const int t0 = v ? 4 * pn : 4 * (pn - npan_v);
     const int bnt = v ? g.nvt : not_;
-    const int tend = std::min(t0 + 4, bnt);
-    for (int R0 = 0; R0 < tend; R0 += RT) items.push_back((pn << 16) | R0);
+    (void)t0;
+    for (int R0 = 0; R0 < bnt; R0 += RT) items.push_back((pn << 16) | R0);
   }
 }
 
 int sigma_variant(const Geometry& g, Store st, int* RT) {
+  (void)g;
   if (st == Store::F64) {
-    if (g.nct <= 16) { *RT = 16; return 0; }
     *RT = 16;
     return 1;
   }
-  if (st == Store::F32) { *RT = 32; return 2; }
+  if (st == Store::F32) { *RT = 32; return 4; }
   *RT = 32;
   return 3;
 }
 
-template <typename T, int CC, int RT>
+template <typename T, int CC, int RT, int OCC>
 static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,
                                hipStream_t s) {
   SandParams p;
@@ -472,7 +513,7 @@ static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const S
   p.zstride = (int64_t)g.nmop * g.nmop;
   p.npan_v = plan.npan_v;
   p.items = plan.d_items;
-  hipLaunchKernelGGL((k_sandwich<T, CC, RT>), dim3(nwg), dim3(256), 0, s, (const T*)la.L,
+  hipLaunchKernelGGL((k_sandwich<T, CC, RT, OCC>), dim3(nwg), dim3(256), 0, s, (const T*)la.L,
                      (const T*)la.ZT, (T*)la.Sp, p);
   return hipGetLastError();
 }
@@ -483,9 +524,8 @@ hipError_t launch_sigma_bf16(const Geometry& g, const SigmaPlan& plan, const Sig
 hipError_t launch_sigma(const Geometry& g, Store st, const SigmaPlan& plan, const SigmaLaunch& la,
                         hipStream_t s) {
   switch (plan.variant) {
-    case 0: return run_sandwich<double, 16, 16>(g, plan, la, s);
-    case 1: return run_sandwich<double, 8, 16>(g, plan, la, s);
-    case 2: return run_sandwich<float, 16, 32>(g, plan, la, s);
+    case 1: return run_sandwich<double, 8, 16, 2>(g, plan, la, s);
+    case 4: return run_sandwich<float, 16, 32, 2>(g, plan, la, s);
     default: return launch_sigma_bf16(g, plan, la, s);
   }
 }
