@@ -226,8 +226,9 @@ template <typename T, int CT, int RT>
 struct SandCfg {
   // LDS tiles are packed row-major (row stride = staged width) because direct global->LDS loads
   // write each wave's 64 x 16 bytes contiguously.
-  static constexpr int S1 = TILE * CT * TILE + TILE * 4 * TILE;  // contraction-1 stage
-  static constexpr int S2 = TILE * RT * TILE;                    // contraction-2 stage
+  static constexpr int SR = 2 * TILE;                             // rows per stage (2 tiles)
+  static constexpr int S1 = SR * CT * TILE + SR * 4 * TILE;      // contraction-1 stage
+  static constexpr int S2 = SR * RT * TILE;                      // contraction-2 stage
   static constexpr int BUF = S1 > S2 ? S1 : S2;                  // elements per LDS buffer
   static constexpr int VEC = 16 / sizeof(T);                     // elements per lane per load
   static constexpr int CHUNK = 1024 / sizeof(T);                 // elements per wave load
@@ -238,10 +239,10 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // Issue this wave's share of the direct global->LDS loads of a rows x cols tile (packed in LDS at
 // dst, row stride cols). Each wave load moves 64 lanes x 16 bytes into 1 KiB of contiguous LDS.
 template <typename T>
-__device__ __forceinline__ void dma_tile(const T* __restrict__ src, int64_t ld, int cols,
+__device__ __forceinline__ void dma_tile(const T* __restrict__ src, int64_t ld, int rows, int cols,
                                          T* dst, int w, int lane) {
   constexpr int VEC = 16 / sizeof(T), CHUNK = 1024 / sizeof(T);
-  const int nchunk = TILE * cols / CHUNK;
+  const int nchunk = rows * cols / CHUNK;
   for (int j = w; j < nchunk; j += 4) {
     const int e = j * CHUNK + lane * VEC;
     const int row = e / cols, col = e - row * cols;
@@ -261,7 +262,8 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict
                 SandParams a) {
   using V = typename AccT<T>::V;
   using Cfg = SandCfg<T, CT, RT>;
-  static_assert(CT % 4 == 0 && RT % 4 == 0, "tile groups of 4");
+  constexpr int GRP = 2;  // tiles per unrolled MFMA group
+  static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
   __shared__ __attribute__((aligned(1024))) T buf[Cfg::BUF];
 
   const int g = blockIdx.x;
@@ -296,6 +298,8 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict
 #pragma unroll
   for (int r = 0; r < RT; ++r) S[r] = V{0, 0, 0, 0};
 
+  constexpr int SR = Cfg::SR;
+  T* const sB = buf + SR * CT * TILE;
   for (int P = P0; P < P1; ++P) {
     const T* __restrict__ Lp = L + (int64_t)P * a.zstride;
     for (int cc0 = 0; cc0 < a.nct; cc0 += CT) {
@@ -303,61 +307,82 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict
       V Tacc[CT];
 #pragma unroll
       for (int i = 0; i < CT; ++i) Tacc[i] = V{0, 0, 0, 0};
-      // contraction 1: T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], d tiles of c's block
-      const int dlo = cc0;
-      for (int dt = dlo; dt < a.nct; ++dt) {
-        if (dt < a.nvt && cc0 >= a.nvt) continue;
-        if (dt >= a.nvt && cc1 <= a.nvt) break;
-        int g0, g1;
-        c_range(dt, cc0, cc1, a.nvt, &g0, &g1);
-        if (g0 >= g1) continue;
-        const int wa = (g1 - g0) * TILE;
-        __syncthreads();
-        dma_tile(Z + (int64_t)(dt * TILE) * a.nmop + g0 * TILE, a.nmop, wa, buf, w, lane);
-        dma_tile(Lp + (int64_t)(dt * TILE) * a.nmop + col0, a.nmop, ncol, buf + TILE * CT * TILE, w,
-                 lane);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        const T* sA = buf;
-        const T* sB = buf + TILE * CT * TILE;
-        T bv[4];
+      // contraction 1: T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], d in c's block, two d
+      // tiles per stage
+      for (int part = 0; part < 2; ++part) {
+        const int lo = part == 0 ? cc0 : max(cc0, a.nvt);
+        const int hi = part == 0 ? (cc0 < a.nvt ? a.nvt : cc0) : (cc1 > a.nvt ? a.nct : lo);
+        for (int dt = lo; dt < hi; dt += 2) {
+          const int nd = min(2, hi - dt);
+          int g0, g1, h0, h1;
+          c_range(dt, cc0, cc1, a.nvt, &g0, &g1);
+          c_range(dt + nd - 1, cc0, cc1, a.nvt, &h0, &h1);
+          const int wa = (h1 - g0) * TILE;
+          __syncthreads();
+          dma_tile(Z + (int64_t)(dt * TILE) * a.nmop + g0 * TILE, a.nmop, nd * TILE, wa, buf, w, lane);
+          dma_tile(Lp + (int64_t)(dt * TILE) * a.nmop + col0, a.nmop, nd * TILE, ncol, sB, w, lane);
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) bv[ks] = sB[(4 * ks + lk) * ncol + wc * TILE + li];
+          for (int sub = 0; sub < 2; ++sub) {
+            if (sub < nd) {
+              int q0, q1g;
+              c_range(dt + sub, cc0, cc1, a.nvt, &q0, &q1g);
+              const int q1 = min(cc1, dt + sub + 1);  // end of the nonzero c tiles (c <= d)
+              const T* sA = buf + sub * TILE * wa;
+              const T* sBs = sB + sub * TILE * ncol;
+              T bv[4];
 #pragma unroll
-        for (int grp = 0; grp < CT / 4; ++grp) {
-          const int cg = cc0 + 4 * grp;
-          if (cg >= g0 && cg < g1) {
+              for (int ks = 0; ks < 4; ++ks) bv[ks] = sBs[(4 * ks + lk) * ncol + wc * TILE + li];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-              T av[4];
+              for (int grp = 0; grp < CT / GRP; ++grp) {
+                const int cg = cc0 + GRP * grp;
+                // groups that reach past d multiply exact zeros of U^T (c > d)
+                if (active && cg >= q0 && cg < q1) {
 #pragma unroll
-              for (int j = 0; j < 4; ++j) av[j] = sA[(4 * ks + lk) * wa + (cg - g0 + j) * TILE + li];
+                  for (int ks = 0; ks < 4; ++ks) {
+                    T av[GRP];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) Tacc[4 * grp + j] = mfma(av[j], bv[ks], Tacc[4 * grp + j]);
+                    for (int j = 0; j < GRP; ++j) av[j] = sA[(4 * ks + lk) * wa + (cg - g0 + j) * TILE + li];
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      Tacc[GRP * grp + j] = mfma(av[j], bv[ks], Tacc[GRP * grp + j]);
+                  }
+                }
+              }
             }
           }
         }
       }
-      // contraction 2: Q[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers
+      // contraction 2: Q[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers, two c tiles
+      // per stage
 #pragma unroll
-      for (int i = 0; i < CT; ++i) {
+      for (int i = 0; i < CT; i += 2) {
         if (cc0 + i < cc1) {
+          const int nb = min(2, cc1 - cc0 - i);
           __syncthreads();
-          dma_tile(Lp + (int64_t)((cc0 + i) * TILE) * a.nmop + row0, a.nmop, wl, buf, w, lane);
+          dma_tile(Lp + (int64_t)((cc0 + i) * TILE) * a.nmop + row0, a.nmop, nb * TILE, wl, buf, w, lane);
           __builtin_amdgcn_s_waitcnt(0);
           __syncthreads();
 #pragma unroll
-          for (int grp = 0; grp < RT / 4; ++grp) {
-            if (4 * grp < nrt) {
+          for (int sub = 0; sub < 2; ++sub) {
+            if (sub < nb) {
+              const T* sL = buf + sub * TILE * wl;
 #pragma unroll
-              for (int ks = 0; ks < 4; ++ks) {
-                T av[4];
-                // row tiles at or beyond nrt read other data of the buffer (in bounds); their
-                // results are never stored
+              for (int grp = 0; grp < RT / GRP; ++grp) {
+                // row tiles at or beyond nrt in the last group read other data of the buffer (in
+                // bounds); their results are never stored
+                if (active && GRP * grp < nrt) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) av[j] = buf[acc_row<T>(lk, ks) * wl + (4 * grp + j) * TILE + li];
+                  for (int ks = 0; ks < 4; ++ks) {
+                    T av[GRP];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) S[4 * grp + j] = mfma(av[j], Tacc[i][ks], S[4 * grp + j]);
+                    for (int j = 0; j < GRP; ++j) av[j] = sL[acc_row<T>(lk, ks) * wl + (GRP * grp + j) * TILE + li];
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      S[GRP * grp + j] = mfma(av[j], Tacc[i + sub][ks], S[GRP * grp + j]);
+                  }
+                }
               }
             }
           }
