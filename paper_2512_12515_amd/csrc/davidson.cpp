@@ -30,7 +30,7 @@ namespace {
 
 struct Ws {
   double *V, *SV, *Vt, *SVt, *Ms, *Ws_, *Mt, *Wt, *Cc, *Q, *Z, *SZ, *R, *Tn, *Tn2, *Cp, *Gb, *Tm;
-  double *omega, *rnorm, *part, *pwork;
+  double *omega, *rnorm, *part, *pwork, *Up;
   int* info;
 };
 
@@ -49,7 +49,7 @@ static pprpa_status get_ws(pprpa_ctx* c, int mmax, int nret, int blk, size_t pwo
                     (size_t)nret * n, (size_t)nret * n, (size_t)nret * n,            // Z SZ R
                     (size_t)blk * n, (size_t)blk * n,                                // Tn Tn2
                     (size_t)mmax * blk, (size_t)blk * blk, (size_t)blk * blk,        // Cp Gb Tm
-                    (size_t)nret, (size_t)nret, part_elems, pwork_elems, 16};
+                    (size_t)nret, (size_t)nret, part_elems, pwork_elems, (size_t)mmax * mmax, 16};
   const int nb = sizeof(sizes) / sizeof(sizes[0]);
   size_t total = 0;
   for (int i = 0; i < nb; ++i) total += align_up(sizes[i] * sizeof(double));
@@ -69,7 +69,7 @@ static pprpa_status get_ws(pprpa_ctx* c, int mmax, int nret, int blk, size_t pwo
   char* p = (char*)c->dws.base;
   double** slots[] = {&w->V,  &w->SV, &w->Vt, &w->SVt, &w->Ms, &w->Ws_, &w->Mt, &w->Wt,
                       &w->Cc, &w->Q,  &w->Z,  &w->SZ,  &w->R,  &w->Tn,  &w->Tn2, &w->Cp,
-                      &w->Gb, &w->Tm, &w->omega, &w->rnorm, &w->part, &w->pwork, nullptr};
+                      &w->Gb, &w->Tm, &w->omega, &w->rnorm, &w->part, &w->pwork, &w->Up, nullptr};
   for (int i = 0; i < nb; ++i) {
     if (slots[i])
       *slots[i] = (double*)p;
@@ -117,13 +117,13 @@ static pprpa_status add_vectors(pprpa_ctx* c, Ws& w, int m, int nsel, int blk, i
 }
 
 static void emit_log(const pprpa_davidson_args* a, int iter, int m, int nconv, double maxr,
-                     double om0, int nsig) {
+                     double om0, int nsig, int sweeps) {
   if (!a->log) return;
-  char buf[256];
+  char buf[320];
   snprintf(buf, sizeof buf,
            "{\"iter\": %d, \"subspace\": %d, \"n_conv\": %d, \"max_resid\": %.3e, \"omega0\": %.12f, "
-           "\"n_sigma\": %d}",
-           iter, m, nconv, maxr, om0, nsig);
+           "\"n_sigma\": %d, \"rr_sweeps\": %d}",
+           iter, m, nconv, maxr, om0, nsig, sweeps);
   a->log(a->user, buf);
 }
 
@@ -182,7 +182,7 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
     // W as a dense matrix in Ws_, M itself as the "projected" matrix
     PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
     PPRPA_HIP(launch_pencil(c->M, w.Ws_, m, m, c->mu2, nroot, nroot, w.omega, w.Cc, nroot, w.pwork,
-                            w.info, s));
+                            w.info, nullptr, 0, 0, s));
     PPRPA_HIP(launch_transpose(w.Cc, nroot, m, nroot, w.Z, n, s));
     PPRPA_HIP(launch_combine(c->M, n, m, w.Cc, nroot, nroot, n, 1.0, 0.0, w.SZ, n, s));
     PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot, n, nvv, w.omega, w.R, w.part, 64, s));
@@ -265,6 +265,7 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
   PPRPA_HIP(hipEventRecord(c->e1, s));
   int nsig = m;
   int mnew0 = 0;
+  int mprev = 0;  // pencil size of the previous iteration (0: no warm start)
   double t_sigma = 0.0;
   bool sigma_pending = true;
 
@@ -280,14 +281,15 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
                             mmax, w.part, nch, s));
     }
     PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax, m, c->mu2, nroot, std::min(nret, m), w.omega, w.Cc,
-                            nret, w.pwork, w.info, s));
+                            nret, w.pwork, w.info, w.Up, mmax, mprev, s));
+    mprev = m;
     PPRPA_HIP(launch_combine(w.V, n, m, w.Cc, nret, nroot, n, 1.0, 0.0, w.Z, n, s));
     PPRPA_HIP(launch_combine(w.SV, n, m, w.Cc, nret, nroot, n, 1.0, 0.0, w.SZ, n, s));
     PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot, n, nvv, w.omega, w.R, w.part, nres, s));
     PPRPA_HIP(launch_reduce_norms(w.part, nres, nroot, w.rnorm, s));
     PPRPA_HIP(hipMemcpyAsync(hp, w.omega, nroot * sizeof(double), hipMemcpyDeviceToHost, s));
     PPRPA_HIP(hipMemcpyAsync(hp + 64, w.rnorm, nroot * sizeof(double), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipMemcpyAsync(hp + 128, w.info, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PPRPA_HIP(hipMemcpyAsync(hp + 128, w.info, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     PPRPA_HIP(hipStreamSynchronize(s));
     if (sigma_pending) {
       float ms = 0.f;
@@ -325,7 +327,7 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
       else if ((int)sel.size() < blk)
         sel.push_back(j);
     }
-    emit_log(a, iter, m, nconv, maxr, om[0], nsig);
+    emit_log(a, iter, m, nconv, maxr, om[0], nsig, info[2]);
     R.n_conv = nconv;
     R.max_resid = maxr;
     if (nconv == nroot) {
@@ -361,6 +363,7 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
       std::swap(w.Ws_, w.Wt);
       m = rank;
       mnew0 = m;
+      mprev = 0;  // the basis was rotated: no warm start
     }
     PPRPA_HIP(launch_precond(w.R, n, sel.data(), nsel, n, nvv, c->epair, w.omega, w.Tn, n, s));
     int added = 0;

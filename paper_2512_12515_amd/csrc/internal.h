@@ -120,9 +120,12 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 // Cout[m][nroot] with c^T Ws c = +1. work: 4*m*m doubles. info: [0] status (0 ok, 1 not
 // definite, 2 fewer than nroot pp roots, 3 no convergence), [1] number of pp roots.
 // Columns nroot..nret-1 of Cout hold the next Ritz vectors (kept on restart).
+// Uprev (ld ldu): eigenvectors of the previous call, used as a warm start when mprev > 1 (the
+// leading mprev x mprev block of the pencil is unchanged); overwritten with this call's. May be
+// NULL (no warm start, nothing kept).
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
                          int nret, double* omega, double* Cout, int ldc, double* work, int* info,
-                         hipStream_t s);
+                         double* Uprev, int ldu, int mprev, hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

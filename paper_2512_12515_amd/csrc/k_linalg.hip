@@ -248,10 +248,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Round-robin ordering: m (padded to even) - 1 rounds of m/2 disjoint rotations per sweep.
 // On return G's diagonal holds the eigenvalues and U's columns the eigenvectors.
 __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, double* cs,
-                           double* sn) {
+                           double* sn, bool init_u = true) {
   const int me = m + (m & 1);
   const int half = me / 2;
-  for (int e = threadIdx.x; e < m * m; e += WG) U[(e / m) * ld + (e % m)] = (e / m == e % m);
+  if (init_u)
+    for (int e = threadIdx.x; e < m * m; e += WG) U[(e / m) * ld + (e % m)] = (e / m == e % m);
   __syncthreads();
   if (m < 2) return 0;
   __shared__ int nrot;
@@ -279,8 +280,9 @@ __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, dou
         if (q < m) {
           const double apq = G[p * ld + q];
           const double app = G[p * ld + p], aqq = G[q * ld + q];
-          // rotate unless |apq| is negligible against the diagonal (relative 1e-17)
-          if (fabs(apq) > 1e-17 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > 1e-300) {
+          // rotate unless |apq| is negligible against the diagonal (relative 1e-15; below that
+          // the rotations only move rounding noise)
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > 1e-300) {
             atomicAdd(&nrot, 1);
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -341,36 +343,47 @@ __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, dou
     if (nrot == 0) break;
     __syncthreads();
   }
-  return sweep >= 60 ? 1 : 0;
+  return sweep >= 60 ? -1 : sweep;
 }
 
-// Pencil: see launch_pencil. work holds 4 m x m matrices (ld = m): K/R, Rinv, G, U.
+// Pencil: see launch_pencil. For m <= PLDS the matrices live in LDS; otherwise in `work`, which
+// holds 4 m x m matrices (ld = m). work always holds the copy of R^-1 and a staging area for G.
+// Warm start: when the leading mprev x mprev block of the pencil is unchanged since the previous
+// call (the subspace only grew), G's leading block is unchanged too (R and R^-1 are lower
+// triangular), so it is rotated by the previous eigenvectors Uprev first: Jacobi then has only
+// the new border to annihilate.
+constexpr int PLDS = 96;
+
 __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
                                                const double* __restrict__ Ws, int ldm, int m,
                                                double mu2, int nroot, int nret,
                                                double* __restrict__ omega, double* __restrict__ Cout,
                                                int ldc, double* __restrict__ work,
-                                               int* __restrict__ info) {
+                                               int* __restrict__ info, double* __restrict__ Uprev,
+                                               int ldu, int mprev) {
+  __shared__ double sA[PLDS * PLDS];
+  __shared__ double sB[PLDS * PLDS];
   __shared__ double red[WG];
   __shared__ double cs[JMAX / 2 + 1], sn[JMAX / 2 + 1];
   __shared__ int flag;
   __shared__ int rank_of[JMAX];
-  double* K = work;
-  double* Ri = work + (size_t)m * m;
-  double* G = work + 2 * (size_t)m * m;
-  double* U = work + 3 * (size_t)m * m;
+  const bool in_lds = m <= PLDS;
+  double* A = in_lds ? sA : work + 2 * (size_t)m * m;  // K -> R -> Y -> U
+  double* B = in_lds ? sB : work + 3 * (size_t)m * m;  // R^-1 -> G
+  double* Ri = work;                                   // global copy of R^-1
+  double* Gt = work + (size_t)m * m;                   // global staging of G
   if (threadIdx.x == 0) flag = 0;
   // K = sym(Ms) - mu2 sym(Ws), from the upper triangles
   for (int e = threadIdx.x; e < m * m; e += WG) {
     const int i = e / m, j = e % m;
     const int a = i < j ? i : j, b = i < j ? j : i;
-    K[e] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
-    Ri[e] = 0.0;
+    A[e] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
+    B[e] = 0.0;
   }
   __syncthreads();
   // Cholesky K = R R^T (lower, in place)
   for (int j = 0; j < m; ++j) {
-    const double d = K[j * m + j];
+    const double d = A[j * m + j];
     if (!(d > 0.0)) {
       if (threadIdx.x == 0) flag = 1;
       __syncthreads();
@@ -378,13 +391,13 @@ __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
     }
     const double rjj = sqrt(d);
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < m; i += WG) K[i * m + j] /= rjj;
-    if (threadIdx.x == 0) K[j * m + j] = rjj;
+    for (int i = j + 1 + threadIdx.x; i < m; i += WG) A[i * m + j] /= rjj;
+    if (threadIdx.x == 0) A[j * m + j] = rjj;
     __syncthreads();
     const int nt = m - j - 1;
     for (int e = threadIdx.x; e < nt * nt; e += WG) {
       const int i = j + 1 + e / nt, k = j + 1 + e % nt;
-      if (k <= i) K[i * m + k] -= K[i * m + j] * K[k * m + j];
+      if (k <= i) A[i * m + k] -= A[i * m + j] * A[k * m + j];
     }
     __syncthreads();
   }
@@ -395,44 +408,94 @@ __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
     }
     return;
   }
-  // Ri = R^-1 (lower): column c by forward substitution, one thread per column
+  // B = R^-1 (lower): column c by forward substitution, one thread per column
   for (int c = threadIdx.x; c < m; c += WG) {
     for (int i = c; i < m; ++i) {
       double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= K[i * m + k] * Ri[k * m + c];
-      Ri[i * m + c] = s / K[i * m + i];
+      for (int k = c; k < i; ++k) s -= A[i * m + k] * B[k * m + c];
+      B[i * m + c] = s / A[i * m + i];
     }
   }
   __syncthreads();
-  // G = Ri Wsym Ri^T: first U = Ri Wsym (U used as scratch)
+  for (int e = threadIdx.x; e < m * m; e += WG) Ri[e] = B[e];
+  // A = Y = R^-1 Wsym
   for (int e = threadIdx.x; e < m * m; e += WG) {
     const int i = e / m, j = e % m;
     double s = 0.0;
     for (int k = 0; k <= i; ++k) {
       const int a = k < j ? k : j, b = k < j ? j : k;
-      s += Ri[i * m + k] * Ws[a * ldm + b];
+      s += B[i * m + k] * Ws[a * ldm + b];
     }
-    U[e] = s;
+    A[e] = s;
   }
   __syncthreads();
+  // G = Y R^-T (symmetric) into the global staging area, then into B
   for (int e = threadIdx.x; e < m * m; e += WG) {
     const int i = e / m, j = e % m;
     if (j < i) continue;
     double s = 0.0;
-    for (int k = 0; k <= j; ++k) s += U[i * m + k] * Ri[j * m + k];
-    G[i * m + j] = s;
-    G[j * m + i] = s;
+    for (int k = 0; k <= j; ++k) s += A[i * m + k] * B[j * m + k];
+    Gt[i * m + j] = s;
+    Gt[j * m + i] = s;
   }
   __syncthreads();
-  const int nconv = jacobi_eigh(G, m, m, U, red, cs, sn);
+  const bool warm = mprev > 1 && mprev <= m && Uprev != nullptr;
+  if (warm) {
+    // A = G diag(Uprev, I)
+    for (int e = threadIdx.x; e < m * m; e += WG) {
+      const int i = e / m, j = e % m;
+      double s;
+      if (j < mprev) {
+        s = 0.0;
+        for (int k = 0; k < mprev; ++k) s += Gt[i * m + k] * Uprev[k * ldu + j];
+      } else {
+        s = Gt[i * m + j];
+      }
+      A[e] = s;
+    }
+    __syncthreads();
+    // B = diag(Uprev, I)^T A
+    for (int e = threadIdx.x; e < m * m; e += WG) {
+      const int i = e / m, j = e % m;
+      double s;
+      if (i < mprev) {
+        s = 0.0;
+        for (int k = 0; k < mprev; ++k) s += Uprev[k * ldu + i] * A[k * m + j];
+      } else {
+        s = A[e];
+      }
+      B[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * m; e += WG) {
+      const int i = e / m, j = e % m;
+      if (j > i) {
+        const double v = 0.5 * (B[i * m + j] + B[j * m + i]);
+        B[i * m + j] = v;
+        B[j * m + i] = v;
+      }
+    }
+    // U starts as diag(Uprev, I)
+    for (int e = threadIdx.x; e < m * m; e += WG) {
+      const int i = e / m, j = e % m;
+      A[e] = (i < mprev && j < mprev) ? Uprev[i * ldu + j] : (double)(i == j);
+    }
+  } else {
+    for (int e = threadIdx.x; e < m * m; e += WG) B[e] = Gt[e];
+  }
+  __syncthreads();
+  const int sweeps = jacobi_eigh(B, m, m, A, red, cs, sn, !warm);
+  // keep the eigenvectors for the next call's warm start
+  if (Uprev)
+    for (int e = threadIdx.x; e < m * m; e += WG) Uprev[(e / m) * ldu + (e % m)] = A[e];
   // rank positive theta in descending order
   for (int i = threadIdx.x; i < m; i += WG) {
-    const double ti = G[i * m + i];
+    const double ti = B[i * m + i];
     int rk = -1;
     if (ti > 0.0) {
       rk = 0;
       for (int j = 0; j < m; ++j) {
-        const double tj = G[j * m + j];
+        const double tj = B[j * m + j];
         if (tj > ti || (tj == ti && j < i)) rk += (tj > 0.0);
       }
     }
@@ -440,17 +503,13 @@ __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
   }
   __syncthreads();
   int npos = 0;
-  for (int i = threadIdx.x; i < m; i += WG) npos += (G[i * m + i] > 0.0);
+  for (int i = threadIdx.x; i < m; i += WG) npos += (B[i * m + i] > 0.0);
   npos = (int)block_sum((double)npos, red);
-  // outputs: columns j < nret: c_j = Ri^T u / sqrt(theta)
   for (int i = threadIdx.x; i < m; i += WG) {
     const int rk = rank_of[i];
-    if (rk >= 0 && rk < nret) {
-      const double th = G[i * m + i];
-      if (rk < nroot) omega[rk] = mu2 + 1.0 / th;
-    }
+    if (rk >= 0 && rk < nroot) omega[rk] = mu2 + 1.0 / B[i * m + i];
   }
-  __syncthreads();
+  // outputs: columns rk < nret: c = R^-T u / sqrt(theta)
   for (int e = threadIdx.x; e < m * nret; e += WG) {
     const int row = e / nret, rk = e % nret;
     if (rk >= npos) {
@@ -460,14 +519,15 @@ __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
     int col = -1;
     for (int i = 0; i < m; ++i)
       if (rank_of[i] == rk) col = i;
-    const double th = G[col * m + col];
+    const double th = B[col * m + col];
     double s = 0.0;
-    for (int k = row; k < m; ++k) s += Ri[k * m + row] * U[k * m + col];
+    for (int k = row; k < m; ++k) s += Ri[k * m + row] * A[k * m + col];
     Cout[row * ldc + rk] = s / sqrt(th);
   }
   if (threadIdx.x == 0) {
-    info[0] = nconv ? 3 : (npos < nroot ? 2 : 0);
+    info[0] = sweeps < 0 ? 3 : (npos < nroot ? 2 : 0);
     info[1] = npos;
+    info[2] = sweeps;
   }
 }
 
@@ -636,10 +696,10 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
                          int nret, double* omega, double* Cout, int ldc, double* work, int* info,
-                         hipStream_t s) {
+                         double* Uprev, int ldu, int mprev, hipStream_t s) {
   if (m > JMAX || nret > WG) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret, omega,
-                     Cout, ldc, work, info);
+                     Cout, ldc, work, info, Uprev, ldu, mprev);
   return hipGetLastError();
 }
 
