@@ -153,11 +153,18 @@ CONFIGS = {
     "davidson_fp64": dict(nocc=20, nvir=200, naux=700, mult=("singlet", "triplet"), nroot=10,
                           block=20, tol=1e-6, seeds=(0, 1)),
     # mixed precision, 20 singlet roots
-    "mixed": dict(nocc=50, nvir=500, naux=1800, mult="singlet", nroot=20, seeds=(0,)),
+    "mixed": dict(nocc=50, nvir=500, naux=1800, mult="singlet", nroot=20, seeds=(0,),
+                  eig_scale=0.7),
     # active-space: full 120/1500/4000, window 40 occ + 400 vir, 16 triplet roots
     "active": dict(nocc=120, nvir=1500, naux=4000, nocc_act=40, nvir_act=400, mult="triplet",
-                   nroot=16, seeds=(0,)),
+                   nroot=16, seeds=(0,), eig_scale=0.7),
 }
+# eig_scale: at these two sizes the unscaled integrals make M - 2 mu W indefinite for every shift
+# (the random interaction spreads wider than the orbital gap) and the pp and hh spectra overlap,
+# which on smaller analogues of the same ratio gives complex roots: there are no well-defined
+# lowest pp roots. Eigenvalue comparisons at these sizes therefore use L * eig_scale (definite
+# with margin: lowest eigenvalue of M - 2 mu W is 0.18 Ha and 0.11 Ha); sigma throughput is
+# measured on the unscaled integrals.
 
 
 def serve_requests(master_seed: int, count: int = 512):
