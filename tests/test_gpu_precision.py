@@ -1,0 +1,134 @@
+"""GPU: the precision pattern and the large workloads.
+
+* sigma at full size (50 occ / 500 vir / 1800 aux and the 40 + 400 window of 120 / 1500 / 4000)
+  against oracle rows computed one by one from the integrals of those rows only;
+* FP32-sigma Davidson against the oracle on small problems and against the FP64 GPU Davidson at
+  full size, per root, within 1e-6 Ha (the integrals scaled by eig_scale = 0.7 at full size,
+  where the unscaled inputs give complex roots; see workloads/gen.py).
+
+Tolerances: FP64 sigma 1e-12 relative to max|sigma|; FP32 sigma 3e-5 relative; eigenvalues 1e-6 Ha.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pprpa_oracle as O
+from workloads import gen
+import paper_2512_12515_amd as P
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def device_lpq(seed, nocc, nvir, naux, nocc_act=None, nvir_act=None, scale=1.0):
+    import torch
+    dev = torch.device("cuda:0")
+    idx = gen.active_indices(nocc, nvir, nocc_act, nvir_act)
+    out = torch.empty((naux, idx.size, idx.size), dtype=torch.float64, device=dev)
+    for p0 in range(0, naux, 256):
+        aux = np.arange(p0, min(naux, p0 + 256))
+        out[p0:p0 + aux.size] = gen.lpq_block_torch(seed, nocc + nvir, naux, idx, idx, aux, dev) * scale
+    return out
+
+
+def oracle_sigma_rows(seed, nocc, nvir, naux, mult, rows, z, nocc_act=None, nvir_act=None):
+    """sigma[rows] from the definition, generating only the integral rows each entry needs."""
+    eps = gen.orbital_energies(seed, nocc, nvir)
+    idx = gen.active_indices(nocc, nvir, nocc_act, nvir_act)
+    no = idx.size - (min(nvir_act, nvir) if nvir_act else nvir)
+    occ, vir = idx[:no], idx[no:]
+    eo, ev = eps[occ], eps[vir]
+    nv = vir.size
+    s = 1.0 if mult == "singlet" else -1.0
+    va, vb = O.pairs(nv, mult)
+    oi, oj = O.pairs(no, mult)
+    nva, noo = O.pair_norm(va, vb, mult), O.pair_norm(oi, oj, mult)
+    nvv = va.size
+    x, y = z[:nvv], z[nvv:]
+    out = []
+    for r in rows:
+        if r < nvv:
+            p, q = vir[va[r]], vir[vb[r]]
+            Lr_v = gen.lpq_block(seed, nocc + nvir, naux, [p, q], vir)
+            Lr_o = gen.lpq_block(seed, nocc + nvir, naux, [p, q], occ)
+            Arow = O.pair_integrals(Lr_v, np.array([0]), np.array([1]), va, vb, s)[0] * nva[r] * nva
+            Brow = O.pair_integrals(Lr_o, np.array([0]), np.array([1]), oi, oj, s)[0] * nva[r] * noo
+            out.append((ev[va[r]] + ev[vb[r]]) * x[r] + Arow @ x + Brow @ y)
+        else:
+            t = r - nvv
+            p, q = occ[oi[t]], occ[oj[t]]
+            Lr_v = gen.lpq_block(seed, nocc + nvir, naux, [p, q], vir)
+            Lr_o = gen.lpq_block(seed, nocc + nvir, naux, [p, q], occ)
+            BTrow = O.pair_integrals(Lr_v, np.array([0]), np.array([1]), va, vb, s)[0] * noo[t] * nva
+            Crow = O.pair_integrals(Lr_o, np.array([0]), np.array([1]), oi, oj, s)[0] * noo[t] * noo
+            out.append(BTrow @ x + Crow @ y - (eo[oi[t]] + eo[oj[t]]) * y[t])
+    return np.array(out)
+
+
+BIG = {
+    "mixed": dict(nocc=50, nvir=500, naux=1800, nocc_act=None, nvir_act=None, mult="singlet"),
+    "active": dict(nocc=120, nvir=1500, naux=4000, nocc_act=40, nvir_act=400, mult="triplet"),
+}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("name", ["mixed", "active"])
+def test_sigma_full_size_sampled_rows(name, prec, tol):
+    import torch
+    c = BIG[name]
+    note("sigma full size", name, prec)
+    eps = gen.orbital_energies(0, c["nocc"], c["nvir"])
+    Ld = device_lpq(0, c["nocc"], c["nvir"], c["naux"], c["nocc_act"], c["nvir_act"])
+    with P.PpRPA(torch.from_numpy(eps).cuda(), Ld, c["nocc"], mult=c["mult"], prec=prec,
+                 nocc_act=c["nocc_act"] or 0, nvir_act=c["nvir_act"] or 0,
+                 lpq_is_active=c["nocc_act"] is not None) as ctx:
+        del Ld
+        z = gen.random_vectors(21, 2, ctx.n)
+        s = ctx.matvec(z)
+        npp, n = ctx.n_pp, ctx.n
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.r_[0, 1, npp - 1, npp, n - 1, rng.integers(0, npp, 6), rng.integers(npp, n, 3)])
+    for v in range(2):
+        ref = oracle_sigma_rows(0, c["nocc"], c["nvir"], c["naux"], c["mult"], rows, z[v],
+                                c["nocc_act"], c["nvir_act"])
+        scale = np.abs(s[v]).max()
+        assert np.max(np.abs(s[v][rows] - ref)) <= tol * scale
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("case,nroot", [((6, 40, 90), 6), ((10, 60, 150), 8)])
+def test_fp32_davidson_vs_oracle(mult, case, nroot):
+    nocc, nvir, naux = case
+    note("fp32 davidson small", mult, case)
+    eps, L = gen.orbital_energies(3, nocc, nvir), gen.lpq_full(3, nocc + nvir, naux)
+    ref = O.solve(eps, L, nocc, mult, nroot)
+    with P.PpRPA(eps, L, nocc, mult=mult, prec="fp32") as ctx:
+        r = ctx.davidson(nroot, block=nroot, tol=1e-6)
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-6
+
+
+@pytest.mark.parametrize("name,nroot", [("mixed", 20), ("active", 16)])
+def test_fp32_vs_fp64_davidson_full_size(name, nroot):
+    """Per-root FP32-sigma eigenvalues against the FP64 GPU Davidson on the same inputs."""
+    import torch
+    c = BIG[name]
+    scale = gen.CONFIGS[name]["eig_scale"]
+    note("fp32 vs fp64 full size", name)
+    eps = torch.from_numpy(gen.orbital_energies(0, c["nocc"], c["nvir"])).cuda()
+    Ld = device_lpq(0, c["nocc"], c["nvir"], c["naux"], c["nocc_act"], c["nvir_act"], scale=scale)
+    kw = dict(mult=c["mult"], nocc_act=c["nocc_act"] or 0, nvir_act=c["nvir_act"] or 0,
+              lpq_is_active=c["nocc_act"] is not None, max_block=20)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        with P.PpRPA(eps, Ld, c["nocc"], prec=prec, **kw) as ctx:
+            r = ctx.davidson(nroot, block=20, tol=1e-6, max_iter=300)
+        note(prec, r["report"])
+        out[prec] = r["omega"]
+    err = np.abs(out["fp32"] - out["fp64"])
+    note("per-root |dOmega| (Ha):", err)
+    assert np.all(err <= 1e-6)

@@ -62,3 +62,17 @@ def test_serve_mix():
     t = gen.poisson_arrivals(0, 512, 10.0)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 512 - 0.1) < 0.02
+
+
+def test_torch_generator_matches_numpy():
+    import torch
+    nmo, naux = 23, 7
+    rows, cols, aux = np.arange(3, 15), np.arange(nmo), np.arange(2, 6)
+    a = gen.lpq_block(4, nmo, naux, rows, cols, aux=aux)
+    b = gen.lpq_block_torch(4, nmo, naux, rows, cols, aux, device="cpu").numpy()
+    assert np.allclose(a, b, rtol=1e-14, atol=0)
+    # the integer hash itself is bit-identical
+    c = np.arange(1000, dtype=np.uint64) * np.uint64(7919) + np.uint64(2 ** 62)
+    ref = gen.uniform(3, gen.STREAM_LPQ, c)
+    got = gen._uniform_t(3, gen.STREAM_LPQ, torch.as_tensor(c.astype(np.int64))).numpy()
+    assert np.array_equal(ref, got)

@@ -187,3 +187,53 @@ def poisson_arrivals(master_seed: int, count: int, rate: float) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate."""
     u = uniform(master_seed, STREAM_SERVE, np.arange(count, dtype=np.uint64) + np.uint64(1 << 40))
     return np.cumsum(-np.log(u) / rate)
+
+
+# ----------------------------------------------------------------------------------------
+# The same generator on torch tensors (any device): for the large workloads, whose integral
+# slices are generated in device memory. The integer hash matches the NumPy version bit for bit
+# (int64 tensors hold the uint64 bit patterns; multiplications wrap); the Box-Muller step uses
+# torch's log/cos/sqrt and may differ from NumPy's in the last bits.
+# ----------------------------------------------------------------------------------------
+
+def _s64(x: int) -> int:
+    x &= 0xFFFFFFFFFFFFFFFF
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def _lsr(z, s: int):
+    """Logical right shift of int64 bit patterns."""
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def _mix64_t(z):
+    z = z ^ _lsr(z, 30)
+    z = z * _s64(0xBF58476D1CE4E5B9)
+    z = z ^ _lsr(z, 27)
+    z = z * _s64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def _uniform_t(seed: int, stream: int, counter):
+    import torch
+    base = _s64(int(_base(seed, stream)))
+    h = _mix64_t(base + (counter + 1) * _s64(0x9E3779B97F4A7C15))
+    return (_lsr(h, 11).to(torch.float64) + 0.5) * _TWO53_INV
+
+
+def lpq_block_torch(seed: int, nmo: int, naux: int, rows, cols, aux, device,
+                    scale: float | None = None):
+    """lpq_block on a torch device: [len(aux), len(rows), len(cols)] float64."""
+    import torch
+    rows = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=device)
+    cols = torch.as_tensor(np.asarray(cols, dtype=np.int64), device=device)
+    aux = torch.as_tensor(np.asarray(aux, dtype=np.int64), device=device)
+    if scale is None:
+        scale = float(lpq_scale(naux))
+    lo = torch.minimum(rows[:, None], cols[None, :])
+    hi = torch.maximum(rows[:, None], cols[None, :])
+    pq = lo * nmo + hi
+    cnt = aux[:, None, None] * (nmo * nmo) + pq[None]
+    u1 = _uniform_t(seed, STREAM_LPQ, cnt * 2)
+    u2 = _uniform_t(seed, STREAM_LPQ, cnt * 2 + 1)
+    return torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * np.pi * u2) * scale
