@@ -147,6 +147,75 @@ typedef struct {
 } pprpa_kernel_stats;
 pprpa_status pprpa_sigma_stats(pprpa_ctx* ctx, pprpa_kernel_stats* out, int32_t reset);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of many independent solves on the current device.
+ *
+ * The method's cost is dominated by the sigma products of the Davidson iterations (section
+ * "Implementation Details"); a server keeps many solves resident and overlaps them: requests
+ * are admitted in arrival order when their device footprint (staged integrals, sigma buffers,
+ * Davidson workspace; computed exactly at submit) fits in the server's HBM arena and one of
+ * max_inflight slots is free; every in-flight solve advances independently on its own stream,
+ * and the sigma products of all solves that need one at the same time run as one grouped grid.
+ * A request's arithmetic is the same as pprpa_build + pprpa_davidson with the same arguments
+ * (same kernels and decomposition), so its roots do not depend on what it was served with.
+ * Threads: an admission thread (builds) and a worker thread (phases, grouped launches); the
+ * Davidson log callback, if any, is called from the worker thread.
+ * --------------------------------------------------------------------------------------- */
+typedef struct pprpa_server pprpa_server; /* opaque */
+
+typedef struct {
+  int32_t state;        /* 0 queued, 1 running (the caller's inputs are no longer read), 2 done */
+  int32_t status;       /* pprpa_status of the solve (meaningful once done)                  */
+  int32_t nroot;
+  int32_t reserved_;
+  double t_submit;      /* seconds on the server's steady clock (0 = creation)               */
+  double t_admit;       /* reservation taken, build started                                  */
+  double t_done;        /* roots copied out, memory released                                 */
+  uint64_t footprint;   /* device bytes reserved for the request                             */
+  char message[256];    /* error text when status != OK                                     */
+} pprpa_request_info;
+
+typedef struct {
+  int64_t submitted, completed, failed;   /* requests                                         */
+  int64_t queued, inflight, peak_inflight;
+  uint64_t budget;                         /* arena bytes                                      */
+  uint64_t reserved, peak_reserved;        /* bytes held by admitted requests (now, highest)   */
+  int64_t group_launches;                  /* grouped sigma grids launched (and timed)         */
+  int64_t grouped_products;                /* block sigma products they carried                */
+  double sigma_seconds;                    /* device time of those grids (HIP events)          */
+  double sigma_flops;                      /* their algorithmic flops (as pprpa_kernel_stats)  */
+} pprpa_serving_stats;
+
+/* Reserve hbm_budget_bytes (>= 1 MiB) of device memory as the admission arena, max_inflight
+ * (1..64) slots (a stream and a pinned status buffer each), and start the server's threads.
+ * Errors: EINVAL, ENOMEM (the arena cannot be allocated), EDEVICE. */
+pprpa_status pprpa_server_create(size_t hbm_budget_bytes, int32_t max_inflight,
+                                 pprpa_server** out);
+
+/* Queue one solve: the problem as for pprpa_build (prec FP64 or FP32; dense, stream and
+ * max_block are chosen by the server) and the Davidson arguments (direct = 0). The memory
+ * that args point to (eps, Lpq, guess) must stay valid and unchanged until pprpa_server_poll
+ * reports state >= 1; device inputs must be complete (their producer synchronised) before the
+ * call. Errors (nothing queued): EINVAL, EUNSUPPORTED (BF16 or direct). A request larger than
+ * the whole arena is accepted and finishes with ENOMEM. */
+pprpa_status pprpa_server_submit(pprpa_server* srv, const pprpa_build_args* build,
+                                 const pprpa_davidson_args* dav, uint64_t* ticket);
+
+/* State of a request. Once done (info->state == 2) the roots ([nroot] host, ascending), residual
+ * norms and report are copied out as pprpa_davidson would return them (omega, resid, rep may
+ * be NULL) and the ticket is retired: polling it again is EINVAL. */
+pprpa_status pprpa_server_poll(pprpa_server* srv, uint64_t ticket, pprpa_request_info* info,
+                               double* omega, double* resid, pprpa_report* rep);
+
+/* Block until the request is done (timeout_s < 0: no limit). EBUSY on timeout, EINVAL for an
+ * unknown ticket. */
+pprpa_status pprpa_server_wait(pprpa_server* srv, uint64_t ticket, double timeout_s);
+
+pprpa_status pprpa_server_stats(pprpa_server* srv, pprpa_serving_stats* out);
+
+/* Finish the in-flight solves, fail the queued ones with EBUSY, release everything. NULL-safe. */
+void pprpa_server_destroy(pprpa_server* srv);
+
 /* Release the context and all its device memory. NULL-safe. */
 void pprpa_free(pprpa_ctx* ctx);
 

@@ -65,9 +65,28 @@ class KernelStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("nroot", C.c_int32),
+                ("reserved_", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("footprint", C.c_uint64), ("message", C.c_char * 256)]
+
+
+class ServingStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int64), ("inflight", C.c_int64), ("peak_inflight", C.c_int64),
+                ("budget", C.c_uint64), ("reserved", C.c_uint64), ("peak_reserved", C.c_uint64),
+                ("group_launches", C.c_int64), ("grouped_products", C.c_int64),
+                ("sigma_seconds", C.c_double), ("sigma_flops", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 EXPORTS = ["pprpa_build", "pprpa_dims", "pprpa_matvec", "pprpa_dense_matrix", "pprpa_davidson",
-           "pprpa_free", "pprpa_strerror", "pprpa_last_error", "pprpa_sigma_stats"]
+           "pprpa_free", "pprpa_strerror", "pprpa_last_error", "pprpa_sigma_stats",
+           "pprpa_server_create", "pprpa_server_submit", "pprpa_server_poll", "pprpa_server_wait",
+           "pprpa_server_stats", "pprpa_server_destroy"]
 
 
 def lib():
@@ -105,6 +124,20 @@ def lib():
     L.pprpa_strerror.restype = C.c_char_p
     L.pprpa_last_error.argtypes = []
     L.pprpa_last_error.restype = C.c_char_p
+    L.pprpa_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]
+    L.pprpa_server_create.restype = C.c_int
+    L.pprpa_server_submit.argtypes = [C.c_void_p, C.POINTER(BuildArgs), C.POINTER(DavidsonArgs),
+                                      C.POINTER(C.c_uint64)]
+    L.pprpa_server_submit.restype = C.c_int
+    L.pprpa_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(RequestInfo), C.c_void_p,
+                                    C.c_void_p, C.POINTER(Report)]
+    L.pprpa_server_poll.restype = C.c_int
+    L.pprpa_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_double]
+    L.pprpa_server_wait.restype = C.c_int
+    L.pprpa_server_stats.argtypes = [C.c_void_p, C.POINTER(ServingStats)]
+    L.pprpa_server_stats.restype = C.c_int
+    L.pprpa_server_destroy.argtypes = [C.c_void_p]
+    L.pprpa_server_destroy.restype = None
     _lib = L
     return L
 
@@ -238,6 +271,87 @@ class PpRPA:
             raise PpRPAError(st, msg)
         return dict(omega=omega, vecs=vecs, resid=resid, report=rep.as_dict(), status=st,
                     log=lines, message=msg)
+
+
+class Server:
+    """Serving loop (pprpa_server_*): admits solves by device footprint into an HBM arena of
+    hbm_budget_bytes, keeps up to max_inflight of them on the device and groups their sigma
+    products. Inputs of a request are kept referenced here until the library reports that it
+    no longer reads them (state >= 1)."""
+
+    QUEUED, RUNNING, DONE = 0, 1, 2
+
+    def __init__(self, hbm_budget_bytes, max_inflight=16):
+        h = C.c_void_p()
+        _check(lib().pprpa_server_create(int(hbm_budget_bytes), int(max_inflight), C.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def submit(self, eps, Lpq, nocc, nroot, mult="singlet", prec="fp64", nocc_act=0, nvir_act=0,
+               lpq_is_active=False, block=0, tol=1e-6, max_iter=0, max_subspace=0):
+        on_dev = _is_torch(Lpq) and Lpq.is_cuda
+        if on_dev:
+            import torch
+            torch.cuda.current_stream(Lpq.device).synchronize()  # inputs complete before submit
+        else:
+            eps = np.ascontiguousarray(eps, dtype=np.float64)
+            Lpq = np.ascontiguousarray(Lpq, dtype=np.float64)
+        b = BuildArgs()
+        b.nmo, b.nocc, b.naux = int(eps.shape[0]), int(nocc), int(Lpq.shape[0])
+        b.nocc_act, b.nvir_act = int(nocc_act or 0), int(nvir_act or 0)
+        b.eps, b.Lpq = _ptr(eps, on_dev).value, _ptr(Lpq, on_dev).value
+        b.lpq_is_active, b.on_device = int(bool(lpq_is_active)), int(on_dev)
+        b.mult, b.prec = MULT[mult], PREC[prec]
+        d = DavidsonArgs()
+        d.nroot, d.block, d.max_iter = int(nroot), int(block), int(max_iter)
+        d.max_subspace, d.tol = int(max_subspace), float(tol)
+        t = C.c_uint64()
+        _check(lib().pprpa_server_submit(self._h, C.byref(b), C.byref(d), C.byref(t)))
+        self._held[t.value] = (eps, Lpq, int(nroot))
+        return t.value
+
+    def poll(self, ticket):
+        """Request state; once done also its roots, residuals and report (the ticket retires)."""
+        info = RequestInfo()
+        nroot = self._held[ticket][2] if ticket in self._held else 64
+        omega, resid, rep = np.empty(nroot), np.empty(nroot), Report()
+        _check(lib().pprpa_server_poll(self._h, int(ticket), C.byref(info), omega.ctypes.data,
+                                       resid.ctypes.data, C.byref(rep)))
+        out = dict(state=info.state, status=info.status, t_submit=info.t_submit,
+                   t_admit=info.t_admit, t_done=info.t_done, footprint=info.footprint,
+                   message=info.message.decode(errors="replace"))
+        if info.state >= self.RUNNING:
+            self._held.pop(ticket, None)
+        if info.state == self.DONE:
+            out.update(omega=omega, resid=resid, report=rep.as_dict())
+        return out
+
+    def wait(self, ticket, timeout=-1.0):
+        _check(lib().pprpa_server_wait(self._h, int(ticket), float(timeout)))
+        return self.poll(ticket)
+
+    def stats(self):
+        st = ServingStats()
+        _check(lib().pprpa_server_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pprpa_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 # Plain-function forms with the C names (thin wrappers over PpRPA).

@@ -6,7 +6,7 @@
 #include <cstring>
 #include <numeric>
 
-#include "ctx.h"
+#include "solver.h"
 
 namespace pprpa {
 
@@ -34,6 +34,17 @@ static pprpa_status einval(const char* fmt, ...) {
 pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
+  if (c->slab) {
+    const size_t b = (bytes + 255) / 256 * 256;
+    if (c->slab->top + b > c->slab->size) {
+      set_error("request footprint exceeded: %zu + %zu > %zu bytes reserved", c->slab->top, b,
+                c->slab->size);
+      return PPRPA_ENOMEM;
+    }
+    *p = c->slab->base + c->slab->top;
+    c->slab->top += b;
+    return PPRPA_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -47,13 +58,15 @@ pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p) {
 
 // Aux-index splits of a sigma launch: about 8192 workgroups (32 per CU), which measured best on
 // MI355X (shorter tails and better balance than 1.5k-4k; partial sums stay small).
-int nsplit_for(const pprpa_ctx* c, int k) {
+int nsplit_of(int nitems, int naux, int k) {
   const int target = 8192;
-  const int per = std::max(1, c->plan.nitems * k);
+  const int per = std::max(1, nitems * k);
   int ns = (target + per - 1) / per;
-  ns = std::min(ns, std::min(c->g.naux, 256));
+  ns = std::min(ns, std::min(naux, 256));
   return std::max(1, ns);
 }
+
+int nsplit_for(const pprpa_ctx* c, int k) { return nsplit_of(c->plan.nitems, c->g.naux, k); }
 
 static pprpa_status get_event(pprpa_ctx* c, hipEvent_t* e) {
   if (!c->pool.empty()) {
@@ -141,8 +154,8 @@ void destroy(pprpa_ctx* c) {
   if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (void* p : c->allocs) (void)hipFree(p);
-  if (c->dws.base) (void)hipFree(c->dws.base);
-  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->dws.base && !c->slab) (void)hipFree(c->dws.base);
+  if (c->pinned && c->own_pinned) (void)hipHostFree(c->pinned);
   for (auto& t : c->pend) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -155,32 +168,47 @@ void destroy(pprpa_ctx* c) {
   delete c;
 }
 
-pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
-  // ---- sizes and window ----------------------------------------------------------------
-  const int nmo = a->nmo, nocc = a->nocc, naux = a->naux;
+// Window, padded layout and pair counts of a problem (argument errors -> EINVAL).
+pprpa_status geometry_of(const pprpa_build_args* a, Geometry* out) {
+  const int nmo = a->nmo, nocc = a->nocc;
   const int nvir = nmo - nocc;
   if (a->nocc_act > nocc) return einval("nocc_act=%d exceeds nocc=%d", a->nocc_act, nocc);
   if (a->nvir_act > nvir) return einval("nvir_act=%d exceeds nvir=%d", a->nvir_act, nvir);
   const int no = a->nocc_act > 0 ? a->nocc_act : nocc;
   const int nv = a->nvir_act > 0 ? a->nvir_act : nvir;
-  const int mult = a->mult;
   if (nv <= 0) return einval("no virtual orbitals in the window");
   if (nv > 16000 || no > 16000) return einval("window too large (nv=%d, no=%d)", nv, no);
-  Geometry& g = c->g;
+  Geometry g;
   g.nv = nv;
   g.no = no;
-  g.naux = naux;
-  g.mult = mult;
+  g.naux = a->naux;
+  g.mult = a->mult;
   g.nvp = round_up(nv, TILE);
   g.nop = round_up(no, TILE);
   g.nmop = g.nvp + g.nop;
   g.nvt = g.nvp / TILE;
   g.nct = g.nmop / TILE;
-  const int k = mult == PPRPA_SINGLET ? 0 : 1;
+  const int k = a->mult == PPRPA_SINGLET ? 0 : 1;
   g.nvv = (int64_t)nv * (nv + 1) / 2 - (int64_t)k * nv;
   g.noo = (int64_t)no * (no + 1) / 2 - (int64_t)k * no;
   g.n = g.nvv + g.noo;
   if (g.nvv <= 0) return einval("no particle pairs (nv=%d, triplet)", nv);
+  *out = g;
+  return PPRPA_OK;
+}
+
+// Aux slices per host-to-device staging copy (about 256 MB of FP64 input at a time).
+int staging_chunk(size_t per) {
+  return (int)std::max<size_t>(1, std::min<size_t>(65535, (size_t(256) << 20) / (per * 8)));
+}
+
+pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
+  // ---- sizes and window ----------------------------------------------------------------
+  const int nmo = a->nmo, nocc = a->nocc, naux = a->naux;
+  PPRPA_TRY(geometry_of(a, &c->g));
+  Geometry& g = c->g;
+  const int no = g.no, nv = g.nv;
+  const int k = a->mult == PPRPA_SINGLET ? 0 : 1;
   c->prec = a->prec;
   c->st = a->prec == PPRPA_FP64 ? Store::F64 : (a->prec == PPRPA_FP32 ? Store::F32 : Store::BF16);
   c->nprod = a->prec == PPRPA_BF16X3 ? 3 : 6;
@@ -209,8 +237,9 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
   }
   PPRPA_HIP(hipEventCreate(&c->e0));
   PPRPA_HIP(hipEventCreate(&c->e1));
-  c->pinned_elems = 4096;
-  PPRPA_HIP(hipHostMalloc((void**)&c->pinned, c->pinned_elems * sizeof(double), hipHostMallocDefault));
+  c->pinned_elems = PINNED_ELEMS;
+  if (!c->pinned)
+    PPRPA_HIP(hipHostMalloc((void**)&c->pinned, c->pinned_elems * sizeof(double), hipHostMallocDefault));
   PPRPA_HIP(prepare_kernels());
 
   // ---- pair table and pair energies ----------------------------------------------------
@@ -247,6 +276,15 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
   const size_t esz = c->st == Store::F64 ? 8 : (c->st == Store::F32 ? 4 : 2);
   const size_t nplanes = c->st == Store::BF16 ? 3 : 1;
   PPRPA_TRY(dalloc(c, c->plane * esz * nplanes, &c->L));
+  double* tmp = nullptr;  // host-input staging buffer
+  bool own_tmp = false;
+  struct FreeTmp {
+    double*& p;
+    bool& own;
+    ~FreeTmp() {
+      if (own && p) (void)hipFree(p);
+    }
+  } free_tmp{tmp, own_tmp};
   auto stage = [&](Store st, void* dst, size_t plane) -> pprpa_status {
     if (a->on_device) {
       for (int p0 = 0; p0 < naux; p0 += 65535) {
@@ -257,9 +295,15 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
       return PPRPA_OK;
     }
     const size_t per = (size_t)nin * nin;
-    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(65535, (size_t(256) << 20) / (per * 8)));
-    double* tmp = nullptr;
-    PPRPA_HIP(hipMalloc((void**)&tmp, (size_t)chunk * per * sizeof(double)));
+    const int chunk = staging_chunk(per);
+    if (!tmp) {
+      if (c->slab) {
+        PPRPA_TRY(dalloc(c, (size_t)chunk * per * sizeof(double), (void**)&tmp));
+      } else {
+        PPRPA_HIP(hipMalloc((void**)&tmp, (size_t)chunk * per * sizeof(double)));
+        own_tmp = true;
+      }
+    }
     pprpa_status rc = PPRPA_OK;
     for (int p0 = 0; p0 < naux && rc == PPRPA_OK; p0 += chunk) {
       const int np = std::min(chunk, naux - p0);
@@ -272,10 +316,14 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
         rc = PPRPA_EDEVICE;
       }
     }
-    (void)hipFree(tmp);
     return rc;
   };
   PPRPA_TRY(stage(c->st, c->L, c->plane));
+  if (own_tmp) {
+    (void)hipFree(tmp);
+    tmp = nullptr;
+    own_tmp = false;
+  }
   if (a->dense) {
     if (c->st == Store::F64) {
       c->L64 = (double*)c->L;
@@ -323,6 +371,89 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
 
 }  // namespace
 
+namespace pprpa {
+
+pprpa_status check_build_args(const pprpa_build_args* a) {
+  if (!a) return einval("args is NULL");
+  if (a->nmo <= 0 || a->naux <= 0) return einval("nmo=%d and naux=%d must be positive", a->nmo, a->naux);
+  if (a->nocc < 0 || a->nocc > a->nmo) return einval("nocc=%d outside [0, nmo=%d]", a->nocc, a->nmo);
+  if (!a->eps || !a->Lpq) return einval("eps and Lpq must not be NULL");
+  if (a->mult != PPRPA_SINGLET && a->mult != PPRPA_TRIPLET) return einval("mult=%d", a->mult);
+  if (a->prec < PPRPA_FP64 || a->prec > PPRPA_BF16X3) return einval("prec=%d", a->prec);
+  return PPRPA_OK;
+}
+
+// Every device allocation build_impl makes (plus the Davidson workspace), each rounded up to the
+// 256-byte granule of the slab allocator. Kept in step with build_impl and get_ws: a served
+// build whose allocations outrun this figure fails with ENOMEM instead of overrunning its slab.
+size_t context_footprint(const pprpa_build_args* a, const pprpa_davidson_args* d) {
+  Geometry g;
+  if (check_build_args(a) != PPRPA_OK || geometry_of(a, &g) != PPRPA_OK) return 0;
+  auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; };
+  const Store st = a->prec == PPRPA_FP64 ? Store::F64 : (a->prec == PPRPA_FP32 ? Store::F32 : Store::BF16);
+  const size_t esz = st == Store::F64 ? 8 : (st == Store::F32 ? 4 : 2);
+  const size_t nplanes = st == Store::BF16 ? 3 : 1;
+  const int kcap = a->max_block > 0 ? std::min(a->max_block, 64) : 32;
+  const size_t plane = (size_t)g.naux * g.nmop * g.nmop;
+  const size_t zz = (size_t)g.nmop * g.nmop;
+  size_t b = 0;
+  b += al(g.n * sizeof(int));                      // pair table
+  b += al(g.nv * sizeof(double));                  // virtual energies
+  b += al(std::max(g.no, 1) * sizeof(double));     // occupied energies
+  b += al(g.n * sizeof(double));                   // pair energies
+  b += al(g.nmop * sizeof(int));                   // source rows
+  b += al(sizeof(int));                            // bad-value flag
+  b += al(plane * esz * nplanes);                  // staged L
+  if (!a->on_device) {
+    const int nin = a->lpq_is_active ? g.no + g.nv : a->nmo;
+    const size_t per = (size_t)nin * nin;
+    b += al((size_t)staging_chunk(per) * per * sizeof(double));
+  }
+  if (a->dense && st != Store::F64) b += al(plane * sizeof(double));
+  int RT = 16, npan_v = 0;
+  (void)sigma_variant(g, st, &RT);
+  std::vector<int> items;
+  make_sigma_items(g, RT, items, npan_v);
+  b += al(items.size() * sizeof(int));
+  b += al((size_t)kcap * zz * esz * nplanes);       // unpacked vectors
+  size_t sp_max = 0;
+  for (int kk = 1; kk <= kcap; ++kk)
+    sp_max = std::max(sp_max, (size_t)nsplit_of((int)items.size(), g.naux, kk) * kk);
+  b += al(sp_max * zz * (st == Store::F64 ? 8 : 4));  // partial sums
+  b += 2 * al((size_t)kcap * g.n * sizeof(double));   // host-vector staging
+  if (a->dense) b += al((size_t)g.n * g.n * sizeof(double));
+  if (d) {
+    const size_t ws = davidson_workspace_bytes(g, *d);
+    if (ws == 0) return 0;
+    b += al(ws);
+  }
+  return b;
+}
+
+pprpa_status build_context(const pprpa_build_args* a, Slab* slab, double* pinned,
+                           pprpa_ctx** out) {
+  *out = nullptr;
+  PPRPA_TRY(check_build_args(a));
+  pprpa_ctx* c = new (std::nothrow) pprpa_ctx();
+  if (!c) return einval("host allocation failed");
+  c->slab = slab;
+  c->pinned = pinned;
+  c->own_pinned = pinned == nullptr;
+  pprpa_status s = build_impl(a, c);
+  if (s != PPRPA_OK) {
+    std::string keep = g_err;
+    destroy(c);
+    g_err = keep;
+    return s;
+  }
+  *out = c;
+  return PPRPA_OK;
+}
+
+void free_context(pprpa_ctx* c) { destroy(c); }
+
+}  // namespace pprpa
+
 extern "C" {
 
 const char* pprpa_strerror(pprpa_status s) {
@@ -345,23 +476,7 @@ pprpa_status pprpa_build(const pprpa_build_args* a, pprpa_ctx** out) {
   g_err.clear();
   if (!out) return einval("out is NULL");
   *out = nullptr;
-  if (!a) return einval("args is NULL");
-  if (a->nmo <= 0 || a->naux <= 0) return einval("nmo=%d and naux=%d must be positive", a->nmo, a->naux);
-  if (a->nocc < 0 || a->nocc > a->nmo) return einval("nocc=%d outside [0, nmo=%d]", a->nocc, a->nmo);
-  if (!a->eps || !a->Lpq) return einval("eps and Lpq must not be NULL");
-  if (a->mult != PPRPA_SINGLET && a->mult != PPRPA_TRIPLET) return einval("mult=%d", a->mult);
-  if (a->prec < PPRPA_FP64 || a->prec > PPRPA_BF16X3) return einval("prec=%d", a->prec);
-  pprpa_ctx* c = new (std::nothrow) pprpa_ctx();
-  if (!c) return einval("host allocation failed");
-  pprpa_status s = build_impl(a, c);
-  if (s != PPRPA_OK) {
-    std::string keep = g_err;
-    destroy(c);
-    g_err = keep;
-    return s;
-  }
-  *out = c;
-  return PPRPA_OK;
+  return build_context(a, nullptr, nullptr, out);
 }
 
 pprpa_status pprpa_dims(const pprpa_ctx* c, int64_t* n_pp, int64_t* n_hh) {

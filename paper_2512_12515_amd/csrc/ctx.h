@@ -36,6 +36,8 @@ struct pprpa_ctx {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double* pinned = nullptr;  // small pinned host buffer for per-iteration status
   size_t pinned_elems = 0;
+  bool own_pinned = true;
+  pprpa::Slab* slab = nullptr;  // served contexts: every device allocation comes from here
   std::vector<void*> allocs;
 
   // per-launch timing of the sandwich kernel (events harvested after stream synchronisation)
@@ -58,9 +60,19 @@ namespace pprpa {
 // sigma = M z for k vectors already on the device ([k][n] each), on the context's stream.
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds);
 int nsplit_for(const pprpa_ctx* c, int k);
+int nsplit_of(int nitems, int naux, int k);
 pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p);
 // Fold completed launch timings into c->stats (call after synchronising the stream).
 pprpa_status harvest_timing(pprpa_ctx* c);
+// Served contexts (the serving loop): argument checks shared with pprpa_build; exact device
+// footprint of a context plus one Davidson solve; build into a slab with a caller-owned pinned
+// buffer (pinned_elems doubles) and stream; release.
+pprpa_status check_build_args(const pprpa_build_args* a);
+size_t context_footprint(const pprpa_build_args* a, const pprpa_davidson_args* d);
+pprpa_status build_context(const pprpa_build_args* a, Slab* slab, double* pinned,
+                           pprpa_ctx** out);
+void free_context(pprpa_ctx* c);
+constexpr size_t PINNED_ELEMS = 4096;
 pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
                           double* vecs, double* resid, pprpa_report* rep);
 }  // namespace pprpa

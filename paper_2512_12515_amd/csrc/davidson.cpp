@@ -17,52 +17,111 @@
 //    them (no new sigma products).
 // All arithmetic is FP64 on the device; the host runs the control loop and reads back nroot
 // eigenvalues, nroot residual norms and a few counters per iteration.
+//
+// The loop is a phase machine (Solver): every phase queues device work on the context's stream
+// and ends with a small device-to-host copy that the next phase reads, so a caller can interleave
+// the phases of many solves and batch their sigma products (the serving loop does).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <numeric>
 
-#include "ctx.h"
+#include "solver.h"
 
 namespace pprpa {
 namespace {
 
-struct Ws {
-  double *V, *SV, *Vt, *SVt, *Ms, *Ws_, *Mt, *Wt, *Cc, *Q, *Z, *SZ, *R, *Tn, *Tn2, *Cp, *Gb, *Tm;
-  double *omega, *rnorm, *part, *pwork, *Up;
-  int* info;
-};
-
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
-}  // namespace
+// Sizes of one Davidson solve (shared by the workspace allocation and the footprint estimate).
+pprpa_status shape_of(const Geometry& g, const pprpa_davidson_args* a, Shape* sh) {
+  const int64_t n = g.n, nvv = g.nvv;
+  Shape s{};
+  s.nroot = a->nroot;
+  if (s.nroot < 1 || s.nroot > nvv) {
+    set_error("nroot=%d outside [1, n_pp=%lld]", s.nroot, (long long)nvv);
+    return PPRPA_EINVAL;
+  }
+  if (s.nroot > 64) {
+    set_error("nroot=%d exceeds 64", s.nroot);
+    return PPRPA_EUNSUPPORTED;
+  }
+  if (!(a->tol > 0.0) && !a->direct) {
+    set_error("tol must be positive");
+    return PPRPA_EINVAL;
+  }
+  int blk = a->block > 0 ? a->block : s.nroot;
+  blk = std::max(blk, 1);
+  s.blk = (int)std::min<int64_t>(std::min(blk, 64), nvv);
+  s.max_iter = a->max_iter > 0 ? a->max_iter : 100;
+  int mmax = a->max_subspace > 0 ? a->max_subspace : std::max(8 * s.nroot, s.nroot + 4 * s.blk);
+  s.mmax = (int)std::min<int64_t>(std::min(mmax, 256), n);
+  s.nguess = (a->guess && a->nguess > 0) ? std::min(a->nguess, s.mmax) : 0;
+  int nb0 = s.nguess > 0 ? s.nguess : (int)std::min<int64_t>(std::max(s.blk, s.nroot), nvv);
+  s.nb0 = std::min(nb0, s.mmax);
+  s.tblk = std::max(s.blk, s.nb0);  // rows of the correction buffers
+  if (s.mmax < s.nroot + 1 && s.mmax < n) {
+    set_error("max_subspace=%d too small for nroot=%d", s.mmax, s.nroot);
+    return PPRPA_EINVAL;
+  }
+  s.nret = std::max(s.nroot, std::min(2 * s.nroot, s.mmax / 2));
+  s.nch = (int)std::min<int64_t>(512, std::max<int64_t>(1, n / 256));
+  *sh = s;
+  return PPRPA_OK;
+}
 
-static pprpa_status get_ws(pprpa_ctx* c, int mmax, int nret, int blk, size_t pwork_elems,
-                           size_t part_elems, Ws* w) {
-  const int64_t n = c->g.n;
+// Workspace element counts, in the order of the DavWork members.
+int ws_sizes(int64_t n, int mmax, int nret, int blk, size_t pwork_elems, size_t part_elems,
+             size_t* sizes) {
   const size_t vecs = (size_t)mmax * n;
-  size_t sizes[] = {vecs, vecs, vecs, vecs,                                          // V SV Vt SVt
-                    (size_t)mmax * mmax, (size_t)mmax * mmax, (size_t)mmax * mmax,   // Ms Ws Mt
-                    (size_t)mmax * mmax,                                             // Wt
-                    (size_t)mmax * nret, (size_t)mmax * nret,                        // Cc Q
-                    (size_t)nret * n, (size_t)nret * n, (size_t)nret * n,            // Z SZ R
-                    (size_t)blk * n, (size_t)blk * n,                                // Tn Tn2
-                    (size_t)mmax * blk, (size_t)blk * blk, (size_t)blk * blk,        // Cp Gb Tm
-                    (size_t)nret, (size_t)nret, part_elems, pwork_elems, (size_t)mmax * mmax, 16};
-  const int nb = sizeof(sizes) / sizeof(sizes[0]);
+  const size_t list[] = {vecs, vecs, vecs, vecs,                                         // V SV Vt SVt
+                         (size_t)mmax * mmax, (size_t)mmax * mmax, (size_t)mmax * mmax,  // Ms Ws Mt
+                         (size_t)mmax * mmax,                                            // Wt
+                         (size_t)mmax * nret, (size_t)mmax * nret,                       // Cc Q
+                         (size_t)nret * n, (size_t)nret * n, (size_t)nret * n,           // Z SZ R
+                         (size_t)blk * n, (size_t)blk * n,                               // Tn Tn2
+                         (size_t)mmax * blk, (size_t)blk * blk, (size_t)blk * blk,       // Cp Gb Tm
+                         (size_t)nret, (size_t)nret, part_elems, pwork_elems,
+                         (size_t)mmax * mmax, 16};
+  const int nb = sizeof(list) / sizeof(list[0]);
+  std::copy(list, list + nb, sizes);
+  return nb;
+}
+
+size_t ws_total(int64_t n, int mmax, int nret, int blk, size_t pwork, size_t part) {
+  size_t sizes[32];
+  const int nb = ws_sizes(n, mmax, nret, blk, pwork, part, sizes);
+  size_t total = 0;
+  for (int i = 0; i < nb; ++i) total += align_up(sizes[i] * sizeof(double));
+  return total;
+}
+
+pprpa_status get_ws(pprpa_ctx* c, int mmax, int nret, int blk, size_t pwork_elems,
+                    size_t part_elems, DavWork* w) {
+  size_t sizes[32];
+  const int nb = ws_sizes(c->g.n, mmax, nret, blk, pwork_elems, part_elems, sizes);
   size_t total = 0;
   for (int i = 0; i < nb; ++i) total += align_up(sizes[i] * sizeof(double));
   if (c->dws.bytes < total) {
-    if (c->dws.base) (void)hipFree(c->dws.base);
-    c->dws.base = nullptr;
-    c->dws.bytes = 0;
-    hipError_t e = hipMalloc(&c->dws.base, total);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
+    if (c->slab) {
+      // a slab-backed context (served request) allocates its workspace once from its slab
+      if (c->dws.base) {
+        set_error("workspace of %zu bytes exceeds the request's reservation", total);
+        return PPRPA_ENOMEM;
+      }
+      PPRPA_TRY(dalloc(c, total, &c->dws.base));
+    } else {
+      if (c->dws.base) (void)hipFree(c->dws.base);
       c->dws.base = nullptr;
-      set_error("Davidson workspace of %zu bytes: %s", total, hipGetErrorString(e));
-      return PPRPA_ENOMEM;
+      c->dws.bytes = 0;
+      hipError_t e = hipMalloc(&c->dws.base, total);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->dws.base = nullptr;
+        set_error("Davidson workspace of %zu bytes: %s", total, hipGetErrorString(e));
+        return PPRPA_ENOMEM;
+      }
     }
     c->dws.bytes = total;
   }
@@ -80,318 +139,414 @@ static pprpa_status get_ws(pprpa_ctx* c, int mmax, int nret, int blk, size_t pwo
   return PPRPA_OK;
 }
 
-// Orthonormalise rows Tn[0:nsel] against V[0:m] and among themselves; append to V at row m.
-// Returns the number of vectors appended in *added.
-static pprpa_status add_vectors(pprpa_ctx* c, Ws& w, int m, int nsel, int blk, int* added) {
-  const int64_t n = c->g.n;
-  const int nch = (int)std::min<int64_t>(512, std::max<int64_t>(1, n / 256));
-  hipStream_t s = c->stream;
-  PPRPA_HIP(launch_normalize_rows(w.Tn, n, nsel, n, s));
-  for (int pass = 0; pass < 2 && m > 0; ++pass) {
-    PPRPA_HIP(launch_dots(w.V, n, m, w.Tn, n, nsel, n, 0, 0, w.Cp, blk, w.part, nch, s));
-    PPRPA_HIP(launch_combine(w.V, n, m, w.Cp, blk, nsel, n, -1.0, 1.0, w.Tn, n, s));
-  }
-  PPRPA_HIP(launch_dots(w.Tn, n, nsel, w.Tn, n, nsel, n, 0, 0, w.Gb, blk, w.part, nch, s));
-  PPRPA_HIP(launch_gram_orth(w.Gb, blk, nsel, 1e-10, w.Tm, blk, w.info + 4, w.pwork, s));
-  PPRPA_HIP(hipMemcpyAsync(c->pinned, w.info + 4, sizeof(int), hipMemcpyDeviceToHost, s));
-  PPRPA_HIP(hipStreamSynchronize(s));
-  const int kept = *(int*)c->pinned;
-  if (kept <= 0) {
-    *added = 0;
-    return PPRPA_OK;
-  }
-  PPRPA_HIP(launch_combine(w.Tn, n, nsel, w.Tm, blk, kept, n, 1.0, 0.0, w.Tn2, n, s));
-  if (m > 0) {
-    PPRPA_HIP(launch_dots(w.V, n, m, w.Tn2, n, kept, n, 0, 0, w.Cp, blk, w.part, nch, s));
-    PPRPA_HIP(launch_combine(w.V, n, m, w.Cp, blk, kept, n, -1.0, 1.0, w.Tn2, n, s));
-  }
-  PPRPA_HIP(launch_dots(w.Tn2, n, kept, w.Tn2, n, kept, n, 0, 0, w.Gb, blk, w.part, nch, s));
-  PPRPA_HIP(launch_gram_orth(w.Gb, blk, kept, 1e-10, w.Tm, blk, w.info + 4, w.pwork, s));
-  PPRPA_HIP(hipMemcpyAsync(c->pinned, w.info + 4, sizeof(int), hipMemcpyDeviceToHost, s));
-  PPRPA_HIP(hipStreamSynchronize(s));
-  const int kept2 = *(int*)c->pinned;
-  if (kept2 > 0)
-    PPRPA_HIP(launch_combine(w.Tn2, n, kept, w.Tm, blk, kept2, n, 1.0, 0.0, w.V + (size_t)m * n, n, s));
-  *added = std::max(kept2, 0);
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+size_t davidson_workspace_bytes(const Geometry& g, const pprpa_davidson_args& a) {
+  Shape sh;
+  if (shape_of(g, &a, &sh) != PPRPA_OK) return 0;
+  return ws_total(g.n, sh.mmax, sh.nret, sh.tblk, (size_t)4 * sh.mmax * sh.mmax,
+                  std::max((size_t)sh.nch * sh.mmax * sh.tblk, (size_t)sh.nret * 64));
+}
+
+pprpa_status Solver::fail(pprpa_status s) {
+  status = s;
+  message = pprpa_last_error();
+  phase = DONE;
+  return s;
+}
+
+pprpa_status Solver::done(pprpa_status s) {
+  status = s;
+  message = s == PPRPA_OK ? std::string() : std::string(pprpa_last_error());
+  phase = DONE;
   return PPRPA_OK;
 }
 
-static void emit_log(const pprpa_davidson_args* a, int iter, int m, int nconv, double maxr,
-                     double om0, int nsig, int sweeps) {
-  if (!a->log) return;
+void Solver::log_iteration(int nconv, double maxr, int sweeps) {
+  if (!a_.log) return;
   char buf[320];
   snprintf(buf, sizeof buf,
            "{\"iter\": %d, \"subspace\": %d, \"n_conv\": %d, \"max_resid\": %.3e, \"omega0\": %.12f, "
            "\"n_sigma\": %d, \"rr_sweeps\": %d}",
-           iter, m, nconv, maxr, om0, nsig, sweeps);
-  a->log(a->user, buf);
+           iter_, m_, nconv, maxr, om_[0], nsig_, sweeps);
+  a_.log(a_.user, buf);
 }
 
-static pprpa_status finish(pprpa_ctx* c, Ws& w, int nroot, double* omega, double* vecs,
-                           double* resid, pprpa_report* rep, const double* h_omega,
-                           const double* h_rn) {
-  const int64_t n = c->g.n;
-  for (int j = 0; j < nroot; ++j) omega[j] = h_omega[j];
-  if (resid)
-    for (int j = 0; j < nroot; ++j) resid[j] = h_rn[j];
-  if (vecs) {
-    PPRPA_HIP(launch_scale_sign(w.Z, n, nroot, n, c->stream));
-    PPRPA_HIP(hipMemcpyAsync(vecs, w.Z, (size_t)nroot * n * sizeof(double), hipMemcpyDeviceToHost,
-                             c->stream));
+pprpa_status Solver::start() {
+  t0_ = std::chrono::steady_clock::now();
+  status = PPRPA_OK;
+  Shape sh;
+  pprpa_status rc = shape_of(c_->g, &a_, &sh);
+  if (rc != PPRPA_OK) return fail(rc);
+  if (a_.direct) {
+    rc = run_direct();
+    return rc == PPRPA_OK ? PPRPA_OK : fail(rc);
   }
-  PPRPA_HIP(hipStreamSynchronize(c->stream));
-  (void)rep;
+  nroot_ = sh.nroot;
+  blk_ = sh.blk;
+  max_iter_ = sh.max_iter;
+  mmax_ = sh.mmax;
+  nret_ = sh.nret;
+  tblk_ = sh.tblk;
+  nch_ = sh.nch;
+  rc = get_ws(c_, mmax_, nret_, tblk_, (size_t)4 * mmax_ * mmax_,
+              std::max((size_t)nch_ * mmax_ * tblk_, (size_t)nret_ * nres_), &w);
+  if (rc != PPRPA_OK) return fail(rc);
+  rc = initial_subspace(sh);
+  if (rc != PPRPA_OK) return fail(rc);
+  sig_m0 = 0;
+  sig_k = m_;
+  nsig_ = m_;
+  mnew0_ = 0;
+  mprev_ = 0;
+  phase = NEED_SIGMA;
   return PPRPA_OK;
 }
 
-pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega, double* vecs,
-                          double* resid, pprpa_report* rep) {
-  const auto t_start = std::chrono::steady_clock::now();
-  const Geometry& g = c->g;
-  const int64_t n = g.n, nvv = g.nvv;
-  hipStream_t s = c->stream;
-  const int nroot = a->nroot;
-  if (nroot < 1 || nroot > nvv) {
-    set_error("nroot=%d outside [1, n_pp=%lld]", nroot, (long long)nvv);
-    return PPRPA_EINVAL;
-  }
-  if (nroot > 64) {
-    set_error("nroot=%d exceeds 64", nroot);
-    return PPRPA_EUNSUPPORTED;
-  }
-  if (!(a->tol > 0.0) && !a->direct) {
-    set_error("tol must be positive");
-    return PPRPA_EINVAL;
-  }
-  pprpa_report R{};
-  double* hp = c->pinned;  // [0,64) omega, [64,128) rnorm, [128,..) ints
-
-  // ------------------------------------------------------------------ direct diagonalisation
-  if (a->direct) {
-    if (!c->M) {
-      set_error("direct diagonalisation needs a dense build");
-      return PPRPA_EUNSUPPORTED;
-    }
-    if (n > 512) {
-      set_error("direct diagonalisation on the device is limited to n <= 512 (n=%lld)", (long long)n);
-      return PPRPA_EUNSUPPORTED;
-    }
-    Ws w{};
-    const int m = (int)n;
-    PPRPA_TRY(get_ws(c, m, nroot, 1, (size_t)4 * m * m, (size_t)nroot * 64, &w));
-    // W as a dense matrix in Ws_, M itself as the "projected" matrix
-    PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
-    PPRPA_HIP(launch_pencil(c->M, w.Ws_, m, m, c->mu2, nroot, nroot, w.omega, w.Cc, nroot, w.pwork,
-                            w.info, nullptr, 0, 0, s));
-    PPRPA_HIP(launch_transpose(w.Cc, nroot, m, nroot, w.Z, n, s));
-    PPRPA_HIP(launch_combine(c->M, n, m, w.Cc, nroot, nroot, n, 1.0, 0.0, w.SZ, n, s));
-    PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot, n, nvv, w.omega, w.R, w.part, 64, s));
-    PPRPA_HIP(launch_reduce_norms(w.part, 64, nroot, w.rnorm, s));
-    PPRPA_HIP(hipMemcpyAsync(hp, w.omega, nroot * sizeof(double), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipMemcpyAsync(hp + 64, w.rnorm, nroot * sizeof(double), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipMemcpyAsync(hp + 128, w.info, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipStreamSynchronize(s));
-    const int* info = (const int*)(hp + 128);
-    if (info[0] == 1) {
-      set_error("M - 2 mu W is not positive definite");
-      return PPRPA_ENONDEF;
-    }
-    if (info[0] == 2) {
-      set_error("fewer than nroot pp roots (%d)", info[1]);
-      return PPRPA_ENONDEF;
-    }
-    double om[64], rn[64];
-    std::copy(hp, hp + nroot, om);
-    std::copy(hp + 64, hp + 64 + nroot, rn);
-    PPRPA_TRY(finish(c, w, nroot, omega, vecs, resid, rep, om, rn));
-    R.iters = 0;
-    R.n_conv = nroot;
-    R.max_resid = *std::max_element(rn, rn + nroot);
-    R.subspace = m;
-    R.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    if (rep) *rep = R;
-    return info[0] == 3 ? PPRPA_ENOCONV : PPRPA_OK;
-  }
-
-  // ------------------------------------------------------------------ Davidson
-  int blk = a->block > 0 ? a->block : nroot;
-  blk = std::max(blk, 1);
-  blk = std::min<int64_t>(std::min(blk, 64), nvv);
-  const int max_iter = a->max_iter > 0 ? a->max_iter : 100;
-  int mmax = a->max_subspace > 0 ? a->max_subspace : std::max(8 * nroot, nroot + 4 * blk);
-  mmax = (int)std::min<int64_t>(std::min(mmax, 256), n);
-  const int nguess = (a->guess && a->nguess > 0) ? std::min(a->nguess, mmax) : 0;
-  int nb0 = nguess > 0 ? nguess : (int)std::min<int64_t>(std::max(blk, nroot), nvv);
-  nb0 = std::min(nb0, mmax);
-  const int tblk = std::max(blk, nb0);  // rows of the correction buffers
-  if (mmax < nroot + 1 && mmax < n) {
-    set_error("max_subspace=%d too small for nroot=%d", mmax, nroot);
-    return PPRPA_EINVAL;
-  }
-  const int nret = std::max(nroot, std::min(2 * nroot, mmax / 2));
-  const int nch = (int)std::min<int64_t>(512, std::max<int64_t>(1, n / 256));
-  const int nres = 64;
-  Ws w{};
-  PPRPA_TRY(get_ws(c, mmax, nret, tblk, (size_t)4 * mmax * mmax,
-                   std::max((size_t)nch * mmax * tblk, (size_t)nret * nres), &w));
-
-  // initial subspace
-  int m = 0;
-  if (nguess > 0) {
-    PPRPA_HIP(hipMemcpyAsync(w.Tn, a->guess, (size_t)nguess * n * sizeof(double),
+pprpa_status Solver::initial_subspace(const Shape& sh) {
+  const int64_t n = c_->g.n, nvv = c_->g.nvv;
+  hipStream_t s = c_->stream;
+  if (sh.nguess > 0) {
+    PPRPA_HIP(hipMemcpyAsync(w.Tn, a_.guess, (size_t)sh.nguess * n * sizeof(double),
                              hipMemcpyHostToDevice, s));
+    m_ = 0;
+    PPRPA_TRY(orth_pass1(sh.nguess));
+    PPRPA_HIP(hipStreamSynchronize(s));
+    const int kept = *(int*)c_->pinned;
     int added = 0;
-    PPRPA_TRY(add_vectors(c, w, 0, nguess, tblk, &added));
-    if (added < nroot) {
+    if (kept > 0) {
+      PPRPA_TRY(orth_pass2(kept));
+      PPRPA_HIP(hipStreamSynchronize(s));
+      added = std::max(*(int*)c_->pinned, 0);
+      if (added > 0) PPRPA_TRY(orth_commit(kept, added));
+    }
+    if (added < nroot_) {
       set_error("initial guesses span only %d directions", added);
       return PPRPA_EINVAL;
     }
-    m = added;
-  } else {
-    // unit vectors on the nb0 lowest virtual-pair energies (ties: lowest index)
-    std::vector<int64_t> idx(nvv);
-    std::iota(idx.begin(), idx.end(), 0);
-    auto epair = [&](int64_t e) {
-      const int pq = c->ptab_h[e];
-      return c->ev_h[pq >> 16] + c->ev_h[pq & 0xFFFF];
-    };
-    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return epair(x) < epair(y); });
-    PPRPA_HIP(launch_fill(w.V, (size_t)nb0 * n, 0.0, s));
-    PPRPA_HIP(launch_set_units(w.V, n, idx.data(), nb0, s));
-    m = nb0;
+    m_ = added;
+    return PPRPA_OK;
   }
-  PPRPA_HIP(hipEventRecord(c->e0, s));
-  PPRPA_TRY(sigma_device(c, m, w.V, w.SV));
-  PPRPA_HIP(hipEventRecord(c->e1, s));
-  int nsig = m;
-  int mnew0 = 0;
-  int mprev = 0;  // pencil size of the previous iteration (0: no warm start)
-  double t_sigma = 0.0;
-  bool sigma_pending = true;
+  // unit vectors on the nb0 lowest virtual-pair energies (ties: lowest index)
+  std::vector<int64_t> idx(nvv);
+  std::iota(idx.begin(), idx.end(), 0);
+  auto epair = [&](int64_t e) {
+    const int pq = c_->ptab_h[e];
+    return c_->ev_h[pq >> 16] + c_->ev_h[pq & 0xFFFF];
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return epair(x) < epair(y); });
+  PPRPA_HIP(launch_fill(w.V, (size_t)sh.nb0 * n, 0.0, s));
+  PPRPA_HIP(launch_set_units(w.V, n, idx.data(), sh.nb0, s));
+  m_ = sh.nb0;
+  return PPRPA_OK;
+}
 
-  double om[64], rn[64];
-  pprpa_status status = PPRPA_ENOCONV;
-  int iter = 0;
-  for (;;) {
-    const int nb = m - mnew0;
-    if (nb > 0) {
-      PPRPA_HIP(launch_dots(w.V, n, m, w.SV + (size_t)mnew0 * n, n, nb, n, 0, 0, w.Ms + mnew0,
-                            mmax, w.part, nch, s));
-      PPRPA_HIP(launch_dots(w.V, n, m, w.V + (size_t)mnew0 * n, n, nb, n, nvv, 1, w.Ws_ + mnew0,
-                            mmax, w.part, nch, s));
-    }
-    PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax, m, c->mu2, nroot, std::min(nret, m), w.omega, w.Cc,
-                            nret, w.pwork, w.info, w.Up, mmax, mprev, s));
-    mprev = m;
-    PPRPA_HIP(launch_combine(w.V, n, m, w.Cc, nret, nroot, n, 1.0, 0.0, w.Z, n, s));
-    PPRPA_HIP(launch_combine(w.SV, n, m, w.Cc, nret, nroot, n, 1.0, 0.0, w.SZ, n, s));
-    PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot, n, nvv, w.omega, w.R, w.part, nres, s));
-    PPRPA_HIP(launch_reduce_norms(w.part, nres, nroot, w.rnorm, s));
-    PPRPA_HIP(hipMemcpyAsync(hp, w.omega, nroot * sizeof(double), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipMemcpyAsync(hp + 64, w.rnorm, nroot * sizeof(double), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipMemcpyAsync(hp + 128, w.info, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-    PPRPA_HIP(hipStreamSynchronize(s));
-    if (sigma_pending) {
-      float ms = 0.f;
-      PPRPA_HIP(hipEventElapsedTime(&ms, c->e0, c->e1));
-      t_sigma += ms * 1e-3;
-      sigma_pending = false;
-    }
-    PPRPA_TRY(harvest_timing(c));
-    const int* info = (const int*)(hp + 128);
-    const int npos = info[1];
-    if (info[0] == 1) {
-      set_error("projected pencil V(M - 2 mu W)V^T not positive definite at iteration %d", iter);
-      status = PPRPA_ENONDEF;
-      break;
-    }
-    if (info[0] == 2) {
-      set_error("projected pencil has %d pp roots, fewer than nroot=%d", npos, nroot);
-      status = PPRPA_ENONDEF;
-      break;
-    }
-    std::copy(hp, hp + nroot, om);
-    std::copy(hp + 64, hp + 64 + nroot, rn);
-    ++iter;
-    int nconv = 0;
-    double maxr = 0.0;
-    std::vector<int> sel;
-    for (int j = 0; j < nroot; ++j) {
-      if (!std::isfinite(rn[j])) {
-        set_error("non-finite residual at iteration %d", iter);
-        return PPRPA_EDEVICE;
-      }
-      maxr = std::max(maxr, rn[j]);
-      if (rn[j] <= a->tol)
-        ++nconv;
-      else if ((int)sel.size() < blk)
-        sel.push_back(j);
-    }
-    emit_log(a, iter, m, nconv, maxr, om[0], nsig, info[2]);
-    R.n_conv = nconv;
-    R.max_resid = maxr;
-    if (nconv == nroot) {
-      status = PPRPA_OK;
-      break;
-    }
-    if (iter >= max_iter) {
-      set_error("Davidson not converged in %d iterations (max residual %.3e)", iter, maxr);
-      status = PPRPA_ENOCONV;
-      break;
-    }
-    const int nsel = (int)sel.size();
-    // restart if the new block does not fit
-    if (m + nsel > mmax) {
-      int nkeep = std::min(std::min(nret, m), std::max(npos, nroot));
-      nkeep = std::max(nroot, std::min(nkeep, mmax - nsel));
-      PPRPA_HIP(launch_small_orth(w.Cc, nret, m, nkeep, w.Q, nret, w.info + 6, s));
-      PPRPA_HIP(hipMemcpyAsync(hp + 130, w.info + 6, sizeof(int), hipMemcpyDeviceToHost, s));
-      PPRPA_HIP(hipStreamSynchronize(s));
-      const int rank = *(int*)(hp + 130);
-      if (rank < nroot) {
-        set_error("restart basis lost rank (%d < %d)", rank, nroot);
-        status = PPRPA_ENOCONV;
-        break;
-      }
-      PPRPA_HIP(launch_combine(w.V, n, m, w.Q, nret, rank, n, 1.0, 0.0, w.Vt, n, s));
-      PPRPA_HIP(launch_combine(w.SV, n, m, w.Q, nret, rank, n, 1.0, 0.0, w.SVt, n, s));
-      PPRPA_HIP(launch_small_congruence(w.Ms, mmax, m, w.Q, nret, rank, w.Mt, mmax, w.pwork, s));
-      PPRPA_HIP(launch_small_congruence(w.Ws_, mmax, m, w.Q, nret, rank, w.Wt, mmax, w.pwork, s));
-      std::swap(w.V, w.Vt);
-      std::swap(w.SV, w.SVt);
-      std::swap(w.Ms, w.Mt);
-      std::swap(w.Ws_, w.Wt);
-      m = rank;
-      mnew0 = m;
-      mprev = 0;  // the basis was rotated: no warm start
-    }
-    PPRPA_HIP(launch_precond(w.R, n, sel.data(), nsel, n, nvv, c->epair, w.omega, w.Tn, n, s));
-    int added = 0;
-    PPRPA_TRY(add_vectors(c, w, m, nsel, tblk, &added));
-    if (added == 0) {
-      set_error("Davidson stagnated: corrections lie in the subspace (max residual %.3e)", maxr);
-      status = PPRPA_ENOCONV;
-      break;
-    }
-    PPRPA_HIP(hipEventRecord(c->e0, s));
-    PPRPA_TRY(sigma_device(c, added, w.V + (size_t)m * n, w.SV + (size_t)m * n));
-    PPRPA_HIP(hipEventRecord(c->e1, s));
-    sigma_pending = true;
-    nsig += added;
-    mnew0 = m;
-    m += added;
+// Orthonormalisation of the correction rows Tn[0:nsel] against V[0:m] and among themselves, in
+// two passes: pass 1 normalises, projects out V twice and forms the block's Gram matrix
+// transform (count kept -> pinned[0]); pass 2 applies it into Tn2, projects out V once more and
+// repeats the Gram step (count -> pinned[0]); commit appends the result to V at row m.
+pprpa_status Solver::orth_pass1(int nsel) {
+  const int64_t n = c_->g.n;
+  hipStream_t s = c_->stream;
+  PPRPA_HIP(launch_normalize_rows(w.Tn, n, nsel, n, s));
+  for (int pass = 0; pass < 2 && m_ > 0; ++pass) {
+    PPRPA_HIP(launch_dots(w.V, n, m_, w.Tn, n, nsel, n, 0, 0, w.Cp, tblk_, w.part, nch_, s));
+    PPRPA_HIP(launch_combine(w.V, n, m_, w.Cp, tblk_, nsel, n, -1.0, 1.0, w.Tn, n, s));
   }
-  if (status == PPRPA_OK || status == PPRPA_ENOCONV) {
-    pprpa_status f = finish(c, w, nroot, omega, vecs, resid, rep, om, rn);
+  PPRPA_HIP(launch_dots(w.Tn, n, nsel, w.Tn, n, nsel, n, 0, 0, w.Gb, tblk_, w.part, nch_, s));
+  PPRPA_HIP(launch_gram_orth(w.Gb, tblk_, nsel, 1e-10, w.Tm, tblk_, w.info + 4, w.pwork, s));
+  PPRPA_HIP(hipMemcpyAsync(c_->pinned, w.info + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+  nsel_ = nsel;
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::orth_pass2(int kept) {
+  const int64_t n = c_->g.n;
+  hipStream_t s = c_->stream;
+  PPRPA_HIP(launch_combine(w.Tn, n, nsel_, w.Tm, tblk_, kept, n, 1.0, 0.0, w.Tn2, n, s));
+  if (m_ > 0) {
+    PPRPA_HIP(launch_dots(w.V, n, m_, w.Tn2, n, kept, n, 0, 0, w.Cp, tblk_, w.part, nch_, s));
+    PPRPA_HIP(launch_combine(w.V, n, m_, w.Cp, tblk_, kept, n, -1.0, 1.0, w.Tn2, n, s));
+  }
+  PPRPA_HIP(launch_dots(w.Tn2, n, kept, w.Tn2, n, kept, n, 0, 0, w.Gb, tblk_, w.part, nch_, s));
+  PPRPA_HIP(launch_gram_orth(w.Gb, tblk_, kept, 1e-10, w.Tm, tblk_, w.info + 4, w.pwork, s));
+  PPRPA_HIP(hipMemcpyAsync(c_->pinned, w.info + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+  kept_ = kept;
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::orth_commit(int kept, int kept2) {
+  const int64_t n = c_->g.n;
+  PPRPA_HIP(launch_combine(w.Tn2, n, kept, w.Tm, tblk_, kept2, n, 1.0, 0.0, w.V + (size_t)m_ * n, n,
+                           c_->stream));
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::rr_launch() {
+  const int64_t n = c_->g.n, nvv = c_->g.nvv;
+  hipStream_t s = c_->stream;
+  double* hp = c_->pinned;  // [0,64) omega, [64,128) rnorm, [128,..) ints
+  const int nb = m_ - mnew0_;
+  if (nb > 0) {
+    PPRPA_HIP(launch_dots(w.V, n, m_, w.SV + (size_t)mnew0_ * n, n, nb, n, 0, 0, w.Ms + mnew0_,
+                          mmax_, w.part, nch_, s));
+    PPRPA_HIP(launch_dots(w.V, n, m_, w.V + (size_t)mnew0_ * n, n, nb, n, nvv, 1, w.Ws_ + mnew0_,
+                          mmax_, w.part, nch_, s));
+  }
+  PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_), w.omega,
+                          w.Cc, nret_, w.pwork, w.info, w.Up, mmax_, mprev_, s));
+  mprev_ = m_;
+  PPRPA_HIP(launch_combine(w.V, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.Z, n, s));
+  PPRPA_HIP(launch_combine(w.SV, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
+  PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, nres_, s));
+  PPRPA_HIP(launch_reduce_norms(w.part, nres_, nroot_, w.rnorm, s));
+  PPRPA_HIP(hipMemcpyAsync(hp, w.omega, nroot_ * sizeof(double), hipMemcpyDeviceToHost, s));
+  PPRPA_HIP(hipMemcpyAsync(hp + 64, w.rnorm, nroot_ * sizeof(double), hipMemcpyDeviceToHost, s));
+  PPRPA_HIP(hipMemcpyAsync(hp + 128, w.info, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  phase = RR_READ;
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::rr_read() {
+  const double* hp = c_->pinned;
+  if (sig_timed_) {
+    float ms = 0.f;
+    PPRPA_HIP(hipEventElapsedTime(&ms, c_->e0, c_->e1));
+    t_sigma += ms * 1e-3;
+    sig_timed_ = false;
+  }
+  PPRPA_TRY(harvest_timing(c_));
+  const int* info = (const int*)(hp + 128);
+  npos_ = info[1];
+  if (info[0] == 1) {
+    set_error("projected pencil V(M - 2 mu W)V^T not positive definite at iteration %d", iter_);
+    return fail(PPRPA_ENONDEF);
+  }
+  if (info[0] == 2) {
+    set_error("projected pencil has %d pp roots, fewer than nroot=%d", npos_, nroot_);
+    return fail(PPRPA_ENONDEF);
+  }
+  std::copy(hp, hp + nroot_, om_);
+  std::copy(hp + 64, hp + 64 + nroot_, rn_);
+  have_iterate_ = true;
+  ++iter_;
+  nconv_ = 0;
+  maxr_ = 0.0;
+  sel_.clear();
+  for (int j = 0; j < nroot_; ++j) {
+    if (!std::isfinite(rn_[j])) {
+      set_error("non-finite residual at iteration %d", iter_);
+      return fail(PPRPA_EDEVICE);
+    }
+    maxr_ = std::max(maxr_, rn_[j]);
+    if (rn_[j] <= a_.tol)
+      ++nconv_;
+    else if ((int)sel_.size() < blk_)
+      sel_.push_back(j);
+  }
+  log_iteration(nconv_, maxr_, info[2]);
+  if (nconv_ == nroot_) return done(PPRPA_OK);
+  if (iter_ >= max_iter_) {
+    set_error("Davidson not converged in %d iterations (max residual %.3e)", iter_, maxr_);
+    return done(PPRPA_ENOCONV);
+  }
+  const int nsel = (int)sel_.size();
+  // restart if the new block does not fit
+  if (m_ + nsel > mmax_) {
+    int nkeep = std::min(std::min(nret_, m_), std::max(npos_, nroot_));
+    nkeep = std::max(nroot_, std::min(nkeep, mmax_ - nsel));
+    PPRPA_HIP(launch_small_orth(w.Cc, nret_, m_, nkeep, w.Q, nret_, w.info + 6, c_->stream));
+    PPRPA_HIP(hipMemcpyAsync(c_->pinned + 130, w.info + 6, sizeof(int), hipMemcpyDeviceToHost,
+                             c_->stream));
+    phase = RESTART_READ;
+    return PPRPA_OK;
+  }
+  return launch_corrections();
+}
+
+pprpa_status Solver::restart_read() {
+  const int64_t n = c_->g.n;
+  hipStream_t s = c_->stream;
+  const int rank = *(const int*)(c_->pinned + 130);
+  if (rank < nroot_) {
+    set_error("restart basis lost rank (%d < %d)", rank, nroot_);
+    return done(PPRPA_ENOCONV);
+  }
+  PPRPA_HIP(launch_combine(w.V, n, m_, w.Q, nret_, rank, n, 1.0, 0.0, w.Vt, n, s));
+  PPRPA_HIP(launch_combine(w.SV, n, m_, w.Q, nret_, rank, n, 1.0, 0.0, w.SVt, n, s));
+  PPRPA_HIP(launch_small_congruence(w.Ms, mmax_, m_, w.Q, nret_, rank, w.Mt, mmax_, w.pwork, s));
+  PPRPA_HIP(launch_small_congruence(w.Ws_, mmax_, m_, w.Q, nret_, rank, w.Wt, mmax_, w.pwork, s));
+  std::swap(w.V, w.Vt);
+  std::swap(w.SV, w.SVt);
+  std::swap(w.Ms, w.Mt);
+  std::swap(w.Ws_, w.Wt);
+  m_ = rank;
+  mnew0_ = m_;
+  mprev_ = 0;  // the basis was rotated: no warm start
+  return launch_corrections();
+}
+
+pprpa_status Solver::launch_corrections() {
+  const int64_t n = c_->g.n, nvv = c_->g.nvv;
+  const int nsel = (int)sel_.size();
+  PPRPA_HIP(launch_precond(w.R, n, sel_.data(), nsel, n, nvv, c_->epair, w.omega, w.Tn, n,
+                           c_->stream));
+  PPRPA_TRY(orth_pass1(nsel));
+  phase = ORTH1_READ;
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::orth1_read() {
+  const int kept = *(const int*)c_->pinned;
+  if (kept <= 0) return stagnated();
+  PPRPA_TRY(orth_pass2(kept));
+  phase = ORTH2_READ;
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::orth2_read() {
+  const int kept2 = *(const int*)c_->pinned;
+  if (kept2 <= 0) return stagnated();
+  PPRPA_TRY(orth_commit(kept_, kept2));
+  sig_m0 = m_;
+  sig_k = kept2;
+  nsig_ += kept2;
+  mnew0_ = m_;
+  m_ += kept2;
+  phase = NEED_SIGMA;
+  return PPRPA_OK;
+}
+
+pprpa_status Solver::stagnated() {
+  set_error("Davidson stagnated: corrections lie in the subspace (max residual %.3e)", maxr_);
+  return done(PPRPA_ENOCONV);
+}
+
+pprpa_status Solver::advance() {
+  pprpa_status rc = PPRPA_OK;
+  switch (phase) {
+    case RR_LAUNCH: rc = rr_launch(); break;
+    case RR_READ: rc = rr_read(); break;
+    case RESTART_READ: rc = restart_read(); break;
+    case ORTH1_READ: rc = orth1_read(); break;
+    case ORTH2_READ: rc = orth2_read(); break;
+    default:
+      set_error("solver advanced in phase %d", (int)phase);
+      rc = PPRPA_EINVAL;
+  }
+  if (rc != PPRPA_OK && phase != DONE) return fail(rc);
+  return rc;
+}
+
+pprpa_status Solver::results(double* omega, double* vecs, double* resid, pprpa_report* rep) {
+  const int64_t n = c_->g.n;
+  const bool filled = (status == PPRPA_OK || status == PPRPA_ENOCONV) && have_iterate_;
+  if (filled) {
+    if (omega) std::copy(om_, om_ + nroot_, omega);
+    if (resid) std::copy(rn_, rn_ + nroot_, resid);
+    if (vecs) {
+      PPRPA_HIP(launch_scale_sign(w.Z, n, nroot_, n, c_->stream));
+      PPRPA_HIP(hipMemcpyAsync(vecs, w.Z, (size_t)nroot_ * n * sizeof(double),
+                               hipMemcpyDeviceToHost, c_->stream));
+    }
+    PPRPA_HIP(hipStreamSynchronize(c_->stream));
+  }
+  if (rep) {
+    pprpa_report R{};
+    R.iters = iter_;
+    R.n_sigma = nsig_;
+    R.n_conv = nconv_;
+    R.subspace = m_;
+    R.max_resid = maxr_;
+    R.t_sigma_s = t_sigma;
+    R.t_total_s = seconds_since(t0_);
+    *rep = R;
+  }
+  return PPRPA_OK;
+}
+
+// Direct diagonalisation of the dense pencil (M, W) with the same device pencil solver.
+pprpa_status Solver::run_direct() {
+  const Geometry& g = c_->g;
+  const int64_t n = g.n, nvv = g.nvv;
+  hipStream_t s = c_->stream;
+  nroot_ = a_.nroot;
+  if (!c_->M) {
+    set_error("direct diagonalisation needs a dense build");
+    return PPRPA_EUNSUPPORTED;
+  }
+  if (n > 512) {
+    set_error("direct diagonalisation on the device is limited to n <= 512 (n=%lld)", (long long)n);
+    return PPRPA_EUNSUPPORTED;
+  }
+  const int m = (int)n;
+  PPRPA_TRY(get_ws(c_, m, nroot_, 1, (size_t)4 * m * m, (size_t)nroot_ * 64, &w));
+  double* hp = c_->pinned;
+  PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
+  PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc, nroot_,
+                          w.pwork, w.info, nullptr, 0, 0, s));
+  PPRPA_HIP(launch_transpose(w.Cc, nroot_, m, nroot_, w.Z, n, s));
+  PPRPA_HIP(launch_combine(c_->M, n, m, w.Cc, nroot_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
+  PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, 64, s));
+  PPRPA_HIP(launch_reduce_norms(w.part, 64, nroot_, w.rnorm, s));
+  PPRPA_HIP(hipMemcpyAsync(hp, w.omega, nroot_ * sizeof(double), hipMemcpyDeviceToHost, s));
+  PPRPA_HIP(hipMemcpyAsync(hp + 64, w.rnorm, nroot_ * sizeof(double), hipMemcpyDeviceToHost, s));
+  PPRPA_HIP(hipMemcpyAsync(hp + 128, w.info, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PPRPA_HIP(hipStreamSynchronize(s));
+  const int* info = (const int*)(hp + 128);
+  if (info[0] == 1) {
+    set_error("M - 2 mu W is not positive definite");
+    return PPRPA_ENONDEF;
+  }
+  if (info[0] == 2) {
+    set_error("fewer than nroot pp roots (%d)", info[1]);
+    return PPRPA_ENONDEF;
+  }
+  std::copy(hp, hp + nroot_, om_);
+  std::copy(hp + 64, hp + 64 + nroot_, rn_);
+  have_iterate_ = true;
+  nconv_ = nroot_;
+  maxr_ = *std::max_element(rn_, rn_ + nroot_);
+  m_ = m;
+  if (info[0] == 3) {
+    set_error("dense pencil eigensolver did not converge");
+    return done(PPRPA_ENOCONV);
+  }
+  return done(PPRPA_OK);
+}
+
+// One solve on one context, phases run back to back.
+pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega, double* vecs,
+                          double* resid, pprpa_report* rep) {
+  Solver sv(c, *a);
+  sv.start();
+  while (sv.phase != Solver::DONE) {
+    if (sv.phase == Solver::NEED_SIGMA) {
+      const int64_t n = c->g.n;
+      PPRPA_HIP(hipEventRecord(c->e0, c->stream));
+      pprpa_status rc = sigma_device(c, sv.sig_k, sv.w.V + (size_t)sv.sig_m0 * n,
+                                     sv.w.SV + (size_t)sv.sig_m0 * n);
+      if (rc != PPRPA_OK) return rc;
+      PPRPA_HIP(hipEventRecord(c->e1, c->stream));
+      sv.sigma_done(true);
+      continue;
+    }
+    if (sv.phase != Solver::RR_LAUNCH) PPRPA_HIP(hipStreamSynchronize(c->stream));
+    sv.advance();
+  }
+  if (sv.status != PPRPA_OK && !sv.message.empty()) set_error("%s", sv.message.c_str());
+  const pprpa_status st = sv.status;
+  if (st == PPRPA_OK || st == PPRPA_ENOCONV || rep) {
+    const std::string keep = sv.message;
+    pprpa_status f = sv.results(omega, vecs, resid, rep);
     if (f != PPRPA_OK) return f;
+    if (!keep.empty()) set_error("%s", keep.c_str());
   }
-  R.iters = iter;
-  R.n_sigma = nsig;
-  R.subspace = m;
-  R.t_sigma_s = t_sigma;
-  R.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  if (rep) *rep = R;
-  return status;
+  return st;
 }
 
 }  // namespace pprpa

@@ -45,6 +45,13 @@ struct Geometry {
   int64_t nvv = 0, noo = 0, n = 0;
 };
 
+// A served context's device memory: one contiguous reservation, handed out by bumping `top`
+// (nothing is freed until the whole reservation is released).
+struct Slab {
+  char* base = nullptr;
+  size_t size = 0, top = 0;
+};
+
 // Sigma precision and storage type.
 enum class Store { F64, F32, BF16 };
 
@@ -80,6 +87,14 @@ hipError_t launch_unpack(const Geometry& g, Store st, const double* z, int k, co
                          void* ZT, size_t zplane, hipStream_t s);
 hipError_t launch_sigma(const Geometry& g, Store st, const SigmaPlan& plan, const SigmaLaunch& a,
                         hipStream_t s);
+// Up to GROUP_MAX sigma products of the same kernel variant in one launch (serving).
+constexpr int GROUP_MAX = 16;
+struct GroupMember {
+  const Geometry* g;
+  const SigmaPlan* plan;
+  SigmaLaunch la;
+};
+hipError_t launch_sigma_group(const GroupMember* m, int n, hipStream_t s);
 hipError_t launch_epilogue(const Geometry& g, Store st, const double* z, int k, const void* Sp,
                            int nsplit, const int* d_ptab, const double* d_epair, double* sigma,
                            hipStream_t s);

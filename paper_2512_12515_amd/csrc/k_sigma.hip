@@ -212,6 +212,19 @@ struct SandParams {
   int npan_v;
 };
 
+// Entries of a grouped sigma launch (passed by value as the kernel argument).
+struct GroupEntry {
+  const void* L;
+  const void* UT;
+  void* Qp;
+  SandParams p;
+};
+struct GroupArgs {
+  int n, per_xcd;
+  int u0[GROUP_MAX + 1];  // first unit of each entry; u0[n] = total units
+  GroupEntry e[GROUP_MAX];
+};
+
 // c tiles of the chunk a contraction-1 step on d tile dt touches, rounded out to groups of 4
 // (columns outside the valid range hold exact zeros in U^T: c > d, or the other block).
 __device__ __forceinline__ void c_range(int dt, int cc0, int cc1, int nvt, int* g0, int* g1) {
@@ -256,19 +269,16 @@ __device__ __forceinline__ void dma_tile(const T* __restrict__ src, int64_t ld, 
 // block is Q + s Q^T, formed in the epilogue). Every wave of a panel does the same work. Each
 // stage is staged by direct global->LDS loads into one buffer; two workgroups per CU overlap one
 // another's staging with their MFMA work.
-template <typename T, int CT, int RT, int OCC>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(OCC, OCC)))
-void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict__ Qp,
-                SandParams a) {
+// Work unit u of one sigma product (u < a.nunits): unit -> (work item, vector, aux split).
+template <typename T, int CT, int RT>
+__device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* __restrict__ UT,
+                                              T* __restrict__ Qp, const SandParams& a, int u,
+                                              T* __restrict__ buf) {
   using V = typename AccT<T>::V;
   using Cfg = SandCfg<T, CT, RT>;
   constexpr int GRP = 2;  // tiles per unrolled MFMA group
   static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
-  __shared__ __attribute__((aligned(1024))) T buf[Cfg::BUF];
 
-  const int g = blockIdx.x;
-  const int u = (g & 7) * a.per_xcd + (g >> 3);
-  if (u >= a.nunits) return;
   const int item = a.items[u % a.nitems];
   const int kv = (u / a.nitems) % a.k;
   const int sp = u / (a.nitems * a.k);
@@ -405,6 +415,36 @@ void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict
   }
 }
 
+// One workgroup per work unit; consecutive units go to the same XCD (workgroups are dealt to
+// the 8 XCDs round-robin), so the units sharing a panel of L^P share that XCD's L2.
+template <typename T, int CT, int RT, int OCC>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(OCC, OCC)))
+void k_sandwich(const T* __restrict__ L, const T* __restrict__ UT, T* __restrict__ Qp,
+                SandParams a) {
+  __shared__ __attribute__((aligned(1024))) T buf[SandCfg<T, CT, RT>::BUF];
+  const int g = blockIdx.x;
+  const int u = (g & 7) * a.per_xcd + (g >> 3);
+  if (u >= a.nunits) return;
+  sandwich_unit<T, CT, RT>(L, UT, Qp, a, u, buf);
+}
+
+// Grouped launch: the work units of several independent sigma products (one per entry, each with
+// its own integrals, vectors, partial-sum buffer and decomposition) laid end to end. A unit does
+// exactly what it does in a launch of its own product, so each product's result does not depend
+// on what it is grouped with.
+template <typename T, int CT, int RT, int OCC>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(OCC, OCC)))
+void k_sandwich_group(GroupArgs ga) {
+  __shared__ __attribute__((aligned(1024))) T buf[SandCfg<T, CT, RT>::BUF];
+  const int g = blockIdx.x;
+  const int u = (g & 7) * ga.per_xcd + (g >> 3);
+  if (u >= ga.u0[ga.n]) return;
+  int e = 0;
+  while (e + 1 < ga.n && u >= ga.u0[e + 1]) ++e;
+  sandwich_unit<T, CT, RT>((const T*)ga.e[e].L, (const T*)ga.e[e].UT, (T*)ga.e[e].Qp, ga.e[e].p,
+                           u - ga.u0[e], buf);
+}
+
 // ------------------------------------------------------------------------------------------
 // Epilogue: sigma = E z + N * (Q + s Q^T), Q summed over the aux splits in a fixed order, FP64.
 // ------------------------------------------------------------------------------------------
@@ -519,9 +559,7 @@ int sigma_variant(const Geometry& g, Store st, int* RT) {
   return 3;
 }
 
-template <typename T, int CC, int RT, int OCC>
-static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,
-                               hipStream_t s) {
+static SandParams sand_params(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la) {
   SandParams p;
   p.nvp = g.nvp;
   p.nop = g.nop;
@@ -538,9 +576,49 @@ static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const S
   p.zstride = (int64_t)g.nmop * g.nmop;
   p.npan_v = plan.npan_v;
   p.items = plan.d_items;
-  hipLaunchKernelGGL((k_sandwich<T, CC, RT, OCC>), dim3(nwg), dim3(256), 0, s, (const T*)la.L,
-                     (const T*)la.ZT, (T*)la.Sp, p);
+  return p;
+}
+
+template <typename T, int CC, int RT, int OCC>
+static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,
+                               hipStream_t s) {
+  const SandParams p = sand_params(g, plan, la);
+  hipLaunchKernelGGL((k_sandwich<T, CC, RT, OCC>), dim3(p.per_xcd * 8), dim3(256), 0, s,
+                     (const T*)la.L, (const T*)la.ZT, (T*)la.Sp, p);
   return hipGetLastError();
+}
+
+template <typename T, int CC, int RT, int OCC>
+static hipError_t run_group(const GroupMember* m, int n, hipStream_t s) {
+  GroupArgs ga{};
+  ga.n = n;
+  int total = 0;
+  for (int i = 0; i < n; ++i) {
+    ga.e[i].L = m[i].la.L;
+    ga.e[i].UT = m[i].la.ZT;
+    ga.e[i].Qp = m[i].la.Sp;
+    ga.e[i].p = sand_params(*m[i].g, *m[i].plan, m[i].la);
+    ga.u0[i] = total;
+    total += ga.e[i].p.nunits;
+  }
+  ga.u0[n] = total;
+  const int nwg = (total + 7) / 8 * 8;
+  ga.per_xcd = nwg / 8;
+  hipLaunchKernelGGL((k_sandwich_group<T, CC, RT, OCC>), dim3(nwg), dim3(256), 0, s, ga);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_group(const GroupMember* m, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > GROUP_MAX) return hipErrorInvalidValue;
+  const int variant = m[0].plan->variant;
+  for (int i = 1; i < n; ++i)
+    if (m[i].plan->variant != variant) return hipErrorInvalidValue;
+  switch (variant) {
+    case 1: return run_group<double, 8, 16, 2>(m, n, s);
+    case 4: return run_group<float, 16, 32, 2>(m, n, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 hipError_t launch_sigma_bf16(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,

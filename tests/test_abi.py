@@ -82,3 +82,20 @@ def test_null_arguments():
     assert L.pprpa_matvec(None, 1, None, None, 0) == B.EINVAL
     d = B.DavidsonArgs()
     assert L.pprpa_davidson(None, C.byref(d), None, None, None, None) == B.EINVAL
+
+
+def test_server_argument_checks():
+    L = B.lib()
+    h = C.c_void_p(1234)
+    assert L.pprpa_server_create(1 << 30, 0, C.byref(h)) == B.EINVAL
+    assert "max_inflight" in L.pprpa_last_error().decode()
+    assert L.pprpa_server_create(1 << 30, 65, C.byref(h)) == B.EINVAL
+    assert L.pprpa_server_create(1000, 4, C.byref(h)) == B.EINVAL
+    assert "1 MiB" in L.pprpa_last_error().decode()
+    assert L.pprpa_server_submit(None, None, None, None) == B.EINVAL
+    info = B.RequestInfo()
+    assert L.pprpa_server_poll(None, 1, C.byref(info), None, None, None) == B.EINVAL
+    assert L.pprpa_server_wait(None, 1, 0.0) == B.EINVAL
+    st = B.ServingStats()
+    assert L.pprpa_server_stats(None, C.byref(st)) == B.EINVAL
+    L.pprpa_server_destroy(None)

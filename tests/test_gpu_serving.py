@@ -1,0 +1,184 @@
+"""GPU: the serving loop (continuous batching with HBM admission and grouped sigma launches).
+
+* every request's roots in a mix equal the same request served alone, and the same problem
+  solved by pprpa_build + pprpa_davidson, bit for bit (a grouped launch runs each member's work
+  units exactly as its own launch would: same decomposition, same reduction order);
+* small requests against the FP64 oracle within 1e-6 Ha;
+* the arena is never over-committed: peak reserved bytes <= budget, and a budget that holds one
+  large request at a time serialises them;
+* failures stay with their request (EINVAL for non-finite integrals, found by the build;
+  ENOCONV at the iteration cap; ENOMEM for a request larger than the arena) while the rest of the
+  mix completes with the same roots.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pprpa_oracle as O
+from workloads import gen
+import paper_2512_12515_amd as P
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def device_inputs(seed, nocc, nvir, naux, scale=1.0):
+    import torch
+    dev = torch.device("cuda:0")
+    nmo = nocc + nvir
+    idx = np.arange(nmo)
+    L = torch.empty((naux, nmo, nmo), dtype=torch.float64, device=dev)
+    for p0 in range(0, naux, 256):
+        aux = np.arange(p0, min(naux, p0 + 256))
+        L[p0:p0 + aux.size] = gen.lpq_block_torch(seed, nmo, naux, idx, idx, aux, dev) * scale
+    eps = torch.from_numpy(gen.orbital_energies(seed, nocc, nvir)).to(dev)
+    torch.cuda.synchronize()
+    return eps, L
+
+
+MIX = [  # (seed, nocc, nvir, mult, nroot, prec)
+    (11, 6, 40, "singlet", 5, "fp64"),
+    (12, 10, 90, "triplet", 8, "fp64"),
+    (13, 4, 30, "triplet", 4, "fp64"),
+    (14, 16, 120, "singlet", 12, "fp64"),
+    (15, 8, 70, "singlet", 6, "fp32"),
+    (16, 12, 100, "triplet", 10, "fp32"),
+    (17, 20, 150, "singlet", 8, "fp64"),
+    (18, 5, 60, "singlet", 7, "fp32"),
+]
+
+
+def naux_of(nocc, nvir):
+    return (7 * (nocc + nvir) + 1) // 2
+
+
+def serve(reqs, budget=8 << 30, max_inflight=8, inputs=None):
+    out = {}
+    with P.Server(budget, max_inflight) as srv:
+        tickets = []
+        for i, (seed, nocc, nvir, mult, nroot, prec) in enumerate(reqs):
+            eps, L = inputs[i] if inputs else device_inputs(seed, nocc, nvir, naux_of(nocc, nvir))
+            tickets.append(srv.submit(eps, L, nocc, nroot, mult=mult, prec=prec, tol=1e-7))
+        for i, t in enumerate(tickets):
+            out[i] = srv.wait(t, timeout=120.0)
+        stats = srv.stats()
+    return out, stats
+
+
+@pytest.fixture(scope="module")
+def mix_inputs():
+    return [device_inputs(s, no, nv, naux_of(no, nv)) for (s, no, nv, *_r) in MIX]
+
+
+@pytest.fixture(scope="module")
+def served_mix(mix_inputs):
+    note("serving the mix of", len(MIX))
+    res, stats = serve(MIX, inputs=mix_inputs)
+    note("stats", stats)
+    return res, stats
+
+
+def test_mix_completes(served_mix):
+    res, stats = served_mix
+    for i, r in res.items():
+        assert r["state"] == 2 and r["status"] == P.binding.OK, (MIX[i], r["message"])
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+    assert stats["completed"] == len(MIX) and stats["failed"] == 0
+    assert stats["group_launches"] > 0
+    # several solves shared launches: fewer grids than block products
+    assert stats["grouped_products"] > stats["group_launches"]
+    assert stats["peak_inflight"] >= 2
+
+
+@pytest.mark.parametrize("i", range(len(MIX)))
+def test_alone_equals_mix(served_mix, mix_inputs, i):
+    res, _ = served_mix
+    alone, _ = serve([MIX[i]], inputs=[mix_inputs[i]])
+    assert np.array_equal(alone[0]["omega"], res[i]["omega"]), (alone[0]["omega"] - res[i]["omega"])
+    assert alone[0]["report"]["iters"] == res[i]["report"]["iters"]
+
+
+@pytest.mark.parametrize("i", [0, 1, 4, 6])
+def test_mix_equals_standalone_context(served_mix, mix_inputs, i):
+    res, _ = served_mix
+    seed, nocc, nvir, mult, nroot, prec = MIX[i]
+    eps, L = mix_inputs[i]
+    with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
+        r = ctx.davidson(nroot, tol=1e-7)
+    assert np.array_equal(r["omega"], res[i]["omega"]), (r["omega"] - res[i]["omega"])
+
+
+@pytest.mark.parametrize("i", [0, 2, 4, 7])
+def test_small_requests_vs_oracle(served_mix, i):
+    res, _ = served_mix
+    seed, nocc, nvir, mult, nroot, prec = MIX[i]
+    eps = gen.orbital_energies(seed, nocc, nvir)
+    L = gen.lpq_full(seed, nocc + nvir, naux_of(nocc, nvir))
+    ref = O.solve(eps, L, nocc, mult, nroot)
+    assert np.max(np.abs(res[i]["omega"] - ref)) <= 1e-6
+
+
+def test_host_inputs_served():
+    seed, nocc, nvir, mult, nroot = 21, 6, 40, "triplet", 5
+    naux = naux_of(nocc, nvir)
+    eps = gen.orbital_energies(seed, nocc, nvir)
+    L = gen.lpq_full(seed, nocc + nvir, naux)
+    with P.Server(1 << 30, 2) as srv:
+        t = srv.submit(eps, L, nocc, nroot, mult=mult, tol=1e-7)
+        r = srv.wait(t, timeout=60.0)
+    assert r["status"] == P.binding.OK, r["message"]
+    assert np.max(np.abs(r["omega"] - O.solve(eps, L, nocc, mult, nroot))) <= 1e-6
+
+
+def test_budget_serialises_large_requests():
+    reqs = [(31 + j, 20, 150, "singlet" if j % 2 else "triplet", 6, "fp64") for j in range(4)]
+    inputs = [device_inputs(s, no, nv, naux_of(no, nv)) for (s, no, nv, *_r) in reqs]
+    # footprint of one request, from a first run with a roomy arena
+    res, stats = serve(reqs[:1], inputs=inputs[:1])
+    fp = res[0]["footprint"]
+    budget = int(fp * 1.5)
+    note("footprint", fp, "budget", budget)
+    res2, stats2 = serve(reqs, budget=budget, max_inflight=4, inputs=inputs)
+    note("stats", stats2)
+    assert stats2["peak_reserved"] <= budget
+    assert stats2["peak_inflight"] == 1
+    assert all(r["status"] == P.binding.OK for r in res2.values())
+    assert np.array_equal(res2[0]["omega"], res[0]["omega"])
+    # admissions were sequential: each request was admitted after the previous one finished
+    order = sorted(res2.values(), key=lambda r: r["t_admit"])
+    for a, b in zip(order, order[1:]):
+        assert b["t_admit"] >= a["t_done"] - 1e-3
+
+
+def test_failures_are_isolated(mix_inputs, served_mix):
+    import torch
+    res, _ = served_mix
+    seed, nocc, nvir, mult, nroot, prec = MIX[1]
+    eps_nan, L_nan = device_inputs(41, 10, 90, naux_of(10, 90))
+    L_nan[3, 12, 40] = float("nan")  # rejected by the build (EINVAL) in the admission thread
+    with P.Server(2 << 30, 4) as srv:
+        t_ok = srv.submit(*mix_inputs[1], nocc, nroot, mult=mult, prec=prec, tol=1e-7)
+        t_nan = srv.submit(eps_nan, L_nan, 10, 6, mult="singlet", tol=1e-7)
+        # iteration cap: ENOCONV with the last iterate's roots
+        t_cap = srv.submit(*mix_inputs[0], MIX[0][1], 5, mult="singlet", tol=1e-13, max_iter=2)
+        big = torch.zeros((4000, 440, 440), dtype=torch.float64, device="cuda:0")
+        eps_big = torch.linspace(-1, 2, 440, dtype=torch.float64, device="cuda:0")
+        t_big = srv.submit(eps_big, big, 40, 4, mult="singlet", tol=1e-7)  # > 2 GiB footprint
+        with pytest.raises(P.PpRPAError):
+            srv.submit(eps_big, big, 40, 10 ** 6, mult="singlet")  # nroot beyond n_pp: rejected
+        r_ok, r_nan = srv.wait(t_ok, 60.0), srv.wait(t_nan, 60.0)
+        r_cap, r_big = srv.wait(t_cap, 60.0), srv.wait(t_big, 60.0)
+        st = srv.stats()
+    del big
+    assert r_ok["status"] == P.binding.OK
+    assert np.array_equal(r_ok["omega"], res[1]["omega"])
+    assert r_nan["status"] == P.binding.EINVAL and "non-finite" in r_nan["message"]
+    assert r_cap["status"] == P.binding.ENOCONV and r_cap["report"]["iters"] == 2
+    assert np.all(np.isfinite(r_cap["omega"]))
+    assert r_big["status"] == P.binding.ENOMEM and "bytes" in r_big["message"]
+    assert st["failed"] == 3 and st["completed"] == 4
