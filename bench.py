@@ -9,7 +9,16 @@ staging (pprpa_build, both spins) + the two Davidson solves (sigma products, FP6
 algebra, Rayleigh-Ritz, residuals). The metric is sigma products per second (single-vector
 products counted over both solves) at an eigenvalue error within 1e-6 Ha of the oracle's.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+Serving stream (--serve-only): 512 seeded requests (workloads/gen.py serve_requests: nocc 4-40,
+nvir 30-400, naux = 3.5 nmo, singlet/triplet 50/50, 4-12 roots, integrals scaled by 0.7, tol
+1e-6) through the library's server, FP32 sigma with FP64 subspace algebra by default
+(--serve-prec fp64 for all-FP64). The saturated rate R_sat is measured first (the first 48
+requests submitted at once); then all 512 arrive as a Poisson process at 0.7 R_sat. Each
+request's integrals are generated on the device ahead of its arrival (not timed); latency =
+finish - submit on the server's clock. The default line carries a shorter sample of the same
+stream under "serving" (R_sat from 32 requests, then the first 64 requests at 0.7 R_sat).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-serve | --serve-only]
 """
 import argparse
 import json
@@ -60,6 +69,145 @@ def cpu_baseline(nocc, nvir, naux, mult, nvec, budget_s=20.0):
                       f"NumPy) at nocc={nocc}, nvir={nvir}, naux={naux}"}
 
 
+def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, prec="fp64",
+                 tol=1e-6, lookahead=12):
+    """The serving workload: saturated rate, then Poisson arrivals at 0.7 of it."""
+    import queue
+    import threading
+    import torch
+    dev = torch.device("cuda:0")
+    reqs = gen.serve_requests(0, n_req)
+    pstream = torch.cuda.Stream(device=dev)  # input generation, off the library's streams
+
+    def inputs(r):
+        nmo = r["nocc"] + r["nvir"]
+        idx = np.arange(nmo)
+        with torch.cuda.stream(pstream):
+            L = torch.empty((r["naux"], nmo, nmo), dtype=torch.float64, device=dev)
+            for p0 in range(0, r["naux"], 128):
+                aux = np.arange(p0, min(r["naux"], p0 + 128))
+                L[p0:p0 + aux.size] = gen.lpq_block_torch(r["seed"], nmo, r["naux"], idx, idx, aux,
+                                                          dev) * r["eig_scale"]
+            eps = torch.from_numpy(gen.orbital_energies(r["seed"], r["nocc"], r["nvir"])).to(dev)
+        pstream.synchronize()
+        return eps, L
+
+    def submit(srv, r, eps, L):
+        return srv.submit(eps, L, r["nocc"], r["nroot"], mult=r["mult"], prec=prec, tol=tol)
+
+    def run(srv, order, arrivals):
+        """Submit requests `order` at `arrivals` (s, from start); poll until all are done. The
+        binding keeps a request's inputs alive until a poll shows the library no longer needs
+        them, so polling as we go bounds the memory held by inputs."""
+        q = queue.Queue(maxsize=lookahead)
+
+        def producer():
+            for i in order:
+                q.put((i, inputs(reqs[i])))
+
+        th = threading.Thread(target=producer, daemon=True)
+        th.start()
+        pending, out, late = {}, {}, []
+
+        def sweep():
+            for t, i in list(pending.items()):
+                r = srv.poll(t)
+                if r["state"] == srv.DONE:
+                    out[i] = r
+                    del pending[t]
+                    if len(out) % 32 == 0:
+                        log(f"  {len(out)}/{len(order)} requests done at "
+                            f"{time.perf_counter() - t_start:.1f}s")
+
+        t_start = time.perf_counter()
+        for j, _ in enumerate(order):
+            i, (eps, L) = q.get()
+            wait = arrivals[j] - (time.perf_counter() - t_start)
+            while wait > 0:
+                time.sleep(min(wait, 0.002))
+                sweep()
+                wait = arrivals[j] - (time.perf_counter() - t_start)
+            if wait < -1e-3:
+                late.append(-wait)
+            pending[submit(srv, reqs[i], eps, L)] = i
+            del eps, L
+            sweep()
+        th.join()
+        while pending:
+            time.sleep(0.001)
+            sweep()
+        return out, time.perf_counter() - t_start, late
+
+    budget = int(budget_gb * (1 << 30))
+    # saturated service rate: n_sat requests, inputs generated beforehand, submitted at once
+    pre = [inputs(reqs[i]) for i in range(n_sat)]
+    with P.Server(budget, max_inflight) as srv:
+        t0 = time.perf_counter()
+        tk = {i: submit(srv, reqs[i], *pre[i]) for i in range(n_sat)}
+        del pre
+        res = {}
+        for i, t in tk.items():
+            res[i] = srv.wait(t, timeout=600.0)
+            if (i + 1) % 16 == 0:
+                log(f"  saturated: {i + 1}/{n_sat} done at {time.perf_counter() - t0:.1f}s")
+        t_sat = time.perf_counter() - t0
+        st_sat = srv.stats()
+    log(f"saturated stats: {st_sat}")
+    sat_ok = sum(r["status"] == P.binding.OK for r in res.values())
+    r_sat = n_sat / t_sat
+    log(f"saturated: {n_sat} requests in {t_sat:.2f}s -> R_sat = {r_sat:.1f}/s")
+    lam = 0.7 * r_sat
+    arr = gen.poisson_arrivals(0, n_req, lam)
+    with P.Server(budget, max_inflight) as srv:
+        res, makespan, late = run(srv, list(range(n_req)), arr)
+        st = srv.stats()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res.values()])
+    qwait = np.array([r["t_admit"] - r["t_submit"] for r in res.values()])
+    status = {}
+    for r in res.values():
+        name = P.binding.STATUS_NAMES[r["status"]]
+        status[name] = status.get(name, 0) + 1
+    ok = [r for r in res.values() if r["status"] == P.binding.OK]
+    failures = [dict(nocc=reqs[i]["nocc"], nvir=reqs[i]["nvir"], mult=reqs[i]["mult"],
+                     nroot=reqs[i]["nroot"], status=P.binding.STATUS_NAMES[r["status"]],
+                     message=r["message"][:80])
+                for i, r in sorted(res.items()) if r["status"] != P.binding.OK]
+    n_sigma = sum(r["report"]["n_sigma"] for r in ok)
+    # accuracy: the smallest served requests against the oracle
+    from oracle import pprpa_oracle as O
+    small = sorted(res, key=lambda i: reqs[i]["nvir"] + reqs[i]["nocc"])[:6]
+    errs = []
+    for i in small:
+        r = reqs[i]
+        if res[i]["status"] != P.binding.OK:
+            continue
+        ref = O.solve(gen.orbital_energies(r["seed"], r["nocc"], r["nvir"]),
+                      gen.lpq_full(r["seed"], r["nocc"] + r["nvir"], r["naux"]) * r["eig_scale"],
+                      r["nocc"], r["mult"], r["nroot"])
+        errs.append(float(np.max(np.abs(res[i]["omega"] - ref))))
+    peak = PEAK_FP64 if prec == "fp64" else PEAK_FP32
+    tf = st["sigma_flops"] / st["sigma_seconds"] if st["sigma_seconds"] > 0 else 0.0
+    return {
+        "requests": n_req, "prec": prec, "tol": tol, "budget_gb": budget_gb,
+        "max_inflight": max_inflight,
+        "saturated_rate_req_s": r_sat, "saturated_sample": n_sat, "saturated_ok": sat_ok,
+        "saturated_mean_group_size": st_sat["grouped_products"] / max(st_sat["group_launches"], 1),
+        "saturated_peak_inflight": st_sat["peak_inflight"],
+        "arrival_rate_req_s": lam,
+        "throughput_req_s": n_req / makespan, "makespan_s": makespan,
+        "sigma_products_per_s": n_sigma / makespan,
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "queue_wait_p50_s": float(np.percentile(qwait, 50)),
+        "queue_wait_p99_s": float(np.percentile(qwait, 99)),
+        "late_submits": len(late), "status": status, "failures": failures[:12],
+        "peak_inflight": st["peak_inflight"], "peak_reserved_gb": st["peak_reserved"] / 2 ** 30,
+        "group_launches": st["group_launches"],
+        "mean_group_size": st["grouped_products"] / max(st["group_launches"], 1),
+        "grouped_sigma_tflops": tf / 1e12, "grouped_sigma_frac": tf / peak,
+        "max_eig_err_ha_smallest6_vs_oracle": max(errs) if errs else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +221,12 @@ def main():
     ap.add_argument("--block", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--prec", default="fp64")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=None,
+                    help="requests in the serving stream (default 512 with --serve-only, else 96)")
+    ap.add_argument("--serve-prec", default="fp32",
+                    help="sigma precision of the served solves (subspace algebra is FP64)")
     ap.add_argument("--serial", dest="concurrent", action="store_false",
                     help="run the singlet and triplet solves one after the other")
     args = ap.parse_args()
@@ -87,6 +241,12 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
+    if args.serve_only:
+        line = {"metric": "served ppRPA requests/s with p50/p99 latency", "n_gpus": 1,
+                "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
+        line.update(serve_stream(P, gen, n_req=args.serve_requests or 512, prec=args.serve_prec))
+        print(json.dumps(line), flush=True)
+        return
     nocc, nvir, naux = args.nocc, args.nvir, args.naux
     t = time.perf_counter()
     eps = gen.orbital_energies(0, nocc, nvir)
@@ -181,6 +341,10 @@ def main():
         "max_eig_err_ha": max_err,
         "iters": {m: results[-1][m]["rep"]["iters"] for m in mults},
     }
+    if not args.no_serve:
+        log("serving stream ...")
+        line["serving"] = serve_stream(P, gen, n_req=args.serve_requests or 64, n_sat=32,
+                                       prec=args.serve_prec)
     if not args.no_cpu:
         log("timing the oracle on the host cores ...")
         line["cpu_baseline"] = cpu_baseline(nocc, nvir, naux, "singlet", 64)

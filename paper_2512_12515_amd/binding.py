@@ -286,6 +286,7 @@ class Server:
         _check(lib().pprpa_server_create(int(hbm_budget_bytes), int(max_inflight), C.byref(h)))
         self._h = h
         self._held = {}
+        self._nroot = {}
 
     def submit(self, eps, Lpq, nocc, nroot, mult="singlet", prec="fp64", nocc_act=0, nvir_act=0,
                lpq_is_active=False, block=0, tol=1e-6, max_iter=0, max_subspace=0):
@@ -307,13 +308,14 @@ class Server:
         d.max_subspace, d.tol = int(max_subspace), float(tol)
         t = C.c_uint64()
         _check(lib().pprpa_server_submit(self._h, C.byref(b), C.byref(d), C.byref(t)))
-        self._held[t.value] = (eps, Lpq, int(nroot))
+        self._held[t.value] = (eps, Lpq)
+        self._nroot[t.value] = int(nroot)
         return t.value
 
     def poll(self, ticket):
         """Request state; once done also its roots, residuals and report (the ticket retires)."""
         info = RequestInfo()
-        nroot = self._held[ticket][2] if ticket in self._held else 64
+        nroot = self._nroot.get(ticket, 64)
         omega, resid, rep = np.empty(nroot), np.empty(nroot), Report()
         _check(lib().pprpa_server_poll(self._h, int(ticket), C.byref(info), omega.ctypes.data,
                                        resid.ctypes.data, C.byref(rep)))
@@ -323,6 +325,7 @@ class Server:
         if info.state >= self.RUNNING:
             self._held.pop(ticket, None)
         if info.state == self.DONE:
+            self._nroot.pop(ticket, None)
             out.update(omega=omega, resid=resid, report=rep.as_dict())
         return out
 
@@ -340,6 +343,7 @@ class Server:
             lib().pprpa_server_destroy(self._h)
             self._h = None
             self._held.clear()
+            self._nroot.clear()
 
     def __del__(self):
         try:

@@ -7,12 +7,14 @@
 //   the whole arena fails with ENOMEM. The build and the initial subspace run on the slot's
 //   stream; after that the caller's input buffers are no longer read.
 // * Progress (worker thread): every in-flight solve is a Davidson phase machine. Each pass the
-//   worker advances every solve whose stream has drained, and gathers every solve waiting for a
-//   sigma product into grouped launches: unpack on the request's stream, one grid for the whole
-//   group on the group stream (ordered after each member's unpack by an event), the epilogue back
-//   on each request's stream (ordered after the grid by an event). A member's work units are those
-//   of a launch of its own (same decomposition, same partial-sum buffer), so its results do not
-//   depend on the mix it was served in.
+//   worker advances every solve whose stream has drained. A solve that needs a sigma product has
+//   its block unpacked at once on its own stream; the solves waiting for sigma are then launched
+//   together as one grouped grid on the group stream, ordered after each member's unpack by an
+//   event, with the epilogue back on each request's stream, ordered after the grid by an event.
+//   One grid is in flight at a time: the solves that become ready while it runs form the next
+//   group (continuous batching), so the groups grow with the load. A member's work units are
+//   those of a launch of its own (same decomposition, same partial-sum buffer), so its results do
+//   not depend on the mix it was served in.
 // * Finished solves copy out their roots, release their reservation and slot, and wake the
 //   admission thread.
 #include <algorithm>
@@ -93,6 +95,7 @@ struct Request {
   Slab slab;
   pprpa_ctx* ctx = nullptr;
   std::unique_ptr<Solver> sv;
+  bool unpacked = false;  // the pending sigma block is unpacked (ctx->e0 marks its end)
   pprpa_status status = PPRPA_OK;
   std::string message;
   double omega[64] = {0}, resid[64] = {0};
@@ -229,7 +232,8 @@ void admission_loop(pprpa_server* S) {
   S->cv_work.notify_all();
 }
 
-// Grouped sigma for the solves in `need` (all waiting in NEED_SIGMA, one kernel variant).
+// Grouped sigma for the solves in `grp` (all in NEED_SIGMA with their block unpacked, one kernel
+// variant).
 // Returns false if the group launch failed (its members are then failed by the caller).
 bool launch_group(pprpa_server* S, std::vector<Request*>& grp, std::vector<TimedGroup>& timed,
                   std::vector<hipEvent_t>& pool) {
@@ -241,14 +245,9 @@ bool launch_group(pprpa_server* S, std::vector<Request*>& grp, std::vector<Timed
     Request* r = grp[i];
     pprpa_ctx* c = r->ctx;
     Solver& sv = *r->sv;
-    const int64_t n = c->g.n;
     const int k = sv.sig_k;
     ns[i] = nsplit_for(c, k);
-    if (launch_unpack(c->g, c->st, sv.w.V + (size_t)sv.sig_m0 * n, k, c->ptab, c->ZT, c->zplane,
-                      c->stream) != hipSuccess ||
-        hipEventRecord(c->e0, c->stream) != hipSuccess ||
-        hipStreamWaitEvent(S->gstream, c->e0, 0) != hipSuccess)
-      return false;
+    if (hipStreamWaitEvent(S->gstream, c->e0, 0) != hipSuccess) return false;
     SigmaLaunch la{};
     la.L = c->L;
     la.ZT = c->ZT;
@@ -288,6 +287,7 @@ bool launch_group(pprpa_server* S, std::vector<Request*>& grp, std::vector<Timed
     if (launch_epilogue(c->g, c->st, sv.w.V + (size_t)sv.sig_m0 * n, sv.sig_k, c->Sp, ns[i], c->ptab,
                         c->epair, sv.w.SV + (size_t)sv.sig_m0 * n, c->stream) != hipSuccess)
       return false;
+    r->unpacked = false;
     sv.sigma_done(false);
   }
   return true;
@@ -342,26 +342,24 @@ void worker_loop(pprpa_server* S) {
           }
           progressed = true;
         } else {
-          (c->st == Store::F64 ? need64 : need32).push_back(r);
+          if (!r->unpacked) {
+            const int64_t n = c->g.n;
+            if (launch_unpack(c->g, c->st, sv.w.V + (size_t)sv.sig_m0 * n, sv.sig_k, c->ptab, c->ZT,
+                              c->zplane, c->stream) != hipSuccess ||
+                hipEventRecord(c->e0, c->stream) != hipSuccess) {
+              (void)hipGetLastError();
+              sv.phase = Solver::DONE;
+              sv.status = PPRPA_EDEVICE;
+              sv.message = "unpack launch failed";
+            } else {
+              r->unpacked = true;
+              progressed = true;
+            }
+          }
+          if (r->unpacked) (c->st == Store::F64 ? need64 : need32).push_back(r);
         }
       }
       if (sv.phase == Solver::DONE) finished.push_back(r);
-    }
-    for (auto* need : {&need64, &need32}) {
-      for (size_t i0 = 0; i0 < need->size(); i0 += GROUP_MAX) {
-        std::vector<Request*> grp(need->begin() + i0,
-                                  need->begin() + std::min(need->size(), i0 + GROUP_MAX));
-        if (!launch_group(S, grp, timed, pool)) {
-          (void)hipGetLastError();
-          for (Request* r : grp) {
-            r->sv->phase = Solver::DONE;
-            r->sv->status = PPRPA_EDEVICE;
-            r->sv->message = "grouped sigma launch failed";
-            if (std::find(finished.begin(), finished.end(), r) == finished.end()) finished.push_back(r);
-          }
-        }
-        progressed = true;
-      }
     }
     // fold finished group timings into the statistics
     size_t nt = 0;
@@ -381,6 +379,24 @@ void worker_loop(pprpa_server* S) {
     }
     timed.erase(timed.begin(), timed.begin() + nt);
 
+    // one grouped grid in flight at a time: launch the waiting solves once the last one is done
+    for (auto* need : {&need64, &need32}) {
+      if (!timed.empty()) break;
+      for (size_t i0 = 0; i0 < need->size(); i0 += GROUP_MAX) {
+        std::vector<Request*> grp(need->begin() + i0,
+                                  need->begin() + std::min(need->size(), i0 + GROUP_MAX));
+        if (!launch_group(S, grp, timed, pool)) {
+          (void)hipGetLastError();
+          for (Request* r : grp) {
+            r->sv->phase = Solver::DONE;
+            r->sv->status = PPRPA_EDEVICE;
+            r->sv->message = "grouped sigma launch failed";
+            if (std::find(finished.begin(), finished.end(), r) == finished.end()) finished.push_back(r);
+          }
+        }
+        progressed = true;
+      }
+    }
     for (Request* r : finished) {
       Solver& sv = *r->sv;
       pprpa_status status = sv.status;

@@ -170,7 +170,9 @@ CONFIGS = {
 def serve_requests(master_seed: int, count: int = 512):
     """Request mix for the serving stream: nocc ~ U{4..40}, nvir ~ U{30..400},
     naux = round-half-up(3.5 * nmo), singlet/triplet 50/50, nroot ~ U{4..12}.
-    Request r draws from sub-seed r."""
+    Request r draws from sub-seed r. Every request carries eig_scale = 0.7 (its integrals are
+    used as L * 0.7), for the reason given for the large workloads above: unscaled, about a fifth
+    of the mix (those with nvir above about 250, mostly triplets) has an indefinite M - 2 mu W."""
     reqs = []
     for r in range(count):
         u = uniform(master_seed, STREAM_SERVE, np.arange(4, dtype=np.uint64) + np.uint64(8 * r))
@@ -179,7 +181,8 @@ def serve_requests(master_seed: int, count: int = 512):
         mult = "singlet" if u[2] < 0.5 else "triplet"
         nroot = 4 + int(u[3] * 9)
         naux = (7 * (nocc + nvir) + 1) // 2
-        reqs.append(dict(rid=r, seed=r, nocc=nocc, nvir=nvir, naux=naux, mult=mult, nroot=nroot))
+        reqs.append(dict(rid=r, seed=r, nocc=nocc, nvir=nvir, naux=naux, mult=mult, nroot=nroot,
+                         eig_scale=0.7))
     return reqs
 
 
