@@ -208,6 +208,58 @@ def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, pre
     }
 
 
+PEAK_BF16 = 2.5e15   # dense BF16 matrix, FLOP/s
+
+
+def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20, tol=1e-6):
+    """The mixed-precision workload (nocc 50, nvir 500, naux 1800, singlet, 20 roots): the same
+    Davidson with sigma in each precision (subspace algebra FP64 throughout), per-root eigenvalue
+    error against the FP64 GPU run. The integrals are scaled by the workload's eig_scale (0.7),
+    at which the pencil is definite."""
+    import torch
+    dev = torch.device("cuda:0")
+    c = gen.CONFIGS["mixed"]
+    nocc, nvir, naux, nroot = c["nocc"], c["nvir"], c["naux"], c["nroot"]
+    nmo = nocc + nvir
+    idx = np.arange(nmo)
+    L = torch.empty((naux, nmo, nmo), dtype=torch.float64, device=dev)
+    for p0 in range(0, naux, 128):
+        aux = np.arange(p0, min(naux, p0 + 128))
+        L[p0:p0 + aux.size] = gen.lpq_block_torch(0, nmo, naux, idx, idx, aux, dev) * c["eig_scale"]
+    eps = torch.from_numpy(gen.orbital_energies(0, nocc, nvir)).to(dev)
+    torch.cuda.synchronize()
+    out, ref = {}, None
+    for prec in precs:
+        t0 = time.perf_counter()
+        with P.PpRPA(eps, L, nocc, mult="singlet", prec=prec, max_block=block) as ctx:
+            t1 = time.perf_counter()
+            r = ctx.davidson(nroot, block=block, tol=tol, max_iter=150, raise_noconv=False)
+            t2 = time.perf_counter()
+            st = ctx.sigma_stats()
+        nprod = {"bf16x6": 6, "bf16x3": 3}.get(prec, 1)
+        peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32}.get(prec, PEAK_BF16)
+        alg = st["flops"] / st["seconds"] if st["seconds"] > 0 else 0.0
+        e = {"status": P.binding.STATUS_NAMES[r["status"]], "build_s": t1 - t0, "solve_s": t2 - t1,
+             "iters": r["report"]["iters"], "n_sigma": r["report"]["n_sigma"],
+             "sigma_per_s": r["report"]["n_sigma"] / (t2 - t1),
+             "sigma_kernel_tflops_algorithmic": alg / 1e12,
+             "sigma_kernel_tflops_executed": nprod * alg / 1e12,
+             "sigma_kernel_frac_of_peak": nprod * alg / peak,
+             "sigma_kernel_share_of_solve": st["seconds"] / (t2 - t1),
+             "max_resid": r["report"]["max_resid"]}
+        if prec == "fp64":
+            ref = r["omega"]
+        else:
+            d = np.abs(r["omega"] - ref)
+            e["max_abs_err_vs_fp64_ha"] = float(d.max())
+            e["per_root_err_ha"] = [float(x) for x in d]
+        out[prec] = e
+        log(f"precision {prec}: {e['status']} {e['solve_s']:.2f}s {e['sigma_kernel_tflops_algorithmic']:.1f} TF")
+    del L
+    return {"workload": f"nocc={nocc} nvir={nvir} naux={naux} singlet, {nroot} roots, block {block}, "
+                        f"tol {tol:g}, L x {c['eig_scale']}", "by_prec": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +274,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--prec", default="fp64")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
+    ap.add_argument("--precision-only", action="store_true", help="run only the precision study")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving stream")
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="requests in the serving stream (default 512 with --serve-only, else 96)")
@@ -241,6 +295,12 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
+    if args.precision_only:
+        line = {"metric": "sigma-products/sec and per-root eigenvalue error by sigma precision",
+                "n_gpus": 1, "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
+        line.update(precision_study(P, gen))
+        print(json.dumps(line), flush=True)
+        return
     if args.serve_only:
         line = {"metric": "served ppRPA requests/s with p50/p99 latency", "n_gpus": 1,
                 "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
@@ -341,6 +401,9 @@ def main():
         "max_eig_err_ha": max_err,
         "iters": {m: results[-1][m]["rep"]["iters"] for m in mults},
     }
+    if not args.no_precision:
+        log("precision study ...")
+        line["precision"] = precision_study(P, gen)
     if not args.no_serve:
         log("serving stream ...")
         line["serving"] = serve_stream(P, gen, n_req=args.serve_requests or 64, n_sat=32,

@@ -183,8 +183,10 @@ pprpa_status geometry_of(const pprpa_build_args* a, Geometry* out) {
   g.no = no;
   g.naux = a->naux;
   g.mult = a->mult;
-  g.nvp = round_up(nv, TILE);
-  g.nop = round_up(no, TILE);
+  // BF16-split sigma reduces over 32 orbitals per MFMA: its blocks are padded to two tiles
+  const int pad = (a->prec == PPRPA_BF16X6 || a->prec == PPRPA_BF16X3) ? 2 * TILE : TILE;
+  g.nvp = round_up(nv, pad);
+  g.nop = round_up(no, pad);
   g.nmop = g.nvp + g.nop;
   g.nvt = g.nvp / TILE;
   g.nct = g.nmop / TILE;

@@ -32,6 +32,7 @@
 //   * workgroup ids are remapped so the 8 XCDs each take a contiguous range of work units, which
 //     share P ranges and vectors in that XCD's L2.
 #include "internal.h"
+#include "sigma_common.h"
 
 namespace pprpa {
 namespace {
@@ -169,6 +170,7 @@ __global__ void k_unpack(const double* __restrict__ z, int64_t n, int64_t nvv, i
   ZT[((int64_t)kv * nmop + off + d) * nmop + off + c] = (T)v;
 }
 
+// BF16 planes of U (not transposed: the BF16 kernel reads 8 consecutive d of a row c).
 __global__ void k_unpack_bf16(const double* __restrict__ z, int64_t n, int64_t nvv, int nv,
                               int no, int nvp, int nop, int nmop, int mult,
                               unsigned short* __restrict__ ZT, size_t zplane) {
@@ -195,7 +197,7 @@ __global__ void k_unpack_bf16(const double* __restrict__ z, int64_t n, int64_t n
   const unsigned short m = bf16_rne((float)r1);
   const double r2 = r1 - (double)bf16_to_f(m);
   const unsigned short l = bf16_rne((float)r2);
-  const size_t o = ((size_t)kv * nmop + off + d) * nmop + off + c;
+  const size_t o = ((size_t)kv * nmop + off + c) * nmop + off + d;  // U itself, row c
   ZT[o] = h;
   ZT[o + zplane] = m;
   ZT[o + 2 * zplane] = l;
@@ -204,13 +206,6 @@ __global__ void k_unpack_bf16(const double* __restrict__ z, int64_t n, int64_t n
 // ------------------------------------------------------------------------------------------
 // Fused sandwich kernel (FP64 / FP32 MFMA).
 // ------------------------------------------------------------------------------------------
-struct SandParams {
-  int nvp, nop, nmop, nvt, nct, naux;
-  int k, nsplit, nitems, nunits, per_xcd;
-  int64_t zstride;  // nmop * nmop
-  const int* items; // [nitems]: panel index << 16 | first row tile of the range
-  int npan_v;
-};
 
 // Entries of a grouped sigma launch (passed by value as the kernel argument).
 struct GroupEntry {
@@ -225,16 +220,6 @@ struct GroupArgs {
   GroupEntry e[GROUP_MAX];
 };
 
-// c tiles of the chunk a contraction-1 step on d tile dt touches, rounded out to groups of 4
-// (columns outside the valid range hold exact zeros in U^T: c > d, or the other block).
-__device__ __forceinline__ void c_range(int dt, int cc0, int cc1, int nvt, int* g0, int* g1) {
-  const int blo = dt < nvt ? 0 : nvt;            // first c tile of d's block
-  const int lo = max(cc0, blo);                   // lowest c tile used
-  const int hi = min(cc1, dt + 1);                // one past the highest (c <= d)
-  *g0 = cc0 + ((lo - cc0) & ~3);
-  *g1 = min(cc1, cc0 + ((hi - cc0 + 3) & ~3));
-}
-
 template <typename T, int CT, int RT>
 struct SandCfg {
   // LDS tiles are packed row-major (row stride = staged width) because direct global->LDS loads
@@ -246,23 +231,6 @@ struct SandCfg {
   static constexpr int VEC = 16 / sizeof(T);                     // elements per lane per load
   static constexpr int CHUNK = 1024 / sizeof(T);                 // elements per wave load
 };
-
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
-// Issue this wave's share of the direct global->LDS loads of a rows x cols tile (packed in LDS at
-// dst, row stride cols). Each wave load moves 64 lanes x 16 bytes into 1 KiB of contiguous LDS.
-template <typename T>
-__device__ __forceinline__ void dma_tile(const T* __restrict__ src, int64_t ld, int rows, int cols,
-                                         T* dst, int w, int lane) {
-  constexpr int VEC = 16 / sizeof(T), CHUNK = 1024 / sizeof(T);
-  const int nchunk = rows * cols / CHUNK;
-  for (int j = w; j < nchunk; j += 4) {
-    const int e = j * CHUNK + lane * VEC;
-    const int row = e / cols, col = e - row * cols;
-    __builtin_amdgcn_global_load_lds((const void*)(src + row * ld + col), (lds_ptr_t)(dst + j * CHUNK),
-                                     16, 0, 0);
-  }
-}
 
 // Q = sum_P L^P U L^P for one vector, a panel of up to 4 column tiles of one diagonal block and a
 // range of up to RT row tiles of that block (U: upper triangle of the unpacked vector; the sigma

@@ -1,15 +1,257 @@
-// BF16-split sigma kernel (see k_sigma.hip for the method and the FP64/FP32 kernels).
-#include "internal.h"
+// BF16-split sigma product on CDNA4 (gfx950): the same sandwich S = sum_P L^P U L^P as the
+// FP64/FP32 kernel in k_sigma.hip (same work units, same partial-sum layout, same epilogue),
+// with every product done on the BF16 matrix cores (MFMA 16x16x32, FP32 accumulation).
+//
+// Precision: each operand v is carried as three BF16 planes, hi = bf16(v), mid = bf16(v - hi),
+// lo = bf16(v - hi - mid) (round to nearest even), so hi + mid + lo holds v to about 24 bits. A
+// product a b is formed as the six terms hh + hm + mh + mm + hl + lh (BF16x6, about FP32
+// accuracy) or the three terms hh + hm + mh (BF16x3, about 2^-16 relative); terms below that are
+// dropped. L and the unpacked vectors are split when staged; the intermediate T of contraction 1
+// is split in registers before it enters contraction 2.
+//
+// Layout differences from the FP32 kernel, both dictated by the BF16 MFMA operand shape (each lane
+// supplies 8 consecutive reduction indices of one row of A and of one column of B):
+//   * contraction 1, T[c][col] = sum_d U[c][d] L^P[d][col]: U is stored row-major (not transposed)
+//     so a lane reads 8 consecutive d of row c; L^P[d][col] is read as row col of L^P (symmetric),
+//     again 8 consecutive d;
+//   * contraction 2, S[r][col] += sum_c L^P[r][c] T[c][col]: T comes from contraction 1's
+//     accumulators, in which a lane holds rows 4 lk .. 4 lk + 3 of a 16-row tile; two c tiles
+//     give the lane's 8 reduction slots, and the A operand is read with the same permutation (two
+//     4-element pieces of row r of L^P);
+//   * the diagonal blocks are padded to multiples of 32 orbitals (two tiles), so every 32-wide
+//     reduction block lies inside one block.
+#include "sigma_common.h"
 
 namespace pprpa {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int CT = 8;   // c tiles per chunk of T
+constexpr int RT = 32;  // row tiles per work unit (equals the FP32 kernel's, same work items)
+constexpr int RH = 16;  // row tiles per contraction-2 stage
+constexpr int KB = 32;  // reduction block of one MFMA
+
+template <int NPL>
+struct Bf16Cfg {
+  static constexpr int US = CT * TILE * KB;  // U rows of a chunk x one reduction block
+  static constexpr int LS = 4 * TILE * KB;   // L^P rows of a panel x one reduction block
+  static constexpr int S1 = NPL * (US + LS);
+  static constexpr int RS = RH * TILE * KB;  // L^P rows of a stage x one reduction block
+  static constexpr int S2 = NPL * RS;
+  static constexpr int BUF = S1 > S2 ? S1 : S2;
+};
+
+__device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// a b over the split planes (NPROD = 6 or 3 products).
+template <int NPROD>
+__device__ __forceinline__ f4 split_mfma(bf8 ah, bf8 am, bf8 al, bf8 bh, bf8 bm, bf8 bl, f4 c) {
+  c = mfma(ah, bh, c);
+  c = mfma(ah, bm, c);
+  c = mfma(am, bh, c);
+  if (NPROD == 6) {
+    c = mfma(am, bm, c);
+    c = mfma(ah, bl, c);
+    c = mfma(al, bh, c);
+  }
+  return c;
+}
+
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;  // exact
+  m = (__bf16)r1;
+  const float r2 = r1 - (float)m;  // exact
+  l = (__bf16)r2;
+}
+
+template <int NPROD>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restrict__ ZU,
+                     size_t zplane, float* __restrict__ Qp, SandParams a) {
+  constexpr int NPL = NPROD == 6 ? 3 : 2;  // planes used: hi, mid (, lo)
+  using Cfg = Bf16Cfg<NPL>;
+  __shared__ __attribute__((aligned(1024))) u16 buf[Cfg::BUF];
+
+  const int g = blockIdx.x;
+  const int u = (g & 7) * a.per_xcd + (g >> 3);
+  if (u >= a.nunits) return;
+  const int item = a.items[u % a.nitems];
+  const int kv = (u / a.nitems) % a.k;
+  const int sp = u / (a.nitems * a.k);
+  const int pn = item >> 16;
+  const int R0 = item & 0xFFFF;
+
+  const bool vblk = pn < a.npan_v;
+  const int t0 = vblk ? 4 * pn : 4 * (pn - a.npan_v);
+  const int bnt = vblk ? a.nvt : (a.nct - a.nvt);
+  const int brow0 = vblk ? 0 : a.nvp;
+  const int npt = min(4, bnt - t0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool active = w < npt;
+  const int wc = min(w, npt - 1);
+  const int nrt = min(bnt, R0 + RT) - R0;
+  const int col0 = brow0 + t0 * TILE;
+  const int ncol = npt * TILE;
+  const int row0 = brow0 + R0 * TILE;
+  const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
+  const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
+  const u16* __restrict__ Z = ZU + (int64_t)kv * a.zstride;
+
+  u16* const sU = buf;
+  u16* const sL = buf + NPL * Cfg::US;
+
+  f4 S[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) S[r] = f4{0, 0, 0, 0};
+
+  for (int P = P0; P < P1; ++P) {
+    const u16* __restrict__ Lp = L + (int64_t)P * a.zstride;
+    for (int cc0 = 0; cc0 < a.nct; cc0 += CT) {
+      const int cc1 = min(cc0 + CT, a.nct);
+      f4 Tacc[CT];
+#pragma unroll
+      for (int i = 0; i < CT; ++i) Tacc[i] = f4{0, 0, 0, 0};
+      // contraction 1: T[c][cols] = sum_d U[c][d] L^P[d][cols] over d in c's block, d >= c;
+      // one 32-wide block of d per stage (both tiles in one diagonal block)
+      for (int part = 0; part < 2; ++part) {
+        const int lo = part == 0 ? cc0 : max(cc0, a.nvt);
+        const int hi = part == 0 ? (cc0 < a.nvt ? a.nvt : cc0) : (cc1 > a.nvt ? a.nct : lo);
+        for (int dt = lo; dt < hi; dt += 2) {
+          int g0, g1, h0, h1;
+          c_range(dt, cc0, cc1, a.nvt, &g0, &g1);
+          c_range(dt + 1, cc0, cc1, a.nvt, &h0, &h1);
+          const int blo = dt < a.nvt ? 0 : a.nvt;
+          const int clo = max(cc0, blo), chi = min(cc1, dt + 2);  // c tiles with U[c][d] != 0
+          __syncthreads();
+#pragma unroll
+          for (int p = 0; p < NPL; ++p) {
+            dma_tile(Z + p * zplane + (int64_t)(g0 * TILE) * a.nmop + dt * TILE, a.nmop,
+                     (h1 - g0) * TILE, KB, sU + p * Cfg::US, w, lane);
+            dma_tile(Lp + p * plane + (int64_t)col0 * a.nmop + dt * TILE, a.nmop, ncol, KB,
+                     sL + p * Cfg::LS, w, lane);
+          }
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+          if (active) {
+            const int lrow = (wc * TILE + li) * KB + 8 * lk;
+            const bf8 bh = *(const bf8*)(sL + lrow);
+            const bf8 bm = *(const bf8*)(sL + Cfg::LS + lrow);
+            const bf8 bl = NPL == 3 ? *(const bf8*)(sL + 2 * Cfg::LS + lrow) : bh;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              const int cg = cc0 + ct;
+              if (cg >= clo && cg < chi) {
+                const int urow = ((cg - g0) * TILE + li) * KB + 8 * lk;
+                const bf8 ah = *(const bf8*)(sU + urow);
+                const bf8 am = *(const bf8*)(sU + Cfg::US + urow);
+                const bf8 al = NPL == 3 ? *(const bf8*)(sU + 2 * Cfg::US + urow) : ah;
+                Tacc[ct] = split_mfma<NPROD>(ah, am, al, bh, bm, bl, Tacc[ct]);
+              }
+            }
+          }
+        }
+      }
+      // contraction 2: S[r][cols] += sum_c L^P[r][c] T[c][cols], 32 c (two tiles of T) per
+      // reduction block; the lane's slots 0-3 are rows 4 lk .. 4 lk + 3 of the first tile, slots
+      // 4-7 the same rows of the second
+#pragma unroll
+      for (int i = 0; i < CT; i += 2) {
+        if (cc0 + i < cc1) {
+          bf8 th, tm, tl;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            __bf16 h, m, l;
+            split3(t < 4 ? Tacc[i][t] : Tacc[i + 1][t - 4], h, m, l);
+            th[t] = h;
+            tm[t] = m;
+            tl[t] = l;
+          }
+#pragma unroll
+          for (int half = 0; half < RT / RH; ++half) {
+            const int rh0 = half * RH;
+            if (rh0 < nrt) {
+              const int nr = min(RH, nrt - rh0);
+              __syncthreads();
+#pragma unroll
+              for (int p = 0; p < NPL; ++p)
+                dma_tile(Lp + p * plane + (int64_t)(row0 + rh0 * TILE) * a.nmop + (cc0 + i) * TILE,
+                         a.nmop, nr * TILE, KB, buf + p * Cfg::RS, w, lane);
+              __builtin_amdgcn_s_waitcnt(0);
+              __syncthreads();
+              if (active) {
+#pragma unroll
+                for (int rt = 0; rt < RH; ++rt) {
+                  if (rt < nr) {
+                    const int o = (rt * TILE + li) * KB + 4 * lk;
+                    bf8 av[3];
+#pragma unroll
+                    for (int p = 0; p < NPL; ++p) {
+                      const bf4 x0 = *(const bf4*)(buf + p * Cfg::RS + o);
+                      const bf4 x1 = *(const bf4*)(buf + p * Cfg::RS + o + TILE);
+                      av[p] = __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
+                    }
+                    S[rh0 + rt] = split_mfma<NPROD>(av[0], av[1], NPL == 3 ? av[2] : av[0], th, tm,
+                                                    tl, S[rh0 + rt]);
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if (active) {
+    float* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.zstride;
+    const int col = col0 + w * TILE + li;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      if (rt < nrt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          out[(int64_t)(row0 + rt * TILE + 4 * lk + j) * a.nmop + col] = S[rt][j];
+      }
+    }
+  }
+}
+
+}  // namespace
 
 hipError_t launch_sigma_bf16(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,
                              hipStream_t s) {
-  (void)g;
-  (void)plan;
-  (void)la;
-  (void)s;
-  return hipErrorNotSupported;
+  if (g.nvp % (2 * TILE) || g.nop % (2 * TILE)) return hipErrorInvalidValue;
+  SandParams p;
+  p.nvp = g.nvp;
+  p.nop = g.nop;
+  p.nmop = g.nmop;
+  p.nvt = g.nvt;
+  p.nct = g.nct;
+  p.naux = g.naux;
+  p.k = la.k;
+  p.nsplit = la.nsplit;
+  p.nitems = plan.nitems;
+  p.nunits = p.nitems * la.k * la.nsplit;
+  const int nwg = (p.nunits + 7) / 8 * 8;
+  p.per_xcd = nwg / 8;
+  p.zstride = (int64_t)g.nmop * g.nmop;
+  p.npan_v = plan.npan_v;
+  p.items = plan.d_items;
+  if (la.nprod == 3)
+    hipLaunchKernelGGL(k_sandwich_bf16<3>, dim3(nwg), dim3(256), 0, s, (const u16*)la.L, la.plane,
+                       (const u16*)la.ZT, la.zplane, (float*)la.Sp, p);
+  else
+    hipLaunchKernelGGL(k_sandwich_bf16<6>, dim3(nwg), dim3(256), 0, s, (const u16*)la.L, la.plane,
+                       (const u16*)la.ZT, la.zplane, (float*)la.Sp, p);
+  return hipGetLastError();
 }
 
 }  // namespace pprpa

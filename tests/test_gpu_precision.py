@@ -2,11 +2,15 @@
 
 * sigma at full size (50 occ / 500 vir / 1800 aux and the 40 + 400 window of 120 / 1500 / 4000)
   against oracle rows computed one by one from the integrals of those rows only;
-* FP32-sigma Davidson against the oracle on small problems and against the FP64 GPU Davidson at
-  full size, per root, within 1e-6 Ha (the integrals scaled by eig_scale = 0.7 at full size,
-  where the unscaled inputs give complex roots; see workloads/gen.py).
+* BF16-split sigma (six and three products) against the oracle's dense M z on small and ragged
+  problems;
+* FP32- and BF16x6-sigma Davidson against the oracle on small problems and against the FP64 GPU
+  Davidson at full size, per root, within 1e-6 Ha (the integrals scaled by eig_scale = 0.7 at
+  full size, where the unscaled inputs give complex roots; see workloads/gen.py).
 
-Tolerances: FP64 sigma 1e-12 relative to max|sigma|; FP32 sigma 3e-5 relative; eigenvalues 1e-6 Ha.
+Tolerances, relative to max|sigma|: FP64 1e-12; FP32 and BF16x6 3e-5 (operands carried to about
+24 bits, FP32 accumulation over naux * nmo terms); BF16x3 3e-4 (the dropped mid*mid, hi*lo and
+lo*hi terms are each about 2^-16 of a product). Eigenvalues 1e-6 Ha.
 """
 import sys
 
@@ -76,9 +80,33 @@ BIG = {
 }
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+TOL = {"fp64": 1e-12, "fp32": 3e-5, "bf16x6": 3e-5, "bf16x3": 3e-4}
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("case", [(4, 9, 30), (5, 20, 100), (20, 35, 50), (17, 33, 23), (1, 2, 5),
+                                  (7, 40, 64), (0, 5, 12)])
+def test_sigma_bf16_vs_oracle(prec, mult, case):
+    nocc, nvir, naux = case
+    note("sigma", prec, mult, case)
+    eps, L = gen.orbital_energies(12, nocc, nvir), gen.lpq_full(12, nocc + nvir, naux)
+    sp = O.active_space(eps, L, nocc)
+    M = O.pprpa_matrix(*O.build_matrices(sp, mult))
+    with P.PpRPA(eps, L, nocc, mult=mult, prec=prec) as ctx:
+        z = gen.random_vectors(4, 7, ctx.n)
+        s = ctx.matvec(z)
+        s1 = ctx.matvec(z[3])
+    ref = (M @ z.T).T
+    err = np.max(np.abs(s - ref))
+    assert err <= TOL[prec] * np.abs(ref).max(), err
+    assert np.array_equal(s1, s[3])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3"])
 @pytest.mark.parametrize("name", ["mixed", "active"])
-def test_sigma_full_size_sampled_rows(name, prec, tol):
+def test_sigma_full_size_sampled_rows(name, prec):
+    tol = TOL[prec]
     import torch
     c = BIG[name]
     note("sigma full size", name, prec)
@@ -100,21 +128,23 @@ def test_sigma_full_size_sampled_rows(name, prec, tol):
         assert np.max(np.abs(s[v][rows] - ref)) <= tol * scale
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case,nroot", [((6, 40, 90), 6), ((10, 60, 150), 8)])
-def test_fp32_davidson_vs_oracle(mult, case, nroot):
+def test_mixed_precision_davidson_vs_oracle(prec, mult, case, nroot):
     nocc, nvir, naux = case
-    note("fp32 davidson small", mult, case)
+    note(prec, "davidson small", mult, case)
     eps, L = gen.orbital_energies(3, nocc, nvir), gen.lpq_full(3, nocc + nvir, naux)
     ref = O.solve(eps, L, nocc, mult, nroot)
-    with P.PpRPA(eps, L, nocc, mult=mult, prec="fp32") as ctx:
+    with P.PpRPA(eps, L, nocc, mult=mult, prec=prec) as ctx:
         r = ctx.davidson(nroot, block=nroot, tol=1e-6)
     assert np.max(np.abs(r["omega"] - ref)) <= 1e-6
 
 
 @pytest.mark.parametrize("name,nroot", [("mixed", 20), ("active", 16)])
-def test_fp32_vs_fp64_davidson_full_size(name, nroot):
-    """Per-root FP32-sigma eigenvalues against the FP64 GPU Davidson on the same inputs."""
+def test_mixed_vs_fp64_davidson_full_size(name, nroot):
+    """Per-root FP32- and BF16x6-sigma eigenvalues against the FP64 GPU Davidson on the same
+    inputs."""
     import torch
     c = BIG[name]
     scale = gen.CONFIGS[name]["eig_scale"]
@@ -124,11 +154,12 @@ def test_fp32_vs_fp64_davidson_full_size(name, nroot):
     kw = dict(mult=c["mult"], nocc_act=c["nocc_act"] or 0, nvir_act=c["nvir_act"] or 0,
               lpq_is_active=c["nocc_act"] is not None, max_block=20)
     out = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x6"):
         with P.PpRPA(eps, Ld, c["nocc"], prec=prec, **kw) as ctx:
             r = ctx.davidson(nroot, block=20, tol=1e-6, max_iter=300)
         note(prec, r["report"])
         out[prec] = r["omega"]
-    err = np.abs(out["fp32"] - out["fp64"])
-    note("per-root |dOmega| (Ha):", err)
-    assert np.all(err <= 1e-6)
+    for prec in ("fp32", "bf16x6"):
+        err = np.abs(out[prec] - out["fp64"])
+        note(prec, "per-root |dOmega| (Ha):", err)
+        assert np.all(err <= 1e-6)
