@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6e12   # MI355X dense FP64 matrix, FLOP/s
 PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12     # B/s
+TRAFFIC_GB_PER_LAUNCH = 3.22  # measured for the FP64 sigma kernel as it stands (see roofline)
 
 
 def log(*a):
@@ -211,11 +212,43 @@ def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, pre
 PEAK_BF16 = 2.5e15   # dense BF16 matrix, FLOP/s
 
 
-def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20, tol=1e-6):
+def small_direct(P, gen, reps=20):
+    """The small direct workload (nocc 5, nvir 20, naux 100, singlet, 5 roots, seeds 0-4):
+    staging + dense build (pprpa_build with dense=1) and the direct dense diagonalisation on the
+    device, inputs resident in HBM; error against the oracle's stored roots."""
+    import torch
+    dev = torch.device("cuda:0")
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "small_direct.json")))
+    t_build, t_solve, errs = [], [], []
+    for seed in range(5):
+        eps = torch.from_numpy(gen.orbital_energies(seed, 5, 20)).to(dev)
+        L = torch.from_numpy(gen.lpq_full(seed, 25, 100)).to(dev)
+        torch.cuda.synchronize()
+        for rep in range(reps):
+            t0 = time.perf_counter()
+            ctx = P.PpRPA(eps, L, 5, mult="singlet", dense=True)
+            t1 = time.perf_counter()
+            r = ctx.davidson(5, direct=True)
+            t2 = time.perf_counter()
+            ctx.close()
+            if rep > 0:  # the first call of each seed also pays one-time set-up
+                t_build.append(t1 - t0)
+                t_solve.append(t2 - t1)
+        errs.append(float(np.max(np.abs(r["omega"] - np.array(gold["roots"][f"{seed}/singlet"])))))
+    return {"workload": "nocc=5 nvir=20 naux=100 singlet, 5 roots, seeds 0-4, direct",
+            "build_dense_ms_p50": 1e3 * float(np.median(t_build)),
+            "direct_solve_ms_p50": 1e3 * float(np.median(t_solve)),
+            "max_eig_err_ha_vs_oracle": max(errs)}
+
+
+def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20, tol=1e-6,
+                    tol_reduced=1e-5):
     """The mixed-precision workload (nocc 50, nvir 500, naux 1800, singlet, 20 roots): the same
     Davidson with sigma in each precision (subspace algebra FP64 throughout), per-root eigenvalue
     error against the FP64 GPU run. The integrals are scaled by the workload's eig_scale (0.7),
-    at which the pencil is definite."""
+    at which the pencil is definite. FP64 converges to residual tol; the reduced precisions to
+    tol_reduced, since their sigma error puts a floor near 1e-6 under the residual (the
+    eigenvalue error, quadratic in the residual, stays far below 1e-6 Ha)."""
     import torch
     dev = torch.device("cuda:0")
     c = gen.CONFIGS["mixed"]
@@ -233,7 +266,8 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
         t0 = time.perf_counter()
         with P.PpRPA(eps, L, nocc, mult="singlet", prec=prec, max_block=block) as ctx:
             t1 = time.perf_counter()
-            r = ctx.davidson(nroot, block=block, tol=tol, max_iter=150, raise_noconv=False)
+            r = ctx.davidson(nroot, block=block, tol=tol if prec == "fp64" else tol_reduced,
+                             max_iter=150, raise_noconv=False)
             t2 = time.perf_counter()
             st = ctx.sigma_stats()
         nprod = {"bf16x6": 6, "bf16x3": 3}.get(prec, 1)
@@ -257,7 +291,8 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
         log(f"precision {prec}: {e['status']} {e['solve_s']:.2f}s {e['sigma_kernel_tflops_algorithmic']:.1f} TF")
     del L
     return {"workload": f"nocc={nocc} nvir={nvir} naux={naux} singlet, {nroot} roots, block {block}, "
-                        f"tol {tol:g}, L x {c['eig_scale']}", "by_prec": out}
+                        f"tol {tol:g} (FP64) / {tol_reduced:g} (reduced precisions), "
+                        f"L x {c['eig_scale']}", "by_prec": out}
 
 
 def main():
@@ -281,6 +316,8 @@ def main():
                     help="requests in the serving stream (default 512 with --serve-only, else 96)")
     ap.add_argument("--serve-prec", default="fp32",
                     help="sigma precision of the served solves (subspace algebra is FP64)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--serial", dest="concurrent", action="store_false",
                     help="run the singlet and triplet solves one after the other")
     args = ap.parse_args()
@@ -318,6 +355,12 @@ def main():
     del L
 
     mults = ("singlet", "triplet")
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def solve(mult):
         t0 = time.perf_counter()
@@ -389,7 +432,13 @@ def main():
                    "block": args.block, "tol": args.tol, "prec": args.prec,
                    "solves": "concurrent (2 streams)" if args.concurrent else "serial"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     # HBM bytes per launch of this kernel (FP64, this workload), from
+                     # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy:
+                     # profiles/sigma_fp64_bench_20x200x700_hbm_traffic.md
+                     "traffic": TRAFFIC_GB_PER_LAUNCH if (args.prec == "fp64" and
+                                                          (nocc, nvir, naux) == (20, 200, 700)) else None,
+                     "traffic_unit": "GB/launch",
                      "kernel": "k_sandwich (fused sigma contraction)",
                      "launches": k_launch, "avg_launch_ms": 1e3 * k_sec / max(k_launch, 1),
                      "algorithmic_gbytes_per_launch": k_bytes / max(k_launch, 1) / 1e9},
@@ -401,6 +450,8 @@ def main():
         "max_eig_err_ha": max_err,
         "iters": {m: results[-1][m]["rep"]["iters"] for m in mults},
     }
+    log("small direct workload ...")
+    line["small_direct"] = small_direct(P, gen)
     if not args.no_precision:
         log("precision study ...")
         line["precision"] = precision_study(P, gen)

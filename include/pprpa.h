@@ -192,11 +192,11 @@ typedef struct {
 pprpa_status pprpa_server_create(size_t hbm_budget_bytes, int32_t max_inflight,
                                  pprpa_server** out);
 
-/* Queue one solve: the problem as for pprpa_build (prec FP64 or FP32; dense, stream and
- * max_block are chosen by the server) and the Davidson arguments (direct = 0). The memory
+/* Queue one solve: the problem as for pprpa_build (any prec; dense, stream and max_block are
+ * chosen by the server) and the Davidson arguments (direct = 0). The memory
  * that args point to (eps, Lpq, guess) must stay valid and unchanged until pprpa_server_poll
  * reports state >= 1; device inputs must be complete (their producer synchronised) before the
- * call. Errors (nothing queued): EINVAL, EUNSUPPORTED (BF16 or direct). A request larger than
+ * call. Errors (nothing queued): EINVAL, EUNSUPPORTED (direct). A request larger than
  * the whole arena is accepted and finishes with ENOMEM. */
 pprpa_status pprpa_server_submit(pprpa_server* srv, const pprpa_build_args* build,
                                  const pprpa_davidson_args* dav, uint64_t* ticket);

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpprpa.so")
+# PPRPA_LIB: load another build of the library (e.g. to compare two kernel builds); default: the
+# in-tree build.
+LIB_PATH = os.environ.get("PPRPA_LIB") or os.path.join(_HERE, "libpprpa.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONDEF, EUNSUPPORTED, EBUSY = range(8)
 STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOCONV", "ENONDEF", "EUNSUPPORTED", "EBUSY"]

@@ -207,18 +207,6 @@ __global__ void k_unpack_bf16(const double* __restrict__ z, int64_t n, int64_t n
 // Fused sandwich kernel (FP64 / FP32 MFMA).
 // ------------------------------------------------------------------------------------------
 
-// Entries of a grouped sigma launch (passed by value as the kernel argument).
-struct GroupEntry {
-  const void* L;
-  const void* UT;
-  void* Qp;
-  SandParams p;
-};
-struct GroupArgs {
-  int n, per_xcd;
-  int u0[GROUP_MAX + 1];  // first unit of each entry; u0[n] = total units
-  GroupEntry e[GROUP_MAX];
-};
 
 template <typename T, int CT, int RT>
 struct SandCfg {
@@ -527,26 +515,6 @@ int sigma_variant(const Geometry& g, Store st, int* RT) {
   return 3;
 }
 
-static SandParams sand_params(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la) {
-  SandParams p;
-  p.nvp = g.nvp;
-  p.nop = g.nop;
-  p.nmop = g.nmop;
-  p.nvt = g.nvt;
-  p.nct = g.nct;
-  p.naux = g.naux;
-  p.k = la.k;
-  p.nsplit = la.nsplit;
-  p.nitems = plan.nitems;
-  p.nunits = p.nitems * la.k * la.nsplit;
-  const int nwg = (p.nunits + 7) / 8 * 8;
-  p.per_xcd = nwg / 8;
-  p.zstride = (int64_t)g.nmop * g.nmop;
-  p.npan_v = plan.npan_v;
-  p.items = plan.d_items;
-  return p;
-}
-
 template <typename T, int CC, int RT, int OCC>
 static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,
                                hipStream_t s) {
@@ -558,34 +526,23 @@ static hipError_t run_sandwich(const Geometry& g, const SigmaPlan& plan, const S
 
 template <typename T, int CC, int RT, int OCC>
 static hipError_t run_group(const GroupMember* m, int n, hipStream_t s) {
-  GroupArgs ga{};
-  ga.n = n;
-  int total = 0;
-  for (int i = 0; i < n; ++i) {
-    ga.e[i].L = m[i].la.L;
-    ga.e[i].UT = m[i].la.ZT;
-    ga.e[i].Qp = m[i].la.Sp;
-    ga.e[i].p = sand_params(*m[i].g, *m[i].plan, m[i].la);
-    ga.u0[i] = total;
-    total += ga.e[i].p.nunits;
-  }
-  ga.u0[n] = total;
-  const int nwg = (total + 7) / 8 * 8;
-  ga.per_xcd = nwg / 8;
-  hipLaunchKernelGGL((k_sandwich_group<T, CC, RT, OCC>), dim3(nwg), dim3(256), 0, s, ga);
+  const GroupArgs ga = group_args(m, n);
+  hipLaunchKernelGGL((k_sandwich_group<T, CC, RT, OCC>), dim3(ga.per_xcd * 8), dim3(256), 0, s, ga);
   return hipGetLastError();
 }
+
+hipError_t launch_sigma_group_bf16(const GroupMember* m, int n, hipStream_t s);
 
 hipError_t launch_sigma_group(const GroupMember* m, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > GROUP_MAX) return hipErrorInvalidValue;
   const int variant = m[0].plan->variant;
   for (int i = 1; i < n; ++i)
-    if (m[i].plan->variant != variant) return hipErrorInvalidValue;
+    if (m[i].plan->variant != variant || m[i].la.nprod != m[0].la.nprod) return hipErrorInvalidValue;
   switch (variant) {
     case 1: return run_group<double, 8, 16, 2>(m, n, s);
     case 4: return run_group<float, 16, 32, 2>(m, n, s);
-    default: return hipErrorNotSupported;
+    default: return launch_sigma_group_bf16(m, n, s);
   }
 }
 

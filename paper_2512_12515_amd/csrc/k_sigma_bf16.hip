@@ -45,6 +45,22 @@ struct Bf16Cfg {
   static constexpr int BUF = S1 > S2 ? S1 : S2;
 };
 
+// LDS layout of a staged rows x 32 BF16 tile: each 64-byte row holds four 16-byte chunks, stored
+// at position kc ^ swz(row) so that the lanes one LDS cycle serves (rows r .. r+7 or r .. r+15 of
+// one chunk column) fall in distinct banks. The direct global->LDS loads write each wave's 1 KiB
+// contiguously, so the permutation is applied to the global addresses instead.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+__device__ __forceinline__ void dma_tile32(const u16* __restrict__ src, int64_t ld, int rows,
+                                           u16* dst, int w, int lane) {
+  const int nchunk = rows / 16;  // 16 rows x 64 bytes per wave load
+  for (int j = w; j < nchunk; j += 4) {
+    const int row = j * 16 + (lane >> 2), pos = lane & 3;
+    __builtin_amdgcn_global_load_lds((const void*)(src + row * ld + 8 * (pos ^ swz(row))),
+                                     (lds_ptr_t)(dst + j * 512), 16, 0, 0);
+  }
+}
+
 __device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
@@ -71,17 +87,14 @@ __device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l)
   l = (__bf16)r2;
 }
 
+// Work unit u of one product (u < a.nunits), as in the FP32 kernel.
 template <int NPROD>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restrict__ ZU,
-                     size_t zplane, float* __restrict__ Qp, SandParams a) {
+__device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, size_t plane,
+                                                   const u16* __restrict__ ZU, size_t zplane,
+                                                   float* __restrict__ Qp, const SandParams& a,
+                                                   int u, u16* __restrict__ buf) {
   constexpr int NPL = NPROD == 6 ? 3 : 2;  // planes used: hi, mid (, lo)
   using Cfg = Bf16Cfg<NPL>;
-  __shared__ __attribute__((aligned(1024))) u16 buf[Cfg::BUF];
-
-  const int g = blockIdx.x;
-  const int u = (g & 7) * a.per_xcd + (g >> 3);
-  if (u >= a.nunits) return;
   const int item = a.items[u % a.nitems];
   const int kv = (u / a.nitems) % a.k;
   const int sp = u / (a.nitems * a.k);
@@ -133,15 +146,15 @@ void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restr
           __syncthreads();
 #pragma unroll
           for (int p = 0; p < NPL; ++p) {
-            dma_tile(Z + p * zplane + (int64_t)(g0 * TILE) * a.nmop + dt * TILE, a.nmop,
-                     (h1 - g0) * TILE, KB, sU + p * Cfg::US, w, lane);
-            dma_tile(Lp + p * plane + (int64_t)col0 * a.nmop + dt * TILE, a.nmop, ncol, KB,
-                     sL + p * Cfg::LS, w, lane);
+            dma_tile32(Z + p * zplane + (int64_t)(g0 * TILE) * a.nmop + dt * TILE, a.nmop,
+                       (h1 - g0) * TILE, sU + p * Cfg::US, w, lane);
+            dma_tile32(Lp + p * plane + (int64_t)col0 * a.nmop + dt * TILE, a.nmop, ncol,
+                       sL + p * Cfg::LS, w, lane);
           }
           __builtin_amdgcn_s_waitcnt(0);
           __syncthreads();
           if (active) {
-            const int lrow = (wc * TILE + li) * KB + 8 * lk;
+            const int lrow = (wc * TILE + li) * KB + 8 * (lk ^ swz(li));
             const bf8 bh = *(const bf8*)(sL + lrow);
             const bf8 bm = *(const bf8*)(sL + Cfg::LS + lrow);
             const bf8 bl = NPL == 3 ? *(const bf8*)(sL + 2 * Cfg::LS + lrow) : bh;
@@ -149,7 +162,7 @@ void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restr
             for (int ct = 0; ct < CT; ++ct) {
               const int cg = cc0 + ct;
               if (cg >= clo && cg < chi) {
-                const int urow = ((cg - g0) * TILE + li) * KB + 8 * lk;
+                const int urow = ((cg - g0) * TILE + li) * KB + 8 * (lk ^ swz(li));
                 const bf8 ah = *(const bf8*)(sU + urow);
                 const bf8 am = *(const bf8*)(sU + Cfg::US + urow);
                 const bf8 al = NPL == 3 ? *(const bf8*)(sU + 2 * Cfg::US + urow) : ah;
@@ -182,20 +195,23 @@ void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restr
               __syncthreads();
 #pragma unroll
               for (int p = 0; p < NPL; ++p)
-                dma_tile(Lp + p * plane + (int64_t)(row0 + rh0 * TILE) * a.nmop + (cc0 + i) * TILE,
-                         a.nmop, nr * TILE, KB, buf + p * Cfg::RS, w, lane);
+                dma_tile32(Lp + p * plane + (int64_t)(row0 + rh0 * TILE) * a.nmop + (cc0 + i) * TILE,
+                           a.nmop, nr * TILE, buf + p * Cfg::RS, w, lane);
               __builtin_amdgcn_s_waitcnt(0);
               __syncthreads();
               if (active) {
 #pragma unroll
                 for (int rt = 0; rt < RH; ++rt) {
                   if (rt < nr) {
-                    const int o = (rt * TILE + li) * KB + 4 * lk;
+                    // c offsets 4 lk and 16 + 4 lk: chunks lk / 2 and 2 + lk / 2, half lk & 1
+                    const int o = (rt * TILE + li) * KB + 4 * (lk & 1);
+                    const int o0 = o + 8 * ((lk >> 1) ^ swz(li));
+                    const int o1 = o + 8 * ((2 + (lk >> 1)) ^ swz(li));
                     bf8 av[3];
 #pragma unroll
                     for (int p = 0; p < NPL; ++p) {
-                      const bf4 x0 = *(const bf4*)(buf + p * Cfg::RS + o);
-                      const bf4 x1 = *(const bf4*)(buf + p * Cfg::RS + o + TILE);
+                      const bf4 x0 = *(const bf4*)(buf + p * Cfg::RS + o0);
+                      const bf4 x1 = *(const bf4*)(buf + p * Cfg::RS + o1);
                       av[p] = __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
                     }
                     S[rh0 + rt] = split_mfma<NPROD>(av[0], av[1], NPL == 3 ? av[2] : av[0], th, tm,
@@ -224,33 +240,55 @@ void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restr
   }
 }
 
+template <int NPROD>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restrict__ ZU,
+                     size_t zplane, float* __restrict__ Qp, SandParams a) {
+  __shared__ __attribute__((aligned(1024))) u16 buf[Bf16Cfg<NPROD == 6 ? 3 : 2>::BUF];
+  const int g = blockIdx.x;
+  const int u = (g & 7) * a.per_xcd + (g >> 3);
+  if (u >= a.nunits) return;
+  sandwich_bf16_unit<NPROD>(L, plane, ZU, zplane, Qp, a, u, buf);
+}
+
+// Grouped launch (serving): each member's units exactly as in its own launch.
+template <int NPROD>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void k_sandwich_bf16_group(GroupArgs ga) {
+  __shared__ __attribute__((aligned(1024))) u16 buf[Bf16Cfg<NPROD == 6 ? 3 : 2>::BUF];
+  const int g = blockIdx.x;
+  const int u = (g & 7) * ga.per_xcd + (g >> 3);
+  if (u >= ga.u0[ga.n]) return;
+  int e = 0;
+  while (e + 1 < ga.n && u >= ga.u0[e + 1]) ++e;
+  sandwich_bf16_unit<NPROD>((const u16*)ga.e[e].L, ga.e[e].plane, (const u16*)ga.e[e].UT,
+                            ga.e[e].zplane, (float*)ga.e[e].Qp, ga.e[e].p, u - ga.u0[e], buf);
+}
+
 }  // namespace
 
 hipError_t launch_sigma_bf16(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la,
                              hipStream_t s) {
   if (g.nvp % (2 * TILE) || g.nop % (2 * TILE)) return hipErrorInvalidValue;
-  SandParams p;
-  p.nvp = g.nvp;
-  p.nop = g.nop;
-  p.nmop = g.nmop;
-  p.nvt = g.nvt;
-  p.nct = g.nct;
-  p.naux = g.naux;
-  p.k = la.k;
-  p.nsplit = la.nsplit;
-  p.nitems = plan.nitems;
-  p.nunits = p.nitems * la.k * la.nsplit;
-  const int nwg = (p.nunits + 7) / 8 * 8;
-  p.per_xcd = nwg / 8;
-  p.zstride = (int64_t)g.nmop * g.nmop;
-  p.npan_v = plan.npan_v;
-  p.items = plan.d_items;
+  const SandParams p = sand_params(g, plan, la);
+  const dim3 grid(p.per_xcd * 8);
   if (la.nprod == 3)
-    hipLaunchKernelGGL(k_sandwich_bf16<3>, dim3(nwg), dim3(256), 0, s, (const u16*)la.L, la.plane,
+    hipLaunchKernelGGL(k_sandwich_bf16<3>, grid, dim3(256), 0, s, (const u16*)la.L, la.plane,
                        (const u16*)la.ZT, la.zplane, (float*)la.Sp, p);
   else
-    hipLaunchKernelGGL(k_sandwich_bf16<6>, dim3(nwg), dim3(256), 0, s, (const u16*)la.L, la.plane,
+    hipLaunchKernelGGL(k_sandwich_bf16<6>, grid, dim3(256), 0, s, (const u16*)la.L, la.plane,
                        (const u16*)la.ZT, la.zplane, (float*)la.Sp, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_group_bf16(const GroupMember* m, int n, hipStream_t s) {
+  for (int i = 0; i < n; ++i)
+    if (m[i].g->nvp % (2 * TILE) || m[i].g->nop % (2 * TILE)) return hipErrorInvalidValue;
+  const GroupArgs ga = group_args(m, n);
+  if (m[0].la.nprod == 3)
+    hipLaunchKernelGGL(k_sandwich_bf16_group<3>, dim3(ga.per_xcd * 8), dim3(256), 0, s, ga);
+  else
+    hipLaunchKernelGGL(k_sandwich_bf16_group<6>, dim3(ga.per_xcd * 8), dim3(256), 0, s, ga);
   return hipGetLastError();
 }
 

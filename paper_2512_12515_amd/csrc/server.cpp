@@ -309,7 +309,8 @@ void worker_loop(pprpa_server* S) {
       S->admitted.clear();
     }
     bool progressed = false;
-    std::vector<Request*> need64, need32, finished;
+    std::map<int, std::vector<Request*>> need;  // by kernel (storage type, products)
+    std::vector<Request*> finished;
     for (Request* r : active) {
       Solver& sv = *r->sv;
       if (sv.phase == Solver::RR_LAUNCH) {
@@ -356,7 +357,7 @@ void worker_loop(pprpa_server* S) {
               progressed = true;
             }
           }
-          if (r->unpacked) (c->st == Store::F64 ? need64 : need32).push_back(r);
+          if (r->unpacked) need[(int)c->st * 8 + c->nprod].push_back(r);
         }
       }
       if (sv.phase == Solver::DONE) finished.push_back(r);
@@ -380,11 +381,12 @@ void worker_loop(pprpa_server* S) {
     timed.erase(timed.begin(), timed.begin() + nt);
 
     // one grouped grid in flight at a time: launch the waiting solves once the last one is done
-    for (auto* need : {&need64, &need32}) {
+    for (auto& kv : need) {
       if (!timed.empty()) break;
-      for (size_t i0 = 0; i0 < need->size(); i0 += GROUP_MAX) {
-        std::vector<Request*> grp(need->begin() + i0,
-                                  need->begin() + std::min(need->size(), i0 + GROUP_MAX));
+      const std::vector<Request*>& list = kv.second;
+      for (size_t i0 = 0; i0 < list.size(); i0 += GROUP_MAX) {
+        std::vector<Request*> grp(list.begin() + i0,
+                                  list.begin() + std::min(list.size(), i0 + GROUP_MAX));
         if (!launch_group(S, grp, timed, pool)) {
           (void)hipGetLastError();
           for (Request* r : grp) {
@@ -514,10 +516,6 @@ pprpa_status pprpa_server_submit(pprpa_server* S, const pprpa_build_args* b,
     return PPRPA_EINVAL;
   }
   PPRPA_TRY(check_build_args(b));
-  if (b->prec == PPRPA_BF16X6 || b->prec == PPRPA_BF16X3) {
-    set_error("the serving loop runs FP64 and FP32 sigma only");
-    return PPRPA_EUNSUPPORTED;
-  }
   if (d->direct) {
     set_error("the serving loop runs the Davidson solver only (direct=0)");
     return PPRPA_EUNSUPPORTED;

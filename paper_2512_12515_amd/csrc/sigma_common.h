@@ -15,6 +15,61 @@ struct SandParams {
   int npan_v;
 };
 
+// Entries of a grouped sigma launch (passed by value as the kernel argument).
+struct GroupEntry {
+  const void* L;
+  const void* UT;
+  void* Qp;
+  size_t plane, zplane;  // BF16 plane strides (elements)
+  SandParams p;
+};
+struct GroupArgs {
+  int n, per_xcd;
+  int u0[GROUP_MAX + 1];  // first unit of each entry; u0[n] = total units
+  GroupEntry e[GROUP_MAX];
+};
+
+// Host-side parameters of one product's launch (shared by the single and grouped launchers).
+inline SandParams sand_params(const Geometry& g, const SigmaPlan& plan, const SigmaLaunch& la) {
+  SandParams p;
+  p.nvp = g.nvp;
+  p.nop = g.nop;
+  p.nmop = g.nmop;
+  p.nvt = g.nvt;
+  p.nct = g.nct;
+  p.naux = g.naux;
+  p.k = la.k;
+  p.nsplit = la.nsplit;
+  p.nitems = plan.nitems;
+  p.nunits = p.nitems * la.k * la.nsplit;
+  const int nwg = (p.nunits + 7) / 8 * 8;
+  p.per_xcd = nwg / 8;
+  p.zstride = (int64_t)g.nmop * g.nmop;
+  p.npan_v = plan.npan_v;
+  p.items = plan.d_items;
+  return p;
+}
+
+// Grouped launch arguments for members m[0..n): units laid end to end.
+inline GroupArgs group_args(const GroupMember* m, int n) {
+  GroupArgs ga{};
+  ga.n = n;
+  int total = 0;
+  for (int i = 0; i < n; ++i) {
+    ga.e[i].L = m[i].la.L;
+    ga.e[i].UT = m[i].la.ZT;
+    ga.e[i].Qp = m[i].la.Sp;
+    ga.e[i].plane = m[i].la.plane;
+    ga.e[i].zplane = m[i].la.zplane;
+    ga.e[i].p = sand_params(*m[i].g, *m[i].plan, m[i].la);
+    ga.u0[i] = total;
+    total += ga.e[i].p.nunits;
+  }
+  ga.u0[n] = total;
+  ga.per_xcd = (total + 7) / 8;
+  return ga;
+}
+
 // c tiles of the chunk a contraction-1 step on d tile dt touches, rounded out to groups of 4
 // (columns outside the valid range hold exact zeros in U^T: c > d, or the other block).
 __device__ __forceinline__ void c_range(int dt, int cc0, int cc1, int nvt, int* g0, int* g1) {

@@ -49,7 +49,8 @@ MIX = [  # (seed, nocc, nvir, mult, nroot, prec)
     (15, 8, 70, "singlet", 6, "fp32"),
     (16, 12, 100, "triplet", 10, "fp32"),
     (17, 20, 150, "singlet", 8, "fp64"),
-    (18, 5, 60, "singlet", 7, "fp32"),
+    (18, 5, 60, "singlet", 7, "bf16x6"),
+    (19, 9, 80, "triplet", 6, "bf16x6"),
 ]
 
 
@@ -103,7 +104,7 @@ def test_alone_equals_mix(served_mix, mix_inputs, i):
     assert alone[0]["report"]["iters"] == res[i]["report"]["iters"]
 
 
-@pytest.mark.parametrize("i", [0, 1, 4, 6])
+@pytest.mark.parametrize("i", [0, 1, 4, 6, 7, 8])
 def test_mix_equals_standalone_context(served_mix, mix_inputs, i):
     res, _ = served_mix
     seed, nocc, nvir, mult, nroot, prec = MIX[i]
@@ -113,7 +114,7 @@ def test_mix_equals_standalone_context(served_mix, mix_inputs, i):
     assert np.array_equal(r["omega"], res[i]["omega"]), (r["omega"] - res[i]["omega"])
 
 
-@pytest.mark.parametrize("i", [0, 2, 4, 7])
+@pytest.mark.parametrize("i", [0, 2, 4, 7, 8])
 def test_small_requests_vs_oracle(served_mix, i):
     res, _ = served_mix
     seed, nocc, nvir, mult, nroot, prec = MIX[i]
