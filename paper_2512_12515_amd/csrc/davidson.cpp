@@ -484,11 +484,16 @@ pprpa_status Solver::run_direct() {
     return PPRPA_EUNSUPPORTED;
   }
   const int m = (int)n;
-  PPRPA_TRY(get_ws(c_, m, nroot_, 1, (size_t)4 * m * m, (size_t)nroot_ * 64, &w));
+  PPRPA_TRY(get_ws(c_, m, nroot_, 1, std::max((size_t)4 * m * m, (size_t)3 * m * m + 4 * 64 * m),
+                   (size_t)nroot_ * 64, &w));
   double* hp = c_->pinned;
   PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
-  PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc, nroot_,
-                          w.pwork, w.info, nullptr, 0, 0, s));
+  if (m <= 96)  // fits the LDS-resident Jacobi pencil solver
+    PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc, nroot_,
+                            w.pwork, w.info, nullptr, 0, 0, s));
+  else
+    PPRPA_HIP(launch_direct_pencil(c_->M, m, nvv, c_->mu2, nroot_, w.omega, w.Cc, nroot_, w.pwork,
+                                   w.info, s));
   PPRPA_HIP(launch_transpose(w.Cc, nroot_, m, nroot_, w.Z, n, s));
   PPRPA_HIP(launch_combine(c_->M, n, m, w.Cc, nroot_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
   PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, 64, s));

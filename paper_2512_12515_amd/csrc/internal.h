@@ -141,6 +141,12 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
                          int nret, double* omega, double* Cout, int ldc, double* work, int* info,
                          double* Uprev, int ldu, int mprev, hipStream_t s);
+// Direct solve of the dense pencil (M, W), W = diag(+1 for i < nvv, -1), for 96 < m <= 512:
+// the same outputs as launch_pencil (nret = nroot, no warm start) by Cholesky, Householder
+// tridiagonalisation, bisection and inverse iteration. work: 3 m^2 + 4 nroot m doubles.
+hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
+                                double* omega, double* Cout, int ldc, double* work, int* info,
+                                hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

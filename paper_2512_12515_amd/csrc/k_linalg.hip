@@ -531,6 +531,337 @@ __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Direct dense pencil solve for orders above the LDS-resident Jacobi (one workgroup; matrices in
+// global memory, L2-resident). M z = Omega W z with W = diag(+1 (i < nvv), -1):
+//   K = M - 2 mu W = R R^T (Cholesky), G = R^-1 W R^-T, Omega = 2 mu + 1 / theta;
+//   G = Q T Q^T by Householder reflections (T symmetric tridiagonal);
+//   the nroot largest theta (> 0: pp roots) by bisection on Sturm counts of T (the count at 0
+//   gives the number of pp roots); their vectors by inverse iteration on T (vectors of nearly
+//   equal theta orthonormalised against each other), back-transformed by the reflections;
+//   c = R^-T u / sqrt(theta), so that c^T W c = +1.
+// work: 3 m^2 + 4 nroot m doubles. info as k_pencil.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int sturm_below(const double* d, const double* e2, int m, double x,
+                                           double tiny) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    if (fabs(q) < tiny) q = -tiny;  // a zero pivot counts as negative (the usual convention)
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
+                                                      int64_t nvv, double mu2, int nroot,
+                                                      double* __restrict__ omega,
+                                                      double* __restrict__ Cout, int ldc,
+                                                      double* __restrict__ work,
+                                                      int* __restrict__ info) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double theta[64];
+  __shared__ int flag, npos_s;
+  const int t = threadIdx.x;
+  double* A = work;                        // K, then R (lower)
+  double* Ri = work + (size_t)m * m;       // R^-1 (lower)
+  double* G = work + 2 * (size_t)m * m;    // G, then the reflection vectors below the diagonal
+  double* X = work + 3 * (size_t)m * m;    // [nroot][m] vectors
+  auto w_of = [&](int i) { return i < nvv ? 1.0 : -1.0; };
+  if (t == 0) flag = 0;
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    A[e_] = M[(size_t)i * m + j] - (i == j ? mu2 * w_of(i) : 0.0);
+  }
+  __syncthreads();
+  // Cholesky K = R R^T, lower, in place
+  for (int j = 0; j < m; ++j) {
+    const double dj = A[j * m + j];
+    if (!(dj > 0.0)) {
+      if (t == 0) flag = 1;
+      __syncthreads();
+      break;
+    }
+    const double rjj = sqrt(dj);
+    __syncthreads();
+    for (int i = j + 1 + t; i < m; i += WG) A[i * m + j] /= rjj;
+    if (t == 0) A[j * m + j] = rjj;
+    __syncthreads();
+    const int nt = m - j - 1;
+    for (int e_ = t; e_ < nt * nt; e_ += WG) {
+      const int i = j + 1 + e_ / nt, k = j + 1 + e_ % nt;
+      if (k <= i) A[i * m + k] -= A[i * m + j] * A[k * m + j];
+    }
+    __syncthreads();
+  }
+  if (flag) {
+    if (t == 0) {
+      info[0] = 1;
+      info[1] = 0;
+      info[2] = 0;
+    }
+    return;
+  }
+  // R^-1 by forward substitution, one row at a time, the columns of the row in parallel
+  for (int i = 0; i < m; ++i) {
+    const double rii = A[i * m + i];
+    for (int c = t; c <= i; c += WG) {
+      double s = (c == i) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= A[i * m + k] * Ri[k * m + c];
+      Ri[i * m + c] = s / rii;
+    }
+    for (int c = i + 1 + t; c < m; c += WG) Ri[i * m + c] = 0.0;
+    __syncthreads();
+  }
+  // G = R^-1 W R^-T (both triangles)
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) s += Ri[i * m + k] * w_of(k) * Ri[j * m + k];
+    G[i * m + j] = s;
+    G[j * m + i] = s;
+  }
+  __syncthreads();
+  // Householder tridiagonalisation: step k annihilates G[k+2:, k]
+  for (int k = 0; k + 2 < m; ++k) {
+    const int s0 = k + 1, ns = m - s0;  // trailing block rows/cols s0 .. m-1
+    double part = 0.0;
+    for (int i = t; i < ns; i += WG) {
+      const double x = G[(s0 + i) * m + k];
+      vv[i] = x;
+      if (i > 0) part += x * x;
+    }
+    const double tail = block_sum(part, red);  // also orders the vv writes
+    const double x0 = vv[0];
+    d[k] = G[k * m + k];
+    if (tail == 0.0) {  // already tridiagonal in this column
+      if (t == 0) {
+        e[k] = x0;
+        beta[k] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double nrm = sqrt(x0 * x0 + tail);
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    const double v0 = x0 - alpha;
+    const double b = 2.0 / (v0 * v0 + tail);  // H = I - b v v^T, v = (v0, x1, x2, ...)
+    __syncthreads();
+    if (t == 0) {
+      vv[0] = v0;
+      e[k] = alpha;
+      beta[k] = b;
+    }
+    __syncthreads();
+    // p = b G' v (4 threads per row)
+    for (int r0 = 0; r0 < ns; r0 += WG / 4) {
+      const int i = r0 + t / 4, q = t % 4;
+      double s = 0.0;
+      if (i < ns)
+        for (int j = q; j < ns; j += 4) s += G[(s0 + i) * m + s0 + j] * vv[j];
+      red[t] = s;
+      __syncthreads();
+      if (q == 0 && i < ns) pq[i] = b * (red[t] + red[t + 1] + red[t + 2] + red[t + 3]);
+      __syncthreads();
+    }
+    double kp = 0.0;
+    for (int i = t; i < ns; i += WG) kp += pq[i] * vv[i];
+    const double K = 0.5 * b * block_sum(kp, red);
+    for (int i = t; i < ns; i += WG) pq[i] -= K * vv[i];  // q = p - K v
+    __syncthreads();
+    // G' -= v q^T + q v^T
+    for (int e_ = t; e_ < ns * ns; e_ += WG) {
+      const int i = e_ / ns, j = e_ % ns;
+      G[(s0 + i) * m + s0 + j] -= vv[i] * pq[j] + pq[i] * vv[j];
+    }
+    // keep v in column k below the diagonal (row k+1 onwards)
+    for (int i = t; i < ns; i += WG) G[(s0 + i) * m + k] = vv[i];
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (m >= 2) {
+      d[m - 2] = G[(m - 2) * m + (m - 2)];
+      e[m - 2] = G[(m - 1) * m + (m - 2)];
+    }
+    d[m - 1] = G[(m - 1) * m + (m - 1)];
+    if (m >= 2) beta[m - 2] = 0.0;
+    beta[m - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
+  // Gershgorin bounds and the size of T
+  double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
+  for (int i = t; i < m; i += WG) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
+    lo_p = fmin(lo_p, d[i] - r);
+    hi_p = fmax(hi_p, d[i] + r);
+    nrm_p = fmax(nrm_p, fabs(d[i]) + r);
+  }
+  red[t] = lo_p;
+  __syncthreads();
+  for (int h = WG / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] = fmin(red[t], red[t + h]);
+    __syncthreads();
+  }
+  const double gmin = red[0];
+  __syncthreads();
+  red[t] = hi_p;
+  __syncthreads();
+  for (int h = WG / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] = fmax(red[t], red[t + h]);
+    __syncthreads();
+  }
+  const double gmax = red[0];
+  __syncthreads();
+  red[t] = nrm_p;
+  __syncthreads();
+  for (int h = WG / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] = fmax(red[t], red[t + h]);
+    __syncthreads();
+  }
+  const double tnorm = fmax(red[0], 1e-300);
+  __syncthreads();
+  const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
+  if (t == 0) npos_s = m - sturm_below(d, e2, m, 0.0, tiny);
+  __syncthreads();
+  const int npos = npos_s;
+  // the nroot largest eigenvalues by bisection (thread j: the j-th largest)
+  if (t < nroot) {
+    const int idx = m - 1 - t;  // ascending index
+    double lo = gmin - 1e-12 * tnorm, hi = gmax + 1e-12 * tnorm;
+    for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_below(d, e2, m, mid, tiny) <= idx)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    theta[t] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // inverse iteration (thread j): (T - theta I) y = b by Gaussian elimination with partial
+  // pivoting on the tridiagonal (fill-in: a second superdiagonal), three solves
+  if (t < nroot) {
+    double* y = X + (size_t)t * m;
+    const double th = theta[t];
+    const double pert = 2.2e-16 * tnorm;
+    // start vector: a fixed pseudo-random sequence, different per root
+    unsigned long long h = 0x9E3779B97F4A7C15ull * (unsigned long long)(t + 1);
+    for (int i = 0; i < m; ++i) {
+      h ^= h >> 33;
+      h *= 0xff51afd7ed558ccdull;
+      h ^= h >> 33;
+      y[i] = 0.5 + (double)(h >> 11) * (1.0 / 9007199254740992.0);
+    }
+    for (int pass = 0; pass < 3; ++pass) {
+      // elimination (O(m) per pass); the rows of U go to three scratch arrays after the vectors,
+      // the transformed right-hand side into y itself
+      double a_d = d[0] - th, a_u = m > 1 ? e[0] : 0.0, a_u2 = 0.0, rhs = y[0];
+      double* U0 = X + (size_t)nroot * m + (size_t)t * 3 * m;
+      double* U1 = U0 + m;
+      double* U2 = U1 + m;
+      for (int i = 0; i + 1 < m; ++i) {
+        const double b_l = e[i], b_d = d[i + 1] - th, b_u = i + 2 < m ? e[i + 1] : 0.0;
+        double rb = y[i + 1];
+        if (fabs(a_d) >= fabs(b_l)) {
+          double piv = a_d;
+          if (fabs(piv) < pert) piv = piv < 0.0 ? -pert : pert;
+          const double l = b_l / piv;
+          U0[i] = piv;
+          U1[i] = a_u;
+          U2[i] = a_u2;
+          y[i] = rhs;
+          a_d = b_d - l * a_u;
+          a_u = b_u - l * a_u2;
+          a_u2 = 0.0;
+          rhs = rb - l * rhs;
+        } else {
+          const double l = a_d / b_l;  // swap rows i and i+1
+          U0[i] = b_l;
+          U1[i] = b_d;
+          U2[i] = b_u;
+          y[i] = rb;
+          const double nd = a_u - l * b_d, nu = a_u2 - l * b_u;
+          a_d = nd;
+          a_u = nu;
+          a_u2 = 0.0;
+          rhs = rhs - l * rb;
+        }
+      }
+      if (fabs(a_d) < pert) a_d = a_d < 0.0 ? -pert : pert;
+      U0[m - 1] = a_d;
+      U1[m - 1] = 0.0;
+      U2[m - 1] = 0.0;
+      y[m - 1] = rhs;
+      // back substitution
+      double y1 = 0.0, y2 = 0.0, nrm2 = 0.0;
+      for (int i = m - 1; i >= 0; --i) {
+        const double v = (y[i] - U1[i] * y1 - U2[i] * y2) / U0[i];
+        y[i] = v;
+        y2 = y1;
+        y1 = v;
+        nrm2 += v * v;
+      }
+      const double inv = 1.0 / sqrt(nrm2);
+      for (int i = 0; i < m; ++i) y[i] *= inv;
+    }
+  }
+  __syncthreads();
+  // vectors of nearly equal theta: orthonormalise in order (modified Gram-Schmidt)
+  for (int j = 1; j < nroot; ++j) {
+    for (int i = 0; i < j; ++i) {
+      if (fabs(theta[i] - theta[j]) > 1e-7 * tnorm) continue;
+      double part2 = 0.0;
+      for (int r = t; r < m; r += WG) part2 += X[(size_t)i * m + r] * X[(size_t)j * m + r];
+      const double dot = block_sum(part2, red);
+      for (int r = t; r < m; r += WG) X[(size_t)j * m + r] -= dot * X[(size_t)i * m + r];
+      __syncthreads();
+      double part3 = 0.0;
+      for (int r = t; r < m; r += WG) part3 += X[(size_t)j * m + r] * X[(size_t)j * m + r];
+      const double nn = sqrt(block_sum(part3, red));
+      for (int r = t; r < m; r += WG) X[(size_t)j * m + r] /= nn;
+      __syncthreads();
+    }
+  }
+  // back-transform u = H_0 H_1 ... H_{m-3} y (last reflection first); 16 threads per vector
+  const int vj = t / 16, ln = t % 16;
+  for (int k = m - 3; k >= 0; --k) {
+    const double b = beta[k];
+    if (b == 0.0) continue;  // uniform
+    const int s0 = k + 1, ns = m - s0;
+    double s = 0.0;
+    if (vj < nroot)
+      for (int i = ln; i < ns; i += 16) s += G[(s0 + i) * m + k] * X[(size_t)vj * m + s0 + i];
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (vj < nroot)
+      for (int i = ln; i < ns; i += 16) X[(size_t)vj * m + s0 + i] -= b * s * G[(s0 + i) * m + k];
+    __syncthreads();
+  }
+  // outputs: omega, and c = R^-T u / sqrt(theta) as columns of Cout
+  for (int j = t; j < nroot; j += WG)
+    omega[j] = j < npos ? mu2 + 1.0 / theta[j] : 0.0;
+  for (int e_ = t; e_ < m * nroot; e_ += WG) {
+    const int row = e_ / nroot, j = e_ % nroot;
+    if (j >= npos) {
+      Cout[row * ldc + j] = 0.0;
+      continue;
+    }
+    double s = 0.0;
+    for (int k = row; k < m; ++k) s += Ri[k * m + row] * X[(size_t)j * m + k];
+    Cout[row * ldc + j] = s / sqrt(theta[j]);
+  }
+  if (t == 0) {
+    info[0] = npos < nroot ? 2 : 0;
+    info[1] = npos;
+    info[2] = 0;
+  }
+}
+
 // Q = orth(C[:, :r]) by modified Gram-Schmidt, twice; columns with relative norm below 1e-10
 // are dropped. Q: [m][ldq]; rank written to rank[0].
 __global__ __launch_bounds__(WG) void k_small_orth(const double* __restrict__ C, int ldc, int m,
@@ -700,6 +1031,15 @@ hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, dou
   if (m > JMAX || nret > WG) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret, omega,
                      Cout, ldc, work, info, Uprev, ldu, mprev);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
+                                double* omega, double* Cout, int ldc, double* work, int* info,
+                                hipStream_t s) {
+  if (m > JMAX || nroot > 64 || nroot > m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_direct_pencil, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, nroot, omega, Cout,
+                     ldc, work, info);
   return hipGetLastError();
 }
 

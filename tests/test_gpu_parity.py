@@ -164,6 +164,25 @@ def test_direct_small(mult, seed):
 
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("case,nroot", [((8, 30, 60), 8), ((6, 14, 40), 5), ((2, 13, 30), 3)])
+def test_direct_orders(mult, case, nroot):
+    """The direct dense path at orders up to the 512 limit (n = 501 / 463 for 8 x 30), above and
+    below the 96 of the LDS-resident solver: eigenvalues, residuals and normalisation."""
+    nocc, nvir, naux = case
+    note("direct orders", mult, case)
+    eps, L = problem(21, nocc, nvir, naux)
+    ref = O.solve(eps, L, nocc, mult, nroot)
+    with P.PpRPA(eps, L, nocc, mult=mult, dense=True) as ctx:
+        r = ctx.davidson(nroot, direct=True, vectors=True)
+        M = ctx.dense_matrix()
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-8
+    w = np.r_[np.ones(ctx.n_pp), -np.ones(ctx.n_hh)]
+    Z = r["vecs"]
+    assert np.allclose(np.einsum("ij,j,ij->i", Z, w, Z), 1.0, atol=1e-10)
+    assert np.max(np.abs(M @ Z.T - (w[:, None] * Z.T) * r["omega"][None, :])) < 1e-9
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case,nroot", [((4, 9, 30), 3), ((3, 17, 40), 6), ((0, 8, 20), 4),
                                         ((12, 25, 60), 8)])
 def test_davidson_small(mult, case, nroot):
