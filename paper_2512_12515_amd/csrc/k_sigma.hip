@@ -14,20 +14,22 @@
 // of the occupied-virtual parts of L^P.
 //
 // Kernel design (one workgroup = 4 waves; MFMA 16x16x4, FP64 or FP32):
+//   * the product is computed as Q = sum_P L^P U L^P with U the upper triangle of Zh (diagonal
+//     halved for the singlet, zero for the triplet), so that the S block is Q + s Q^T (formed in
+//     the epilogue); the triangle halves contraction 1 and every work unit does the same work;
 //   * a workgroup owns one vector, a panel of up to 4 adjacent 16-column tiles of one diagonal
-//     block of S, a range of up to RT row tiles, and a contiguous range of the aux index P;
-//     wave w owns column tile w of the panel;
-//   * per P: contraction 1, T[c][cols] = sum_d Zh[c][d] L^P[d][cols], accumulates in registers
-//     (CC row blocks of T at a time); contraction 2, S[r][cols] += sum_c L^P[r][c] T[c][cols],
-//     takes T straight from those registers as its B operand (the reduction index c is
-//     permuted to match the MFMA output layout, acc_row, and the A operand is read with the
+//     block, a range of up to RT row tiles of that block, and a contiguous range of the aux
+//     index P; wave w owns column tile w of the panel (a panel of one or two tiles gives its
+//     other waves a share of the rows instead);
+//   * per P: contraction 1, T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], accumulates in
+//     registers (CT row tiles of T at a time); contraction 2, Q[r][cols] += sum_c L^P[r][c]
+//     T[c][cols], takes T straight from those registers as its B operand (the reduction index c
+//     is permuted to match the MFMA output layout, acc_row, and the A operand is read with the
 //     same permutation), so T never leaves the register file;
-//   * the A operands (rows of Zh and of L^P) are shared by the 4 waves and staged in LDS with
-//     coalesced 16-byte loads; L^P and Zh being symmetric (antisymmetric), every staged tile is a
-//     contiguous row segment in HBM;
-//   * S is symmetric (antisymmetric for the triplet) so only row tiles <= the column tile are
-//     computed (upper triangle of tiles);
-//   * the aux index is split over workgroups; partial S per split are summed in the epilogue in
+//   * the A operands (rows of U^T and of L^P) are shared by the 4 waves and staged in LDS by
+//     direct global-to-LDS loads; L^P being symmetric, every staged tile is a contiguous row
+//     segment in HBM;
+//   * the aux index is split over workgroups; partial Q per split are summed in the epilogue in
 //     a fixed order (deterministic);
 //   * workgroup ids are remapped so the 8 XCDs each take a contiguous range of work units, which
 //     share P ranges and vectors in that XCD's L2.
@@ -248,8 +250,12 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   const int npt = min(4, bnt - t0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const bool active = w < npt;
-  const int wc = min(w, npt - 1);  // idle waves of a short panel repeat the last column
+  // a panel of one or two column tiles gives the waves it has no column for a share of the rows
+  // instead (each wave of a column computes its own copy of T); a three-tile panel idles one wave
+  const int parts = npt == 1 ? 4 : (npt == 2 ? 2 : 1);
+  const bool active = w < npt * parts;
+  const int wc = parts == 1 ? min(w, npt - 1) : w % npt;  // column tile (idle waves: the last)
+  const int rsel = parts == 1 ? 0 : w / npt;               // row groups g with g % parts == rsel
   const int rend = min(bnt, R0 + RT);
   const int nrt = rend - R0;
   const int col0 = brow0 + t0 * TILE;
@@ -338,7 +344,7 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
               for (int grp = 0; grp < RT / GRP; ++grp) {
                 // row tiles at or beyond nrt in the last group read other data of the buffer (in
                 // bounds); their results are never stored
-                if (active && GRP * grp < nrt) {
+                if (active && GRP * grp < nrt && grp % parts == rsel) {
 #pragma unroll
                   for (int ks = 0; ks < 4; ++ks) {
                     T av[GRP];
@@ -359,10 +365,10 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
 
   if (active) {
     T* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.zstride;
-    const int col = col0 + w * TILE + li;
+    const int col = col0 + wc * TILE + li;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      if (rt < nrt) {
+      if (rt < nrt && (rt / GRP) % parts == rsel) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           out[(int64_t)(row0 + rt * TILE + acc_row<T>(lk, j)) * a.nmop + col] = S[rt][j];

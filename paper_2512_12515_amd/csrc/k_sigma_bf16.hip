@@ -108,6 +108,8 @@ __device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, si
   const int npt = min(4, bnt - t0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  // (waves of a short panel stay idle: giving them rows, as the FP32 kernel does, would repeat
+  // contraction 1 and its LDS reads, which bound this kernel)
   const bool active = w < npt;
   const int wc = min(w, npt - 1);
   const int nrt = min(bnt, R0 + RT) - R0;
@@ -228,7 +230,7 @@ __device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, si
 
   if (active) {
     float* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.zstride;
-    const int col = col0 + w * TILE + li;
+    const int col = col0 + wc * TILE + li;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       if (rt < nrt) {
