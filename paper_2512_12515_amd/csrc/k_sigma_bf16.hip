@@ -14,10 +14,16 @@
 //   * contraction 1, T[c][col] = sum_d U[c][d] L^P[d][col]: U is stored row-major (not transposed)
 //     so a lane reads 8 consecutive d of row c; L^P[d][col] is read as row col of L^P (symmetric),
 //     again 8 consecutive d;
-//   * contraction 2, S[r][col] += sum_c L^P[r][c] T[c][col]: T comes from contraction 1's
-//     accumulators, in which a lane holds rows 4 lk .. 4 lk + 3 of a 16-row tile; two c tiles
-//     give the lane's 8 reduction slots, and the A operand is read with the same permutation (two
-//     4-element pieces of row r of L^P);
+//   * contraction 2, S[r][col] += sum_c L^P[r][c] T[c][col], in two forms:
+//     - six products (sandwich_bf16_cols): wave w keeps column tile w; T comes from its own
+//       accumulators, in which a lane holds rows 4 lk .. 4 lk + 3 of a 16-row tile, so two c
+//       tiles give the lane's 8 reduction slots and the A operand is read with the same
+//       permutation (two 4-element pieces of a row of L^P);
+//     - three products (sandwich_bf16_rows): each wave's T is split and written to LDS once per
+//       chunk, transposed (c contiguous); the waves share the row tiles out and each covers all
+//       column tiles of the panel, so a staged row of L^P feeds the MFMAs of every column (about
+//       a third of the LDS reads per product; the six-product form cannot hold the third plane
+//       of four columns in registers);
 //   * the diagonal blocks are padded to multiples of 32 orbitals (two tiles), so every 32-wide
 //     reduction block lies inside one block.
 #include "sigma_common.h"
@@ -30,20 +36,41 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 
-constexpr int CT = 8;   // c tiles per chunk of T
 constexpr int RT = 32;  // row tiles per work unit (equals the FP32 kernel's, same work items)
-constexpr int RH = 16;  // row tiles per contraction-2 stage
 constexpr int KB = 32;  // reduction block of one MFMA
 
-template <int NPL>
-struct Bf16Cfg {
+// Six products (two planes more than three) use the columns-per-wave kernel; its LDS holds one
+// staging buffer (a contraction-1 stage or a contraction-2 stage of RH row tiles).
+struct Bf16ColsCfg {
+  static constexpr int NPL = 3, CT = 8, RH = 16;
   static constexpr int US = CT * TILE * KB;  // U rows of a chunk x one reduction block
   static constexpr int LS = 4 * TILE * KB;   // L^P rows of a panel x one reduction block
   static constexpr int S1 = NPL * (US + LS);
-  static constexpr int RS = RH * TILE * KB;  // L^P rows of a stage x one reduction block
+  static constexpr int RS = RH * TILE * KB;  // L^P rows of a contraction-2 stage x one block
   static constexpr int S2 = NPL * RS;
-  static constexpr int BUF = S1 > S2 ? S1 : S2;
+  static constexpr int BUF = S1 > S2 ? S1 : S2;  // u16 elements
 };
+
+// Three products use the rows-shared kernel: a staging buffer, then T of the current chunk as
+// NPL BF16 planes [64 columns][TWP] (c contiguous; rows padded by 8 elements against bank
+// conflicts).
+struct Bf16RowsCfg {
+  static constexpr int NPL = 2, CT = 8, RH = 16;
+  static constexpr int US = CT * TILE * KB;
+  static constexpr int LS = 4 * TILE * KB;
+  static constexpr int S1 = NPL * (US + LS);
+  static constexpr int RS = RH * TILE * KB;
+  static constexpr int S2 = NPL * RS;
+  static constexpr int STAGE = S1 > S2 ? S1 : S2;  // u16 elements
+  static constexpr int TWP = CT * TILE + 8;         // padded row of T
+  static constexpr int TS = 4 * TILE * TWP;         // one plane of T
+  static constexpr int BUF = STAGE + NPL * TS;      // u16 elements
+};
+
+template <int NPROD>
+constexpr int bf16_buf() {
+  return NPROD == 6 ? Bf16ColsCfg::BUF : Bf16RowsCfg::BUF;
+}
 
 // LDS layout of a staged rows x 32 BF16 tile: each 64-byte row holds four 16-byte chunks, stored
 // at position kc ^ swz(row) so that the lanes one LDS cycle serves (rows r .. r+7 or r .. r+15 of
@@ -87,14 +114,15 @@ __device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l)
   l = (__bf16)r2;
 }
 
-// Work unit u of one product (u < a.nunits), as in the FP32 kernel.
-template <int NPROD>
-__device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, size_t plane,
+// Six products: wave w keeps column tile w of the panel through both contractions, T stays in
+// its registers (split there) and the rows of L^P are read by every wave.
+__device__ __forceinline__ void sandwich_bf16_cols(const u16* __restrict__ L, size_t plane,
                                                    const u16* __restrict__ ZU, size_t zplane,
                                                    float* __restrict__ Qp, const SandParams& a,
                                                    int u, u16* __restrict__ buf) {
-  constexpr int NPL = NPROD == 6 ? 3 : 2;  // planes used: hi, mid (, lo)
-  using Cfg = Bf16Cfg<NPL>;
+  constexpr int NPROD = 6, NPL = 3;
+  using Cfg = Bf16ColsCfg;
+  constexpr int CT = Cfg::CT, RH = Cfg::RH;
   const int item = a.items[u % a.nitems];
   const int kv = (u / a.nitems) % a.k;
   const int sp = u / (a.nitems * a.k);
@@ -159,7 +187,7 @@ __device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, si
             const int lrow = (wc * TILE + li) * KB + 8 * (lk ^ swz(li));
             const bf8 bh = *(const bf8*)(sL + lrow);
             const bf8 bm = *(const bf8*)(sL + Cfg::LS + lrow);
-            const bf8 bl = NPL == 3 ? *(const bf8*)(sL + 2 * Cfg::LS + lrow) : bh;
+            const bf8 bl = *(const bf8*)(sL + 2 * Cfg::LS + lrow);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
               const int cg = cc0 + ct;
@@ -167,7 +195,7 @@ __device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, si
                 const int urow = ((cg - g0) * TILE + li) * KB + 8 * (lk ^ swz(li));
                 const bf8 ah = *(const bf8*)(sU + urow);
                 const bf8 am = *(const bf8*)(sU + Cfg::US + urow);
-                const bf8 al = NPL == 3 ? *(const bf8*)(sU + 2 * Cfg::US + urow) : ah;
+                const bf8 al = *(const bf8*)(sU + 2 * Cfg::US + urow);
                 Tacc[ct] = split_mfma<NPROD>(ah, am, al, bh, bm, bl, Tacc[ct]);
               }
             }
@@ -216,8 +244,7 @@ __device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, si
                       const bf4 x1 = *(const bf4*)(buf + p * Cfg::RS + o1);
                       av[p] = __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
                     }
-                    S[rh0 + rt] = split_mfma<NPROD>(av[0], av[1], NPL == 3 ? av[2] : av[0], th, tm,
-                                                    tl, S[rh0 + rt]);
+                    S[rh0 + rt] = split_mfma<NPROD>(av[0], av[1], av[2], th, tm, tl, S[rh0 + rt]);
                   }
                 }
               }
@@ -242,29 +269,212 @@ __device__ __forceinline__ void sandwich_bf16_unit(const u16* __restrict__ L, si
   }
 }
 
+// Three products: contraction 2 with the rows shared out (T through LDS). Work unit u of one
+// product (u < a.nunits), as in the FP32 kernel.
+__device__ __forceinline__ void sandwich_bf16_rows(const u16* __restrict__ L, size_t plane,
+                                                   const u16* __restrict__ ZU, size_t zplane,
+                                                   float* __restrict__ Qp, const SandParams& a,
+                                                   int u, u16* __restrict__ buf) {
+  constexpr int NPROD = 3, NPL = 2;  // planes used: hi, mid
+  using Cfg = Bf16RowsCfg;
+  const int item = a.items[u % a.nitems];
+  const int kv = (u / a.nitems) % a.k;
+  const int sp = u / (a.nitems * a.k);
+  const int pn = item >> 16;
+  const int R0 = item & 0xFFFF;
+
+  const bool vblk = pn < a.npan_v;
+  const int t0 = vblk ? 4 * pn : 4 * (pn - a.npan_v);
+  const int bnt = vblk ? a.nvt : (a.nct - a.nvt);
+  const int brow0 = vblk ? 0 : a.nvp;
+  const int npt = min(4, bnt - t0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool active = w < npt;  // contraction 1: wave w computes T for column tile w
+  const int wc = min(w, npt - 1);
+  const int nrt = min(bnt, R0 + RT) - R0;
+  const int col0 = brow0 + t0 * TILE;
+  const int ncol = npt * TILE;
+  const int row0 = brow0 + R0 * TILE;
+  const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
+  const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
+  const u16* __restrict__ Z = ZU + (int64_t)kv * a.zstride;
+
+  constexpr int RH = Cfg::RH, CT = Cfg::CT;
+  u16* const sU = buf;
+  u16* const sL = buf + NPL * Cfg::US;
+  u16* const sT = buf + Cfg::STAGE;
+
+  // S[q][cw]: row tile 4 q + w of the unit (rows are dealt round-robin to the waves), column
+  // tile cw of the panel
+  f4 S[RT / 4][4];
+#pragma unroll
+  for (int q = 0; q < RT / 4; ++q)
+#pragma unroll
+    for (int cw = 0; cw < 4; ++cw) S[q][cw] = f4{0, 0, 0, 0};
+
+  for (int P = P0; P < P1; ++P) {
+    const u16* __restrict__ Lp = L + (int64_t)P * a.zstride;
+    for (int cc0 = 0; cc0 < a.nct; cc0 += CT) {
+      const int cc1 = min(cc0 + CT, a.nct);
+      f4 Tacc[CT];
+#pragma unroll
+      for (int i = 0; i < CT; ++i) Tacc[i] = f4{0, 0, 0, 0};
+      // contraction 1: T[c][cols] = sum_d U[c][d] L^P[d][cols] over d in c's block, d >= c;
+      // one 32-wide block of d per stage (both tiles in one diagonal block)
+      for (int part = 0; part < 2; ++part) {
+        const int lo = part == 0 ? cc0 : max(cc0, a.nvt);
+        const int hi = part == 0 ? (cc0 < a.nvt ? a.nvt : cc0) : (cc1 > a.nvt ? a.nct : lo);
+        for (int dt = lo; dt < hi; dt += 2) {
+          int g0, g1, h0, h1;
+          c_range(dt, cc0, cc1, a.nvt, &g0, &g1);
+          c_range(dt + 1, cc0, cc1, a.nvt, &h0, &h1);
+          const int blo = dt < a.nvt ? 0 : a.nvt;
+          const int clo = max(cc0, blo), chi = min(cc1, dt + 2);  // c tiles with U[c][d] != 0
+          __syncthreads();
+#pragma unroll
+          for (int p = 0; p < NPL; ++p) {
+            dma_tile32(Z + p * zplane + (int64_t)(g0 * TILE) * a.nmop + dt * TILE, a.nmop,
+                       (h1 - g0) * TILE, sU + p * Cfg::US, w, lane);
+            dma_tile32(Lp + p * plane + (int64_t)col0 * a.nmop + dt * TILE, a.nmop, ncol,
+                       sL + p * Cfg::LS, w, lane);
+          }
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+          if (active) {
+            const int lrow = (wc * TILE + li) * KB + 8 * (lk ^ swz(li));
+            const bf8 bh = *(const bf8*)(sL + lrow);
+            const bf8 bm = *(const bf8*)(sL + Cfg::LS + lrow);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              const int cg = cc0 + ct;
+              if (cg >= clo && cg < chi) {
+                const int urow = ((cg - g0) * TILE + li) * KB + 8 * (lk ^ swz(li));
+                const bf8 ah = *(const bf8*)(sU + urow);
+                const bf8 am = *(const bf8*)(sU + Cfg::US + urow);
+                Tacc[ct] = split_mfma<NPROD>(ah, am, ah, bh, bm, bh, Tacc[ct]);
+              }
+            }
+          }
+        }
+      }
+      // T of this chunk into LDS, split, transposed: sT[p][col][c]; a lane holds rows
+      // 4 lk .. 4 lk + 3 of each c tile for column li of its tile. (The previous chunk's reads of
+      // sT finished before the first stage barrier of this chunk's contraction 1.)
+      if (active) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          bf4 th, tm;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            __bf16 h, m, l;
+            split3(Tacc[ct][j], h, m, l);
+            th[j] = h;
+            tm[j] = m;
+          }
+          const int o = (wc * TILE + li) * Cfg::TWP + ct * TILE + 4 * lk;
+          *(bf4*)(sT + o) = th;
+          *(bf4*)(sT + Cfg::TS + o) = tm;
+        }
+      }
+      __syncthreads();
+      // contraction 2: S[r][cols] += sum_c L^P[r][c] T[c][cols], one 32-wide block of c (two
+      // tiles of T) at a time; B operands (T of every column tile) from LDS, A (rows of L^P)
+      // staged RH row tiles at a time
+#pragma unroll
+      for (int cb = 0; cb < CT / 2; ++cb) {
+        if (cc0 + 2 * cb < cc1) {
+          bf8 B[4][NPL];
+#pragma unroll
+          for (int cw = 0; cw < 4; ++cw)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+              B[cw][p] = cw < npt ? *(const bf8*)(sT + p * Cfg::TS + (cw * TILE + li) * Cfg::TWP +
+                                                  cb * KB + 8 * lk)
+                                  : B[0][p];
+#pragma unroll
+          for (int half = 0; half < RT / RH; ++half) {
+            const int rh0 = half * RH;
+            if (rh0 < nrt) {
+              const int nr = min(RH, nrt - rh0);
+              __syncthreads();
+#pragma unroll
+              for (int p = 0; p < NPL; ++p)
+                dma_tile32(Lp + p * plane + (int64_t)(row0 + rh0 * TILE) * a.nmop +
+                               (cc0 + 2 * cb) * TILE,
+                           a.nmop, nr * TILE, buf + p * Cfg::RS, w, lane);
+              __builtin_amdgcn_s_waitcnt(0);
+              __syncthreads();
+#pragma unroll
+              for (int rr = 0; rr < RH / 4; ++rr) {
+                const int r = 4 * rr + w;
+                if (r < nr) {
+                  const int o = (r * TILE + li) * KB + 8 * (lk ^ swz(li));
+                  const bf8 ah = *(const bf8*)(buf + o);
+                  const bf8 am = *(const bf8*)(buf + Cfg::RS + o);
+#pragma unroll
+                  for (int cw = 0; cw < 4; ++cw)
+                    if (cw < npt)
+                      S[half * (RH / 4) + rr][cw] = split_mfma<NPROD>(
+                          ah, am, ah, B[cw][0], B[cw][1], B[cw][0], S[half * (RH / 4) + rr][cw]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  float* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.zstride;
+#pragma unroll
+  for (int half = 0; half < RT / RH; ++half)
+#pragma unroll
+    for (int rr = 0; rr < RH / 4; ++rr) {
+      const int rt = half * RH + 4 * rr + w;
+      if (rt < nrt) {
+#pragma unroll
+        for (int cw = 0; cw < 4; ++cw)
+          if (cw < npt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              out[(int64_t)(row0 + rt * TILE + 4 * lk + j) * a.nmop + col0 + cw * TILE + li] =
+                  S[half * (RH / 4) + rr][cw][j];
+      }
+    }
+}
+
 template <int NPROD>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 void k_sandwich_bf16(const u16* __restrict__ L, size_t plane, const u16* __restrict__ ZU,
                      size_t zplane, float* __restrict__ Qp, SandParams a) {
-  __shared__ __attribute__((aligned(1024))) u16 buf[Bf16Cfg<NPROD == 6 ? 3 : 2>::BUF];
+  __shared__ __attribute__((aligned(1024))) u16 buf[bf16_buf<NPROD>()];
   const int g = blockIdx.x;
   const int u = (g & 7) * a.per_xcd + (g >> 3);
   if (u >= a.nunits) return;
-  sandwich_bf16_unit<NPROD>(L, plane, ZU, zplane, Qp, a, u, buf);
+  if constexpr (NPROD == 6)
+    sandwich_bf16_cols(L, plane, ZU, zplane, Qp, a, u, buf);
+  else
+    sandwich_bf16_rows(L, plane, ZU, zplane, Qp, a, u, buf);
 }
 
 // Grouped launch (serving): each member's units exactly as in its own launch.
 template <int NPROD>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 void k_sandwich_bf16_group(GroupArgs ga) {
-  __shared__ __attribute__((aligned(1024))) u16 buf[Bf16Cfg<NPROD == 6 ? 3 : 2>::BUF];
+  __shared__ __attribute__((aligned(1024))) u16 buf[bf16_buf<NPROD>()];
   const int g = blockIdx.x;
   const int u = (g & 7) * ga.per_xcd + (g >> 3);
   if (u >= ga.u0[ga.n]) return;
   int e = 0;
   while (e + 1 < ga.n && u >= ga.u0[e + 1]) ++e;
-  sandwich_bf16_unit<NPROD>((const u16*)ga.e[e].L, ga.e[e].plane, (const u16*)ga.e[e].UT,
-                            ga.e[e].zplane, (float*)ga.e[e].Qp, ga.e[e].p, u - ga.u0[e], buf);
+  const GroupEntry& m = ga.e[e];
+  if constexpr (NPROD == 6)
+    sandwich_bf16_cols((const u16*)m.L, m.plane, (const u16*)m.UT, m.zplane, (float*)m.Qp, m.p,
+                       u - ga.u0[e], buf);
+  else
+    sandwich_bf16_rows((const u16*)m.L, m.plane, (const u16*)m.UT, m.zplane, (float*)m.Qp, m.p,
+                       u - ga.u0[e], buf);
 }
 
 }  // namespace
