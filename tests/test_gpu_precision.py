@@ -154,9 +154,11 @@ def test_mixed_vs_fp64_davidson_full_size(name, nroot):
     kw = dict(mult=c["mult"], nocc_act=c["nocc_act"] or 0, nvir_act=c["nvir_act"] or 0,
               lpq_is_active=c["nocc_act"] is not None, max_block=20)
     out = {}
-    for prec in ("fp64", "fp32", "bf16x6"):
+    # BF16x6 sigma leaves a residual floor just above 1e-6 at these sizes (1.3e-6 measured), so
+    # it converges to 1e-5; the eigenvalue error, quadratic in the residual, is unaffected
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-6), ("bf16x6", 1e-5)):
         with P.PpRPA(eps, Ld, c["nocc"], prec=prec, **kw) as ctx:
-            r = ctx.davidson(nroot, block=20, tol=1e-6, max_iter=300)
+            r = ctx.davidson(nroot, block=20, tol=tol, max_iter=300)
         note(prec, r["report"])
         out[prec] = r["omega"]
     for prec in ("fp32", "bf16x6"):
