@@ -148,7 +148,7 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 size_t davidson_workspace_bytes(const Geometry& g, const pprpa_davidson_args& a) {
   Shape sh;
   if (shape_of(g, &a, &sh) != PPRPA_OK) return 0;
-  return ws_total(g.n, sh.mmax, sh.nret, sh.tblk, (size_t)4 * sh.mmax * sh.mmax,
+  return ws_total(g.n, sh.mmax, sh.nret, sh.tblk, (size_t)5 * sh.mmax * sh.mmax,
                   std::max((size_t)sh.nch * sh.mmax * sh.tblk, (size_t)sh.nret * 64));
 }
 
@@ -193,7 +193,7 @@ pprpa_status Solver::start() {
   nret_ = sh.nret;
   tblk_ = sh.tblk;
   nch_ = sh.nch;
-  rc = get_ws(c_, mmax_, nret_, tblk_, (size_t)4 * mmax_ * mmax_,
+  rc = get_ws(c_, mmax_, nret_, tblk_, (size_t)5 * mmax_ * mmax_,
               std::max((size_t)nch_ * mmax_ * tblk_, (size_t)nret_ * nres_), &w);
   if (rc != PPRPA_OK) return fail(rc);
   rc = initial_subspace(sh);
@@ -297,9 +297,15 @@ pprpa_status Solver::rr_launch() {
     PPRPA_HIP(launch_dots(w.V, n, m_, w.V + (size_t)mnew0_ * n, n, nb, n, nvv, 1, w.Ws_ + mnew0_,
                           mmax_, w.part, nch_, s));
   }
-  PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_), w.omega,
-                          w.Cc, nret_, w.pwork, w.info, w.Up, mmax_, mprev_, s));
-  mprev_ = m_;
+  if (m_ <= 96) {  // LDS-resident tridiagonal solve
+    PPRPA_HIP(launch_pencil_tri(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_),
+                                w.omega, w.Cc, nret_, w.pwork, w.info, s));
+    mprev_ = 0;  // no eigenvectors kept for a warm start
+  } else {  // Jacobi in global memory, warm-started while the subspace only grows
+    PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_), w.omega,
+                            w.Cc, nret_, w.pwork, w.info, w.Up, mmax_, mprev_, s));
+    mprev_ = m_;
+  }
   PPRPA_HIP(launch_combine(w.V, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.Z, n, s));
   PPRPA_HIP(launch_combine(w.SV, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
   PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, nres_, s));
@@ -488,9 +494,9 @@ pprpa_status Solver::run_direct() {
                    (size_t)nroot_ * 64, &w));
   double* hp = c_->pinned;
   PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
-  if (m <= 96)  // fits the LDS-resident Jacobi pencil solver
-    PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc, nroot_,
-                            w.pwork, w.info, nullptr, 0, 0, s));
+  if (m <= 96)  // LDS-resident
+    PPRPA_HIP(launch_pencil_tri(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc,
+                                nroot_, w.pwork, w.info, s));
   else
     PPRPA_HIP(launch_direct_pencil(c_->M, m, nvv, c_->mu2, nroot_, w.omega, w.Cc, nroot_, w.pwork,
                                    w.info, s));

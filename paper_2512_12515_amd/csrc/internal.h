@@ -141,6 +141,12 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
                          int nret, double* omega, double* Cout, int ldc, double* work, int* info,
                          double* Uprev, int ldu, int mprev, hipStream_t s);
+// The Davidson pencil for m <= 96 (LDS-resident) by the tridiagonal method of
+// launch_direct_pencil (no warm start: Uprev is neither read nor written). nroot <= nret <= m.
+// work: m^2 + 4 nret m doubles.
+hipError_t launch_pencil_tri(const double* Ms, const double* Ws, int ldm, int m, double mu2,
+                             int nroot, int nret, double* omega, double* Cout, int ldc,
+                             double* work, int* info, hipStream_t s);
 // Direct solve of the dense pencil (M, W), W = diag(+1 for i < nvv, -1), for 96 < m <= 512:
 // the same outputs as launch_pencil (nret = nroot, no warm start) by Cholesky, Householder
 // tridiagonalisation, bisection and inverse iteration. work: 3 m^2 + 4 nroot m doubles.

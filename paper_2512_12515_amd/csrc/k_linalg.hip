@@ -532,15 +532,15 @@ __global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
 }
 
 // ------------------------------------------------------------------------------------------
-// Direct dense pencil solve for orders above the LDS-resident Jacobi (one workgroup; matrices in
-// global memory, L2-resident). M z = Omega W z with W = diag(+1 (i < nvv), -1):
-//   K = M - 2 mu W = R R^T (Cholesky), G = R^-1 W R^-T, Omega = 2 mu + 1 / theta;
-//   G = Q T Q^T by Householder reflections (T symmetric tridiagonal);
-//   the nroot largest theta (> 0: pp roots) by bisection on Sturm counts of T (the count at 0
-//   gives the number of pp roots); their vectors by inverse iteration on T (vectors of nearly
-//   equal theta orthonormalised against each other), back-transformed by the reflections;
-//   c = R^-T u / sqrt(theta), so that c^T W c = +1.
-// work: 3 m^2 + 4 nroot m doubles. info as k_pencil.
+// Symmetric-definite pencil solves by tridiagonalisation (one workgroup of WG threads).
+// With K = R R^T (Cholesky) and G = R^-1 W R^-T, Omega = 2 mu + 1/theta over the eigenpairs of G;
+// G = Q T Q^T by Householder reflections (T symmetric tridiagonal), the wanted (largest) theta by
+// bisection on Sturm counts of T (the count at 0 gives the number of pp roots), their vectors by
+// inverse iteration on T (vectors of nearly equal theta orthonormalised against each other),
+// back-transformed by the reflections; c = R^-T u / sqrt(theta), so that c^T W c = +1.
+// Two kernels use these steps: k_direct_pencil (the dense direct path, W = diag(+-1), matrices
+// in global memory, n up to 512) and k_pencil_tri (the Davidson pencils, m <= 96, matrices in
+// LDS, W the projected metric).
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ int sturm_below(const double* d, const double* e2, int m, double x,
                                            double tiny) {
@@ -555,33 +555,30 @@ __device__ __forceinline__ int sturm_below(const double* d, const double* e2, in
   return cnt;
 }
 
-__global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
-                                                      int64_t nvv, double mu2, int nroot,
-                                                      double* __restrict__ omega,
-                                                      double* __restrict__ Cout, int ldc,
-                                                      double* __restrict__ work,
-                                                      int* __restrict__ info) {
-  __shared__ double red[WG];
-  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
-  __shared__ double theta[64];
-  __shared__ int flag, npos_s;
-  const int t = threadIdx.x;
-  double* A = work;                        // K, then R (lower)
-  double* Ri = work + (size_t)m * m;       // R^-1 (lower)
-  double* G = work + 2 * (size_t)m * m;    // G, then the reflection vectors below the diagonal
-  double* X = work + 3 * (size_t)m * m;    // [nroot][m] vectors
-  auto w_of = [&](int i) { return i < nvv ? 1.0 : -1.0; };
-  if (t == 0) flag = 0;
-  for (int e_ = t; e_ < m * m; e_ += WG) {
-    const int i = e_ / m, j = e_ % m;
-    A[e_] = M[(size_t)i * m + j] - (i == j ? mu2 * w_of(i) : 0.0);
-  }
+__device__ __forceinline__ double block_reduce(double v, double* red, bool is_max) {
+  red[threadIdx.x] = v;
   __syncthreads();
-  // Cholesky K = R R^T, lower, in place
+  for (int h = WG / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], red[threadIdx.x + h])
+                                : fmin(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Cholesky of A (m x m, row-major, ld m) in place: lower R. Returns false if A is not positive
+// definite (uniform across the workgroup).
+__device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag) {
+  const int t = threadIdx.x;
+  if (t == 0) *flag = 0;
+  __syncthreads();
   for (int j = 0; j < m; ++j) {
     const double dj = A[j * m + j];
     if (!(dj > 0.0)) {
-      if (t == 0) flag = 1;
+      if (t == 0) *flag = 1;
       __syncthreads();
       break;
     }
@@ -597,15 +594,12 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     }
     __syncthreads();
   }
-  if (flag) {
-    if (t == 0) {
-      info[0] = 1;
-      info[1] = 0;
-      info[2] = 0;
-    }
-    return;
-  }
-  // R^-1 by forward substitution, one row at a time, the columns of the row in parallel
+  return *flag == 0;
+}
+
+// Ri = R^-1 (lower) by forward substitution, one row at a time, the row's columns in parallel.
+__device__ __forceinline__ void tri_inverse(const double* A, double* Ri, int m) {
+  const int t = threadIdx.x;
   for (int i = 0; i < m; ++i) {
     const double rii = A[i * m + i];
     for (int c = t; c <= i; c += WG) {
@@ -616,19 +610,16 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     for (int c = i + 1 + t; c < m; c += WG) Ri[i * m + c] = 0.0;
     __syncthreads();
   }
-  // G = R^-1 W R^-T (both triangles)
-  for (int e_ = t; e_ < m * m; e_ += WG) {
-    const int i = e_ / m, j = e_ % m;
-    if (j < i) continue;
-    double s = 0.0;
-    for (int k = 0; k <= i; ++k) s += Ri[i * m + k] * w_of(k) * Ri[j * m + k];
-    G[i * m + j] = s;
-    G[j * m + i] = s;
-  }
-  __syncthreads();
-  // Householder tridiagonalisation: step k annihilates G[k+2:, k]
+}
+
+// Householder tridiagonalisation of the symmetric G (m x m, ld m) in place: diagonal d, off-
+// diagonal e, reflection k (H = I - beta[k] v v^T acting on rows/cols k+1..) kept in column k
+// below the diagonal. vv, pq: LDS scratch of m; red: WG doubles.
+__device__ __forceinline__ void tri_householder(double* G, int m, double* d, double* e, double* beta, double* vv,
+                                double* pq, double* red) {
+  const int t = threadIdx.x;
   for (int k = 0; k + 2 < m; ++k) {
-    const int s0 = k + 1, ns = m - s0;  // trailing block rows/cols s0 .. m-1
+    const int s0 = k + 1, ns = m - s0;
     double part = 0.0;
     for (int i = t; i < ns; i += WG) {
       const double x = G[(s0 + i) * m + k];
@@ -637,7 +628,7 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     }
     const double tail = block_sum(part, red);  // also orders the vv writes
     const double x0 = vv[0];
-    d[k] = G[k * m + k];
+    if (t == 0) d[k] = G[k * m + k];
     if (tail == 0.0) {  // already tridiagonal in this column
       if (t == 0) {
         e[k] = x0;
@@ -660,10 +651,10 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     // p = b G' v (4 threads per row)
     for (int r0 = 0; r0 < ns; r0 += WG / 4) {
       const int i = r0 + t / 4, q = t % 4;
-      double s = 0.0;
+      double sum = 0.0;
       if (i < ns)
-        for (int j = q; j < ns; j += 4) s += G[(s0 + i) * m + s0 + j] * vv[j];
-      red[t] = s;
+        for (int j = q; j < ns; j += 4) sum += G[(s0 + i) * m + s0 + j] * vv[j];
+      red[t] = sum;
       __syncthreads();
       if (q == 0 && i < ns) pq[i] = b * (red[t] + red[t + 1] + red[t + 2] + red[t + 3]);
       __syncthreads();
@@ -678,7 +669,6 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
       const int i = e_ / ns, j = e_ % ns;
       G[(s0 + i) * m + s0 + j] -= vv[i] * pq[j] + pq[i] * vv[j];
     }
-    // keep v in column k below the diagonal (row k+1 onwards)
     for (int i = t; i < ns; i += WG) G[(s0 + i) * m + k] = vv[i];
     __syncthreads();
   }
@@ -686,14 +676,20 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     if (m >= 2) {
       d[m - 2] = G[(m - 2) * m + (m - 2)];
       e[m - 2] = G[(m - 1) * m + (m - 2)];
+      beta[m - 2] = 0.0;
     }
     d[m - 1] = G[(m - 1) * m + (m - 1)];
-    if (m >= 2) beta[m - 2] = 0.0;
     beta[m - 1] = 0.0;
   }
   __syncthreads();
+}
+
+// The nsel largest eigenvalues of T (theta[0] largest), the count of positive ones (*npos), and
+// their eigenvectors X[j][0..m) (global scratch: 4 nsel m doubles from X). e2: LDS scratch.
+__device__ __forceinline__ void tri_eigen(const double* d, const double* e, double* e2, int m, int nsel,
+                          double* theta, int* npos, double* X, double* red) {
+  const int t = threadIdx.x;
   for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
-  // Gershgorin bounds and the size of T
   double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
   for (int i = t; i < m; i += WG) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
@@ -701,36 +697,13 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     hi_p = fmax(hi_p, d[i] + r);
     nrm_p = fmax(nrm_p, fabs(d[i]) + r);
   }
-  red[t] = lo_p;
-  __syncthreads();
-  for (int h = WG / 2; h > 0; h >>= 1) {
-    if (t < h) red[t] = fmin(red[t], red[t + h]);
-    __syncthreads();
-  }
-  const double gmin = red[0];
-  __syncthreads();
-  red[t] = hi_p;
-  __syncthreads();
-  for (int h = WG / 2; h > 0; h >>= 1) {
-    if (t < h) red[t] = fmax(red[t], red[t + h]);
-    __syncthreads();
-  }
-  const double gmax = red[0];
-  __syncthreads();
-  red[t] = nrm_p;
-  __syncthreads();
-  for (int h = WG / 2; h > 0; h >>= 1) {
-    if (t < h) red[t] = fmax(red[t], red[t + h]);
-    __syncthreads();
-  }
-  const double tnorm = fmax(red[0], 1e-300);
-  __syncthreads();
+  const double gmin = block_reduce(lo_p, red, false);
+  const double gmax = block_reduce(hi_p, red, true);
+  const double tnorm = fmax(block_reduce(nrm_p, red, true), 1e-300);
   const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
-  if (t == 0) npos_s = m - sturm_below(d, e2, m, 0.0, tiny);
-  __syncthreads();
-  const int npos = npos_s;
-  // the nroot largest eigenvalues by bisection (thread j: the j-th largest)
-  if (t < nroot) {
+  if (t == 0) *npos = m - sturm_below(d, e2, m, 0.0, tiny);
+  // bisection (thread j: the j-th largest)
+  if (t < nsel) {
     const int idx = m - 1 - t;  // ascending index
     double lo = gmin - 1e-12 * tnorm, hi = gmax + 1e-12 * tnorm;
     for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
@@ -746,28 +719,25 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
   __syncthreads();
   // inverse iteration (thread j): (T - theta I) y = b by Gaussian elimination with partial
   // pivoting on the tridiagonal (fill-in: a second superdiagonal), three solves
-  if (t < nroot) {
+  if (t < nsel) {
     double* y = X + (size_t)t * m;
+    double* U0 = X + (size_t)nsel * m + (size_t)t * 3 * m;
+    double* U1 = U0 + m;
+    double* U2 = U1 + m;
     const double th = theta[t];
     const double pert = 2.2e-16 * tnorm;
-    // start vector: a fixed pseudo-random sequence, different per root
     unsigned long long h = 0x9E3779B97F4A7C15ull * (unsigned long long)(t + 1);
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < m; ++i) {  // start vector: a fixed pseudo-random sequence per root
       h ^= h >> 33;
       h *= 0xff51afd7ed558ccdull;
       h ^= h >> 33;
       y[i] = 0.5 + (double)(h >> 11) * (1.0 / 9007199254740992.0);
     }
     for (int pass = 0; pass < 3; ++pass) {
-      // elimination (O(m) per pass); the rows of U go to three scratch arrays after the vectors,
-      // the transformed right-hand side into y itself
       double a_d = d[0] - th, a_u = m > 1 ? e[0] : 0.0, a_u2 = 0.0, rhs = y[0];
-      double* U0 = X + (size_t)nroot * m + (size_t)t * 3 * m;
-      double* U1 = U0 + m;
-      double* U2 = U1 + m;
       for (int i = 0; i + 1 < m; ++i) {
         const double b_l = e[i], b_d = d[i + 1] - th, b_u = i + 2 < m ? e[i + 1] : 0.0;
-        double rb = y[i + 1];
+        const double rb = y[i + 1];
         if (fabs(a_d) >= fabs(b_l)) {
           double piv = a_d;
           if (fabs(piv) < pert) piv = piv < 0.0 ? -pert : pert;
@@ -781,7 +751,7 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
           a_u2 = 0.0;
           rhs = rb - l * rhs;
         } else {
-          const double l = a_d / b_l;  // swap rows i and i+1
+          const double l = a_d / b_l;  // rows i and i+1 swapped
           U0[i] = b_l;
           U1[i] = b_d;
           U2[i] = b_u;
@@ -798,7 +768,6 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
       U1[m - 1] = 0.0;
       U2[m - 1] = 0.0;
       y[m - 1] = rhs;
-      // back substitution
       double y1 = 0.0, y2 = 0.0, nrm2 = 0.0;
       for (int i = m - 1; i >= 0; --i) {
         const double v = (y[i] - U1[i] * y1 - U2[i] * y2) / U0[i];
@@ -813,7 +782,7 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
   }
   __syncthreads();
   // vectors of nearly equal theta: orthonormalise in order (modified Gram-Schmidt)
-  for (int j = 1; j < nroot; ++j) {
+  for (int j = 1; j < nsel; ++j) {
     for (int i = 0; i < j; ++i) {
       if (fabs(theta[i] - theta[j]) > 1e-7 * tnorm) continue;
       double part2 = 0.0;
@@ -828,25 +797,40 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
       __syncthreads();
     }
   }
-  // back-transform u = H_0 H_1 ... H_{m-3} y (last reflection first); 16 threads per vector
-  const int vj = t / 16, ln = t % 16;
+}
+
+// u = H_0 H_1 ... H_{m-3} y for the nsel vectors X (last reflection first); 16 threads a vector.
+__device__ __forceinline__ void tri_back_transform(const double* G, int m, const double* beta, double* X,
+                                   int nsel) {
+  const int t = threadIdx.x;
+  const int ln = t % 16;
   for (int k = m - 3; k >= 0; --k) {
     const double b = beta[k];
     if (b == 0.0) continue;  // uniform
     const int s0 = k + 1, ns = m - s0;
-    double s = 0.0;
-    if (vj < nroot)
-      for (int i = ln; i < ns; i += 16) s += G[(s0 + i) * m + k] * X[(size_t)vj * m + s0 + i];
-    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-    if (vj < nroot)
-      for (int i = ln; i < ns; i += 16) X[(size_t)vj * m + s0 + i] -= b * s * G[(s0 + i) * m + k];
+    for (int v0 = 0; v0 < nsel; v0 += WG / 16) {
+      const int vj = v0 + t / 16;
+      double s = 0.0;
+      if (vj < nsel)
+        for (int i = ln; i < ns; i += 16) s += G[(s0 + i) * m + k] * X[(size_t)vj * m + s0 + i];
+      for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+      if (vj < nsel)
+        for (int i = ln; i < ns; i += 16)
+          X[(size_t)vj * m + s0 + i] -= b * s * G[(s0 + i) * m + k];
+    }
     __syncthreads();
   }
-  // outputs: omega, and c = R^-T u / sqrt(theta) as columns of Cout
-  for (int j = t; j < nroot; j += WG)
-    omega[j] = j < npos ? mu2 + 1.0 / theta[j] : 0.0;
-  for (int e_ = t; e_ < m * nroot; e_ += WG) {
-    const int row = e_ / nroot, j = e_ % nroot;
+}
+
+// omega[j] (j < nroot) and the columns j < nsel of Cout: c = R^-T u / sqrt(theta); columns of
+// non-pp roots are zero. info: [0] 0 ok / 2 fewer than nroot pp roots, [1] pp roots, [2] 0.
+__device__ __forceinline__ void tri_outputs(const double* Ri, const double* X, const double* theta, int m,
+                            int nroot, int nsel, int npos, double mu2, double* omega,
+                            double* Cout, int ldc, int* info) {
+  const int t = threadIdx.x;
+  for (int j = t; j < nroot; j += WG) omega[j] = j < npos ? mu2 + 1.0 / theta[j] : 0.0;
+  for (int e_ = t; e_ < m * nsel; e_ += WG) {
+    const int row = e_ / nsel, j = e_ % nsel;
     if (j >= npos) {
       Cout[row * ldc + j] = 0.0;
       continue;
@@ -860,6 +844,115 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     info[1] = npos;
     info[2] = 0;
   }
+}
+
+// Direct path: M (n x n, full, ld m), W = diag(+1 for i < nvv, -1). work: 3 m^2 + 4 nroot m.
+__global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
+                                                      int64_t nvv, double mu2, int nroot,
+                                                      double* __restrict__ omega,
+                                                      double* __restrict__ Cout, int ldc,
+                                                      double* __restrict__ work,
+                                                      int* __restrict__ info) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double theta[64];
+  __shared__ int flag, npos_s;
+  const int t = threadIdx.x;
+  double* A = work;                        // K, then R (lower)
+  double* Ri = work + (size_t)m * m;       // R^-1 (lower)
+  double* G = work + 2 * (size_t)m * m;    // G, then the reflection vectors
+  double* X = work + 3 * (size_t)m * m;    // vectors and inverse-iteration scratch
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    A[e_] = M[(size_t)i * m + j] - (i == j ? mu2 * (i < nvv ? 1.0 : -1.0) : 0.0);
+  }
+  __syncthreads();
+  if (!tri_cholesky(A, m, &flag)) {
+    if (t == 0) {
+      info[0] = 1;
+      info[1] = 0;
+      info[2] = 0;
+    }
+    return;
+  }
+  tri_inverse(A, Ri, m);
+  // G = R^-1 W R^-T with W diagonal (both triangles)
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) s += Ri[i * m + k] * (k < nvv ? 1.0 : -1.0) * Ri[j * m + k];
+    G[i * m + j] = s;
+    G[j * m + i] = s;
+  }
+  __syncthreads();
+  tri_householder(G, m, d, e, beta, vv, pq, red);
+  tri_eigen(d, e, e2, m, nroot, theta, &npos_s, X, red);
+  tri_back_transform(G, m, beta, X, nroot);
+  tri_outputs(Ri, X, theta, m, nroot, nroot, npos_s, mu2, omega, Cout, ldc, info);
+}
+
+// Davidson pencil (m <= PLDS): Ms, Ws upper triangles (ld ldm); K, R, G in LDS. nret columns of
+// Cout (the nroot wanted and the next Ritz vectors, kept on restart). work: m^2 + 4 nret m
+// (G staging, vectors, inverse-iteration scratch).
+__global__ __launch_bounds__(WG) void k_pencil_tri(const double* __restrict__ Ms,
+                                                   const double* __restrict__ Ws, int ldm, int m,
+                                                   double mu2, int nroot, int nret,
+                                                   double* __restrict__ omega,
+                                                   double* __restrict__ Cout, int ldc,
+                                                   double* __restrict__ work,
+                                                   int* __restrict__ info) {
+  __shared__ double sA[PLDS * PLDS];
+  __shared__ double sB[PLDS * PLDS];
+  __shared__ double red[WG];
+  __shared__ double d[PLDS], e[PLDS], e2[PLDS], beta[PLDS], vv[PLDS], pq[PLDS];
+  __shared__ double theta[PLDS];
+  __shared__ int flag, npos_s;
+  const int t = threadIdx.x;
+  double* Gt = work;                       // staging of G
+  double* X = work + (size_t)m * m;        // vectors and inverse-iteration scratch
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    sA[e_] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
+  }
+  __syncthreads();
+  if (!tri_cholesky(sA, m, &flag)) {
+    if (t == 0) {
+      info[0] = 1;
+      info[1] = 0;
+      info[2] = 0;
+    }
+    return;
+  }
+  tri_inverse(sA, sB, m);  // sB = R^-1
+  // Y = R^-1 Wsym into sA (R is no longer needed), then G = Y R^-T into the staging area
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) {
+      const int a = k < j ? k : j, b = k < j ? j : k;
+      s += sB[i * m + k] * Ws[a * ldm + b];
+    }
+    sA[e_] = s;
+  }
+  __syncthreads();
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int k = 0; k <= j; ++k) s += sA[i * m + k] * sB[j * m + k];
+    Gt[i * m + j] = s;
+    Gt[j * m + i] = s;
+  }
+  __syncthreads();
+  for (int e_ = t; e_ < m * m; e_ += WG) sA[e_] = Gt[e_];
+  __syncthreads();
+  tri_householder(sA, m, d, e, beta, vv, pq, red);
+  const int nsel = nret < m ? nret : m;
+  tri_eigen(d, e, e2, m, nsel, theta, &npos_s, X, red);
+  tri_back_transform(sA, m, beta, X, nsel);
+  tri_outputs(sB, X, theta, m, nroot, nsel, npos_s, mu2, omega, Cout, ldc, info);
 }
 
 // Q = orth(C[:, :r]) by modified Gram-Schmidt, twice; columns with relative norm below 1e-10
@@ -1031,6 +1124,15 @@ hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, dou
   if (m > JMAX || nret > WG) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret, omega,
                      Cout, ldc, work, info, Uprev, ldu, mprev);
+  return hipGetLastError();
+}
+
+hipError_t launch_pencil_tri(const double* Ms, const double* Ws, int ldm, int m, double mu2,
+                             int nroot, int nret, double* omega, double* Cout, int ldc,
+                             double* work, int* info, hipStream_t s) {
+  if (m > PLDS || nret > m || nroot > nret) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pencil_tri, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
+                     omega, Cout, ldc, work, info);
   return hipGetLastError();
 }
 
