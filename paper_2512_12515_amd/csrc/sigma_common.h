@@ -70,14 +70,15 @@ inline GroupArgs group_args(const GroupMember* m, int n) {
   return ga;
 }
 
-// c tiles of the chunk a contraction-1 step on d tile dt touches, rounded out to groups of 4
-// (columns outside the valid range hold exact zeros in U^T: c > d, or the other block).
+// c tiles of the chunk a contraction-1 step on d tile dt touches, rounded out to pairs counted
+// from cc0 (the MFMA loops take tiles two at a time; columns outside the valid range hold exact
+// zeros in U^T: c > d, or the other block).
 __device__ __forceinline__ void c_range(int dt, int cc0, int cc1, int nvt, int* g0, int* g1) {
   const int blo = dt < nvt ? 0 : nvt;            // first c tile of d's block
   const int lo = max(cc0, blo);                   // lowest c tile used
   const int hi = min(cc1, dt + 1);                // one past the highest (c <= d)
-  *g0 = cc0 + ((lo - cc0) & ~3);
-  *g1 = min(cc1, cc0 + ((hi - cc0 + 3) & ~3));
+  *g0 = cc0 + ((lo - cc0) & ~1);
+  *g1 = min(cc1, cc0 + ((hi - cc0 + 1) & ~1));
 }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
