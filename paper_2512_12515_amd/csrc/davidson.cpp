@@ -82,8 +82,7 @@ int ws_sizes(int64_t n, int mmax, int nret, int blk, size_t pwork_elems, size_t 
                          (size_t)nret * n, (size_t)nret * n, (size_t)nret * n,           // Z SZ R
                          (size_t)blk * n, (size_t)blk * n,                               // Tn Tn2
                          (size_t)mmax * blk, (size_t)blk * blk, (size_t)blk * blk,       // Cp Gb Tm
-                         (size_t)nret, (size_t)nret, part_elems, pwork_elems,
-                         (size_t)mmax * mmax, 16};
+                         (size_t)nret, (size_t)nret, part_elems, pwork_elems, 16};
   const int nb = sizeof(list) / sizeof(list[0]);
   std::copy(list, list + nb, sizes);
   return nb;
@@ -128,7 +127,7 @@ pprpa_status get_ws(pprpa_ctx* c, int mmax, int nret, int blk, size_t pwork_elem
   char* p = (char*)c->dws.base;
   double** slots[] = {&w->V,  &w->SV, &w->Vt, &w->SVt, &w->Ms, &w->Ws_, &w->Mt, &w->Wt,
                       &w->Cc, &w->Q,  &w->Z,  &w->SZ,  &w->R,  &w->Tn,  &w->Tn2, &w->Cp,
-                      &w->Gb, &w->Tm, &w->omega, &w->rnorm, &w->part, &w->pwork, &w->Up, nullptr};
+                      &w->Gb, &w->Tm, &w->omega, &w->rnorm, &w->part, &w->pwork, nullptr};
   for (int i = 0; i < nb; ++i) {
     if (slots[i])
       *slots[i] = (double*)p;
@@ -148,7 +147,7 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 size_t davidson_workspace_bytes(const Geometry& g, const pprpa_davidson_args& a) {
   Shape sh;
   if (shape_of(g, &a, &sh) != PPRPA_OK) return 0;
-  return ws_total(g.n, sh.mmax, sh.nret, sh.tblk, (size_t)5 * sh.mmax * sh.mmax,
+  return ws_total(g.n, sh.mmax, sh.nret, sh.tblk, (size_t)7 * sh.mmax * sh.mmax,
                   std::max((size_t)sh.nch * sh.mmax * sh.tblk, (size_t)sh.nret * 64));
 }
 
@@ -193,7 +192,7 @@ pprpa_status Solver::start() {
   nret_ = sh.nret;
   tblk_ = sh.tblk;
   nch_ = sh.nch;
-  rc = get_ws(c_, mmax_, nret_, tblk_, (size_t)5 * mmax_ * mmax_,
+  rc = get_ws(c_, mmax_, nret_, tblk_, (size_t)7 * mmax_ * mmax_,
               std::max((size_t)nch_ * mmax_ * tblk_, (size_t)nret_ * nres_), &w);
   if (rc != PPRPA_OK) return fail(rc);
   rc = initial_subspace(sh);
@@ -202,7 +201,6 @@ pprpa_status Solver::start() {
   sig_k = m_;
   nsig_ = m_;
   mnew0_ = 0;
-  mprev_ = 0;
   phase = NEED_SIGMA;
   return PPRPA_OK;
 }
@@ -297,15 +295,8 @@ pprpa_status Solver::rr_launch() {
     PPRPA_HIP(launch_dots(w.V, n, m_, w.V + (size_t)mnew0_ * n, n, nb, n, nvv, 1, w.Ws_ + mnew0_,
                           mmax_, w.part, nch_, s));
   }
-  if (m_ <= 96) {  // LDS-resident tridiagonal solve
-    PPRPA_HIP(launch_pencil_tri(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_),
-                                w.omega, w.Cc, nret_, w.pwork, w.info, s));
-    mprev_ = 0;  // no eigenvectors kept for a warm start
-  } else {  // Jacobi in global memory, warm-started while the subspace only grows
-    PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_), w.omega,
-                            w.Cc, nret_, w.pwork, w.info, w.Up, mmax_, mprev_, s));
-    mprev_ = m_;
-  }
+  PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_), w.omega,
+                          w.Cc, nret_, w.pwork, w.info, s));
   PPRPA_HIP(launch_combine(w.V, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.Z, n, s));
   PPRPA_HIP(launch_combine(w.SV, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
   PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, nres_, s));
@@ -392,7 +383,6 @@ pprpa_status Solver::restart_read() {
   std::swap(w.Ws_, w.Wt);
   m_ = rank;
   mnew0_ = m_;
-  mprev_ = 0;  // the basis was rotated: no warm start
   return launch_corrections();
 }
 
@@ -494,10 +484,11 @@ pprpa_status Solver::run_direct() {
                    (size_t)nroot_ * 64, &w));
   double* hp = c_->pinned;
   PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
-  if (m <= 96)  // LDS-resident
-    PPRPA_HIP(launch_pencil_tri(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc,
-                                nroot_, w.pwork, w.info, s));
-  else
+  if (m <= 96)  // W as a dense matrix: the Davidson pencil solver on the whole problem
+    PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc, nroot_,
+                            w.pwork, w.info, s));
+  else  // W diagonal exploited
+
     PPRPA_HIP(launch_direct_pencil(c_->M, m, nvv, c_->mu2, nroot_, w.omega, w.Cc, nroot_, w.pwork,
                                    w.info, s));
   PPRPA_HIP(launch_transpose(w.Cc, nroot_, m, nroot_, w.Z, n, s));

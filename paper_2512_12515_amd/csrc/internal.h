@@ -130,26 +130,18 @@ hipError_t launch_reduce_norms(const double* part, int nchunk, int r, double* ou
 hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nsel, int64_t n,
                           int64_t nvv, const double* d_diag, const double* d_omega, double* T,
                           int64_t ldt, hipStream_t s);
-// Pencil solve on one workgroup: K = Ms - 2 mu Ws = R R^T, G = R^-1 Ws R^-T = U diag(theta) U^T,
-// Omega = 2 mu + 1/theta; returns the nroot lowest pp roots and coefficient columns
-// Cout[m][nroot] with c^T Ws c = +1. work: 4*m*m doubles. info: [0] status (0 ok, 1 not
-// definite, 2 fewer than nroot pp roots, 3 no convergence), [1] number of pp roots.
-// Columns nroot..nret-1 of Cout hold the next Ritz vectors (kept on restart).
-// Uprev (ld ldu): eigenvectors of the previous call, used as a warm start when mprev > 1 (the
-// leading mprev x mprev block of the pencil is unchanged); overwritten with this call's. May be
-// NULL (no warm start, nothing kept).
-hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
-                         int nret, double* omega, double* Cout, int ldc, double* work, int* info,
-                         double* Uprev, int ldu, int mprev, hipStream_t s);
-// The Davidson pencil for m <= 96 (LDS-resident) by the tridiagonal method of
-// launch_direct_pencil (no warm start: Uprev is neither read nor written). nroot <= nret <= m.
-// work: m^2 + 4 nret m doubles.
-hipError_t launch_pencil_tri(const double* Ms, const double* Ws, int ldm, int m, double mu2,
-                             int nroot, int nret, double* omega, double* Cout, int ldc,
-                             double* work, int* info, hipStream_t s);
+// Pencil solve on one workgroup: K = Ms - 2 mu Ws = R R^T, G = R^-1 Ws R^-T = U diag(theta) U^T
+// (Householder tridiagonalisation, bisection, inverse iteration), Omega = 2 mu + 1/theta; returns
+// the nroot lowest pp roots and coefficient columns Cout[m][ldc] with c^T Ws c = +1; columns
+// nroot..nret-1 hold the next Ritz vectors (kept on restart). Ms, Ws: upper triangles (ld ldm).
+// m <= 512, nroot <= nret <= m. work: m^2 + 4 nret m doubles (m <= 96, matrices in LDS) or
+// 3 m^2 + 4 nret m (larger m). info: [0] status (0 ok, 1 not definite, 2 fewer than nroot pp
+// roots), [1] number of pp roots, [2] 0.
+hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2,
+                         int nroot, int nret, double* omega, double* Cout, int ldc, double* work,
+                         int* info, hipStream_t s);
 // Direct solve of the dense pencil (M, W), W = diag(+1 for i < nvv, -1), for 96 < m <= 512:
-// the same outputs as launch_pencil (nret = nroot, no warm start) by Cholesky, Householder
-// tridiagonalisation, bisection and inverse iteration. work: 3 m^2 + 4 nroot m doubles.
+// the same outputs as launch_pencil (nret = nroot), W diagonal. work: 3 m^2 + 4 nroot m doubles.
 hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
                                 double* omega, double* Cout, int ldc, double* work, int* info,
                                 hipStream_t s);

@@ -346,190 +346,8 @@ __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, dou
   return sweep >= 60 ? -1 : sweep;
 }
 
-// Pencil: see launch_pencil. For m <= PLDS the matrices live in LDS; otherwise in `work`, which
-// holds 4 m x m matrices (ld = m). work always holds the copy of R^-1 and a staging area for G.
-// Warm start: when the leading mprev x mprev block of the pencil is unchanged since the previous
-// call (the subspace only grew), G's leading block is unchanged too (R and R^-1 are lower
-// triangular), so it is rotated by the previous eigenvectors Uprev first: Jacobi then has only
-// the new border to annihilate.
+// Pencils of order up to PLDS keep their matrices in LDS.
 constexpr int PLDS = 96;
-
-__global__ __launch_bounds__(WG) void k_pencil(const double* __restrict__ Ms,
-                                               const double* __restrict__ Ws, int ldm, int m,
-                                               double mu2, int nroot, int nret,
-                                               double* __restrict__ omega, double* __restrict__ Cout,
-                                               int ldc, double* __restrict__ work,
-                                               int* __restrict__ info, double* __restrict__ Uprev,
-                                               int ldu, int mprev) {
-  __shared__ double sA[PLDS * PLDS];
-  __shared__ double sB[PLDS * PLDS];
-  __shared__ double red[WG];
-  __shared__ double cs[JMAX / 2 + 1], sn[JMAX / 2 + 1];
-  __shared__ int flag;
-  __shared__ int rank_of[JMAX];
-  const bool in_lds = m <= PLDS;
-  double* A = in_lds ? sA : work + 2 * (size_t)m * m;  // K -> R -> Y -> U
-  double* B = in_lds ? sB : work + 3 * (size_t)m * m;  // R^-1 -> G
-  double* Ri = work;                                   // global copy of R^-1
-  double* Gt = work + (size_t)m * m;                   // global staging of G
-  if (threadIdx.x == 0) flag = 0;
-  // K = sym(Ms) - mu2 sym(Ws), from the upper triangles
-  for (int e = threadIdx.x; e < m * m; e += WG) {
-    const int i = e / m, j = e % m;
-    const int a = i < j ? i : j, b = i < j ? j : i;
-    A[e] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
-    B[e] = 0.0;
-  }
-  __syncthreads();
-  // Cholesky K = R R^T (lower, in place)
-  for (int j = 0; j < m; ++j) {
-    const double d = A[j * m + j];
-    if (!(d > 0.0)) {
-      if (threadIdx.x == 0) flag = 1;
-      __syncthreads();
-      break;
-    }
-    const double rjj = sqrt(d);
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < m; i += WG) A[i * m + j] /= rjj;
-    if (threadIdx.x == 0) A[j * m + j] = rjj;
-    __syncthreads();
-    const int nt = m - j - 1;
-    for (int e = threadIdx.x; e < nt * nt; e += WG) {
-      const int i = j + 1 + e / nt, k = j + 1 + e % nt;
-      if (k <= i) A[i * m + k] -= A[i * m + j] * A[k * m + j];
-    }
-    __syncthreads();
-  }
-  if (flag) {
-    if (threadIdx.x == 0) {
-      info[0] = 1;
-      info[1] = 0;
-    }
-    return;
-  }
-  // B = R^-1 (lower): column c by forward substitution, one thread per column
-  for (int c = threadIdx.x; c < m; c += WG) {
-    for (int i = c; i < m; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= A[i * m + k] * B[k * m + c];
-      B[i * m + c] = s / A[i * m + i];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < m * m; e += WG) Ri[e] = B[e];
-  // A = Y = R^-1 Wsym
-  for (int e = threadIdx.x; e < m * m; e += WG) {
-    const int i = e / m, j = e % m;
-    double s = 0.0;
-    for (int k = 0; k <= i; ++k) {
-      const int a = k < j ? k : j, b = k < j ? j : k;
-      s += B[i * m + k] * Ws[a * ldm + b];
-    }
-    A[e] = s;
-  }
-  __syncthreads();
-  // G = Y R^-T (symmetric) into the global staging area, then into B
-  for (int e = threadIdx.x; e < m * m; e += WG) {
-    const int i = e / m, j = e % m;
-    if (j < i) continue;
-    double s = 0.0;
-    for (int k = 0; k <= j; ++k) s += A[i * m + k] * B[j * m + k];
-    Gt[i * m + j] = s;
-    Gt[j * m + i] = s;
-  }
-  __syncthreads();
-  const bool warm = mprev > 1 && mprev <= m && Uprev != nullptr;
-  if (warm) {
-    // A = G diag(Uprev, I)
-    for (int e = threadIdx.x; e < m * m; e += WG) {
-      const int i = e / m, j = e % m;
-      double s;
-      if (j < mprev) {
-        s = 0.0;
-        for (int k = 0; k < mprev; ++k) s += Gt[i * m + k] * Uprev[k * ldu + j];
-      } else {
-        s = Gt[i * m + j];
-      }
-      A[e] = s;
-    }
-    __syncthreads();
-    // B = diag(Uprev, I)^T A
-    for (int e = threadIdx.x; e < m * m; e += WG) {
-      const int i = e / m, j = e % m;
-      double s;
-      if (i < mprev) {
-        s = 0.0;
-        for (int k = 0; k < mprev; ++k) s += Uprev[k * ldu + i] * A[k * m + j];
-      } else {
-        s = A[e];
-      }
-      B[e] = s;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += WG) {
-      const int i = e / m, j = e % m;
-      if (j > i) {
-        const double v = 0.5 * (B[i * m + j] + B[j * m + i]);
-        B[i * m + j] = v;
-        B[j * m + i] = v;
-      }
-    }
-    // U starts as diag(Uprev, I)
-    for (int e = threadIdx.x; e < m * m; e += WG) {
-      const int i = e / m, j = e % m;
-      A[e] = (i < mprev && j < mprev) ? Uprev[i * ldu + j] : (double)(i == j);
-    }
-  } else {
-    for (int e = threadIdx.x; e < m * m; e += WG) B[e] = Gt[e];
-  }
-  __syncthreads();
-  const int sweeps = jacobi_eigh(B, m, m, A, red, cs, sn, !warm);
-  // keep the eigenvectors for the next call's warm start
-  if (Uprev)
-    for (int e = threadIdx.x; e < m * m; e += WG) Uprev[(e / m) * ldu + (e % m)] = A[e];
-  // rank positive theta in descending order
-  for (int i = threadIdx.x; i < m; i += WG) {
-    const double ti = B[i * m + i];
-    int rk = -1;
-    if (ti > 0.0) {
-      rk = 0;
-      for (int j = 0; j < m; ++j) {
-        const double tj = B[j * m + j];
-        if (tj > ti || (tj == ti && j < i)) rk += (tj > 0.0);
-      }
-    }
-    rank_of[i] = rk;
-  }
-  __syncthreads();
-  int npos = 0;
-  for (int i = threadIdx.x; i < m; i += WG) npos += (B[i * m + i] > 0.0);
-  npos = (int)block_sum((double)npos, red);
-  for (int i = threadIdx.x; i < m; i += WG) {
-    const int rk = rank_of[i];
-    if (rk >= 0 && rk < nroot) omega[rk] = mu2 + 1.0 / B[i * m + i];
-  }
-  // outputs: columns rk < nret: c = R^-T u / sqrt(theta)
-  for (int e = threadIdx.x; e < m * nret; e += WG) {
-    const int row = e / nret, rk = e % nret;
-    if (rk >= npos) {
-      Cout[row * ldc + rk] = 0.0;
-      continue;
-    }
-    int col = -1;
-    for (int i = 0; i < m; ++i)
-      if (rank_of[i] == rk) col = i;
-    const double th = B[col * m + col];
-    double s = 0.0;
-    for (int k = row; k < m; ++k) s += Ri[k * m + row] * A[k * m + col];
-    Cout[row * ldc + rk] = s / sqrt(th);
-  }
-  if (threadIdx.x == 0) {
-    info[0] = sweeps < 0 ? 3 : (npos < nroot ? 2 : 0);
-    info[1] = npos;
-    info[2] = sweeps;
-  }
-}
 
 // ------------------------------------------------------------------------------------------
 // Symmetric-definite pencil solves by tridiagonalisation (one workgroup of WG threads).
@@ -892,9 +710,66 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
   tri_outputs(Ri, X, theta, m, nroot, nroot, npos_s, mu2, omega, Cout, ldc, info);
 }
 
-// Davidson pencil (m <= PLDS): Ms, Ws upper triangles (ld ldm); K, R, G in LDS. nret columns of
-// Cout (the nroot wanted and the next Ritz vectors, kept on restart). work: m^2 + 4 nret m
-// (G staging, vectors, inverse-iteration scratch).
+// Davidson pencil: Ms, Ws upper triangles (ld ldm). nret columns of Cout (the nroot wanted and
+// the next Ritz vectors, kept on restart). A, B, G: m x m matrices (LDS or global; G may alias A:
+// then Gt stages G), X: 4 nret m doubles of global scratch (vectors, inverse-iteration rows).
+__device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
+                                                const double* __restrict__ Ws, int ldm, int m,
+                                                double mu2, int nroot, int nret, double* omega,
+                                                double* Cout, int ldc, double* A, double* B,
+                                                double* G, double* Gt, double* X, int* info,
+                                                double* red, double* d, double* e, double* e2,
+                                                double* beta, double* vv, double* pq,
+                                                double* theta, int* flag, int* npos_s) {
+  const int t = threadIdx.x;
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    A[e_] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
+  }
+  __syncthreads();
+  if (!tri_cholesky(A, m, flag)) {
+    if (t == 0) {
+      info[0] = 1;
+      info[1] = 0;
+      info[2] = 0;
+    }
+    return;
+  }
+  tri_inverse(A, B, m);  // B = R^-1
+  // Y = R^-1 Wsym into A (R is no longer needed), then G = Y R^-T
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) {
+      const int a = k < j ? k : j, b = k < j ? j : k;
+      s += B[i * m + k] * Ws[a * ldm + b];
+    }
+    A[e_] = s;
+  }
+  __syncthreads();
+  double* Gw = G == A ? Gt : G;
+  for (int e_ = t; e_ < m * m; e_ += WG) {
+    const int i = e_ / m, j = e_ % m;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int k = 0; k <= j; ++k) s += A[i * m + k] * B[j * m + k];
+    Gw[i * m + j] = s;
+    Gw[j * m + i] = s;
+  }
+  __syncthreads();
+  if (G == A) {
+    for (int e_ = t; e_ < m * m; e_ += WG) G[e_] = Gt[e_];
+    __syncthreads();
+  }
+  tri_householder(G, m, d, e, beta, vv, pq, red);
+  const int nsel = nret < m ? nret : m;
+  tri_eigen(d, e, e2, m, nsel, theta, npos_s, X, red);
+  tri_back_transform(G, m, beta, X, nsel);
+  tri_outputs(B, X, theta, m, nroot, nsel, *npos_s, mu2, omega, Cout, ldc, info);
+}
+
+// m <= PLDS: K, R, G in LDS (G over K); work: m^2 (G staging) + 4 nret m.
 __global__ __launch_bounds__(WG) void k_pencil_tri(const double* __restrict__ Ms,
                                                    const double* __restrict__ Ws, int ldm, int m,
                                                    double mu2, int nroot, int nret,
@@ -908,51 +783,26 @@ __global__ __launch_bounds__(WG) void k_pencil_tri(const double* __restrict__ Ms
   __shared__ double d[PLDS], e[PLDS], e2[PLDS], beta[PLDS], vv[PLDS], pq[PLDS];
   __shared__ double theta[PLDS];
   __shared__ int flag, npos_s;
-  const int t = threadIdx.x;
-  double* Gt = work;                       // staging of G
-  double* X = work + (size_t)m * m;        // vectors and inverse-iteration scratch
-  for (int e_ = t; e_ < m * m; e_ += WG) {
-    const int i = e_ / m, j = e_ % m;
-    const int a = i < j ? i : j, b = i < j ? j : i;
-    sA[e_] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
-  }
-  __syncthreads();
-  if (!tri_cholesky(sA, m, &flag)) {
-    if (t == 0) {
-      info[0] = 1;
-      info[1] = 0;
-      info[2] = 0;
-    }
-    return;
-  }
-  tri_inverse(sA, sB, m);  // sB = R^-1
-  // Y = R^-1 Wsym into sA (R is no longer needed), then G = Y R^-T into the staging area
-  for (int e_ = t; e_ < m * m; e_ += WG) {
-    const int i = e_ / m, j = e_ % m;
-    double s = 0.0;
-    for (int k = 0; k <= i; ++k) {
-      const int a = k < j ? k : j, b = k < j ? j : k;
-      s += sB[i * m + k] * Ws[a * ldm + b];
-    }
-    sA[e_] = s;
-  }
-  __syncthreads();
-  for (int e_ = t; e_ < m * m; e_ += WG) {
-    const int i = e_ / m, j = e_ % m;
-    if (j < i) continue;
-    double s = 0.0;
-    for (int k = 0; k <= j; ++k) s += sA[i * m + k] * sB[j * m + k];
-    Gt[i * m + j] = s;
-    Gt[j * m + i] = s;
-  }
-  __syncthreads();
-  for (int e_ = t; e_ < m * m; e_ += WG) sA[e_] = Gt[e_];
-  __syncthreads();
-  tri_householder(sA, m, d, e, beta, vv, pq, red);
-  const int nsel = nret < m ? nret : m;
-  tri_eigen(d, e, e2, m, nsel, theta, &npos_s, X, red);
-  tri_back_transform(sA, m, beta, X, nsel);
-  tri_outputs(sB, X, theta, m, nroot, nsel, npos_s, mu2, omega, Cout, ldc, info);
+  pencil_tri_body(Ms, Ws, ldm, m, mu2, nroot, nret, omega, Cout, ldc, sA, sB, sA, work,
+                  work + (size_t)m * m, info, red, d, e, e2, beta, vv, pq, theta, &flag, &npos_s);
+}
+
+// PLDS < m <= JMAX: matrices L2-resident in work: 3 m^2 + 4 nret m.
+__global__ __launch_bounds__(WG) void k_pencil_tri_l2(const double* __restrict__ Ms,
+                                                      const double* __restrict__ Ws, int ldm,
+                                                      int m, double mu2, int nroot, int nret,
+                                                      double* __restrict__ omega,
+                                                      double* __restrict__ Cout, int ldc,
+                                                      double* __restrict__ work,
+                                                      int* __restrict__ info) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double theta[JMAX];
+  __shared__ int flag, npos_s;
+  const size_t mm = (size_t)m * m;
+  pencil_tri_body(Ms, Ws, ldm, m, mu2, nroot, nret, omega, Cout, ldc, work, work + mm,
+                  work + 2 * mm, nullptr, work + 3 * mm, info, red, d, e, e2, beta, vv, pq, theta,
+                  &flag, &npos_s);
 }
 
 // Q = orth(C[:, :r]) by modified Gram-Schmidt, twice; columns with relative norm below 1e-10
@@ -1118,21 +968,16 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
   return hipGetLastError();
 }
 
-hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2, int nroot,
-                         int nret, double* omega, double* Cout, int ldc, double* work, int* info,
-                         double* Uprev, int ldu, int mprev, hipStream_t s) {
-  if (m > JMAX || nret > WG) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pencil, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret, omega,
-                     Cout, ldc, work, info, Uprev, ldu, mprev);
-  return hipGetLastError();
-}
-
-hipError_t launch_pencil_tri(const double* Ms, const double* Ws, int ldm, int m, double mu2,
-                             int nroot, int nret, double* omega, double* Cout, int ldc,
-                             double* work, int* info, hipStream_t s) {
-  if (m > PLDS || nret > m || nroot > nret) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pencil_tri, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
-                     omega, Cout, ldc, work, info);
+hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2,
+                         int nroot, int nret, double* omega, double* Cout, int ldc, double* work,
+                         int* info, hipStream_t s) {
+  if (m > JMAX || nret > m || nroot > nret) return hipErrorInvalidValue;
+  if (m <= PLDS)
+    hipLaunchKernelGGL(k_pencil_tri, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
+                       omega, Cout, ldc, work, info);
+  else
+    hipLaunchKernelGGL(k_pencil_tri_l2, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
+                       omega, Cout, ldc, work, info);
   return hipGetLastError();
 }
 

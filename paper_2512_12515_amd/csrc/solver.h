@@ -18,7 +18,7 @@ namespace pprpa {
 
 struct DavWork {
   double *V, *SV, *Vt, *SVt, *Ms, *Ws_, *Mt, *Wt, *Cc, *Q, *Z, *SZ, *R, *Tn, *Tn2, *Cp, *Gb, *Tm;
-  double *omega, *rnorm, *part, *pwork, *Up;
+  double *omega, *rnorm, *part, *pwork;
   int* info;
 };
 
@@ -82,7 +82,7 @@ class Solver {
   pprpa_davidson_args a_;
   std::chrono::steady_clock::time_point t0_;
   int nroot_ = 0, blk_ = 0, max_iter_ = 0, mmax_ = 0, nret_ = 0, tblk_ = 0, nch_ = 0, nres_ = 64;
-  int m_ = 0, mnew0_ = 0, mprev_ = 0, iter_ = 0, nsig_ = 0;
+  int m_ = 0, mnew0_ = 0, iter_ = 0, nsig_ = 0;
   int npos_ = 0, nsel_ = 0, kept_ = 0;
   bool sig_timed_ = false, have_iterate_ = false;
   std::vector<int> sel_;
