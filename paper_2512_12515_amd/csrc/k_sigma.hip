@@ -248,7 +248,9 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   const int bnt = vblk ? a.nvt : (a.nct - a.nvt);
   const int brow0 = vblk ? 0 : a.nvp;
   const int npt = min(4, bnt - t0);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index is uniform: kept in a scalar register, the per-wave conditions below become
+  // scalar branches
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   // a panel of one or two column tiles gives the waves it has no column for a share of the rows
   // instead (each wave of a column computes its own copy of T); a three-tile panel idles one wave
@@ -311,15 +313,19 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
                 const int cg = cc0 + GRP * grp;
                 // groups that reach past d multiply exact zeros of U^T (c > d)
                 if (active && cg >= q0 && cg < q1) {
+                  // all four k steps of the group's A operands first: one LDS wait per group
+                  T av[4][GRP];
 #pragma unroll
-                  for (int ks = 0; ks < 4; ++ks) {
-                    T av[GRP];
-#pragma unroll
-                    for (int j = 0; j < GRP; ++j) av[j] = sA[(4 * ks + lk) * wa + (cg - g0 + j) * TILE + li];
+                  for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
                     for (int j = 0; j < GRP; ++j)
-                      Tacc[GRP * grp + j] = mfma(av[j], bv[ks], Tacc[GRP * grp + j]);
-                  }
+                      av[ks][j] = sA[(4 * ks + lk) * wa + (cg - g0 + j) * TILE + li];
+                  __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+                  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      Tacc[GRP * grp + j] = mfma(av[ks][j], bv[ks], Tacc[GRP * grp + j]);
                 }
               }
             }
@@ -345,15 +351,18 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
                 // row tiles at or beyond nrt in the last group read other data of the buffer (in
                 // bounds); their results are never stored
                 if (active && GRP * grp < nrt && grp % parts == rsel) {
+                  T av[4][GRP];
 #pragma unroll
-                  for (int ks = 0; ks < 4; ++ks) {
-                    T av[GRP];
-#pragma unroll
-                    for (int j = 0; j < GRP; ++j) av[j] = sL[acc_row<T>(lk, ks) * wl + (GRP * grp + j) * TILE + li];
+                  for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
                     for (int j = 0; j < GRP; ++j)
-                      S[GRP * grp + j] = mfma(av[j], Tacc[i + sub][ks], S[GRP * grp + j]);
-                  }
+                      av[ks][j] = sL[acc_row<T>(lk, ks) * wl + (GRP * grp + j) * TILE + li];
+                  __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+                  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      S[GRP * grp + j] = mfma(av[ks][j], Tacc[i + sub][ks], S[GRP * grp + j]);
                 }
               }
             }
