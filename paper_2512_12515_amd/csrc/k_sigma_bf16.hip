@@ -134,7 +134,7 @@ __device__ __forceinline__ void sandwich_bf16_cols(const u16* __restrict__ L, si
   const int bnt = vblk ? a.nvt : (a.nct - a.nvt);
   const int brow0 = vblk ? 0 : a.nvp;
   const int npt = min(4, bnt - t0);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   // (waves of a short panel stay idle: giving them rows, as the FP32 kernel does, would repeat
   // contraction 1 and its LDS reads, which bound this kernel)
@@ -288,7 +288,7 @@ __device__ __forceinline__ void sandwich_bf16_rows(const u16* __restrict__ L, si
   const int bnt = vblk ? a.nvt : (a.nct - a.nvt);
   const int brow0 = vblk ? 0 : a.nvp;
   const int npt = min(4, bnt - t0);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const bool active = w < npt;  // contraction 1: wave w computes T for column tile w
   const int wc = min(w, npt - 1);
