@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "solver.h"
@@ -93,6 +94,20 @@ pprpa_status harvest_timing(pprpa_ctx* c) {
   return PPRPA_OK;
 }
 
+// Order of sandwich launches on one device across contexts: each launch waits, on the GPU, for
+// the end of the previous launch issued on the same device by any context, so the sandwiches of
+// solves running side by side on several streams do not split the compute units between them
+// (each one fills the chip alone, and its per-launch time is its own) while their other kernels
+// still overlap. The event lives until the process ends; the host is never blocked.
+namespace {
+struct SigmaGate {
+  std::mutex mu;
+  hipEvent_t last = nullptr;
+};
+constexpr int GATE_DEVICES = 64;
+SigmaGate g_gate[GATE_DEVICES];
+}  // namespace
+
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
   const int64_t n = c->g.n;
   for (int k0 = 0; k0 < k; k0 += c->kcap) {
@@ -121,9 +136,20 @@ pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
     const double esz = c->st == Store::F64 ? 8.0 : (c->st == Store::F32 ? 4.0 : 2.0 * (c->nprod == 3 ? 2 : 3));
     tm.bytes = (double)g.naux * ((double)g.nv * g.nv + (double)g.nv * g.no + (double)g.no * g.no) * esz +
                2.0 * kk * (double)n * 8.0;
-    PPRPA_HIP(hipEventRecord(tm.a, c->stream));
-    PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
-    PPRPA_HIP(hipEventRecord(tm.b, c->stream));
+    if (c->device >= 0 && c->device < GATE_DEVICES) {
+      SigmaGate& gt = g_gate[c->device];
+      std::lock_guard<std::mutex> lk(gt.mu);
+      if (!gt.last) PPRPA_HIP(hipEventCreateWithFlags(&gt.last, hipEventDisableTiming));
+      PPRPA_HIP(hipStreamWaitEvent(c->stream, gt.last, 0));
+      PPRPA_HIP(hipEventRecord(tm.a, c->stream));
+      PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
+      PPRPA_HIP(hipEventRecord(tm.b, c->stream));
+      PPRPA_HIP(hipEventRecord(gt.last, c->stream));
+    } else {
+      PPRPA_HIP(hipEventRecord(tm.a, c->stream));
+      PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
+      PPRPA_HIP(hipEventRecord(tm.b, c->stream));
+    }
     c->pend.push_back(tm);
     PPRPA_HIP(launch_epilogue(c->g, c->st, z, kk, c->Sp, ns, c->ptab, c->epair, s, c->stream));
   }

@@ -66,7 +66,7 @@ pprpa_status shape_of(const Geometry& g, const pprpa_davidson_args* a, Shape* sh
     return PPRPA_EINVAL;
   }
   s.nret = std::max(s.nroot, std::min(2 * s.nroot, s.mmax / 2));
-  s.nch = (int)std::min<int64_t>(512, std::max<int64_t>(1, n / 256));
+  s.nch = (int)std::min<int64_t>(256, std::max<int64_t>(1, n / 128));  // t-chunks of the dots
   *sh = s;
   return PPRPA_OK;
 }
