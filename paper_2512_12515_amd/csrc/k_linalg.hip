@@ -1,15 +1,17 @@
 // FP64 linear algebra of the Davidson solver and of the direct path, on the GPU.
 //
-//  * tall-skinny products over the long pair dimension (HBM-bound, VALU FP64):
+//  * tall-skinny products over the long pair dimension (HBM-bound, FP64 MFMA):
 //      dots     C = A diag(w) B^T       (subspace matrices V^T M V, V^T W V, projections)
 //      combine  Y = beta Y + alpha C^T X (Ritz vectors, projections, basis rotations)
 //      residual r = sigma(z) - Omega W z and its 2-norm; Davidson diagonal preconditioner
 //  * one-workgroup dense solvers for the small projected problems:
 //      pencil   the definite generalised eigenproblem M c = Omega W c via
-//               M - 2 mu W = R R^T (Cholesky), G = R^-1 W R^-T, G = U diag(theta) U^T (cyclic
-//               Jacobi, round-robin parallel ordering), Omega = 2 mu + 1/theta; pp roots have
-//               theta > 0 (c^T W c = +1 after scaling by 1/sqrt(theta))
-//      gram_orth / small_orth / congruence for the basis bookkeeping.
+//               M - 2 mu W = R R^T (Cholesky), G = R^-1 W R^-T, Householder tridiagonal form of
+//               G, Sturm-count bisection for the wanted eigenvalues theta and inverse iteration
+//               for their vectors, Omega = 2 mu + 1/theta; pp roots have theta > 0
+//               (c^T W c = +1 after scaling by 1/sqrt(theta))
+//      gram_orth / small_orth / congruence for the basis bookkeeping (cyclic Jacobi on the small
+//               Gram matrices).
 #include "internal.h"
 
 namespace pprpa {
