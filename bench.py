@@ -287,7 +287,7 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
              "max_resid": r["report"]["max_resid"]}
         if prec == "fp64":
             ref = r["omega"]
-        else:
+        elif ref is not None:
             d = np.abs(r["omega"] - ref)
             e["max_abs_err_vs_fp64_ha"] = float(d.max())
             e["per_root_err_ha"] = [float(x) for x in d]
@@ -316,6 +316,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
     ap.add_argument("--precision-only", action="store_true", help="run only the precision study")
+    ap.add_argument("--precs", default="fp64,fp32,bf16x6,bf16x3",
+                    help="sigma precisions of the precision / active-window study (comma list; "
+                         "errors are reported against fp64 when it is included)")
     ap.add_argument("--active-only", action="store_true",
                     help="run only the active-window workload in each precision")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving stream")
@@ -342,13 +345,13 @@ def main():
     if args.precision_only:
         line = {"metric": "sigma-products/sec and per-root eigenvalue error by sigma precision",
                 "n_gpus": 1, "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
-        line.update(precision_study(P, gen))
+        line.update(precision_study(P, gen, precs=tuple(args.precs.split(","))))
         print(json.dumps(line), flush=True)
         return
     if args.active_only:
         line = {"metric": "sigma-products/sec and per-root eigenvalue error by sigma precision",
                 "n_gpus": 1, "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
-        line.update(precision_study(P, gen, name="active"))
+        line.update(precision_study(P, gen, precs=tuple(args.precs.split(",")), name="active"))
         print(json.dumps(line), flush=True)
         return
     if args.serve_only:
