@@ -214,8 +214,9 @@ template <typename T, int CT, int RT>
 struct SandCfg {
   // LDS tiles are packed row-major (row stride = staged width) because direct global->LDS loads
   // write each wave's 64 x 16 bytes contiguously.
-  static constexpr int SR = 2 * TILE;                             // rows per stage (2 tiles)
-  static constexpr int S1 = SR * CT * TILE + SR * 4 * TILE;      // contraction-1 stage
+  static constexpr int SR1 = 3 * TILE;                            // contraction-1 rows (3 tiles)
+  static constexpr int SR = 2 * TILE;                             // contraction-2 rows (2 tiles)
+  static constexpr int S1 = SR1 * CT * TILE + SR1 * 4 * TILE;    // contraction-1 stage
   static constexpr int S2 = SR * RT * TILE;                      // contraction-2 stage
   static constexpr int BUF = S1 > S2 ? S1 : S2;                  // elements per LDS buffer
   static constexpr int VEC = 16 / sizeof(T);                     // elements per lane per load
@@ -272,8 +273,7 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
 #pragma unroll
   for (int r = 0; r < RT; ++r) S[r] = V{0, 0, 0, 0};
 
-  constexpr int SR = Cfg::SR;
-  T* const sB = buf + SR * CT * TILE;
+  T* const sB = buf + Cfg::SR1 * CT * TILE;
   for (int P = P0; P < P1; ++P) {
     const T* __restrict__ Lp = L + (int64_t)P * a.zstride;
     for (int cc0 = 0; cc0 < a.nct; cc0 += CT) {
@@ -281,13 +281,13 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
       V Tacc[CT];
 #pragma unroll
       for (int i = 0; i < CT; ++i) Tacc[i] = V{0, 0, 0, 0};
-      // contraction 1: T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], d in c's block, two d
+      // contraction 1: T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], d in c's block, three d
       // tiles per stage
       for (int part = 0; part < 2; ++part) {
         const int lo = part == 0 ? cc0 : max(cc0, a.nvt);
         const int hi = part == 0 ? (cc0 < a.nvt ? a.nvt : cc0) : (cc1 > a.nvt ? a.nct : lo);
-        for (int dt = lo; dt < hi; dt += 2) {
-          const int nd = min(2, hi - dt);
+        for (int dt = lo; dt < hi; dt += 3) {
+          const int nd = min(3, hi - dt);
           int g0, g1, h0, h1;
           c_range(dt, cc0, cc1, a.nvt, &g0, &g1);
           c_range(dt + nd - 1, cc0, cc1, a.nvt, &h0, &h1);
@@ -298,7 +298,7 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
           __builtin_amdgcn_s_waitcnt(0);
           __syncthreads();
 #pragma unroll
-          for (int sub = 0; sub < 2; ++sub) {
+          for (int sub = 0; sub < 3; ++sub) {
             if (sub < nd) {
               int q0, q1g;
               c_range(dt + sub, cc0, cc1, a.nvt, &q0, &q1g);
