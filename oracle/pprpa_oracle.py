@@ -21,6 +21,9 @@ It is the plain definition written out in NumPy/SciPy, FP64 throughout:
 Readings where the paper is silent (listed with reasons in the design notes):
 * pair order: upper triangle, row-major; singlet (p <= q), triplet (p < q); z = [x; y];
 * "lowest roots" are the smallest Omega among eigenvectors with z^T W z = +1;
+* the hh channel (two-electron removal, z^T W z = -1) returns the roots nearest the gap, i.e.
+  the largest Omega_hh first (the states of the (N-2)-electron system closest to its ground
+  state);
 * the pencil is solved through the definite shift K = M - 2 mu W (mu = mid-gap), which is
   positive definite for the synthetic inputs; the general non-symmetric solver (route G)
   serves as the cross-check on small inputs.
@@ -185,11 +188,12 @@ class NotDefinite(RuntimeError):
     pass
 
 
-def solve_definite(M, nvv, mu, nroot=None):
+def solve_definite(M, nvv, mu, nroot=None, channel="pp"):
     """Route D. K = M - 2 mu W = R R^T (Cholesky); G = R^-1 W R^-T (symmetric);
     G u = theta u gives Omega = 2 mu + 1/theta and z = R^-T u / sqrt|theta|, z^T W z = sign(theta).
 
-    With nroot, only the nroot largest theta (the lowest pp roots) are computed.
+    With nroot, only the nroot largest theta (channel "pp": the lowest pp roots) or the nroot
+    smallest theta (channel "hh": the hh roots nearest 2 mu) are computed.
     Returns (Omega, Z, sign) with Z columns as eigenvectors, sorted by Omega."""
     n = M.shape[0]
     w = metric(nvv, n - nvv)
@@ -203,8 +207,10 @@ def solve_definite(M, nvv, mu, nroot=None):
     G = 0.5 * (G + G.T)
     if nroot is None:
         theta, U = sla.eigh(G)
-    else:
+    elif channel == "pp":
         theta, U = sla.eigh(G, subset_by_index=[n - nroot, n - 1])
+    else:
+        theta, U = sla.eigh(G, subset_by_index=[0, nroot - 1])
     Z = sla.solve_triangular(R, U, lower=True, trans="T") / np.sqrt(np.abs(theta))
     Omega = 2.0 * mu + 1.0 / theta
     order = np.argsort(Omega)
@@ -245,6 +251,14 @@ def hh_roots(Omega, Z, sign):
     return Omega[sel], fix_sign(Z[:, sel])
 
 
+def hh_nearest(Omega, Z, sign, nroot):
+    """The nroot two-electron removal (hh) roots nearest the gap: negative norm in Eq. xy_norm,
+    largest Omega first (Omega < 2 mu for every hh root)."""
+    sel = np.where(sign < 0)[0]
+    sel = sel[np.argsort(-Omega[sel], kind="stable")][:nroot]
+    return Omega[sel], fix_sign(Z[:, sel])
+
+
 def correlation_energy(Omega_pp, Omega_hh, A, C):
     """Both expressions of Eq. correlation_energy: (sum pp - Tr A, -sum hh - Tr C)."""
     return np.sum(Omega_pp) - np.trace(A), -np.sum(Omega_hh) - np.trace(C)
@@ -255,17 +269,19 @@ def correlation_energy(Omega_pp, Omega_hh, A, C):
 # ----------------------------------------------------------------------------------------
 
 def solve(eps, L, nocc, mult, nroot, nocc_act=None, nvir_act=None, lpq_is_active=False,
-          route="D", vectors=False):
-    """Lowest nroot pp roots (Hartree) of the ppRPA problem; optionally their vectors."""
+          route="D", vectors=False, channel="pp"):
+    """Lowest nroot pp roots (Hartree) of the ppRPA problem, ascending (channel "pp"), or the
+    nroot hh roots nearest the gap, descending (channel "hh"); optionally their vectors."""
     sp = active_space(eps, L, nocc, nocc_act, nvir_act, lpq_is_active)
     A, B, C = build_matrices(sp, mult)
     M = pprpa_matrix(A, B, C)
     nvv = A.shape[0]
     if route == "D":
-        Om, Z, sg = solve_definite(M, nvv, midgap(sp), nroot=nroot if M.shape[0] > 3000 else None)
+        Om, Z, sg = solve_definite(M, nvv, midgap(sp), nroot=nroot if M.shape[0] > 3000 else None,
+                                   channel=channel)
     else:
         Om, Z, sg = solve_general(M, nvv)
-    om, z = pp_roots(Om, Z, sg, nroot)
+    om, z = pp_roots(Om, Z, sg, nroot) if channel == "pp" else hh_nearest(Om, Z, sg, nroot)
     return (om, z) if vectors else om
 
 

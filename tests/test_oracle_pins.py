@@ -12,6 +12,8 @@ P6  second order: with A/C interactions off and L_vo scaled by lam,
 P7  two electrons: with no occupied orbitals the singlet and triplet A spectra together are
     the spectrum of the two-electron CI Hamiltonian (Slater-Condon).
 P8  the factorised sigma equals the dense M z; route D equals route G.
+hh  the removal channel's selection: L = 0 closed form (highest e_i + e_j first), B = 0 against
+    -eigvalsh(C), the subset solve against the full spectrum.
 Plus mutation checks: plausible mistakes planted in a copy of the oracle fail a pin.
 """
 import numpy as np
@@ -160,6 +162,59 @@ def test_subset_route_matches_full():
     Om5, Z5, sg5 = O.solve_definite(M, A.shape[0], O.midgap(sp), nroot=5)
     assert np.all(sg5 > 0)
     assert np.allclose(Om5, Om[sg > 0][:5], atol=1e-12)
+
+
+# ----------------------------------------------------------------------------------------
+# hh channel selection (two-electron removal roots nearest the gap, largest Omega first)
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mult", MULTS)
+@pytest.mark.parametrize("nocc,nvir,naux", [(4, 9, 30), (6, 5, 20)])
+def test_hh_channel_zero_interaction(mult, nocc, nvir, naux):
+    """L = 0: the hh roots are e_i + e_j; the channel returns the highest pairs, descending."""
+    eps = gen.orbital_energies(3, nocc, nvir)
+    L = np.zeros((naux, nocc + nvir, nocc + nvir))
+    k = 0 if mult == "singlet" else 1
+    eo = eps[:nocc]
+    hh = np.sort([eo[i] + eo[j] for i in range(nocc) for j in range(i + k, nocc)])[::-1]
+    nroot = min(5, hh.size)
+    for route in ("D", "G"):
+        om = O.solve(eps, L, nocc, mult, nroot, route=route, channel="hh")
+        assert np.allclose(om, hh[:nroot], atol=1e-13)
+        assert np.all(np.diff(om) <= 0.0)
+
+
+@pytest.mark.parametrize("mult", MULTS)
+def test_hh_channel_no_coupling(mult):
+    """B = 0: the hh roots are -eigvalsh(C) (LAPACK on C alone); the channel returns the
+    largest of them."""
+    eps, L, sp = make_sp(4, 6, 9, 30)
+    sp["Lov"] = np.zeros_like(sp["Lov"])
+    A, B, C = O.build_matrices(sp, mult)
+    M = O.pprpa_matrix(A, B, C)
+    Om, Z, sg = O.solve_definite(M, A.shape[0], O.midgap(sp))
+    om, z = O.hh_nearest(Om, Z, sg, 4)
+    ref = np.sort(-np.linalg.eigvalsh(C))[::-1][:4]
+    assert np.allclose(om, ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("mult", MULTS)
+def test_hh_subset_route_matches_full(mult):
+    """The nroot smallest theta of route D are the hh roots nearest the gap; their vectors
+    satisfy M z = Omega W z with z^T W z = -1 (Eq. xy_norm, removal sign)."""
+    eps, L, sp = make_sp(0, 5, 20, 100)
+    A, B, C = O.build_matrices(sp, mult)
+    M = O.pprpa_matrix(A, B, C)
+    nvv = A.shape[0]
+    Om, Z, sg = O.solve_definite(M, nvv, O.midgap(sp))
+    full, _ = O.hh_nearest(Om, Z, sg, 5)
+    Om5, Z5, sg5 = O.solve_definite(M, nvv, O.midgap(sp), nroot=5, channel="hh")
+    assert np.all(sg5 < 0)
+    assert np.allclose(np.sort(Om5)[::-1], full, atol=1e-12)
+    assert np.all(Om5 < 2.0 * O.midgap(sp))
+    w = O.metric(nvv, M.shape[0] - nvv)
+    assert np.allclose(M @ Z5, (w[:, None] * Z5) * Om5[None, :], atol=1e-10)
+    assert np.allclose(np.einsum("i,ij,ij->j", w, Z5, Z5), -1.0, atol=1e-12)
 
 
 def test_active_window_equals_oracle_on_sliced_input():
