@@ -241,6 +241,34 @@ def small_direct(P, gen, reps=20):
             "max_eig_err_ha_vs_oracle": max(errs)}
 
 
+def hh_channel(P, eps_d, L_d, nocc, nroot, block, tol, reps=2):
+    """The hh channel (two-electron removal roots nearest the gap) on the FP64 Davidson workload:
+    singlet and triplet solved one after the other, reps times; sigma products per second,
+    solve latency and the error against the oracle's stored hh roots."""
+    gold_path = os.path.join(ROOT, "tests", "golden", "davidson_hh_fp64.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    n_sigma, secs, lat, errs, iters = 0, 0.0, [], [], {}
+    for rep in range(reps + 1):
+        for mult in ("singlet", "triplet"):
+            t0 = time.perf_counter()
+            with P.PpRPA(eps_d, L_d, nocc, mult=mult, max_block=block) as ctx:
+                r = ctx.davidson(nroot, block=block, tol=tol, channel="hh")
+            dt = time.perf_counter() - t0
+            if rep == 0:
+                continue  # warm-up
+            n_sigma += r["report"]["n_sigma"]
+            secs += dt
+            lat.append(dt)
+            iters[mult] = r["report"]["iters"]
+            if gold is not None and nroot <= len(gold["roots"][f"0/{mult}"]):
+                ref = np.array(gold["roots"][f"0/{mult}"][:nroot])
+                errs.append(float(np.max(np.abs(r["omega"] - ref))))
+    return {"workload": f"hh channel, {nroot} roots per spin, block {block}, tol {tol:g}, "
+                        "singlet then triplet",
+            "sigma_per_s": n_sigma / secs, "latency_p50_s": float(np.percentile(lat, 50)),
+            "iters": iters, "max_eig_err_ha_vs_oracle": max(errs) if errs else None}
+
+
 def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20, tol=1e-6,
                     tol_reduced=1e-5, name="mixed"):
     """A large workload (default: the mixed-precision one, nocc 50, nvir 500, naux 1800, singlet,
@@ -468,6 +496,9 @@ def main():
     }
     log("small direct workload ...")
     line["small_direct"] = small_direct(P, gen)
+    if (nocc, nvir, naux) == (20, 200, 700):
+        log("hh channel ...")
+        line["hh_channel"] = hh_channel(P, eps_d, L_d, nocc, args.nroot, args.block, args.tol)
     if not args.no_precision:
         log("precision study ...")
         line["precision"] = precision_study(P, gen)

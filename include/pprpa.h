@@ -103,7 +103,7 @@ pprpa_status pprpa_matvec(pprpa_ctx* ctx, int32_t k, const double* z, double* si
 pprpa_status pprpa_dense_matrix(pprpa_ctx* ctx, double* M, int32_t on_device);
 
 typedef struct {
-  int32_t nroot;        /* number of lowest pp roots wanted (>= 1)                          */
+  int32_t nroot;        /* number of roots wanted (>= 1)                                    */
   int32_t block;        /* max correction vectors added per iteration (<= 0: nroot)         */
   int32_t max_iter;     /* iteration cap (<= 0: 100)                                        */
   int32_t max_subspace; /* subspace size that triggers a restart (<= 0: automatic)          */
@@ -113,6 +113,9 @@ typedef struct {
   int32_t direct;       /* 1: dense direct diagonalisation (requires dense=1 at build)     */
   void (*log)(void* user, const char* json_line); /* optional per-iteration log            */
   void* user;
+  int32_t channel;      /* 0: pp, two-electron addition roots (Omega > 2 mu, X^T X - Y^T Y = +1);
+                         * 1: hh, two-electron removal roots (Omega < 2 mu, X^T X - Y^T Y = -1),
+                         * section "ppRPA Equation", Eq. xy_norm. Other values: EINVAL.       */
 } pprpa_davidson_args;
 
 typedef struct {
@@ -125,12 +128,13 @@ typedef struct {
   double t_total_s;     /* seconds for the whole call (host clock)                         */
 } pprpa_report;
 
-/* Lowest nroot two-electron-addition (pp) roots Omega of Eq. eigen_equation, ascending,
- * by the block Davidson method (direct=0) or by dense diagonalisation (direct=1).
- * omega: [nroot] host. vecs: [nroot][n] host or NULL. resid: [nroot] host or NULL.
- * rep: host or NULL. Returns ENOCONV (outputs filled with the last iterate) when max_iter is
- * reached, ENONDEF if the projected pencil is not definite, EUNSUPPORTED for direct without
- * a dense build, EINVAL for nroot > n_pp. */
+/* Lowest nroot two-electron-addition (pp) roots Omega of Eq. eigen_equation, ascending
+ * (channel 0), or the nroot two-electron-removal (hh) roots nearest the gap, descending
+ * (channel 1), by the block Davidson method (direct=0) or by dense diagonalisation (direct=1).
+ * omega: [nroot] host. vecs: [nroot][n] host or NULL, normalised to z^T W z = +1 (pp) or -1
+ * (hh). resid: [nroot] host or NULL. rep: host or NULL. Returns ENOCONV (outputs filled with
+ * the last iterate) when max_iter is reached, ENONDEF if the projected pencil is not definite,
+ * EUNSUPPORTED for direct without a dense build, EINVAL for nroot > n_pp (pp) or > n_hh (hh). */
 pprpa_status pprpa_davidson(pprpa_ctx* ctx, const pprpa_davidson_args* args, double* omega,
                             double* vecs, double* resid, pprpa_report* rep);
 

@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONDEF, EUNSUPPORTED, EBUSY = range(8)
 STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOCONV", "ENONDEF", "EUNSUPPORTED", "EBUSY"]
 MULT = {"singlet": 0, "triplet": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2, "bf16x3": 3}
+CHANNEL = {"pp": 0, "hh": 1}
 
 
 class PpRPAError(RuntimeError):
@@ -47,7 +48,7 @@ class DavidsonArgs(C.Structure):
     _fields_ = [("nroot", C.c_int32), ("block", C.c_int32), ("max_iter", C.c_int32),
                 ("max_subspace", C.c_int32), ("tol", C.c_double), ("guess", C.c_void_p),
                 ("nguess", C.c_int32), ("direct", C.c_int32), ("log", LOGFN),
-                ("user", C.c_void_p)]
+                ("user", C.c_void_p), ("channel", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -245,9 +246,12 @@ class PpRPA:
 
     # -- eigensolvers ------------------------------------------------------------------------
     def davidson(self, nroot, block=0, tol=1e-6, max_iter=0, max_subspace=0, guess=None,
-                 direct=False, vectors=False, log=None, raise_noconv=True):
+                 direct=False, vectors=False, log=None, raise_noconv=True, channel="pp"):
+        """channel "pp": the lowest nroot two-electron addition roots, ascending; "hh": the nroot
+        two-electron removal roots nearest the gap, descending."""
         a = DavidsonArgs()
         a.nroot = int(nroot)
+        a.channel = CHANNEL[channel]
         a.block = int(block)
         a.max_iter = int(max_iter)
         a.max_subspace = int(max_subspace)
@@ -291,7 +295,7 @@ class Server:
         self._nroot = {}
 
     def submit(self, eps, Lpq, nocc, nroot, mult="singlet", prec="fp64", nocc_act=0, nvir_act=0,
-               lpq_is_active=False, block=0, tol=1e-6, max_iter=0, max_subspace=0):
+               lpq_is_active=False, block=0, tol=1e-6, max_iter=0, max_subspace=0, channel="pp"):
         on_dev = _is_torch(Lpq) and Lpq.is_cuda
         if on_dev:
             import torch
@@ -307,7 +311,7 @@ class Server:
         b.mult, b.prec = MULT[mult], PREC[prec]
         d = DavidsonArgs()
         d.nroot, d.block, d.max_iter = int(nroot), int(block), int(max_iter)
-        d.max_subspace, d.tol = int(max_subspace), float(tol)
+        d.max_subspace, d.tol, d.channel = int(max_subspace), float(tol), CHANNEL[channel]
         t = C.c_uint64()
         _check(lib().pprpa_server_submit(self._h, C.byref(b), C.byref(d), C.byref(t)))
         self._held[t.value] = (eps, Lpq)

@@ -1,4 +1,5 @@
-// Block Davidson solver for the lowest pp roots of M z = Omega W z, and the direct dense path.
+// Block Davidson solver for the lowest pp roots (or the hh roots nearest the gap) of
+// M z = Omega W z, and the direct dense path.
 //
 // arXiv 2512.12515 (sections "ppRPA Equation" and "Implementation Details") names the Davidson
 // algorithm and direct diagonalisation as the two solvers but gives no algorithmic detail; the
@@ -6,8 +7,11 @@
 //  * subspace V (orthonormal rows, Euclidean) grown by blocks; projected pencil
 //    (V M V^T, V W V^T) solved on the device through the definite shift M - 2 mu W
 //    (mu = mid-gap of the active window), whose positive-theta roots are the pp roots, so the
-//    wanted roots are the nroot largest theta (lowest Omega > 2 mu);
-//  * Ritz vectors z = V^T c with z^T W z = +1 (Eq. xy_norm); residual r = M z - Omega W z,
+//    wanted roots are the nroot largest theta (lowest Omega > 2 mu); in the hh channel the
+//    negative-theta roots are the hh roots and the wanted ones the nroot smallest theta (the
+//    largest Omega < 2 mu, nearest the gap);
+//  * Ritz vectors z = V^T c with z^T W z = +1 (pp) or -1 (hh) (Eq. xy_norm); residual
+//    r = M z - Omega W z,
 //    converged when ||r||_2 <= tol for every wanted root;
 //  * corrections t = r / (Omega w - D) from the diagonal pair energies D, normalised, projected
 //    out of V twice (classical Gram-Schmidt, two passes) and orthonormalised within the block
@@ -36,11 +40,18 @@ size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 // Sizes of one Davidson solve (shared by the workspace allocation and the footprint estimate).
 pprpa_status shape_of(const Geometry& g, const pprpa_davidson_args* a, Shape* sh) {
-  const int64_t n = g.n, nvv = g.nvv;
+  const int64_t n = g.n;
+  if (a->channel != 0 && a->channel != 1) {
+    set_error("channel=%d is neither 0 (pp) nor 1 (hh)", a->channel);
+    return PPRPA_EINVAL;
+  }
+  // pair space of the wanted channel: virtual pairs (pp) or occupied pairs (hh)
+  const int64_t nwant = a->channel == 0 ? g.nvv : g.n - g.nvv;
   Shape s{};
   s.nroot = a->nroot;
-  if (s.nroot < 1 || s.nroot > nvv) {
-    set_error("nroot=%d outside [1, n_pp=%lld]", s.nroot, (long long)nvv);
+  if (s.nroot < 1 || s.nroot > nwant) {
+    set_error("nroot=%d outside [1, n_%s=%lld]", s.nroot, a->channel == 0 ? "pp" : "hh",
+              (long long)nwant);
     return PPRPA_EINVAL;
   }
   if (s.nroot > 64) {
@@ -53,12 +64,12 @@ pprpa_status shape_of(const Geometry& g, const pprpa_davidson_args* a, Shape* sh
   }
   int blk = a->block > 0 ? a->block : s.nroot;
   blk = std::max(blk, 1);
-  s.blk = (int)std::min<int64_t>(std::min(blk, 64), nvv);
+  s.blk = (int)std::min<int64_t>(std::min(blk, 64), nwant);
   s.max_iter = a->max_iter > 0 ? a->max_iter : 100;
   int mmax = a->max_subspace > 0 ? a->max_subspace : std::max(8 * s.nroot, s.nroot + 4 * s.blk);
   s.mmax = (int)std::min<int64_t>(std::min(mmax, 256), n);
   s.nguess = (a->guess && a->nguess > 0) ? std::min(a->nguess, s.mmax) : 0;
-  int nb0 = s.nguess > 0 ? s.nguess : (int)std::min<int64_t>(std::max(s.blk, s.nroot), nvv);
+  int nb0 = s.nguess > 0 ? s.nguess : (int)std::min<int64_t>(std::max(s.blk, s.nroot), nwant);
   s.nb0 = std::min(nb0, s.mmax);
   s.tblk = std::max(s.blk, s.nb0);  // rows of the correction buffers
   if (s.mmax < s.nroot + 1 && s.mmax < n) {
@@ -229,14 +240,18 @@ pprpa_status Solver::initial_subspace(const Shape& sh) {
     m_ = added;
     return PPRPA_OK;
   }
-  // unit vectors on the nb0 lowest virtual-pair energies (ties: lowest index)
-  std::vector<int64_t> idx(nvv);
-  std::iota(idx.begin(), idx.end(), 0);
+  // unit vectors on the nb0 lowest virtual-pair energies (pp) or the nb0 highest occupied-pair
+  // energies (hh), ties: lowest index
+  const bool hh = a_.channel == 1;
+  std::vector<int64_t> idx(hh ? n - nvv : nvv);
+  std::iota(idx.begin(), idx.end(), hh ? nvv : 0);
   auto epair = [&](int64_t e) {
     const int pq = c_->ptab_h[e];
-    return c_->ev_h[pq >> 16] + c_->ev_h[pq & 0xFFFF];
+    return hh ? c_->eo_h[pq >> 16] + c_->eo_h[pq & 0xFFFF] : c_->ev_h[pq >> 16] + c_->ev_h[pq & 0xFFFF];
   };
-  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return epair(x) < epair(y); });
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+    return hh ? epair(x) > epair(y) : epair(x) < epair(y);
+  });
   PPRPA_HIP(launch_fill(w.V, (size_t)sh.nb0 * n, 0.0, s));
   PPRPA_HIP(launch_set_units(w.V, n, idx.data(), sh.nb0, s));
   m_ = sh.nb0;
@@ -295,8 +310,8 @@ pprpa_status Solver::rr_launch() {
     PPRPA_HIP(launch_dots(w.V, n, m_, w.V + (size_t)mnew0_ * n, n, nb, n, nvv, 1, w.Ws_ + mnew0_,
                           mmax_, w.part, nch_, s));
   }
-  PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_), w.omega,
-                          w.Cc, nret_, w.pwork, w.info, s));
+  PPRPA_HIP(launch_pencil(w.Ms, w.Ws_, mmax_, m_, c_->mu2, nroot_, std::min(nret_, m_),
+                          a_.channel, w.omega, w.Cc, nret_, w.pwork, w.info, s));
   PPRPA_HIP(launch_combine(w.V, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.Z, n, s));
   PPRPA_HIP(launch_combine(w.SV, n, m_, w.Cc, nret_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
   PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, nres_, s));
@@ -324,7 +339,8 @@ pprpa_status Solver::rr_read() {
     return fail(PPRPA_ENONDEF);
   }
   if (info[0] == 2) {
-    set_error("projected pencil has %d pp roots, fewer than nroot=%d", npos_, nroot_);
+    set_error("projected pencil has %d %s roots, fewer than nroot=%d", npos_,
+              a_.channel == 0 ? "pp" : "hh", nroot_);
     return fail(PPRPA_ENONDEF);
   }
   std::copy(hp, hp + nroot_, om_);
@@ -485,12 +501,12 @@ pprpa_status Solver::run_direct() {
   double* hp = c_->pinned;
   PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
   if (m <= 96)  // W as a dense matrix: the Davidson pencil solver on the whole problem
-    PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, w.omega, w.Cc, nroot_,
-                            w.pwork, w.info, s));
+    PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, a_.channel, w.omega,
+                            w.Cc, nroot_, w.pwork, w.info, s));
   else  // W diagonal exploited
 
-    PPRPA_HIP(launch_direct_pencil(c_->M, m, nvv, c_->mu2, nroot_, w.omega, w.Cc, nroot_, w.pwork,
-                                   w.info, s));
+    PPRPA_HIP(launch_direct_pencil(c_->M, m, nvv, c_->mu2, nroot_, a_.channel, w.omega, w.Cc,
+                                   nroot_, w.pwork, w.info, s));
   PPRPA_HIP(launch_transpose(w.Cc, nroot_, m, nroot_, w.Z, n, s));
   PPRPA_HIP(launch_combine(c_->M, n, m, w.Cc, nroot_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
   PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, 64, s));
@@ -505,7 +521,7 @@ pprpa_status Solver::run_direct() {
     return PPRPA_ENONDEF;
   }
   if (info[0] == 2) {
-    set_error("fewer than nroot pp roots (%d)", info[1]);
+    set_error("fewer than nroot %s roots (%d)", a_.channel == 0 ? "pp" : "hh", info[1]);
     return PPRPA_ENONDEF;
   }
   std::copy(hp, hp + nroot_, om_);

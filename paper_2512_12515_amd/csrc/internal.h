@@ -132,19 +132,22 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
                           int64_t ldt, hipStream_t s);
 // Pencil solve on one workgroup: K = Ms - 2 mu Ws = R R^T, G = R^-1 Ws R^-T = U diag(theta) U^T
 // (Householder tridiagonalisation, bisection, inverse iteration), Omega = 2 mu + 1/theta; returns
-// the nroot lowest pp roots and coefficient columns Cout[m][ldc] with c^T Ws c = +1; columns
+// the nroot wanted roots of the channel and coefficient columns Cout[m][ldc] with c^T Ws c = +1
+// (pp) or -1 (hh); columns
 // nroot..nret-1 hold the next Ritz vectors (kept on restart). Ms, Ws: upper triangles (ld ldm).
-// m <= 512, nroot <= nret <= m. work: m^2 + 4 nret m doubles (m <= 96, matrices in LDS) or
-// 3 m^2 + 4 nret m (larger m). info: [0] status (0 ok, 1 not definite, 2 fewer than nroot pp
-// roots), [1] number of pp roots, [2] 0.
+// m <= 512, nroot <= nret <= m. channel 0 (pp): the largest theta, roots ascending in Omega;
+// channel 1 (hh): the smallest theta, the hh roots nearest 2 mu first (Omega descending).
+// work: m^2 + 4 nret m doubles (m <= 96, matrices in LDS) or 3 m^2 + 4 nret m (larger m).
+// info: [0] status (0 ok, 1 not definite, 2 fewer than nroot roots of the channel), [1] number
+// of roots of the channel, [2] 0.
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2,
-                         int nroot, int nret, double* omega, double* Cout, int ldc, double* work,
-                         int* info, hipStream_t s);
+                         int nroot, int nret, int channel, double* omega, double* Cout, int ldc,
+                         double* work, int* info, hipStream_t s);
 // Direct solve of the dense pencil (M, W), W = diag(+1 for i < nvv, -1), for 96 < m <= 512:
 // the same outputs as launch_pencil (nret = nroot), W diagonal. work: 3 m^2 + 4 nroot m doubles.
 hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
-                                double* omega, double* Cout, int ldc, double* work, int* info,
-                                hipStream_t s);
+                                int channel, double* omega, double* Cout, int ldc, double* work,
+                                int* info, hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

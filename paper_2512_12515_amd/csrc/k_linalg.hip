@@ -594,10 +594,12 @@ __device__ __forceinline__ void tri_householder(double* G, int m, double* d, dou
   __syncthreads();
 }
 
-// The nsel largest eigenvalues of T (theta[0] largest), the count of positive ones (*npos), and
-// their eigenvectors X[j][0..m) (global scratch: 4 nsel m doubles from X). e2: LDS scratch.
+// The nsel eigenvalues of T at the wanted end (channel 0, pp: the largest, theta[0] largest;
+// channel 1, hh: the smallest, theta[0] smallest), the count of roots of the channel's sign
+// (*npos: positive theta for pp, negative for hh), and their eigenvectors X[j][0..m) (global
+// scratch: 4 nsel m doubles from X). e2: LDS scratch.
 __device__ __forceinline__ void tri_eigen(const double* d, const double* e, double* e2, int m, int nsel,
-                          double* theta, int* npos, double* X, double* red) {
+                          int channel, double* theta, int* npos, double* X, double* red) {
   const int t = threadIdx.x;
   for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
   double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
@@ -611,10 +613,13 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
   const double gmax = block_reduce(hi_p, red, true);
   const double tnorm = fmax(block_reduce(nrm_p, red, true), 1e-300);
   const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
-  if (t == 0) *npos = m - sturm_below(d, e2, m, 0.0, tiny);
-  // bisection (thread j: the j-th largest)
+  if (t == 0) {
+    const int nbelow = sturm_below(d, e2, m, 0.0, tiny);
+    *npos = channel == 0 ? m - nbelow : nbelow;
+  }
+  // bisection (thread j: the j-th from the wanted end)
   if (t < nsel) {
-    const int idx = m - 1 - t;  // ascending index
+    const int idx = channel == 0 ? m - 1 - t : t;  // ascending index
     double lo = gmin - 1e-12 * tnorm, hi = gmax + 1e-12 * tnorm;
     for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
       const double mid = 0.5 * (lo + hi);
@@ -732,8 +737,9 @@ __device__ __forceinline__ void tri_back_transform(const double* G, int m, const
   }
 }
 
-// omega[j] (j < nroot) and the columns j < nsel of Cout: c = R^-T u / sqrt(theta); columns of
-// non-pp roots are zero. info: [0] 0 ok / 2 fewer than nroot pp roots, [1] pp roots, [2] 0.
+// omega[j] (j < nroot) and the columns j < nsel of Cout: c = R^-T u / sqrt|theta| (c^T W c = +1
+// for pp, -1 for hh); columns of roots of the other channel are zero. info: [0] 0 ok / 2 fewer
+// than nroot roots of the channel, [1] roots of the channel, [2] 0.
 __device__ __forceinline__ void tri_outputs(const double* Ri, const double* X, const double* theta, int m,
                             int nroot, int nsel, int npos, double mu2, double* omega,
                             double* Cout, int ldc, int* info) {
@@ -747,7 +753,7 @@ __device__ __forceinline__ void tri_outputs(const double* Ri, const double* X, c
     }
     double s = 0.0;
     for (int k = row; k < m; ++k) s += Ri[k * m + row] * X[(size_t)j * m + k];
-    Cout[row * ldc + j] = s / sqrt(theta[j]);
+    Cout[row * ldc + j] = s / sqrt(fabs(theta[j]));
   }
   if (t == 0) {
     info[0] = npos < nroot ? 2 : 0;
@@ -759,7 +765,7 @@ __device__ __forceinline__ void tri_outputs(const double* Ri, const double* X, c
 // Direct path: M (n x n, full, ld m), W = diag(+1 for i < nvv, -1). work: 3 m^2 + 4 nroot m.
 __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
                                                       int64_t nvv, double mu2, int nroot,
-                                                      double* __restrict__ omega,
+                                                      int channel, double* __restrict__ omega,
                                                       double* __restrict__ Cout, int ldc,
                                                       double* __restrict__ work,
                                                       int* __restrict__ info) {
@@ -797,7 +803,7 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
   }
   __syncthreads();
   tri_householder(G, m, d, e, beta, vv, pq, red);
-  tri_eigen(d, e, e2, m, nroot, theta, &npos_s, X, red);
+  tri_eigen(d, e, e2, m, nroot, channel, theta, &npos_s, X, red);
   tri_back_transform(G, m, beta, X, nroot);
   tri_outputs(Ri, X, theta, m, nroot, nroot, npos_s, mu2, omega, Cout, ldc, info);
 }
@@ -807,8 +813,9 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
 // then Gt stages G), X: 4 nret m doubles of global scratch (vectors, inverse-iteration rows).
 __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
                                                 const double* __restrict__ Ws, int ldm, int m,
-                                                double mu2, int nroot, int nret, double* omega,
-                                                double* Cout, int ldc, double* A, double* B,
+                                                double mu2, int nroot, int nret, int channel,
+                                                double* omega, double* Cout, int ldc, double* A,
+                                                double* B,
                                                 double* G, double* Gt, double* X, int* info,
                                                 double* red, double* d, double* e, double* e2,
                                                 double* beta, double* vv, double* pq,
@@ -856,7 +863,7 @@ __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
   }
   tri_householder(G, m, d, e, beta, vv, pq, red);
   const int nsel = nret < m ? nret : m;
-  tri_eigen(d, e, e2, m, nsel, theta, npos_s, X, red);
+  tri_eigen(d, e, e2, m, nsel, channel, theta, npos_s, X, red);
   tri_back_transform(G, m, beta, X, nsel);
   tri_outputs(B, X, theta, m, nroot, nsel, *npos_s, mu2, omega, Cout, ldc, info);
 }
@@ -864,7 +871,7 @@ __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
 // m <= PLDS: K, R, G in LDS (G over K); work: m^2 (G staging) + 4 nret m.
 __global__ __launch_bounds__(WG) void k_pencil_tri(const double* __restrict__ Ms,
                                                    const double* __restrict__ Ws, int ldm, int m,
-                                                   double mu2, int nroot, int nret,
+                                                   double mu2, int nroot, int nret, int channel,
                                                    double* __restrict__ omega,
                                                    double* __restrict__ Cout, int ldc,
                                                    double* __restrict__ work,
@@ -875,7 +882,7 @@ __global__ __launch_bounds__(WG) void k_pencil_tri(const double* __restrict__ Ms
   __shared__ double d[PLDS], e[PLDS], e2[PLDS], beta[PLDS], vv[PLDS], pq[PLDS];
   __shared__ double theta[PLDS];
   __shared__ int flag, npos_s;
-  pencil_tri_body(Ms, Ws, ldm, m, mu2, nroot, nret, omega, Cout, ldc, sA, sB, sA, work,
+  pencil_tri_body(Ms, Ws, ldm, m, mu2, nroot, nret, channel, omega, Cout, ldc, sA, sB, sA, work,
                   work + (size_t)m * m, info, red, d, e, e2, beta, vv, pq, theta, &flag, &npos_s);
 }
 
@@ -883,7 +890,7 @@ __global__ __launch_bounds__(WG) void k_pencil_tri(const double* __restrict__ Ms
 __global__ __launch_bounds__(WG) void k_pencil_tri_l2(const double* __restrict__ Ms,
                                                       const double* __restrict__ Ws, int ldm,
                                                       int m, double mu2, int nroot, int nret,
-                                                      double* __restrict__ omega,
+                                                      int channel, double* __restrict__ omega,
                                                       double* __restrict__ Cout, int ldc,
                                                       double* __restrict__ work,
                                                       int* __restrict__ info) {
@@ -892,7 +899,7 @@ __global__ __launch_bounds__(WG) void k_pencil_tri_l2(const double* __restrict__
   __shared__ double theta[JMAX];
   __shared__ int flag, npos_s;
   const size_t mm = (size_t)m * m;
-  pencil_tri_body(Ms, Ws, ldm, m, mu2, nroot, nret, omega, Cout, ldc, work, work + mm,
+  pencil_tri_body(Ms, Ws, ldm, m, mu2, nroot, nret, channel, omega, Cout, ldc, work, work + mm,
                   work + 2 * mm, nullptr, work + 3 * mm, info, red, d, e, e2, beta, vv, pq, theta,
                   &flag, &npos_s);
 }
@@ -1065,24 +1072,26 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 }
 
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2,
-                         int nroot, int nret, double* omega, double* Cout, int ldc, double* work,
-                         int* info, hipStream_t s) {
-  if (m > JMAX || nret > m || nroot > nret) return hipErrorInvalidValue;
+                         int nroot, int nret, int channel, double* omega, double* Cout, int ldc,
+                         double* work, int* info, hipStream_t s) {
+  if (m > JMAX || nret > m || nroot > nret || (channel != 0 && channel != 1))
+    return hipErrorInvalidValue;
   if (m <= PLDS)
     hipLaunchKernelGGL(k_pencil_tri, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
-                       omega, Cout, ldc, work, info);
+                       channel, omega, Cout, ldc, work, info);
   else
     hipLaunchKernelGGL(k_pencil_tri_l2, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
-                       omega, Cout, ldc, work, info);
+                       channel, omega, Cout, ldc, work, info);
   return hipGetLastError();
 }
 
 hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
-                                double* omega, double* Cout, int ldc, double* work, int* info,
-                                hipStream_t s) {
-  if (m > JMAX || nroot > 64 || nroot > m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_direct_pencil, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, nroot, omega, Cout,
-                     ldc, work, info);
+                                int channel, double* omega, double* Cout, int ldc, double* work,
+                                int* info, hipStream_t s) {
+  if (m > JMAX || nroot > 64 || nroot > m || (channel != 0 && channel != 1))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_direct_pencil, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, nroot, channel,
+                     omega, Cout, ldc, work, info);
   return hipGetLastError();
 }
 

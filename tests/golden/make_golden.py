@@ -5,6 +5,7 @@ paper prints no worked example for this path, so every stored value here is the 
 
     python tests/golden/make_golden.py small      # 5 x 20 x 100, seeds 0-4, both spins (seconds)
     python tests/golden/make_golden.py davidson   # 20 x 200 x 700, seed 0, both spins (minutes)
+    python tests/golden/make_golden.py hh         # the same, hh channel (minutes)
 """
 import json
 import os
@@ -20,9 +21,10 @@ from oracle import pprpa_oracle as O  # noqa: E402
 from workloads import gen  # noqa: E402
 
 
-def run(name, nocc, nvir, naux, seeds, mults, nroot):
+def run(name, nocc, nvir, naux, seeds, mults, nroot, channel="pp"):
     out = dict(
         source="oracle/pprpa_oracle.py, dense build + route D (Cholesky of M - 2 mu W, eigh)",
+        channel=channel,
         inputs=f"workloads/gen.py: orbital_energies(seed, {nocc}, {nvir}), lpq_full(seed, {nocc + nvir}, {naux})",
         units="Hartree", nocc=nocc, nvir=nvir, naux=naux, nroot=nroot, roots={})
     for seed in seeds:
@@ -30,7 +32,7 @@ def run(name, nocc, nvir, naux, seeds, mults, nroot):
         L = gen.lpq_full(seed, nocc + nvir, naux)
         for mult in mults:
             t = time.time()
-            om = O.solve(eps, L, nocc, mult, nroot)
+            om = O.solve(eps, L, nocc, mult, nroot, channel=channel)
             out["roots"][f"{seed}/{mult}"] = [float(x) for x in om]
             print(name, seed, mult, f"{time.time() - t:.1f}s", om[:3], flush=True)
     with open(os.path.join(HERE, f"{name}.json"), "w") as f:
@@ -43,3 +45,5 @@ if __name__ == "__main__":
         run("small_direct", 5, 20, 100, (0, 1, 2, 3, 4), ("singlet", "triplet"), 5)
     if "davidson" in which:
         run("davidson_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10)
+    if "hh" in which:
+        run("davidson_hh_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10, channel="hh")

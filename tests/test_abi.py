@@ -99,3 +99,35 @@ def test_server_argument_checks():
     st = B.ServingStats()
     assert L.pprpa_server_stats(None, C.byref(st)) == B.EINVAL
     L.pprpa_server_destroy(None)
+
+
+STRUCTS = [("pprpa_build_args", "BuildArgs"), ("pprpa_davidson_args", "DavidsonArgs"),
+           ("pprpa_report", "Report"), ("pprpa_kernel_stats", "KernelStats"),
+           ("pprpa_request_info", "RequestInfo"), ("pprpa_serving_stats", "ServingStats")]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every field of the header's argument/result structs sits at the same offset in the
+    binding's ctypes mirror, and the sizes agree (compiled against include/pprpa.h with gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pprpa.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS:
+        lines.append(f'  printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for f, _ in getattr(B, pyname)._fields_:
+            lines.append(f'  printf("{pyname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        pyname, field, val = line.split()
+        cls = getattr(B, pyname)
+        got = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), (pyname, field, got, int(val))
+
