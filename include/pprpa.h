@@ -138,6 +138,22 @@ typedef struct {
 pprpa_status pprpa_davidson(pprpa_ctx* ctx, const pprpa_davidson_args* args, double* omega,
                             double* vecs, double* resid, pprpa_report* rep);
 
+/* ppRPA correlation energy (section "Total Energy", Eq. correlation_energy) of the context's
+ * spin block from the whole spectrum of the dense pencil (eigenvalues only, on the device):
+ * ec_pp = sum of the pp roots - Tr A and, from the same spectrum, ec_hh = -(sum of the hh
+ * roots) - Tr C; the two agree by the sum rule of the method, their difference measures the
+ * eigenvalue accuracy. For a closed shell the total is E(singlet) + 3 E(triplet).
+ * Requires dense=1 at build and n <= 512 (else EUNSUPPORTED). ENONDEF if M - 2 mu W is not
+ * positive definite or the spectrum does not split into n_pp pp and n_hh hh roots (out is
+ * still filled in the latter case). The call allocates 3 n^2 doubles of device scratch. */
+typedef struct {
+  double ec_pp;         /* sum(Omega_pp) - Tr A                                             */
+  double ec_hh;         /* -sum(Omega_hh) - Tr C                                            */
+  double trace_a, trace_c;
+  int32_t n_pp_roots, n_hh_roots;
+} pprpa_corr_energy;
+pprpa_status pprpa_correlation_energy(pprpa_ctx* ctx, pprpa_corr_energy* out);
+
 /* Timing of the sigma contraction kernel (the fused sandwich kernel only, without the unpack
  * and epilogue kernels), measured with HIP events recorded on the context's stream around
  * every launch since the last reset. flops and bytes are algorithmic counts: per vector

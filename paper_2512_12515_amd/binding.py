@@ -68,6 +68,14 @@ class KernelStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CorrEnergy(C.Structure):
+    _fields_ = [("ec_pp", C.c_double), ("ec_hh", C.c_double), ("trace_a", C.c_double),
+                ("trace_c", C.c_double), ("n_pp_roots", C.c_int32), ("n_hh_roots", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class RequestInfo(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("nroot", C.c_int32),
                 ("reserved_", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
@@ -119,6 +127,8 @@ def lib():
     L.pprpa_davidson.argtypes = [C.c_void_p, C.POINTER(DavidsonArgs), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.POINTER(Report)]
     L.pprpa_davidson.restype = C.c_int
+    L.pprpa_correlation_energy.argtypes = [C.c_void_p, C.POINTER(CorrEnergy)]
+    L.pprpa_correlation_energy.restype = C.c_int
     L.pprpa_sigma_stats.argtypes = [C.c_void_p, C.POINTER(KernelStats), C.c_int32]
     L.pprpa_sigma_stats.restype = C.c_int
     L.pprpa_free.argtypes = [C.c_void_p]
@@ -238,6 +248,14 @@ class PpRPA:
         st = KernelStats()
         _check(lib().pprpa_sigma_stats(self._h, C.byref(st), int(bool(reset))))
         return st.as_dict()
+
+    def correlation_energy(self):
+        """ppRPA correlation energy of this spin block from the whole spectrum of the dense
+        pencil (requires dense=True and n <= 512): both sides of the sum rule, ec_pp = sum of
+        the pp roots - Tr A and ec_hh = -(sum of the hh roots) - Tr C, and the root counts."""
+        out = CorrEnergy()
+        _check(lib().pprpa_correlation_energy(self._h, C.byref(out)))
+        return out.as_dict()
 
     def dense_matrix(self):
         M = np.empty((self.n, self.n))

@@ -581,6 +581,66 @@ pprpa_status pprpa_dense_matrix(pprpa_ctx* c, double* M, int32_t on_device) {
   return PPRPA_OK;
 }
 
+pprpa_status pprpa_correlation_energy(pprpa_ctx* c, pprpa_corr_energy* out) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  if (!out) return einval("out is NULL");
+  if (!c->M) {
+    set_error("the correlation energy needs a dense build (dense=1)");
+    return PPRPA_EUNSUPPORTED;
+  }
+  const int64_t n = c->g.n, nvv = c->g.nvv;
+  if (n > 512) {
+    set_error("the whole-spectrum solve on the device is limited to n <= 512 (n=%lld)", (long long)n);
+    return PPRPA_EUNSUPPORTED;
+  }
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  const size_t work_bytes = 3 * (size_t)n * n * sizeof(double) + 256;
+  void* work = nullptr;
+  hipError_t e = hipMalloc(&work, work_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("correlation-energy workspace of %zu bytes: %s", work_bytes, hipGetErrorString(e));
+    return PPRPA_ENOMEM;
+  }
+  double* dout = (double*)work + 3 * (size_t)n * n;  // 4 doubles, then 3 ints
+  int* dinfo = (int*)(dout + 4);
+  double* hp = c->pinned;
+  hipError_t le = launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, (double*)work, dinfo, c->stream);
+  if (le == hipSuccess) le = hipMemcpyAsync(hp, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (le == hipSuccess) le = hipMemcpyAsync(hp + 4, dinfo, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (le == hipSuccess) le = hipStreamSynchronize(c->stream);
+  (void)hipFree(work);
+  if (le != hipSuccess) {
+    set_error("correlation energy: %s", hipGetErrorString(le));
+    return PPRPA_EDEVICE;
+  }
+  const int* info = (const int*)(hp + 4);
+  if (info[0] == 1) {
+    set_error("M - 2 mu W is not positive definite");
+    return PPRPA_ENONDEF;
+  }
+  pprpa_corr_energy r{};
+  r.ec_pp = hp[0];
+  r.ec_hh = hp[1];
+  r.trace_a = hp[2];
+  r.trace_c = hp[3];
+  r.n_pp_roots = info[1];
+  r.n_hh_roots = info[2];
+  *out = r;
+  if (info[1] != nvv || info[2] != n - nvv) {
+    set_error("the spectrum splits into %d pp and %d hh roots, not %lld and %lld", info[1], info[2],
+              (long long)nvv, (long long)(n - nvv));
+    return PPRPA_ENONDEF;
+  }
+  return PPRPA_OK;
+}
+
 pprpa_status pprpa_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
                             double* vecs, double* resid, pprpa_report* rep) {
   g_err.clear();

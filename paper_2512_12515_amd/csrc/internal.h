@@ -148,6 +148,11 @@ hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, dou
 hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
                                 int channel, double* omega, double* Cout, int ldc, double* work,
                                 int* info, hipStream_t s);
+// Whole spectrum of the dense pencil (M, W) for m <= 512 (eigenvalues only): out[0] = sum of the
+// pp roots - Tr A, out[1] = -(sum of the hh roots) - Tr C, out[2] = Tr A, out[3] = Tr C;
+// info: [0] 0 ok / 1 not definite, [1] pp roots, [2] hh roots. work: 3 m^2 doubles.
+hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2, double* out,
+                                double* work, int* info, hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

@@ -322,7 +322,7 @@ __global__ void k_fill(double* __restrict__ p, size_t n, double v) {
 // One-workgroup dense kernels (1024 threads). Matrices live in global memory (L2-resident).
 // ------------------------------------------------------------------------------------------
 constexpr int WG = 1024;
-constexpr int JMAX = 512;  // largest matrix order handled by the Jacobi solver
+constexpr int JMAX = 512;  // largest matrix order of the one-workgroup dense solvers
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -762,35 +762,21 @@ __device__ __forceinline__ void tri_outputs(const double* Ri, const double* X, c
   }
 }
 
-// Direct path: M (n x n, full, ld m), W = diag(+1 for i < nvv, -1). work: 3 m^2 + 4 nroot m.
-__global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
-                                                      int64_t nvv, double mu2, int nroot,
-                                                      int channel, double* __restrict__ omega,
-                                                      double* __restrict__ Cout, int ldc,
-                                                      double* __restrict__ work,
-                                                      int* __restrict__ info) {
-  __shared__ double red[WG];
-  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
-  __shared__ double theta[64];
-  __shared__ int flag, npos_s;
+// Dense pencil (M, W), W = diag(+1 for i < nvv, -1), brought to tridiagonal form: K = M - 2 mu W
+// = R R^T (Cholesky, A), Ri = R^-1, G = R^-1 W R^-T (Householder reflections kept in G), T in
+// (d, e). Returns false (uniform) if K is not positive definite. work: A, Ri, G (3 m^2).
+__device__ __forceinline__ bool dense_pencil_tridiag(const double* __restrict__ M, int m,
+                                                     int64_t nvv, double mu2, double* A,
+                                                     double* Ri, double* G, double* d, double* e,
+                                                     double* beta, double* vv, double* pq,
+                                                     double* red, int* flag) {
   const int t = threadIdx.x;
-  double* A = work;                        // K, then R (lower)
-  double* Ri = work + (size_t)m * m;       // R^-1 (lower)
-  double* G = work + 2 * (size_t)m * m;    // G, then the reflection vectors
-  double* X = work + 3 * (size_t)m * m;    // vectors and inverse-iteration scratch
   for (int e_ = t; e_ < m * m; e_ += WG) {
     const int i = e_ / m, j = e_ % m;
     A[e_] = M[(size_t)i * m + j] - (i == j ? mu2 * (i < nvv ? 1.0 : -1.0) : 0.0);
   }
   __syncthreads();
-  if (!tri_cholesky(A, m, &flag)) {
-    if (t == 0) {
-      info[0] = 1;
-      info[1] = 0;
-      info[2] = 0;
-    }
-    return;
-  }
+  if (!tri_cholesky(A, m, flag)) return false;
   tri_inverse(A, Ri, m);
   // G = R^-1 W R^-T with W diagonal (both triangles)
   for (int e_ = t; e_ < m * m; e_ += WG) {
@@ -803,9 +789,114 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
   }
   __syncthreads();
   tri_householder(G, m, d, e, beta, vv, pq, red);
+  return true;
+}
+
+// Direct path: M (n x n, full, ld m), W = diag(+1 for i < nvv, -1). work: 3 m^2 + 4 nroot m.
+__global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
+                                                      int64_t nvv, double mu2, int nroot,
+                                                      int channel, double* __restrict__ omega,
+                                                      double* __restrict__ Cout, int ldc,
+                                                      double* __restrict__ work,
+                                                      int* __restrict__ info) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double theta[64];
+  __shared__ int flag, npos_s;
+  double* A = work;                        // K, then R (lower)
+  double* Ri = work + (size_t)m * m;       // R^-1 (lower)
+  double* G = work + 2 * (size_t)m * m;    // G, then the reflection vectors
+  double* X = work + 3 * (size_t)m * m;    // vectors and inverse-iteration scratch
+  if (!dense_pencil_tridiag(M, m, nvv, mu2, A, Ri, G, d, e, beta, vv, pq, red, &flag)) {
+    if (threadIdx.x == 0) {
+      info[0] = 1;
+      info[1] = 0;
+      info[2] = 0;
+    }
+    return;
+  }
   tri_eigen(d, e, e2, m, nroot, channel, theta, &npos_s, X, red);
   tri_back_transform(G, m, beta, X, nroot);
   tri_outputs(Ri, X, theta, m, nroot, nroot, npos_s, mu2, omega, Cout, ldc, info);
+}
+
+// Correlation energy from the whole spectrum of the dense pencil (section "Total Energy", Eq.
+// correlation_energy): every eigenvalue theta of T by bisection (thread t: ascending indices t,
+// t + WG, ...), Omega = 2 mu + 1/theta; out[0] = sum over theta > 0 of Omega - Tr A, out[1] =
+// -(sum over theta < 0 of Omega) - Tr C (the two sides of the sum rule), out[2] = Tr A,
+// out[3] = Tr C. info: [0] 0 ok / 1 not definite, [1] roots with theta > 0, [2] with theta < 0.
+// Sums in a fixed order (deterministic). work: 3 m^2.
+__global__ __launch_bounds__(WG) void k_pencil_energy(const double* __restrict__ M, int m,
+                                                      int64_t nvv, double mu2,
+                                                      double* __restrict__ out,
+                                                      double* __restrict__ work,
+                                                      int* __restrict__ info) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ int flag;
+  const int t = threadIdx.x;
+  double* A = work;
+  double* Ri = work + (size_t)m * m;
+  double* G = work + 2 * (size_t)m * m;
+  if (!dense_pencil_tridiag(M, m, nvv, mu2, A, Ri, G, d, e, beta, vv, pq, red, &flag)) {
+    if (t == 0) {
+      info[0] = 1;
+      info[1] = 0;
+      info[2] = 0;
+    }
+    return;
+  }
+  for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
+  double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
+  for (int i = t; i < m; i += WG) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
+    lo_p = fmin(lo_p, d[i] - r);
+    hi_p = fmax(hi_p, d[i] + r);
+    nrm_p = fmax(nrm_p, fabs(d[i]) + r);
+  }
+  const double gmin = block_reduce(lo_p, red, false);
+  const double gmax = block_reduce(hi_p, red, true);
+  const double tnorm = fmax(block_reduce(nrm_p, red, true), 1e-300);
+  const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
+  double spp = 0.0, shh = 0.0, npp = 0.0, nhh = 0.0, tra = 0.0, trc = 0.0;
+  for (int idx = t; idx < m; idx += WG) {
+    double lo = gmin - 1e-12 * tnorm, hi = gmax + 1e-12 * tnorm;
+    for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_below(d, e2, m, mid, tiny) <= idx)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const double th = 0.5 * (lo + hi);
+    const double om = mu2 + 1.0 / th;
+    if (th > 0.0) {
+      spp += om;
+      npp += 1.0;
+    } else {
+      shh += om;
+      nhh += 1.0;
+    }
+  }
+  for (int i = t; i < m; i += WG) {
+    if (i < nvv)
+      tra += M[(size_t)i * m + i];
+    else
+      trc += M[(size_t)i * m + i];
+  }
+  const double SPP = block_sum(spp, red), SHH = block_sum(shh, red);
+  const double NPP = block_sum(npp, red), NHH = block_sum(nhh, red);
+  const double TA = block_sum(tra, red), TC = block_sum(trc, red);
+  if (t == 0) {
+    out[0] = SPP - TA;
+    out[1] = -SHH - TC;
+    out[2] = TA;
+    out[3] = TC;
+    info[0] = 0;
+    info[1] = (int)NPP;
+    info[2] = (int)NHH;
+  }
 }
 
 // Davidson pencil: Ms, Ws upper triangles (ld ldm). nret columns of Cout (the nroot wanted and
@@ -1092,6 +1183,13 @@ hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2,
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_direct_pencil, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, nroot, channel,
                      omega, Cout, ldc, work, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2, double* out,
+                                double* work, int* info, hipStream_t s) {
+  if (m < 1 || m > JMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pencil_energy, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, out, work, info);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@ paper prints no worked example for this path, so every stored value here is the 
     python tests/golden/make_golden.py small      # 5 x 20 x 100, seeds 0-4, both spins (seconds)
     python tests/golden/make_golden.py davidson   # 20 x 200 x 700, seed 0, both spins (minutes)
     python tests/golden/make_golden.py hh         # the same, hh channel (minutes)
+    python tests/golden/make_golden.py energy     # correlation energies, 5 x 20 x 100 (seconds)
 """
 import json
 import os
@@ -39,11 +40,37 @@ def run(name, nocc, nvir, naux, seeds, mults, nroot, channel="pp"):
         json.dump(out, f, indent=1)
 
 
+def run_energy(name, nocc, nvir, naux, seeds):
+    """Correlation energy of Eq. correlation_energy per spin block, from the oracle's whole
+    spectrum (both sides of the sum rule), and the closed-shell total E_s + 3 E_t."""
+    out = dict(source="oracle/pprpa_oracle.py: dense build, route D full spectrum, correlation_energy",
+               inputs=f"workloads/gen.py: orbital_energies(seed, {nocc}, {nvir}), lpq_full(seed, {nocc + nvir}, {naux})",
+               units="Hartree", nocc=nocc, nvir=nvir, naux=naux, energies={})
+    for seed in seeds:
+        eps = gen.orbital_energies(seed, nocc, nvir)
+        L = gen.lpq_full(seed, nocc + nvir, naux)
+        sp = O.active_space(eps, L, nocc)
+        e = {}
+        for mult in ("singlet", "triplet"):
+            A, B, C = O.build_matrices(sp, mult)
+            M = O.pprpa_matrix(A, B, C)
+            Om, Z, sg = O.solve_definite(M, A.shape[0], O.midgap(sp))
+            ec_pp, ec_hh = O.correlation_energy(Om[sg > 0], Om[sg < 0], A, C)
+            e[mult] = [float(ec_pp), float(ec_hh)]
+        e["closed_shell"] = e["singlet"][0] + 3.0 * e["triplet"][0]
+        out["energies"][str(seed)] = e
+        print(name, seed, e, flush=True)
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["small"]
     if "small" in which:
         run("small_direct", 5, 20, 100, (0, 1, 2, 3, 4), ("singlet", "triplet"), 5)
     if "davidson" in which:
         run("davidson_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10)
+    if "energy" in which:
+        run_energy("correlation_energy", 5, 20, 100, (0, 1, 2, 3, 4))
     if "hh" in which:
         run("davidson_hh_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10, channel="hh")

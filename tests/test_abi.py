@@ -103,7 +103,8 @@ def test_server_argument_checks():
 
 STRUCTS = [("pprpa_build_args", "BuildArgs"), ("pprpa_davidson_args", "DavidsonArgs"),
            ("pprpa_report", "Report"), ("pprpa_kernel_stats", "KernelStats"),
-           ("pprpa_request_info", "RequestInfo"), ("pprpa_serving_stats", "ServingStats")]
+           ("pprpa_request_info", "RequestInfo"), ("pprpa_serving_stats", "ServingStats"),
+           ("pprpa_corr_energy", "CorrEnergy")]
 
 
 def test_struct_layouts_match_header(tmp_path):
