@@ -15,12 +15,17 @@ It is the plain definition written out in NumPy/SciPy, FP64 throughout:
 * the normalisation X^T X - Y^T Y = +1 (pp) / -1 (hh) of Eq. xy_norm;
 * the correlation energy sum(Omega_pp) - Tr A = -sum(Omega_hh) - Tr C of
   Eq. correlation_energy (section "Total Energy");
+* the natural transition orbitals (section "Natural Transition Orbital", Eqs. nto_pp and
+  nto_hh) and the two-electron part of the density matrix (section "Density Matrix");
 * the canonical active window (section "ppRPA Equation", last paragraph; section
   "Implementation Details"): the highest occupied and lowest virtual orbitals.
 
 Readings where the paper is silent (listed with reasons in the design notes):
 * pair order: upper triangle, row-major; singlet (p <= q), triplet (p < q); z = [x; y];
 * "lowest roots" are the smallest Omega among eigenvectors with z^T W z = +1;
+* the NTO amplitude matrices are the packed amplitudes placed on the upper triangle (p <= q,
+  p < q for the triplet), as the section describes them; the weights are the squared singular
+  values, so sum(lam^p) - sum(lam^h) = x^T x - y^T y;
 * the hh channel (two-electron removal, z^T W z = -1) returns the roots nearest the gap, i.e.
   the largest Omega_hh first (the states of the (N-2)-electron system closest to its ground
   state);
@@ -262,6 +267,40 @@ def hh_nearest(Omega, Z, sign, nroot):
 def correlation_energy(Omega_pp, Omega_hh, A, C):
     """Both expressions of Eq. correlation_energy: (sum pp - Tr A, -sum hh - Tr C)."""
     return np.sum(Omega_pp) - np.trace(A), -np.sum(Omega_hh) - np.trace(C)
+
+
+# ----------------------------------------------------------------------------------------
+# Natural transition orbitals and the two-electron density matrix of a root
+# ----------------------------------------------------------------------------------------
+
+def triangular(v, n, mult):
+    """The packed pair amplitudes v (pair order of ``pairs``) as the n x n triangular matrix of
+    section "Natural Transition Orbital": entry (p, q) for every packed pair, zero elsewhere."""
+    T = np.zeros((n, n))
+    p, q = pairs(n, mult)
+    T[p, q] = v
+    return T
+
+
+def nto(z, nv, no, mult):
+    """NTOs of one root z = [x; y] (Eqs. nto_pp, nto_hh): the SVDs X = C^p1 sqrt(lam^p) C^p2^T
+    and Y = C^h1 sqrt(lam^h) C^h2^T of the triangular matrices. Returns the weights lam^p (nv)
+    and lam^h (no), descending, and the coefficient matrices (C^p1, C^p2, C^h1, C^h2)."""
+    nvv = pairs(nv, mult)[0].size
+    X = triangular(z[:nvv], nv, mult)
+    Y = triangular(z[nvv:], no, mult)
+    U, sx, Vt = np.linalg.svd(X)
+    Uh, sy, Vht = np.linalg.svd(Y)
+    return sx ** 2, sy ** 2, (U, Vt.T, Uh, Vht.T)
+
+
+def density_2e(z, nv, no, mult):
+    """Two-electron addition/removal part of the one-particle density matrix of a root (section
+    "Density Matrix"): D_ab = [X X^T + X^T X]_ab, D_ij = -[Y Y^T + Y^T Y]_ij."""
+    nvv = pairs(nv, mult)[0].size
+    X = triangular(z[:nvv], nv, mult)
+    Y = triangular(z[nvv:], no, mult)
+    return X @ X.T + X.T @ X, -(Y @ Y.T + Y.T @ Y)
 
 
 # ----------------------------------------------------------------------------------------

@@ -12,6 +12,8 @@ P6  second order: with A/C interactions off and L_vo scaled by lam,
 P7  two electrons: with no occupied orbitals the singlet and triplet A spectra together are
     the spectrum of the two-electron CI Hamiltonian (Slater-Condon).
 P8  the factorised sigma equals the dense M z; route D equals route G.
+NTO the natural transition orbital weights and the two-electron density matrix: L = 0 closed
+    form, the weight sum rule and Tr D = +-2 (Eq. dm_constrain) on every root.
 hh  the removal channel's selection: L = 0 closed form (highest e_i + e_j first), B = 0 against
     -eigvalsh(C), the subset solve against the full spectrum.
 Plus mutation checks: plausible mistakes planted in a copy of the oracle fail a pin.
@@ -215,6 +217,61 @@ def test_hh_subset_route_matches_full(mult):
     w = O.metric(nvv, M.shape[0] - nvv)
     assert np.allclose(M @ Z5, (w[:, None] * Z5) * Om5[None, :], atol=1e-10)
     assert np.allclose(np.einsum("i,ij,ij->j", w, Z5, Z5), -1.0, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------------------
+# NTOs and the two-electron density matrix
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mult", MULTS)
+def test_nto_zero_interaction_closed_form(mult):
+    """L = 0: a pp root is a unit vector on one pair (a, b): one NTO pair of weight 1, and the
+    density block is E_aa + E_bb (D = 2 E_aa for a = b); an hh root likewise with -1."""
+    nocc, nvir, naux = 4, 7, 5
+    eps = gen.orbital_energies(5, nocc, nvir)
+    L = np.zeros((naux, nocc + nvir, nocc + nvir))
+    sp = O.active_space(eps, L, nocc)
+    A, B, C, M, Om, Z, sg = full_spectrum(sp, mult)
+    nvv = A.shape[0]
+    for j in range(Z.shape[1]):
+        z = O.fix_sign(Z[:, j:j + 1])[:, 0]
+        lp, lh, _ = O.nto(z, nvir, nocc, mult)
+        Dv, Do = O.density_2e(z, nvir, nocc, mult)
+        k = int(np.argmax(np.abs(z)))
+        if sg[j] > 0:
+            pa, pb = O.pairs(nvir, mult)
+            a, b = pa[k], pb[k]
+            assert np.allclose(lp, np.r_[1.0, np.zeros(nvir - 1)], atol=1e-14) and np.allclose(lh, 0.0)
+            ref = np.zeros((nvir, nvir))
+            ref[a, a] += 1.0
+            ref[b, b] += 1.0
+            assert np.allclose(Dv, ref, atol=1e-14) and np.allclose(Do, 0.0)
+        else:
+            pi, pj = O.pairs(nocc, mult)
+            i, jj = pi[k - nvv], pj[k - nvv]
+            assert np.allclose(lh, np.r_[1.0, np.zeros(nocc - 1)], atol=1e-14) and np.allclose(lp, 0.0)
+            ref = np.zeros((nocc, nocc))
+            ref[i, i] -= 1.0
+            ref[jj, jj] -= 1.0
+            assert np.allclose(Do, ref, atol=1e-14) and np.allclose(Dv, 0.0)
+
+
+@pytest.mark.parametrize("mult", MULTS)
+def test_nto_weight_and_density_sum_rules(mult):
+    """Every root: sum(lam^p) - sum(lam^h) = +1 (pp) / -1 (hh) (NTO section) and
+    Tr D^2e = +2 / -2 (Eq. dm_constrain); the SVD factors reproduce X and Y."""
+    eps, L, sp = make_sp(6, 5, 12, 40)
+    A, B, C, M, Om, Z, sg = full_spectrum(sp, mult)
+    for j in range(Z.shape[1]):
+        z = Z[:, j]
+        lp, lh, (U, V, Uh, Vh) = O.nto(z, 12, 5, mult)
+        assert abs(lp.sum() - lh.sum() - sg[j]) <= 1e-12
+        Dv, Do = O.density_2e(z, 12, 5, mult)
+        assert abs(np.trace(Dv) + np.trace(Do) - 2.0 * sg[j]) <= 1e-12
+        nvv = A.shape[0]
+        X = O.triangular(z[:nvv], 12, mult)
+        assert np.allclose(U @ np.diag(np.sqrt(lp)) @ V.T, X, atol=1e-13)
+        assert np.all(np.diff(lp) <= 1e-15) and np.all(lp >= 0.0)
 
 
 def test_active_window_equals_oracle_on_sliced_input():
