@@ -271,6 +271,27 @@ def correlation_energy(P, gen, reps=10):
             "max_err_ha_vs_oracle": max(errs), "max_sum_rule_gap_ha": max(gaps)}
 
 
+def nto_analysis(P, eps_d, L_d, nocc, nroot, block, tol, reps=5):
+    """NTO weights and two-electron density blocks of the nroot singlet pp roots of the FP64
+    Davidson workload (vectors handed over from the host, density blocks copied back): time per
+    call and the largest deviations from the sum rules sum lam^p - sum lam^h = 1, Tr D = 2."""
+    with P.PpRPA(eps_d, L_d, nocc, mult="singlet", max_block=block) as ctx:
+        r = ctx.davidson(nroot, block=block, tol=tol, vectors=True)
+        ctx.nto(r["vecs"])
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = ctx.nto(r["vecs"])
+            t.append(time.perf_counter() - t0)
+    w = res["lam_p"].sum(axis=1) - res["lam_h"].sum(axis=1)
+    tr = np.trace(res["d_vv"], axis1=1, axis2=2) + np.trace(res["d_oo"], axis1=1, axis2=2)
+    return {"workload": f"{nroot} singlet pp roots, nv {ctx.nv}, no {ctx.no}, weights + density blocks",
+            "ms_per_call_p50": 1e3 * float(np.median(t)),
+            "max_weight_sum_rule_dev": float(np.max(np.abs(w - 1.0))),
+            "max_trace_rule_dev": float(np.max(np.abs(tr - 2.0))),
+            "leading_weight_root0": float(res["lam_p"][0, 0])}
+
+
 def hh_channel(P, eps_d, L_d, nocc, nroot, block, tol, reps=2):
     """The hh channel (two-electron removal roots nearest the gap) on the FP64 Davidson workload:
     singlet and triplet solved one after the other, reps times; sigma products per second,
@@ -530,6 +551,8 @@ def main():
     if (nocc, nvir, naux) == (20, 200, 700):
         log("hh channel ...")
         line["hh_channel"] = hh_channel(P, eps_d, L_d, nocc, args.nroot, args.block, args.tol)
+        log("NTO analysis ...")
+        line["nto_analysis"] = nto_analysis(P, eps_d, L_d, nocc, args.nroot, args.block, args.tol)
     if not args.no_precision:
         log("precision study ...")
         line["precision"] = precision_study(P, gen)

@@ -154,6 +154,19 @@ typedef struct {
 } pprpa_corr_energy;
 pprpa_status pprpa_correlation_energy(pprpa_ctx* ctx, pprpa_corr_energy* out);
 
+/* Natural transition orbital weights (section "Natural Transition Orbital", Eqs. nto_pp and
+ * nto_hh) and the two-electron part of the one-particle density matrix (section "Density
+ * Matrix") of k roots z ([k][n] packed FP64, host or device per on_device, e.g. the vectors of
+ * pprpa_davidson). The amplitudes of each root are placed on the upper triangle of an nv x nv
+ * matrix X (pp pairs) and an no x no matrix Y (hh pairs), nv and no being the active window's;
+ * lam_p [k][nv] and lam_h [k][no] (host) receive the squared singular values of X and Y,
+ * descending (sum lam_p - sum lam_h = z^T W z = +1 for a pp root, -1 for an hh root);
+ * d_vv [k][nv][nv] = X X^T + X^T X and d_oo [k][no][no] = -(Y Y^T + Y^T Y) (host, may be NULL;
+ * trace of the pair = +-2). 1 <= k <= 64, nv, no <= 512 (else EINVAL / EUNSUPPORTED). The call
+ * allocates its device scratch (about 3 k (nv^2 + no^2) doubles) and frees it before returning. */
+pprpa_status pprpa_nto(pprpa_ctx* ctx, int32_t k, const double* z, int32_t on_device,
+                       double* lam_p, double* lam_h, double* d_vv, double* d_oo);
+
 /* Timing of the sigma contraction kernel (the fused sandwich kernel only, without the unpack
  * and epilogue kernels), measured with HIP events recorded on the context's stream around
  * every launch since the last reset. flops and bytes are algorithmic counts: per vector

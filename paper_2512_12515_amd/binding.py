@@ -127,6 +127,9 @@ def lib():
     L.pprpa_davidson.argtypes = [C.c_void_p, C.POINTER(DavidsonArgs), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.POINTER(Report)]
     L.pprpa_davidson.restype = C.c_int
+    L.pprpa_nto.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_void_p]
+    L.pprpa_nto.restype = C.c_int
     L.pprpa_correlation_energy.argtypes = [C.c_void_p, C.POINTER(CorrEnergy)]
     L.pprpa_correlation_energy.restype = C.c_int
     L.pprpa_sigma_stats.argtypes = [C.c_void_p, C.POINTER(KernelStats), C.c_int32]
@@ -208,6 +211,12 @@ class PpRPA:
         self.n_pp, self.n_hh = npp.value, nhh.value
         self.n = self.n_pp + self.n_hh
         self.mult, self.prec = mult, prec
+        # orbitals of the active window (all virtual / occupied orbitals without one)
+        self.nv = int(nvir_act) if nvir_act else a.nmo - a.nocc
+        self.no = int(nocc_act) if nocc_act else a.nocc
+
+    def _dims_active(self):
+        return self.nv, self.no
 
     def close(self):
         if getattr(self, "_h", None):
@@ -256,6 +265,25 @@ class PpRPA:
         out = CorrEnergy()
         _check(lib().pprpa_correlation_energy(self._h, C.byref(out)))
         return out.as_dict()
+
+    def nto(self, z, density=True):
+        """NTO weights and two-electron density blocks of the packed roots z ([k][n], e.g. the
+        vectors of davidson(..., vectors=True)): lam_p [k][nv], lam_h [k][no] (squared singular
+        values of the triangular amplitude matrices, descending), and with density=True
+        d_vv [k][nv][nv], d_oo [k][no][no]."""
+        on_dev = _is_torch(z) and z.is_cuda
+        if not on_dev:
+            z = np.ascontiguousarray(np.atleast_2d(z), dtype=np.float64)
+        k = int(z.shape[0])
+        nv, no = self._dims_active()
+        lam_p, lam_h = np.empty((k, nv)), np.empty((k, no))
+        d_vv = np.empty((k, nv, nv)) if density else None
+        d_oo = np.empty((k, no, no)) if density else None
+        _check(lib().pprpa_nto(self._h, k, _ptr(z, on_dev), int(on_dev), lam_p.ctypes.data,
+                               lam_h.ctypes.data if no else None,
+                               d_vv.ctypes.data if density else None,
+                               d_oo.ctypes.data if (density and no) else None))
+        return dict(lam_p=lam_p, lam_h=lam_h, d_vv=d_vv, d_oo=d_oo)
 
     def dense_matrix(self):
         M = np.empty((self.n, self.n))

@@ -641,6 +641,66 @@ pprpa_status pprpa_correlation_energy(pprpa_ctx* c, pprpa_corr_energy* out) {
   return PPRPA_OK;
 }
 
+pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_device, double* lam_p,
+                       double* lam_h, double* d_vv, double* d_oo) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  if (!z || !lam_p || (!lam_h && c->g.no > 0)) return einval("z, lam_p and lam_h must not be NULL");
+  if (k < 1 || k > 64) return einval("k=%d outside [1, 64]", k);
+  const Geometry& g = c->g;
+  if (g.nv > 512 || g.no > 512) {
+    set_error("NTOs on the device are limited to nv, no <= 512 (nv=%d, no=%d)", g.nv, g.no);
+    return PPRPA_EUNSUPPORTED;
+  }
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  const size_t zv = (size_t)k * g.n, mv = (size_t)k * g.nv * g.nv, mo = (size_t)k * g.no * g.no;
+  const size_t lv = (size_t)k * g.nv, lo = (size_t)k * g.no;
+  // z (when on the host), X, Y, Gx, Gy, Dv, Do, lam_p, lam_h
+  const size_t total = (on_device ? 0 : zv) + 3 * mv + 3 * mo + lv + lo;
+  double* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, std::max<size_t>(total, 1) * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("NTO workspace of %zu bytes: %s", total * sizeof(double), hipGetErrorString(e));
+    return PPRPA_ENOMEM;
+  }
+  double* p = buf;
+  const double* dz = z;
+  if (!on_device) {
+    dz = p;
+    p += zv;
+  }
+  double* X = p; p += mv;
+  double* Gx = p; p += mv;
+  double* Dv = p; p += mv;
+  double* Y = p; p += mo;
+  double* Gy = p; p += mo;
+  double* Do = p; p += mo;
+  double* lp = p; p += lv;
+  double* lh = p;
+  hipStream_t s = c->stream;
+  hipError_t le = hipSuccess;
+  if (!on_device) le = hipMemcpyAsync((void*)dz, z, zv * sizeof(double), hipMemcpyHostToDevice, s);
+  if (le == hipSuccess)
+    le = launch_nto(dz, g.n, k, g, c->ptab, X, Y, Gx, Gy, Dv, Do, lp, lh, s);
+  if (le == hipSuccess) le = hipMemcpyAsync(lam_p, lp, lv * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && lo) le = hipMemcpyAsync(lam_h, lh, lo * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && d_vv) le = hipMemcpyAsync(d_vv, Dv, mv * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && d_oo && mo) le = hipMemcpyAsync(d_oo, Do, mo * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess) le = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (le != hipSuccess) {
+    set_error("NTO analysis: %s", hipGetErrorString(le));
+    return PPRPA_EDEVICE;
+  }
+  return PPRPA_OK;
+}
+
 pprpa_status pprpa_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
                             double* vecs, double* resid, pprpa_report* rep) {
   g_err.clear();

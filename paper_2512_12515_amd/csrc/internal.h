@@ -153,6 +153,13 @@ hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2,
 // info: [0] 0 ok / 1 not definite, [1] pp roots, [2] hh roots. work: 3 m^2 doubles.
 hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2, double* out,
                                 double* work, int* info, hipStream_t s);
+// NTO weights and two-electron density blocks of k packed roots Z [k][ldz] (nv, no <= 512):
+// X [k][nv][nv], Y [k][no][no] (triangular amplitude matrices), Gx, Gy (their T^T T, destroyed),
+// Dv = X X^T + X^T X, Do = -(Y Y^T + Y^T Y) (may be null), lam_p [k][nv], lam_h [k][no]
+// (squared singular values, descending).
+hipError_t launch_nto(const double* Z, int64_t ldz, int k, const Geometry& g, const int* ptab,
+                      double* X, double* Y, double* Gx, double* Gy, double* Dv, double* Do,
+                      double* lam_p, double* lam_h, hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

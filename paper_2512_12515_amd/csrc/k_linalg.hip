@@ -899,6 +899,79 @@ __global__ __launch_bounds__(WG) void k_pencil_energy(const double* __restrict__
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Natural transition orbitals and the two-electron density matrix of k roots
+// ------------------------------------------------------------------------------------------
+// Packed amplitudes onto the triangular matrices X [k][nv][nv] (pp pairs) and Y [k][no][no]
+// (hh pairs), which are zero beforehand: entry (p, q) of every packed pair.
+__global__ void k_unpack_triangular(const double* __restrict__ Z, int64_t ldz, int64_t n,
+                                    int64_t nvv, int nv, int no, const int* __restrict__ ptab,
+                                    double* __restrict__ X, double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= n) return;
+  const int pq = ptab[e];
+  const int p = pq >> 16, q = pq & 0xFFFF;
+  const double v = Z[(int64_t)r * ldz + e];
+  if (e < nvv)
+    X[((int64_t)r * nv + p) * nv + q] = v;
+  else
+    Y[((int64_t)r * no + p) * no + q] = v;
+}
+
+// Per root (blockIdx.y): Gt = T^T T and D = sgn (T T^T + T^T T) for the m x m matrices T.
+__global__ void k_triangular_products(const double* __restrict__ T, int m, double sgn,
+                                      double* __restrict__ Gt, double* __restrict__ D) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  const double* A = T + (int64_t)r * m * m;
+  double tt = 0.0, ttt = 0.0;  // (T T^T)_ij, (T^T T)_ij
+  for (int c = 0; c < m; ++c) {
+    tt += A[i * m + c] * A[j * m + c];
+    ttt += A[c * m + i] * A[c * m + j];
+  }
+  Gt[(int64_t)r * m * m + e] = ttt;
+  if (D) D[(int64_t)r * m * m + e] = sgn * (tt + ttt);
+}
+
+// Eigenvalues of the symmetric m x m matrices G (one workgroup per matrix, blockIdx.x; G is
+// overwritten by the Householder reflections), descending and clamped at zero (they are
+// squared singular values): lam [k][m].
+__global__ __launch_bounds__(WG) void k_gram_eigenvalues(double* __restrict__ Gall, int m,
+                                                         double* __restrict__ lam) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  const int t = threadIdx.x;
+  double* G = Gall + (int64_t)blockIdx.x * m * m;
+  tri_householder(G, m, d, e, beta, vv, pq, red);
+  for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
+  double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
+  for (int i = t; i < m; i += WG) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
+    lo_p = fmin(lo_p, d[i] - r);
+    hi_p = fmax(hi_p, d[i] + r);
+    nrm_p = fmax(nrm_p, fabs(d[i]) + r);
+  }
+  const double gmin = block_reduce(lo_p, red, false);
+  const double gmax = block_reduce(hi_p, red, true);
+  const double tnorm = fmax(block_reduce(nrm_p, red, true), 1e-300);
+  const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
+  for (int idx = t; idx < m; idx += WG) {
+    double lo = gmin - 1e-12 * tnorm, hi = gmax + 1e-12 * tnorm;
+    for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_below(d, e2, m, mid, tiny) <= idx)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    lam[(int64_t)blockIdx.x * m + (m - 1 - idx)] = fmax(0.5 * (lo + hi), 0.0);
+  }
+}
+
 // Davidson pencil: Ms, Ws upper triangles (ld ldm). nret columns of Cout (the nroot wanted and
 // the next Ritz vectors, kept on restart). A, B, G: m x m matrices (LDS or global; G may alias A:
 // then Gt stages G), X: 4 nret m doubles of global scratch (vectors, inverse-iteration rows).
@@ -1191,6 +1264,33 @@ hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2,
   if (m < 1 || m > JMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil_energy, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, out, work, info);
   return hipGetLastError();
+}
+
+hipError_t launch_nto(const double* Z, int64_t ldz, int k, const Geometry& g, const int* ptab,
+                      double* X, double* Y, double* Gx, double* Gy, double* Dv, double* Do,
+                      double* lam_p, double* lam_h, hipStream_t s) {
+  if (k < 1 || g.nv > JMAX || g.no > JMAX) return hipErrorInvalidValue;
+  const size_t xv = (size_t)k * g.nv * g.nv, yo = (size_t)k * g.no * g.no;
+  hipError_t e = launch_fill(X, xv, 0.0, s);
+  if (e == hipSuccess && yo) e = launch_fill(Y, yo, 0.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpack_triangular, dim3((unsigned)((g.n + NT - 1) / NT), k), dim3(NT), 0, s,
+                     Z, ldz, g.n, g.nvv, g.nv, g.no, ptab, X, Y);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t mv = (int64_t)g.nv * g.nv, mo = (int64_t)g.no * g.no;
+  hipLaunchKernelGGL(k_triangular_products, dim3((unsigned)((mv + NT - 1) / NT), k), dim3(NT), 0, s,
+                     X, g.nv, 1.0, Gx, Dv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_eigenvalues, dim3(k), dim3(WG), 0, s, Gx, g.nv, lam_p);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (g.no > 0) {
+    hipLaunchKernelGGL(k_triangular_products, dim3((unsigned)((mo + NT - 1) / NT), k), dim3(NT), 0,
+                       s, Y, g.no, -1.0, Gy, Do);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_eigenvalues, dim3(k), dim3(WG), 0, s, Gy, g.no, lam_h);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_small_orth(const double* C, int ldc, int m, int r, double* Q, int ldq,
