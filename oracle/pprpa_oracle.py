@@ -17,6 +17,7 @@ It is the plain definition written out in NumPy/SciPy, FP64 throughout:
   Eq. correlation_energy (section "Total Energy");
 * the natural transition orbitals (section "Natural Transition Orbital", Eqs. nto_pp and
   nto_hh) and the two-electron part of the density matrix (section "Density Matrix");
+* spin-unrestricted ppRPA in its three spin sectors (section "Implementation Details");
 * the canonical active window (section "ppRPA Equation", last paragraph; section
   "Implementation Details"): the highest occupied and lowest virtual orbitals.
 
@@ -325,8 +326,81 @@ def solve(eps, L, nocc, mult, nroot, nocc_act=None, nvir_act=None, lpq_is_active
 
 
 # ----------------------------------------------------------------------------------------
+# Spin-unrestricted ppRPA (section "Implementation Details": the matrix built and diagonalised
+# in three spin subspaces). The alpha-alpha and beta-beta sectors have the triplet elements
+# (pairs a<b, antisymmetrised integrals) of the one spin's orbitals and integrals, so
+# build_matrices(active_space(eps_s, L_s, nocc_s), "triplet") is that sector. The alpha-beta
+# sector is below.
+# ----------------------------------------------------------------------------------------
+
+def ab_sector(eps_a, eps_b, La, Lb, nocc_a, nocc_b):
+    """Alpha-beta sector: pairs (a_alpha, b_beta) and (i_alpha, j_beta), every combination, the
+    alpha index outer; <ab|cd> = (ac|bd) = sum_P La^P_ac Lb^P_bd, with no exchange term (its
+    partner pairs orbitals of different spin):
+        A = d(e^alpha_a + e^beta_b) + (ac|bd),  B = (ai|bj),  C = -d(e^alpha_i + e^beta_j) + (ik|jl).
+    Returns (M, nvv) with M = [[A, B], [B^T, C]]."""
+    nmo = eps_a.size
+    oa, va = slice(0, nocc_a), slice(nocc_a, nmo)
+    ob, vb = slice(0, nocc_b), slice(nocc_b, nmo)
+    nva, nvb, noa, nob = nmo - nocc_a, nmo - nocc_b, nocc_a, nocc_b
+    A = np.einsum("Pac,Pbd->abcd", La[:, va, va], Lb[:, vb, vb]).reshape(nva * nvb, nva * nvb)
+    A += np.diag((eps_a[va][:, None] + eps_b[vb][None, :]).ravel())
+    B = np.einsum("Pai,Pbj->abij", La[:, va, oa], Lb[:, vb, ob]).reshape(nva * nvb, noa * nob)
+    C = np.einsum("Pik,Pjl->ijkl", La[:, oa, oa], Lb[:, ob, ob]).reshape(noa * nob, noa * nob)
+    C -= np.diag((eps_a[oa][:, None] + eps_b[ob][None, :]).ravel())
+    return pprpa_matrix(A, B, C), nva * nvb
+
+
+def midgap_ab(eps_a, eps_b, nocc_a, nocc_b):
+    """2 mu between the alpha-beta hh and pp pair energies: mu = (e^a_HOMO + e^b_HOMO +
+    e^a_LUMO + e^b_LUMO) / 4 (the restricted mid-gap when alpha = beta)."""
+    lumo = eps_a[nocc_a] + eps_b[nocc_b]
+    if nocc_a > 0 and nocc_b > 0:
+        return 0.25 * (lumo + eps_a[nocc_a - 1] + eps_b[nocc_b - 1])
+    return 0.5 * lumo - 1.0
+
+
+def solve_ab(eps_a, eps_b, La, Lb, nocc_a, nocc_b, nroot, channel="pp", vectors=False):
+    """Lowest nroot pp roots (or the nroot hh roots nearest the gap) of the alpha-beta sector."""
+    M, nvv = ab_sector(eps_a, eps_b, La, Lb, nocc_a, nocc_b)
+    Om, Z, sg = solve_definite(M, nvv, midgap_ab(eps_a, eps_b, nocc_a, nocc_b))
+    om, z = pp_roots(Om, Z, sg, nroot) if channel == "pp" else hh_nearest(Om, Z, sg, nroot)
+    return (om, z) if vectors else om
+
+
+# ----------------------------------------------------------------------------------------
 # Independent references used only by the pins
 # ----------------------------------------------------------------------------------------
+
+def spin_orbital_matrix_u(eps_a, eps_b, La, Lb, nocc_a, nocc_b):
+    """Unrestricted ppRPA matrix in spin orbitals from the general elements (<pq||rs> over spin
+    orbitals, (pr|qs) = sum_P L^{s_p P}_pr L^{s_q P}_qs when the spins of p, r and of q, s
+    agree, zero otherwise), pairs p<q over all occupied or all virtual spin orbitals. Returns
+    (M, nvv). Small sizes only (explicit loops)."""
+    nmo = eps_a.size
+    eps = (eps_a, eps_b)
+    Ls = (La, Lb)
+    occ = [(p, 0) for p in range(nocc_a)] + [(p, 1) for p in range(nocc_b)]
+    vir = [(p, 0) for p in range(nocc_a, nmo)] + [(p, 1) for p in range(nocc_b, nmo)]
+
+    def phys(p, q, r, s):
+        if p[1] != r[1] or q[1] != s[1]:
+            return 0.0
+        return float(np.dot(Ls[p[1]][:, p[0], r[0]], Ls[q[1]][:, q[0], s[0]]))
+
+    def block(P1, P2):
+        out = np.empty((len(P1), len(P2)))
+        for x, (p, q) in enumerate(P1):
+            for y, (r, s) in enumerate(P2):
+                out[x, y] = phys(p, q, r, s) - phys(p, q, s, r)
+        return out
+
+    vp = [(a, b) for i, a in enumerate(vir) for b in vir[i + 1:]]
+    op = [(a, b) for i, a in enumerate(occ) for b in occ[i + 1:]]
+    A = block(vp, vp) + np.diag([eps[a[1]][a[0]] + eps[b[1]][b[0]] for a, b in vp])
+    B = block(vp, op)
+    C = block(op, op) - np.diag([eps[a[1]][a[0]] + eps[b[1]][b[0]] for a, b in op])
+    return pprpa_matrix(A, B, C), len(vp)
 
 def spin_orbital_matrix(sp):
     """ppRPA matrix in spin orbitals from the general (not spin-adapted) elements:

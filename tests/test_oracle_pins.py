@@ -14,6 +14,9 @@ P7  two electrons: with no occupied orbitals the singlet and triplet A spectra t
 P8  the factorised sigma equals the dense M z; route D equals route G.
 NTO the natural transition orbital weights and the two-electron density matrix: L = 0 closed
     form, the weight sum rule and Tr D = +-2 (Eq. dm_constrain) on every root.
+UHF the spin-unrestricted sectors: alpha = beta gives singlet U triplet in the alpha-beta
+    sector; alpha != beta: the general spin-orbital build equals alpha-alpha U alpha-beta U
+    beta-beta; L = 0 closed form.
 hh  the removal channel's selection: L = 0 closed form (highest e_i + e_j first), B = 0 against
     -eigvalsh(C), the subset solve against the full spectrum.
 Plus mutation checks: plausible mistakes planted in a copy of the oracle fail a pin.
@@ -272,6 +275,69 @@ def test_nto_weight_and_density_sum_rules(mult):
         X = O.triangular(z[:nvv], 12, mult)
         assert np.allclose(U @ np.diag(np.sqrt(lp)) @ V.T, X, atol=1e-13)
         assert np.all(np.diff(lp) <= 1e-15) and np.all(lp >= 0.0)
+
+
+# ----------------------------------------------------------------------------------------
+# Spin-unrestricted sectors
+# ----------------------------------------------------------------------------------------
+
+def unrestricted(seed, nmo, nocc_a, nocc_b, naux):
+    return (gen.orbital_energies(seed, nocc_a, nmo - nocc_a),
+            gen.orbital_energies(seed + 1000, nocc_b, nmo - nocc_b),
+            gen.lpq_full(seed, nmo, naux), gen.lpq_full(seed + 1000, nmo, naux))
+
+
+@pytest.mark.parametrize("nocc,nvir,naux", [(2, 3, 7), (3, 5, 11), (4, 6, 20)])
+def test_ab_sector_with_alpha_equal_beta_is_singlet_plus_triplet(nocc, nvir, naux):
+    """alpha = beta: the alpha-beta pairs carry both spin couplings, so the sector's spectrum is
+    the union of the singlet and triplet spectra (spin-adapted elements, built independently)."""
+    eps, L, sp = make_sp(7, nocc, nvir, naux)
+    M, nvv = O.ab_sector(eps, eps, L, L, nocc, nocc)
+    Om, _, sg = O.solve_definite(M, nvv, O.midgap_ab(eps, eps, nocc, nocc))
+    ref_pp, ref_hh = [], []
+    for mult in MULTS:
+        _, _, _, _, Om_s, _, sg_s = full_spectrum(sp, mult)
+        ref_pp += list(Om_s[sg_s > 0])
+        ref_hh += list(Om_s[sg_s < 0])
+    assert np.allclose(np.sort(Om[sg > 0]), np.sort(ref_pp), atol=1e-12)
+    assert np.allclose(np.sort(Om[sg < 0]), np.sort(ref_hh), atol=1e-12)
+
+
+@pytest.mark.parametrize("nmo,nocc_a,nocc_b,naux", [(6, 2, 1, 9), (7, 3, 2, 12), (6, 2, 2, 10)])
+def test_unrestricted_sectors_equal_spin_orbital_matrix(nmo, nocc_a, nocc_b, naux):
+    """alpha != beta (energies, integrals and occupations): the spectrum of the general
+    spin-orbital build is the union of the alpha-alpha, alpha-beta and beta-beta sectors."""
+    ea, eb, La, Lb = unrestricted(8, nmo, nocc_a, nocc_b, naux)
+    Mso, nvv_so = O.spin_orbital_matrix_u(ea, eb, La, Lb, nocc_a, nocc_b)
+    Om_so, _, sg_so = O.solve_general(Mso, nvv_so)
+    parts_pp, parts_hh = [], []
+    for e_s, L_s, no_s in ((ea, La, nocc_a), (eb, Lb, nocc_b)):
+        sp = O.active_space(e_s, L_s, no_s)
+        A, B, C = O.build_matrices(sp, "triplet")
+        Om, _, sg = O.solve_general(O.pprpa_matrix(A, B, C), A.shape[0])
+        parts_pp += list(Om[sg > 0])
+        parts_hh += list(Om[sg < 0])
+    M, nvv = O.ab_sector(ea, eb, La, Lb, nocc_a, nocc_b)
+    Om, _, sg = O.solve_general(M, nvv)
+    parts_pp += list(Om[sg > 0])
+    parts_hh += list(Om[sg < 0])
+    assert np.allclose(np.sort(Om_so[sg_so > 0]), np.sort(parts_pp), atol=1e-12)
+    assert np.allclose(np.sort(Om_so[sg_so < 0]), np.sort(parts_hh), atol=1e-12)
+    # route D with the alpha-beta shift agrees with the general solver
+    OmD, _, sgD = O.solve_definite(M, nvv, O.midgap_ab(ea, eb, nocc_a, nocc_b))
+    assert np.array_equal(sgD, sg) and np.allclose(OmD, Om, atol=1e-11)
+
+
+def test_ab_sector_zero_interaction():
+    nmo, nocc_a, nocc_b = 7, 3, 2
+    ea, eb, La, Lb = unrestricted(9, nmo, nocc_a, nocc_b, 5)
+    z = np.zeros_like(La)
+    om = O.solve_ab(ea, eb, z, z, nocc_a, nocc_b, 6)
+    ref = np.sort((ea[nocc_a:][:, None] + eb[nocc_b:][None, :]).ravel())[:6]
+    assert np.allclose(om, ref, atol=1e-13)
+    hh = O.solve_ab(ea, eb, z, z, nocc_a, nocc_b, 4, channel="hh")
+    ref_hh = np.sort((ea[:nocc_a][:, None] + eb[:nocc_b][None, :]).ravel())[::-1][:4]
+    assert np.allclose(hh, ref_hh, atol=1e-13)
 
 
 def test_active_window_equals_oracle_on_sliced_input():
