@@ -88,6 +88,33 @@ typedef struct {
  * pairs), ENOMEM, EDEVICE. On error *out is set to NULL. */
 pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
 
+/* Spin-unrestricted ppRPA (section "Implementation Details": the matrix is built and
+ * diagonalised in three spin subspaces). The alpha-alpha and beta-beta sectors carry the triplet
+ * elements of one spin's orbitals and integrals: build them with pprpa_build (mult = TRIPLET) on
+ * that spin's eps, nocc and Lpq. The alpha-beta sector, pairs (a_alpha, b_beta) and
+ * (i_alpha, j_beta) of every combination with the alpha index outer,
+ *   A = d(e^a_a + e^b_b) + (ac|bd),  B = (ai|bj),  C = -d(e^a_i + e^b_j) + (ik|jl),
+ * (pq|rs) = sum_P La^P_pq Lb^P_rs, no exchange term, is built here as a dense FP64 context:
+ * pprpa_dims, pprpa_matvec (dense sigma = M z), pprpa_davidson (Davidson or direct, both
+ * channels), pprpa_dense_matrix and pprpa_correlation_energy apply; pprpa_nto returns
+ * EUNSUPPORTED. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO) / 2. Order n = nvir_a nvir_b
+ * + nocc_a nocc_b <= 32768. Inputs (host, or device with on_device) are read during the call
+ * only. Errors: EINVAL (arguments, non-finite input), ENOMEM, EDEVICE. */
+typedef struct {
+  int32_t nmo;          /* orbitals per spin                                                 */
+  int32_t nocc_a;       /* occupied alpha orbitals (< nmo)                                   */
+  int32_t nocc_b;       /* occupied beta orbitals (< nmo)                                    */
+  int32_t naux;
+  const double* eps_a;  /* [nmo] alpha orbital energies (occupied first)                     */
+  const double* eps_b;  /* [nmo] beta orbital energies                                       */
+  const double* Lpq_a;  /* [naux][nmo][nmo] alpha MO three-centre integrals, symmetric in pq */
+  const double* Lpq_b;  /* [naux][nmo][nmo] beta                                             */
+  int32_t on_device;
+  int32_t max_block;    /* largest sigma block per call (<= 0: 32, at most 64)               */
+  void* stream;         /* hipStream_t to run on, or NULL for a new non-blocking stream      */
+} pprpa_build_ab_args;
+pprpa_status pprpa_build_ab(const pprpa_build_ab_args* args, pprpa_ctx** out);
+
 /* Packed dimensions of the context: n_pp (virtual pairs) and n_hh (occupied pairs). */
 pprpa_status pprpa_dims(const pprpa_ctx* ctx, int64_t* n_pp, int64_t* n_hh);
 

@@ -44,6 +44,13 @@ class BuildArgs(C.Structure):
 LOGFN = C.CFUNCTYPE(None, C.c_void_p, C.c_char_p)
 
 
+class BuildAbArgs(C.Structure):
+    _fields_ = [("nmo", C.c_int32), ("nocc_a", C.c_int32), ("nocc_b", C.c_int32),
+                ("naux", C.c_int32), ("eps_a", C.c_void_p), ("eps_b", C.c_void_p),
+                ("Lpq_a", C.c_void_p), ("Lpq_b", C.c_void_p), ("on_device", C.c_int32),
+                ("max_block", C.c_int32), ("stream", C.c_void_p)]
+
+
 class DavidsonArgs(C.Structure):
     _fields_ = [("nroot", C.c_int32), ("block", C.c_int32), ("max_iter", C.c_int32),
                 ("max_subspace", C.c_int32), ("tol", C.c_double), ("guess", C.c_void_p),
@@ -118,6 +125,8 @@ def lib():
     L = C.CDLL(LIB_PATH)
     L.pprpa_build.argtypes = [C.POINTER(BuildArgs), C.POINTER(C.c_void_p)]
     L.pprpa_build.restype = C.c_int
+    L.pprpa_build_ab.argtypes = [C.POINTER(BuildAbArgs), C.POINTER(C.c_void_p)]
+    L.pprpa_build_ab.restype = C.c_int
     L.pprpa_dims.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.pprpa_dims.restype = C.c_int
     L.pprpa_matvec.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]
@@ -217,6 +226,32 @@ class PpRPA:
 
     def _dims_active(self):
         return self.nv, self.no
+
+    @classmethod
+    def alpha_beta(cls, eps_a, eps_b, Lpq_a, Lpq_b, nocc_a, nocc_b, max_block=32, stream=None):
+        """The alpha-beta sector of spin-unrestricted ppRPA as a dense context (pprpa_build_ab);
+        the alpha-alpha and beta-beta sectors are PpRPA(eps_s, Lpq_s, nocc_s, mult="triplet")."""
+        on_dev = _is_torch(Lpq_a) and Lpq_a.is_cuda
+        if not on_dev:
+            eps_a, eps_b = (np.ascontiguousarray(x, dtype=np.float64) for x in (eps_a, eps_b))
+            Lpq_a, Lpq_b = (np.ascontiguousarray(x, dtype=np.float64) for x in (Lpq_a, Lpq_b))
+        a = BuildAbArgs()
+        a.nmo, a.nocc_a, a.nocc_b = int(eps_a.shape[0]), int(nocc_a), int(nocc_b)
+        a.naux = int(Lpq_a.shape[0])
+        a.eps_a, a.eps_b = _ptr(eps_a, on_dev).value, _ptr(eps_b, on_dev).value
+        a.Lpq_a, a.Lpq_b = _ptr(Lpq_a, on_dev).value, _ptr(Lpq_b, on_dev).value
+        a.on_device, a.max_block, a.stream = int(on_dev), int(max_block), stream
+        h = C.c_void_p()
+        _check(lib().pprpa_build_ab(C.byref(a), C.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        npp, nhh = C.c_int64(), C.c_int64()
+        _check(lib().pprpa_dims(h, C.byref(npp), C.byref(nhh)))
+        self.n_pp, self.n_hh = npp.value, nhh.value
+        self.n = self.n_pp + self.n_hh
+        self.mult, self.prec = "alpha-beta", "fp64"
+        self.nv, self.no = a.nmo - a.nocc_a, a.nocc_a
+        return self
 
     def close(self):
         if getattr(self, "_h", None):

@@ -110,6 +110,10 @@ SigmaGate g_gate[GATE_DEVICES];
 
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
   const int64_t n = c->g.n;
+  if (c->ab) {  // dense context (alpha-beta sector): sigma = M z
+    PPRPA_HIP(launch_dense_sigma(c->M, n, dz, k, ds, c->stream));
+    return PPRPA_OK;
+  }
   for (int k0 = 0; k0 < k; k0 += c->kcap) {
     const int kk = std::min(c->kcap, k - k0);
     const double* z = dz + (int64_t)k0 * n;
@@ -230,6 +234,25 @@ int staging_chunk(size_t per) {
   return (int)std::max<size_t>(1, std::min<size_t>(65535, (size_t(256) << 20) / (per * 8)));
 }
 
+// Stream (the caller's or a new non-blocking one), timing events and the pinned status buffer of
+// a context, on the current device.
+pprpa_status setup_runtime(pprpa_ctx* c, void* stream) {
+  PPRPA_HIP(hipGetDevice(&c->device));
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    PPRPA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  PPRPA_HIP(hipEventCreate(&c->e0));
+  PPRPA_HIP(hipEventCreate(&c->e1));
+  c->pinned_elems = PINNED_ELEMS;
+  if (!c->pinned)
+    PPRPA_HIP(hipHostMalloc((void**)&c->pinned, c->pinned_elems * sizeof(double), hipHostMallocDefault));
+  PPRPA_HIP(prepare_kernels());
+  return PPRPA_OK;
+}
+
 pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
   // ---- sizes and window ----------------------------------------------------------------
   const int nmo = a->nmo, nocc = a->nocc, naux = a->naux;
@@ -255,20 +278,7 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
   c->ev_h.assign(eps.begin() + nocc, eps.begin() + nocc + nv);
   c->mu2 = no > 0 ? c->eo_h.back() + c->ev_h.front() : 2.0 * (c->ev_h.front() - 1.0);
 
-  // ---- stream, events, pinned status buffer --------------------------------------------
-  PPRPA_HIP(hipGetDevice(&c->device));
-  if (a->stream) {
-    c->stream = (hipStream_t)a->stream;
-  } else {
-    PPRPA_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-  }
-  PPRPA_HIP(hipEventCreate(&c->e0));
-  PPRPA_HIP(hipEventCreate(&c->e1));
-  c->pinned_elems = PINNED_ELEMS;
-  if (!c->pinned)
-    PPRPA_HIP(hipHostMalloc((void**)&c->pinned, c->pinned_elems * sizeof(double), hipHostMallocDefault));
-  PPRPA_HIP(prepare_kernels());
+  PPRPA_TRY(setup_runtime(c, a->stream));
 
   // ---- pair table and pair energies ----------------------------------------------------
   c->ptab_h.resize(g.n);
@@ -278,6 +288,11 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
       for (int q = p + k; q < nv; ++q) c->ptab_h[e++] = (p << 16) | q;
     for (int p = 0; p < no; ++p)
       for (int q = p + k; q < no; ++q) c->ptab_h[e++] = (p << 16) | q;
+  }
+  c->epair_h.resize(g.n);
+  for (int64_t e = 0; e < g.n; ++e) {
+    const int p = c->ptab_h[e] >> 16, q = c->ptab_h[e] & 0xFFFF;
+    c->epair_h[e] = e < g.nvv ? c->ev_h[p] + c->ev_h[q] : -(c->eo_h[p] + c->eo_h[q]);
   }
   PPRPA_TRY(dalloc(c, g.n * sizeof(int), (void**)&c->ptab));
   PPRPA_TRY(dalloc(c, nv * sizeof(double), (void**)&c->ev));
@@ -397,6 +412,102 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
   return PPRPA_OK;
 }
 
+// Alpha-beta sector of spin-unrestricted ppRPA: a dense context (the matrix built on the device,
+// sigma = M z by the dense product).
+pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
+  const int nmo = a->nmo, noa = a->nocc_a, nob = a->nocc_b, naux = a->naux;
+  const int nva = nmo - noa, nvb = nmo - nob;
+  Geometry& g = c->g;
+  g.nv = nva;
+  g.no = noa;
+  g.naux = naux;
+  g.mult = 0;
+  g.nvv = (int64_t)nva * nvb;
+  g.noo = (int64_t)noa * nob;
+  g.n = g.nvv + g.noo;
+  if (g.n > 32768) return einval("alpha-beta sector of order %lld exceeds 32768", (long long)g.n);
+  c->ab = true;
+  c->ab_nocc_b = nob;
+  c->prec = PPRPA_FP64;
+  c->st = Store::F64;
+  c->kcap = a->max_block > 0 ? std::min(a->max_block, 64) : 32;
+
+  std::vector<double> ea(nmo), eb(nmo);
+  const hipMemcpyKind kind = a->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  PPRPA_HIP(hipMemcpy(ea.data(), a->eps_a, nmo * sizeof(double), kind));
+  PPRPA_HIP(hipMemcpy(eb.data(), a->eps_b, nmo * sizeof(double), kind));
+  for (int i = 0; i < nmo; ++i)
+    if (!std::isfinite(ea[i]) || !std::isfinite(eb[i])) return einval("eps[%d] is not finite", i);
+  c->eo_h.assign(ea.begin(), ea.begin() + noa);
+  c->ev_h.assign(ea.begin() + noa, ea.end());
+  const double lumo = ea[noa] + eb[nob];
+  c->mu2 = (noa > 0 && nob > 0) ? 0.5 * (lumo + ea[noa - 1] + eb[nob - 1]) : lumo - 2.0;
+
+  PPRPA_TRY(setup_runtime(c, a->stream));
+
+  c->ptab_h.resize(g.n);
+  c->epair_h.resize(g.n);
+  {
+    int64_t e = 0;
+    for (int p = 0; p < nva; ++p)
+      for (int q = 0; q < nvb; ++q, ++e) {
+        c->ptab_h[e] = (p << 16) | q;
+        c->epair_h[e] = ea[noa + p] + eb[nob + q];
+      }
+    for (int p = 0; p < noa; ++p)
+      for (int q = 0; q < nob; ++q, ++e) {
+        c->ptab_h[e] = (p << 16) | q;
+        c->epair_h[e] = -(ea[p] + eb[q]);
+      }
+  }
+  PPRPA_TRY(dalloc(c, g.n * sizeof(int), (void**)&c->ptab));
+  PPRPA_TRY(dalloc(c, g.n * sizeof(double), (void**)&c->epair));
+  PPRPA_HIP(hipMemcpyAsync(c->ptab, c->ptab_h.data(), g.n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  PPRPA_HIP(hipMemcpyAsync(c->epair, c->epair_h.data(), g.n * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+
+  // integrals of both spins on the device (the caller's, or temporary copies of host inputs)
+  const size_t per = (size_t)naux * nmo * nmo;
+  const double* La = a->Lpq_a;
+  const double* Lb = a->Lpq_b;
+  double* tmp = nullptr;
+  struct FreeTmp {
+    double*& p;
+    ~FreeTmp() {
+      if (p) (void)hipFree(p);
+    }
+  } free_tmp{tmp};
+  if (!a->on_device) {
+    hipError_t e = hipMalloc((void**)&tmp, 2 * per * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      tmp = nullptr;
+      set_error("staging %zu bytes of integrals: %s", 2 * per * sizeof(double), hipGetErrorString(e));
+      return PPRPA_ENOMEM;
+    }
+    PPRPA_HIP(hipMemcpyAsync(tmp, a->Lpq_a, per * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    PPRPA_HIP(hipMemcpyAsync(tmp + per, a->Lpq_b, per * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+    La = tmp;
+    Lb = tmp + per;
+  }
+  int* d_bad = nullptr;
+  PPRPA_TRY(dalloc(c, sizeof(int), (void**)&d_bad));
+  PPRPA_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
+  PPRPA_HIP(launch_check_finite(La, per, d_bad, c->stream));
+  PPRPA_HIP(launch_check_finite(Lb, per, d_bad, c->stream));
+  PPRPA_TRY(dalloc(c, (size_t)g.n * g.n * sizeof(double), (void**)&c->M));
+  PPRPA_HIP(launch_dense_build_ab(La, Lb, naux, nmo, noa, nob, g.n, g.nvv, c->ptab, c->epair, c->M,
+                                  c->stream));
+  PPRPA_TRY(dalloc(c, (size_t)c->kcap * g.n * sizeof(double), (void**)&c->zbuf));
+  PPRPA_TRY(dalloc(c, (size_t)c->kcap * g.n * sizeof(double), (void**)&c->sbuf));
+  int bad = 0;
+  PPRPA_HIP(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  if (bad) return einval("Lpq_a or Lpq_b contains non-finite values");
+  return PPRPA_OK;
+}
+
 }  // namespace
 
 namespace pprpa {
@@ -505,6 +616,30 @@ pprpa_status pprpa_build(const pprpa_build_args* a, pprpa_ctx** out) {
   if (!out) return einval("out is NULL");
   *out = nullptr;
   return build_context(a, nullptr, nullptr, out);
+}
+
+pprpa_status pprpa_build_ab(const pprpa_build_ab_args* a, pprpa_ctx** out) {
+  g_err.clear();
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (!a) return einval("args is NULL");
+  if (a->nmo <= 0 || a->naux <= 0) return einval("nmo=%d and naux=%d must be positive", a->nmo, a->naux);
+  if (a->nocc_a < 0 || a->nocc_a >= a->nmo || a->nocc_b < 0 || a->nocc_b >= a->nmo)
+    return einval("nocc_a=%d, nocc_b=%d outside [0, nmo=%d)", a->nocc_a, a->nocc_b, a->nmo);
+  if (a->nmo > 65535) return einval("nmo=%d exceeds 65535", a->nmo);
+  if (!a->eps_a || !a->eps_b || !a->Lpq_a || !a->Lpq_b)
+    return einval("eps_a, eps_b, Lpq_a and Lpq_b must not be NULL");
+  pprpa_ctx* c = new (std::nothrow) pprpa_ctx();
+  if (!c) return einval("host allocation failed");
+  pprpa_status s = build_ab_impl(a, c);
+  if (s != PPRPA_OK) {
+    std::string keep = g_err;
+    destroy(c);
+    g_err = keep;
+    return s;
+  }
+  *out = c;
+  return PPRPA_OK;
 }
 
 pprpa_status pprpa_dims(const pprpa_ctx* c, int64_t* n_pp, int64_t* n_hh) {
@@ -647,6 +782,10 @@ pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_devi
   if (!c) return einval("ctx is NULL");
   if (!z || !lam_p || (!lam_h && c->g.no > 0)) return einval("z, lam_p and lam_h must not be NULL");
   if (k < 1 || k > 64) return einval("k=%d outside [1, 64]", k);
+  if (c->ab) {
+    set_error("NTOs of the alpha-beta sector (rectangular amplitude matrices) are not provided");
+    return PPRPA_EUNSUPPORTED;
+  }
   const Geometry& g = c->g;
   if (g.nv > 512 || g.no > 512) {
     set_error("NTOs on the device are limited to nv, no <= 512 (nv=%d, no=%d)", g.nv, g.no);

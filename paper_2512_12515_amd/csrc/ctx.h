@@ -30,7 +30,10 @@ struct pprpa_ctx {
   double* M = nullptr;      // dense matrix [n][n] (dense builds)
   pprpa::SigmaPlan plan;
 
-  std::vector<double> ev_h, eo_h;
+  std::vector<double> ev_h, eo_h;  // active virtual / occupied energies (alpha for the ab sector)
+  std::vector<double> epair_h;     // host copy of epair
+  bool ab = false;                 // alpha-beta sector of unrestricted ppRPA (dense only)
+  int ab_nocc_b = 0;
   std::vector<int> ptab_h;
   std::atomic<int> busy{0};
   hipEvent_t e0 = nullptr, e1 = nullptr;

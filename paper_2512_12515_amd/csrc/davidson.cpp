@@ -242,16 +242,13 @@ pprpa_status Solver::initial_subspace(const Shape& sh) {
   }
   // unit vectors on the nb0 lowest virtual-pair energies (pp) or the nb0 highest occupied-pair
   // energies (hh), ties: lowest index
+  // (the diagonal pair energies: +(e_a + e_b) for pp pairs, -(e_i + e_j) for hh pairs, so both
+  // channels take the smallest values)
   const bool hh = a_.channel == 1;
   std::vector<int64_t> idx(hh ? n - nvv : nvv);
   std::iota(idx.begin(), idx.end(), hh ? nvv : 0);
-  auto epair = [&](int64_t e) {
-    const int pq = c_->ptab_h[e];
-    return hh ? c_->eo_h[pq >> 16] + c_->eo_h[pq & 0xFFFF] : c_->ev_h[pq >> 16] + c_->ev_h[pq & 0xFFFF];
-  };
-  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
-    return hh ? epair(x) > epair(y) : epair(x) < epair(y);
-  });
+  const std::vector<double>& ep = c_->epair_h;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return ep[x] < ep[y]; });
   PPRPA_HIP(launch_fill(w.V, (size_t)sh.nb0 * n, 0.0, s));
   PPRPA_HIP(launch_set_units(w.V, n, idx.data(), sh.nb0, s));
   m_ = sh.nb0;

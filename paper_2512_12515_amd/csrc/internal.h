@@ -103,6 +103,13 @@ hipError_t launch_check_finite(const double* x, size_t n, int* d_bad, hipStream_
 // --- dense (k_dense.hip) -------------------------------------------------------------------
 hipError_t launch_dense_build(const Geometry& g, const double* L64, const int* d_ptab,
                               const double* d_epair, double* M, hipStream_t s);
+// Alpha-beta sector of unrestricted ppRPA as a dense matrix (La, Lb: full [naux][nmo][nmo]
+// FP64 integrals of each spin on the device), and sigma = M z for k vectors of a dense matrix.
+hipError_t launch_dense_build_ab(const double* La, const double* Lb, int naux, int nmo, int nocc_a,
+                                 int nocc_b, int64_t n, int64_t nvv, const int* d_ptab,
+                                 const double* d_epair, double* M, hipStream_t s);
+hipError_t launch_dense_sigma(const double* M, int64_t n, const double* z, int k, double* sigma,
+                              hipStream_t s);
 hipError_t launch_epair(const Geometry& g, const int* d_ptab, const double* d_ev,
                         const double* d_eo, double* d_epair, hipStream_t s);
 hipError_t launch_set_units(double* V, int64_t ld, const int64_t* idx, int r, hipStream_t s);

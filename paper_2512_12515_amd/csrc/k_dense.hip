@@ -44,6 +44,57 @@ __global__ __launch_bounds__(256) void k_dense_build(const double* __restrict__ 
   M[e] = val;
 }
 
+// Alpha-beta sector of spin-unrestricted ppRPA (section "Implementation Details": the matrix
+// built and diagonalised in three spin subspaces): pair e = (p_alpha, q_beta), alpha index
+// outer, virtual pairs first; M[r][c] = d_rc epair[r] + sum_P La^P[p_r][p_c] Lb^P[q_r][q_c]
+// (<pq|uv> = (pu|qv); no exchange term between orbitals of different spin). La, Lb: the full
+// [naux][nmo][nmo] FP64 integrals of each spin; orbital index of a virtual pair's alpha member
+// nocc_a + p, of an occupied pair's p (beta likewise). One thread per element.
+__global__ __launch_bounds__(256) void k_dense_build_ab(const double* __restrict__ La,
+                                                        const double* __restrict__ Lb, int naux,
+                                                        int nmo, int nocc_a, int nocc_b,
+                                                        int64_t n, int64_t nvv,
+                                                        const int* __restrict__ ptab,
+                                                        const double* __restrict__ epair,
+                                                        double* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t r = e / n, c = e % n;
+  const int pr = ptab[r], pc = ptab[c];
+  const int p = (pr >> 16) + (r < nvv ? nocc_a : 0), q = (pr & 0xFFFF) + (r < nvv ? nocc_b : 0);
+  const int u = (pc >> 16) + (c < nvv ? nocc_a : 0), v = (pc & 0xFFFF) + (c < nvv ? nocc_b : 0);
+  const size_t z = (size_t)nmo * nmo;
+  double s = 0.0;
+  for (int P = 0; P < naux; ++P)
+    s += La[P * z + (size_t)p * nmo + u] * Lb[P * z + (size_t)q * nmo + v];
+  if (r == c) s += epair[r];
+  M[e] = s;
+}
+
+// sigma[j][t] = sum_i M[i][t] z[j][i] for j < k (M symmetric, so this is M z): one thread per t
+// (column t of M read down its rows, coalesced across the threads), KB vectors per pass.
+template <int KB>
+__global__ __launch_bounds__(256) void k_dense_sigma(const double* __restrict__ M, int64_t n,
+                                                     const double* __restrict__ z, int k,
+                                                     double* __restrict__ sigma) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  for (int j0 = 0; j0 < k; j0 += KB) {
+    double acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double m = M[i * n + t];
+#pragma unroll
+      for (int j = 0; j < KB; ++j)
+        if (j0 + j < k) acc[j] += m * z[(int64_t)(j0 + j) * n + i];
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j0 + j < k) sigma[(int64_t)(j0 + j) * n + t] = acc[j];
+  }
+}
+
 // epair[e] = +(e_a + e_b) for virtual pairs, -(e_i + e_j) for occupied pairs.
 __global__ void k_epair(const int* __restrict__ ptab, const double* __restrict__ ev,
                         const double* __restrict__ eo, int64_t n, int64_t nvv,
@@ -118,6 +169,23 @@ hipError_t launch_transpose(const double* in, int ldi, int m, int r, double* out
   if (e == 0) return hipSuccess;
   hipLaunchKernelGGL(k_transpose, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, in, ldi, m,
                      r, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_build_ab(const double* La, const double* Lb, int naux, int nmo, int nocc_a,
+                                 int nocc_b, int64_t n, int64_t nvv, const int* d_ptab,
+                                 const double* d_epair, double* M, hipStream_t s) {
+  const int64_t nn = n * n;
+  hipLaunchKernelGGL(k_dense_build_ab, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, La, Lb,
+                     naux, nmo, nocc_a, nocc_b, n, nvv, d_ptab, d_epair, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_sigma(const double* M, int64_t n, const double* z, int k, double* sigma,
+                              hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_sigma<8>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, n, z,
+                     k, sigma);
   return hipGetLastError();
 }
 

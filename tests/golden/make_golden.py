@@ -7,6 +7,7 @@ paper prints no worked example for this path, so every stored value here is the 
     python tests/golden/make_golden.py davidson   # 20 x 200 x 700, seed 0, both spins (minutes)
     python tests/golden/make_golden.py hh         # the same, hh channel (minutes)
     python tests/golden/make_golden.py energy     # correlation energies, 5 x 20 x 100 (seconds)
+    python tests/golden/make_golden.py unrestricted  # three spin sectors, nmo 60 (seconds)
 """
 import json
 import os
@@ -64,12 +65,35 @@ def run_energy(name, nocc, nvir, naux, seeds):
         json.dump(out, f, indent=1)
 
 
+def run_unrestricted(name, nmo, nocc_a, nocc_b, naux, seed, nroot):
+    """Lowest nroot pp roots of each spin sector of unrestricted ppRPA and of all three together
+    (alpha = seed, beta = seed + 1000 of the same generators)."""
+    ea = gen.orbital_energies(seed, nocc_a, nmo - nocc_a)
+    eb = gen.orbital_energies(seed + 1000, nocc_b, nmo - nocc_b)
+    La = gen.lpq_full(seed, nmo, naux)
+    Lb = gen.lpq_full(seed + 1000, nmo, naux)
+    out = dict(source="oracle/pprpa_oracle.py: triplet sectors (build_matrices) and ab_sector, route D",
+               inputs=f"workloads/gen.py: alpha orbital_energies({seed}, {nocc_a}, {nmo - nocc_a}), "
+                      f"lpq_full({seed}, {nmo}, {naux}); beta the same with seed {seed + 1000} and nocc {nocc_b}",
+               units="Hartree", nmo=nmo, nocc_a=nocc_a, nocc_b=nocc_b, naux=naux, seed=seed,
+               nroot=nroot, roots={})
+    for label, e_s, L_s, no_s in (("aa", ea, La, nocc_a), ("bb", eb, Lb, nocc_b)):
+        out["roots"][label] = [float(x) for x in O.solve(e_s, L_s, no_s, "triplet", nroot)]
+    out["roots"]["ab"] = [float(x) for x in O.solve_ab(ea, eb, La, Lb, nocc_a, nocc_b, nroot)]
+    out["roots"]["all"] = sorted(out["roots"]["aa"] + out["roots"]["bb"] + out["roots"]["ab"])[:nroot]
+    print(name, out["roots"]["all"][:3], flush=True)
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["small"]
     if "small" in which:
         run("small_direct", 5, 20, 100, (0, 1, 2, 3, 4), ("singlet", "triplet"), 5)
     if "davidson" in which:
         run("davidson_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10)
+    if "unrestricted" in which:
+        run_unrestricted("unrestricted", 60, 10, 9, 200, 0, 8)
     if "energy" in which:
         run_energy("correlation_energy", 5, 20, 100, (0, 1, 2, 3, 4))
     if "hh" in which:

@@ -104,7 +104,7 @@ def test_server_argument_checks():
 STRUCTS = [("pprpa_build_args", "BuildArgs"), ("pprpa_davidson_args", "DavidsonArgs"),
            ("pprpa_report", "Report"), ("pprpa_kernel_stats", "KernelStats"),
            ("pprpa_request_info", "RequestInfo"), ("pprpa_serving_stats", "ServingStats"),
-           ("pprpa_corr_energy", "CorrEnergy")]
+           ("pprpa_corr_energy", "CorrEnergy"), ("pprpa_build_ab_args", "BuildAbArgs")]
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -132,3 +132,21 @@ def test_struct_layouts_match_header(tmp_path):
         got = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
         assert got == int(val), (pyname, field, got, int(val))
 
+
+
+def test_build_ab_rejects_invalid_arguments():
+    L = B.lib()
+    eps = np.linspace(-1, 1, 6)
+    Lq = np.zeros((3, 6, 6))
+    for over, msg in [(dict(nocc_a=6), "nocc_a"), (dict(nocc_b=-1), "nocc_b"), (dict(naux=0), "naux"),
+                      (dict(eps_b=None), "NULL")]:
+        a = B.BuildAbArgs()
+        a.nmo, a.nocc_a, a.nocc_b, a.naux = 6, 2, 1, 3
+        a.eps_a = a.eps_b = eps.ctypes.data
+        a.Lpq_a = a.Lpq_b = Lq.ctypes.data
+        for k, v in over.items():
+            setattr(a, k, v)
+        h = C.c_void_p(1234)
+        assert L.pprpa_build_ab(C.byref(a), C.byref(h)) == B.EINVAL
+        assert h.value is None
+        assert msg in L.pprpa_last_error().decode()

@@ -1,0 +1,125 @@
+"""GPU: spin-unrestricted ppRPA (three spin sectors), through the C ABI, against the FP64 oracle.
+
+* the alpha-beta sector as a dense context: its matrix, direct and Davidson roots in both
+  channels, sigma = M z and the correlation energy against the oracle's alpha-beta sector;
+* alpha = beta: the alpha-beta roots are the singlet and triplet roots together;
+* alpha != beta end to end: the lowest pp roots of the three GPU sectors (alpha-alpha and
+  beta-beta as triplet contexts of one spin's data) equal the lowest pp roots of the oracle's
+  general spin-orbital build;
+* argument checks.
+Tolerances: matrices and sigma 1e-12 relative, eigenvalues 1e-9 Ha (FP64, tol 1e-10).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pprpa_oracle as O
+from workloads import gen
+import paper_2512_12515_amd as P
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def unrestricted(seed, nmo, nocc_a, nocc_b, naux):
+    return (gen.orbital_energies(seed, nocc_a, nmo - nocc_a),
+            gen.orbital_energies(seed + 1000, nocc_b, nmo - nocc_b),
+            gen.lpq_full(seed, nmo, naux), gen.lpq_full(seed + 1000, nmo, naux))
+
+
+@pytest.mark.parametrize("case", [(8, 3, 2, 20), (12, 5, 5, 40), (16, 4, 6, 50)])
+def test_ab_matrix_sigma_and_direct(case):
+    nmo, noa, nob, naux = case
+    note("ab dense", case)
+    ea, eb, La, Lb = unrestricted(71, nmo, noa, nob, naux)
+    Mref, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob) as ctx:
+        assert ctx.n_pp == nvv and ctx.n == Mref.shape[0]
+        M = ctx.dense_matrix()
+        z = gen.random_vectors(72, 5, ctx.n)
+        s = ctx.matvec(z)
+        if ctx.n <= 512:
+            d = ctx.davidson(4, direct=True)
+            dh = ctx.davidson(3, direct=True, channel="hh")
+    assert np.max(np.abs(M - Mref)) <= 1e-12 * np.abs(Mref).max()
+    sref = z @ Mref.T
+    assert np.max(np.abs(s - sref)) <= 1e-12 * np.abs(sref).max()
+    if Mref.shape[0] <= 512:
+        assert np.max(np.abs(d["omega"] - O.solve_ab(ea, eb, La, Lb, noa, nob, 4))) <= 1e-9
+        assert np.max(np.abs(dh["omega"] - O.solve_ab(ea, eb, La, Lb, noa, nob, 3, channel="hh"))) <= 1e-9
+
+
+@pytest.mark.parametrize("channel,nroot", [("pp", 6), ("hh", 4)])
+def test_ab_davidson_vs_oracle(channel, nroot):
+    nmo, noa, nob, naux = 30, 6, 5, 80   # n = 24 * 25 + 30 = 630: beyond the direct solver
+    note("ab davidson", channel)
+    ea, eb, La, Lb = unrestricted(73, nmo, noa, nob, naux)
+    ref = O.solve_ab(ea, eb, La, Lb, noa, nob, nroot, channel=channel)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob) as ctx:
+        r = ctx.davidson(nroot, block=nroot, tol=1e-10, channel=channel)
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-9
+
+
+def test_ab_with_alpha_equal_beta_is_singlet_plus_triplet():
+    note("ab alpha = beta")
+    nocc, nvir, naux = 4, 10, 30
+    eps = gen.orbital_energies(74, nocc, nvir)
+    L = gen.lpq_full(74, nocc + nvir, naux)
+    with P.PpRPA.alpha_beta(eps, eps, L, L, nocc, nocc) as ctx:
+        ab = ctx.davidson(8, direct=True)["omega"]
+    parts = []
+    for mult in ("singlet", "triplet"):
+        with P.PpRPA(eps, L, nocc, mult=mult, dense=True) as ctx:
+            parts += list(ctx.davidson(8, direct=True)["omega"])
+    assert np.max(np.abs(ab - np.sort(parts)[:8])) <= 1e-9
+
+
+def test_three_sectors_equal_spin_orbital_build():
+    """alpha != beta: lowest pp roots over alpha-alpha, beta-beta (triplet contexts of each spin)
+    and alpha-beta (dense context) on the GPU equal the lowest pp roots of the oracle's general
+    spin-orbital build."""
+    note("three sectors")
+    nmo, noa, nob, naux = 7, 3, 2, 12
+    ea, eb, La, Lb = unrestricted(75, nmo, noa, nob, naux)
+    Mso, nvv_so = O.spin_orbital_matrix_u(ea, eb, La, Lb, noa, nob)
+    Om, _, sg = O.solve_general(Mso, nvv_so)
+    ref = np.sort(Om[sg > 0])[:8]
+    got = []
+    for e_s, L_s, no_s in ((ea, La, noa), (eb, Lb, nob)):
+        with P.PpRPA(e_s, L_s, no_s, mult="triplet", dense=True) as ctx:
+            got += list(ctx.davidson(min(8, ctx.n_pp), direct=True)["omega"])
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob) as ctx:
+        got += list(ctx.davidson(8, direct=True)["omega"])
+    assert np.max(np.abs(np.sort(got)[:8] - ref)) <= 1e-9
+
+
+def test_ab_correlation_energy():
+    note("ab correlation energy")
+    nmo, noa, nob, naux = 14, 4, 3, 40
+    ea, eb, La, Lb = unrestricted(76, nmo, noa, nob, naux)
+    M, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    Om, _, sg = O.solve_definite(M, nvv, O.midgap_ab(ea, eb, noa, nob))
+    A, C = M[:nvv, :nvv], M[nvv:, nvv:]
+    ref_pp, ref_hh = O.correlation_energy(Om[sg > 0], Om[sg < 0], A, C)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob) as ctx:
+        r = ctx.correlation_energy()
+    assert abs(r["ec_pp"] - ref_pp) <= 1e-10 and abs(r["ec_hh"] - ref_hh) <= 1e-10
+
+
+def test_ab_argument_checks():
+    note("ab argument checks")
+    ea, eb, La, Lb = unrestricted(77, 8, 3, 2, 10)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, 3, 2) as ctx:
+        with pytest.raises(P.PpRPAError) as e:
+            ctx.nto(np.ones((1, ctx.n)))
+        assert e.value.status == P.binding.EUNSUPPORTED
+    bad = Lb.copy()
+    bad[1, 2, 3] = np.nan
+    with pytest.raises(P.PpRPAError) as e:
+        P.PpRPA.alpha_beta(ea, eb, La, bad, 3, 2)
+    assert e.value.status == P.binding.EINVAL
