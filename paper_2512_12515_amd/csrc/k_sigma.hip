@@ -418,27 +418,56 @@ void k_sandwich_group(GroupArgs ga) {
 
 // ------------------------------------------------------------------------------------------
 // Epilogue: sigma = E z + N * (Q + s Q^T), Q summed over the aux splits in a fixed order, FP64.
+// One workgroup per 16 x 16 tile (I, J), I <= J, of the upper triangle of a diagonal block and
+// one vector: thread (r, c) sums Q[I r][J c] and the mirror tile's Q[J r][I c] over the splits
+// (both read with 128-byte row segments), the mirror goes through LDS transposed, and the
+// packed pairs (p, q) of the tile get sigma. (Reading Q[q][p] directly for each packed pair
+// touches one memory line per element.)
 // ------------------------------------------------------------------------------------------
+constexpr int ET = 16;
+
 template <typename T>
-__global__ void k_epilogue(const double* __restrict__ z, int64_t n, int64_t nvv, int nvp,
-                           int nmop, int mult, const T* __restrict__ Sp, int nsplit,
-                           int64_t split_stride, const int* __restrict__ ptab,
-                           const double* __restrict__ epair, double* __restrict__ sigma) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_epilogue(const double* __restrict__ z, int64_t n,
+                                                  int64_t nvv, int nv, int no, int nvp, int nmop,
+                                                  int mult, const T* __restrict__ Sp, int nsplit,
+                                                  int64_t split_stride, int ntv, int npv,
+                                                  const double* __restrict__ epair,
+                                                  double* __restrict__ sigma) {
+  __shared__ double mirror[ET][ET + 1];
   const int kv = blockIdx.y;
-  if (e >= n) return;
-  const int pq = ptab[e];
-  const int p = pq >> 16, q = pq & 0xFFFF;
-  const int off = e < nvv ? 0 : nvp;
-  // S[p][q] = Q[p][q] + s Q[q][p]
-  const int64_t spq = ((int64_t)kv * nmop + off + p) * nmop + off + q;
-  const int64_t sqp = ((int64_t)kv * nmop + off + q) * nmop + off + p;
-  double a = 0.0, b = 0.0;
-  for (int t = 0; t < nsplit; ++t) {
-    a += (double)Sp[t * split_stride + spq];
-    b += (double)Sp[t * split_stride + sqp];
+  int tp = blockIdx.x;
+  const bool vblk = tp < npv;
+  if (!vblk) tp -= npv;
+  const int nb = vblk ? nv : no;
+  const int nt = (nb + ET - 1) / ET;
+  const int off = vblk ? 0 : nvp;
+  int I = 0;  // tile pair tp -> (I, J), row-major over the upper triangle of tiles
+  while (tp >= nt - I) {
+    tp -= nt - I;
+    ++I;
   }
-  const double s = mult == 0 ? a + b : a - b;
+  const int J = I + tp;
+  const int r = threadIdx.x / ET, c = threadIdx.x % ET;
+  const int pa = I * ET + r, qa = J * ET + c;  // element of the tile
+  const int pb = J * ET + r, qb = I * ET + c;  // element of the mirror tile
+  const bool oka = pa < nb && qa < nb, okb = pb < nb && qb < nb;
+  const T* Q = Sp + (int64_t)kv * nmop * nmop;
+  const int64_t ia = (int64_t)(off + pa) * nmop + off + qa;
+  const int64_t ib = (int64_t)(off + pb) * nmop + off + qb;
+  double a = 0.0, b = 0.0;
+#pragma unroll 8
+  for (int t = 0; t < nsplit; ++t) {
+    if (oka) a += (double)Q[t * split_stride + ia];
+    if (okb) b += (double)Q[t * split_stride + ib];
+  }
+  mirror[r][c] = b;
+  __syncthreads();
+  const int k = mult == 0 ? 0 : 1;
+  if (!oka || qa < pa + k) return;
+  // Q[q][p] for (p, q) = (pa, qa) is the mirror tile's element (qa - J ET, pa - I ET) = (c, r)
+  const double s = mult == 0 ? a + mirror[c][r] : a - mirror[c][r];
+  const int64_t p = pa, q = qa;
+  const int64_t e = (vblk ? 0 : nvv) + p * (nb - k) - p * (p - 1) / 2 + (q - p - k);
   const double nrm = (mult == 0 && p == q) ? 0.70710678118654752440 : 1.0;
   sigma[(int64_t)kv * n + e] = epair[e] * z[(int64_t)kv * n + e] + nrm * s;
 }
@@ -493,14 +522,19 @@ hipError_t launch_unpack(const Geometry& g, Store st, const double* z, int k, co
 hipError_t launch_epilogue(const Geometry& g, Store st, const double* z, int k, const void* Sp,
                            int nsplit, const int* d_ptab, const double* d_epair, double* sigma,
                            hipStream_t s) {
-  dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
+  (void)d_ptab;
+  const int ntv = (g.nv + ET - 1) / ET, nto = (g.no + ET - 1) / ET;
+  const int npv = ntv * (ntv + 1) / 2, npo = nto * (nto + 1) / 2;
+  dim3 grid((unsigned)(npv + npo), (unsigned)k);
   const int64_t split_stride = (int64_t)k * g.nmop * g.nmop;
   if (st == Store::F64)
-    hipLaunchKernelGGL(k_epilogue<double>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvp, g.nmop,
-                       g.mult, (const double*)Sp, nsplit, split_stride, d_ptab, d_epair, sigma);
+    hipLaunchKernelGGL(k_epilogue<double>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nv, g.no, g.nvp,
+                       g.nmop, g.mult, (const double*)Sp, nsplit, split_stride, ntv, npv, d_epair,
+                       sigma);
   else
-    hipLaunchKernelGGL(k_epilogue<float>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvp, g.nmop,
-                       g.mult, (const float*)Sp, nsplit, split_stride, d_ptab, d_epair, sigma);
+    hipLaunchKernelGGL(k_epilogue<float>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nv, g.no, g.nvp,
+                       g.nmop, g.mult, (const float*)Sp, nsplit, split_stride, ntv, npv, d_epair,
+                       sigma);
   return hipGetLastError();
 }
 
