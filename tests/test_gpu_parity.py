@@ -256,3 +256,25 @@ def test_non_definite_is_reported():
         with pytest.raises(P.PpRPAError) as e:
             ctx.davidson(3, direct=True)
     assert e.value.status == P.binding.ENONDEF
+
+
+def test_concurrent_solves_match_serial():
+    """Solves on several contexts from several host threads (each context on its own stream;
+    their sandwich launches ordered on the device) give bitwise the roots of the same solves run
+    one after the other."""
+    from concurrent.futures import ThreadPoolExecutor
+    note("concurrent solves")
+    probs = [(81, 6, 30, 60, "singlet"), (82, 8, 25, 70, "triplet"), (83, 5, 40, 50, "singlet"),
+             (84, 7, 33, 64, "triplet")]
+    inputs = [problem(s, no, nv, na) for (s, no, nv, na, _m) in probs]
+
+    def solve(i):
+        eps, L = inputs[i]
+        with P.PpRPA(eps, L, probs[i][1], mult=probs[i][4]) as ctx:
+            return ctx.davidson(6, block=6, tol=1e-9)["omega"]
+
+    serial = [solve(i) for i in range(len(probs))]
+    with ThreadPoolExecutor(max_workers=len(probs)) as ex:
+        conc = list(ex.map(solve, range(len(probs))))
+    for a, b in zip(serial, conc):
+        assert np.array_equal(a, b)
