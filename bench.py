@@ -198,6 +198,7 @@ def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, pre
         "throughput_req_s": n_req / makespan, "makespan_s": makespan,
         "sigma_products_per_s": n_sigma / makespan,
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_mean_s": float(np.mean(lat)), "latency_max_s": float(np.max(lat)),
         "queue_wait_p50_s": float(np.percentile(qwait, 50)),
         "queue_wait_p99_s": float(np.percentile(qwait, 99)),
         "late_submits": len(late), "status": status, "failures": failures[:12],
@@ -322,6 +323,32 @@ def unrestricted(P, gen, reps=3, tol=1e-8):
     return {"workload": f"nmo {nmo}, nocc {noa}/{nob}, naux {naux}: aa + bb (triplet, DF sigma) + "
                         f"ab (dense, n {n_ab}), {nroot} roots each, tol {tol:g}",
             "s_per_three_sectors_p50": float(np.median(times)), "max_eig_err_ha_vs_oracle": err}
+
+
+def isolated_sigma(P, gen, eps_d, L_d, nocc, block, warm=3, reps=20):
+    """Isolated sigma: pprpa_matvec on block random FP64 vectors resident on the device, 3 warm-up
+    calls, then the median of 20 timed calls (unpack + sandwich + epilogue, host clock around
+    the synchronous call) and the sandwich kernel's own event time; sigma/s = block / t."""
+    import torch
+    out = {}
+    for mult in ("singlet", "triplet"):
+        with P.PpRPA(eps_d, L_d, nocc, mult=mult, max_block=block) as ctx:
+            z = torch.from_numpy(gen.random_vectors(5, block, ctx.n)).to(eps_d.device)
+            for _ in range(warm):
+                ctx.matvec(z)
+            ctx.sigma_stats(reset=True)
+            t = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                ctx.matvec(z)
+                t.append(time.perf_counter() - t0)
+            st = ctx.sigma_stats()
+        tm = float(np.median(t))
+        out[mult] = {"ms_per_call_p50": 1e3 * tm, "sigma_per_s": block / tm,
+                     "kernel_ms_per_launch": 1e3 * st["seconds"] / st["launches"],
+                     "kernel_tflops_algorithmic": st["flops"] / st["seconds"] / 1e12}
+    return dict(workload=f"pprpa_matvec, {block} vectors, median of {reps} after {warm} warm-ups",
+                **out)
 
 
 def hh_channel(P, eps_d, L_d, nocc, nroot, block, tol, reps=2):
@@ -580,6 +607,8 @@ def main():
         "max_eig_err_ha": max_err,
         "iters": {m: results[-1][m]["rep"]["iters"] for m in mults},
     }
+    log("isolated sigma ...")
+    line["isolated_sigma"] = isolated_sigma(P, gen, eps_d, L_d, nocc, args.block)
     if not args.no_extras:
         log("small direct workload ...")
         line["small_direct"] = small_direct(P, gen)
