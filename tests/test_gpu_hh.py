@@ -140,6 +140,18 @@ def test_hh_served_equals_standalone():
         assert np.max(np.abs(sv["omega"] - ref)) <= 1e-7
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x3"])
+def test_hh_reduced_precision_sigma(prec):
+    """hh roots with FP32 / BF16-split sigma (FP64 subspace algebra) against the FP64 oracle."""
+    note("hh reduced precision", prec)
+    nocc, nvir, naux = 14, 30, 90
+    eps, L = problem(50, nocc, nvir, naux)
+    ref = O.solve(eps, L, nocc, "singlet", 6, channel="hh")
+    with P.PpRPA(eps, L, nocc, prec=prec) as ctx:
+        r = ctx.davidson(6, block=6, tol=1e-6 if prec == "fp32" else 1e-5, channel="hh")
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-6
+
+
 def test_hh_argument_checks():
     note("hh argument checks")
     eps, L = problem(49, 4, 10, 20)

@@ -51,7 +51,17 @@ MIX = [  # (seed, nocc, nvir, mult, nroot, prec)
     (17, 20, 150, "singlet", 8, "fp64"),
     (18, 5, 60, "singlet", 7, "bf16x6"),
     (19, 9, 80, "triplet", 6, "bf16x6"),
+    (20, 7, 55, "singlet", 5, "bf16x3"),
 ]
+
+
+# residual tolerance per sigma precision (the three-product BF16 split leaves a residual floor
+# near 1e-6; the eigenvalue error, quadratic in the residual, stays far below 1e-6 Ha)
+TOL = {"bf16x3": 1e-5}
+
+
+def tol_of(prec):
+    return TOL.get(prec, 1e-7)
 
 
 def naux_of(nocc, nvir):
@@ -64,7 +74,7 @@ def serve(reqs, budget=8 << 30, max_inflight=8, inputs=None):
         tickets = []
         for i, (seed, nocc, nvir, mult, nroot, prec) in enumerate(reqs):
             eps, L = inputs[i] if inputs else device_inputs(seed, nocc, nvir, naux_of(nocc, nvir))
-            tickets.append(srv.submit(eps, L, nocc, nroot, mult=mult, prec=prec, tol=1e-7))
+            tickets.append(srv.submit(eps, L, nocc, nroot, mult=mult, prec=prec, tol=tol_of(prec)))
         for i, t in enumerate(tickets):
             out[i] = srv.wait(t, timeout=120.0)
         stats = srv.stats()
@@ -104,17 +114,17 @@ def test_alone_equals_mix(served_mix, mix_inputs, i):
     assert alone[0]["report"]["iters"] == res[i]["report"]["iters"]
 
 
-@pytest.mark.parametrize("i", [0, 1, 4, 6, 7, 8])
+@pytest.mark.parametrize("i", [0, 1, 4, 6, 7, 8, 9])
 def test_mix_equals_standalone_context(served_mix, mix_inputs, i):
     res, _ = served_mix
     seed, nocc, nvir, mult, nroot, prec = MIX[i]
     eps, L = mix_inputs[i]
     with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
-        r = ctx.davidson(nroot, tol=1e-7)
+        r = ctx.davidson(nroot, tol=tol_of(prec))
     assert np.array_equal(r["omega"], res[i]["omega"]), (r["omega"] - res[i]["omega"])
 
 
-@pytest.mark.parametrize("i", [0, 2, 4, 7, 8])
+@pytest.mark.parametrize("i", [0, 2, 4, 7, 8, 9])
 def test_small_requests_vs_oracle(served_mix, i):
     res, _ = served_mix
     seed, nocc, nvir, mult, nroot, prec = MIX[i]
