@@ -597,9 +597,11 @@ __device__ __forceinline__ void tri_householder(double* G, int m, double* d, dou
 // The nsel eigenvalues of T at the wanted end (channel 0, pp: the largest, theta[0] largest;
 // channel 1, hh: the smallest, theta[0] smallest), the count of roots of the channel's sign
 // (*npos: positive theta for pp, negative for hh), and their eigenvectors X[j][0..m) (global
-// scratch: 4 nsel m doubles from X). e2: LDS scratch.
+// scratch: 4 nsel m doubles from X). e2, lo_s, hi_s (nsel each): LDS scratch; xs: LDS scratch of
+// 4 nsel m doubles for the inverse iteration, or null (then it works in X). nsel <= WG.
 __device__ __forceinline__ void tri_eigen(const double* d, const double* e, double* e2, int m, int nsel,
-                          int channel, double* theta, int* npos, double* X, double* red) {
+                          int channel, double* theta, int* npos, double* X, double* red,
+                          double* lo_s, double* hi_s, double* xs) {
   const int t = threadIdx.x;
   for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
   double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
@@ -617,26 +619,56 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
     const int nbelow = sturm_below(d, e2, m, 0.0, tiny);
     *npos = channel == 0 ? m - nbelow : nbelow;
   }
-  // bisection (thread j: the j-th from the wanted end)
-  if (t < nsel) {
-    const int idx = channel == 0 ? m - 1 - t : t;  // ascending index
-    double lo = gmin - 1e-12 * tnorm, hi = gmax + 1e-12 * tnorm;
-    for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (sturm_below(d, e2, m, mid, tiny) <= idx)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    theta[t] = 0.5 * (lo + hi);
+  // multisection: root j (the j-th from the wanted end) gets G threads, which evaluate the
+  // Sturm count at G interior points of its bracket per round; the bracket shrinks to the two
+  // neighbouring points that enclose the root's index, until its width is at the rounding level
+  const int G = max(1, min(32, WG / max(nsel, 1)));
+  for (int j = t; j < nsel; j += WG) {
+    lo_s[j] = gmin - 1e-12 * tnorm;
+    hi_s[j] = gmax + 1e-12 * tnorm;
   }
+  __syncthreads();
+  for (int round = 0; round < 200; ++round) {
+    const int j = t / G, g = t % G;
+    double cnt = -1.0;  // -1: not evaluated
+    if (j < nsel) {
+      const double lo = lo_s[j], hi = hi_s[j];
+      const double x = lo + (hi - lo) * (double)(g + 1) / (double)(G + 1);
+      if (hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny && x > lo && x < hi)
+        cnt = (double)sturm_below(d, e2, m, x, tiny);
+    }
+    red[t] = cnt;
+    __syncthreads();
+    int moved = 0;
+    if (t < nsel) {
+      const int idx = channel == 0 ? m - 1 - t : t;  // ascending index
+      const double lo = lo_s[t], hi = hi_s[t];
+      double nlo = lo, nhi = hi;
+      for (int q = 0; q < G; ++q) {
+        const double c = red[t * G + q];
+        if (c < 0.0) continue;
+        moved = 1;
+        const double x = lo + (hi - lo) * (double)(q + 1) / (double)(G + 1);
+        if (c <= (double)idx)
+          nlo = fmax(nlo, x);
+        else
+          nhi = fmin(nhi, x);
+      }
+      if (nlo <= nhi) {
+        lo_s[t] = nlo;
+        hi_s[t] = nhi;
+      }
+    }
+    if (!__syncthreads_or(moved)) break;
+  }
+  for (int j = t; j < nsel; j += WG) theta[j] = 0.5 * (lo_s[j] + hi_s[j]);
   __syncthreads();
   // inverse iteration (thread j): (T - theta I) y = b by Gaussian elimination with partial
   // pivoting on the tridiagonal (fill-in: a second superdiagonal), three solves
   if (t < nsel) {
-    double* y = X + (size_t)t * m;
-    double* U0 = X + (size_t)nsel * m + (size_t)t * 3 * m;
+    double* const base = xs ? xs : X;
+    double* y = base + (size_t)t * m;
+    double* U0 = base + (size_t)nsel * m + (size_t)t * 3 * m;
     double* U1 = U0 + m;
     double* U2 = U1 + m;
     const double th = theta[t];
@@ -694,6 +726,8 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
       const double inv = 1.0 / sqrt(nrm2);
       for (int i = 0; i < m; ++i) y[i] *= inv;
     }
+    if (xs)  // the vector goes on to the orthonormalisation and back-transformation in X
+      for (int i = 0; i < m; ++i) X[(size_t)t * m + i] = y[i];
   }
   __syncthreads();
   // vectors of nearly equal theta: orthonormalise in order (modified Gram-Schmidt)
@@ -815,7 +849,7 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
     }
     return;
   }
-  tri_eigen(d, e, e2, m, nroot, channel, theta, &npos_s, X, red);
+  tri_eigen(d, e, e2, m, nroot, channel, theta, &npos_s, X, red, vv, pq, nullptr);
   tri_back_transform(G, m, beta, X, nroot);
   tri_outputs(Ri, X, theta, m, nroot, nroot, npos_s, mu2, omega, Cout, ldc, info);
 }
@@ -1027,9 +1061,19 @@ __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
   }
   tri_householder(G, m, d, e, beta, vv, pq, red);
   const int nsel = nret < m ? nret : m;
-  tri_eigen(d, e, e2, m, nsel, channel, theta, npos_s, X, red);
+  // with the matrices in LDS (Gt given): R^-1 moves to the global staging area and its LDS
+  // holds the inverse-iteration rows when they fit (B spans PLDS^2 doubles)
+  double* Rinv = B;
+  double* xs = nullptr;
+  if (Gt && (size_t)4 * nsel * m <= (size_t)PLDS * PLDS) {
+    for (int e_ = threadIdx.x; e_ < m * m; e_ += WG) Gt[e_] = B[e_];
+    __syncthreads();
+    Rinv = Gt;
+    xs = B;
+  }
+  tri_eigen(d, e, e2, m, nsel, channel, theta, npos_s, X, red, vv, pq, xs);
   tri_back_transform(G, m, beta, X, nsel);
-  tri_outputs(B, X, theta, m, nroot, nsel, *npos_s, mu2, omega, Cout, ldc, info);
+  tri_outputs(Rinv, X, theta, m, nroot, nsel, *npos_s, mu2, omega, Cout, ldc, info);
 }
 
 // m <= PLDS: K, R, G in LDS (G over K); work: m^2 (G staging) + 4 nret m.
@@ -1238,7 +1282,7 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2,
                          int nroot, int nret, int channel, double* omega, double* Cout, int ldc,
                          double* work, int* info, hipStream_t s) {
-  if (m > JMAX || nret > m || nroot > nret || (channel != 0 && channel != 1))
+  if (m > JMAX || nret > m || nroot > nret || nret > WG || (channel != 0 && channel != 1))
     return hipErrorInvalidValue;
   if (m <= PLDS)
     hipLaunchKernelGGL(k_pencil_tri, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
