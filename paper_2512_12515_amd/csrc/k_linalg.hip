@@ -324,14 +324,15 @@ __global__ void k_fill(double* __restrict__ p, size_t n, double v) {
 constexpr int WG = 1024;
 constexpr int JMAX = 512;  // largest matrix order of the one-workgroup dense solvers
 
+// Workgroup-wide sum / min / max (every thread calls it; every thread gets the result): a
+// butterfly within each wave, then the WG / 64 wave results in a fixed order (deterministic).
+// The first barrier also orders the caller's earlier LDS writes.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int h = WG / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int w = 1; w < WG / 64; ++w) r += red[w];
   __syncthreads();
   return r;
 }
@@ -466,15 +467,14 @@ __device__ __forceinline__ int sturm_below(const double* d, const double* e2, in
 }
 
 __device__ __forceinline__ double block_reduce(double v, double* red, bool is_max) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = WG / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
-      red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], red[threadIdx.x + h])
-                                : fmin(red[threadIdx.x], red[threadIdx.x + h]);
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    v = is_max ? fmax(v, o) : fmin(v, o);
   }
-  const double r = red[0];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < WG / 64; ++w) r = is_max ? fmax(r, red[w]) : fmin(r, red[w]);
   __syncthreads();
   return r;
 }
