@@ -480,8 +480,9 @@ __device__ __forceinline__ double block_reduce(double v, double* red, bool is_ma
 }
 
 // Cholesky of A (m x m, row-major, ld m) in place: lower R. Returns false if A is not positive
-// definite (uniform across the workgroup).
-__device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag) {
+// definite (uniform across the workgroup). col: scratch of m doubles (LDS when A is in global
+// memory: the scaled column j is read from there by the trailing update, or null).
+__device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag, double* col = nullptr) {
   const int t = threadIdx.x;
   if (t == 0) *flag = 0;
   __syncthreads();
@@ -494,13 +495,17 @@ __device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag) {
     }
     const double rjj = sqrt(dj);
     __syncthreads();
-    for (int i = j + 1 + t; i < m; i += WG) A[i * m + j] /= rjj;
+    for (int i = j + 1 + t; i < m; i += WG) {
+      const double v = A[i * m + j] / rjj;
+      A[i * m + j] = v;
+      if (col) col[i] = v;
+    }
     if (t == 0) A[j * m + j] = rjj;
     __syncthreads();
     const int nt = m - j - 1;
     for (int e_ = t; e_ < nt * nt; e_ += WG) {
       const int i = j + 1 + e_ / nt, k = j + 1 + e_ % nt;
-      if (k <= i) A[i * m + k] -= A[i * m + j] * A[k * m + j];
+      if (k <= i) A[i * m + k] -= col ? col[i] * col[k] : A[i * m + j] * A[k * m + j];
     }
     __syncthreads();
   }
@@ -508,14 +513,24 @@ __device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag) {
 }
 
 // Ri = R^-1 (lower) by forward substitution, one row at a time, the row's columns in parallel.
-__device__ __forceinline__ void tri_inverse(const double* A, double* Ri, int m) {
+// RiT: scratch of m^2 doubles (global matrices) that keeps the transposed copy, so that thread c
+// reads its column c of R^-1 as a contiguous row, or null.
+__device__ __forceinline__ void tri_inverse(const double* A, double* Ri, int m,
+                                            double* RiT = nullptr) {
   const int t = threadIdx.x;
   for (int i = 0; i < m; ++i) {
     const double rii = A[i * m + i];
     for (int c = t; c <= i; c += WG) {
       double s = (c == i) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= A[i * m + k] * Ri[k * m + c];
-      Ri[i * m + c] = s / rii;
+      if (RiT) {
+        const double* rc = RiT + (size_t)c * m;
+        for (int k = c; k < i; ++k) s -= A[i * m + k] * rc[k];
+      } else {
+        for (int k = c; k < i; ++k) s -= A[i * m + k] * Ri[k * m + c];
+      }
+      const double v = s / rii;
+      Ri[i * m + c] = v;
+      if (RiT) RiT[(size_t)c * m + i] = v;
     }
     for (int c = i + 1 + t; c < m; c += WG) Ri[i * m + c] = 0.0;
     __syncthreads();
@@ -810,8 +825,8 @@ __device__ __forceinline__ bool dense_pencil_tridiag(const double* __restrict__ 
     A[e_] = M[(size_t)i * m + j] - (i == j ? mu2 * (i < nvv ? 1.0 : -1.0) : 0.0);
   }
   __syncthreads();
-  if (!tri_cholesky(A, m, flag)) return false;
-  tri_inverse(A, Ri, m);
+  if (!tri_cholesky(A, m, flag, vv)) return false;
+  tri_inverse(A, Ri, m, G);  // G holds the transposed copy until G itself is formed
   // G = R^-1 W R^-T with W diagonal (both triangles)
   for (int e_ = t; e_ < m * m; e_ += WG) {
     const int i = e_ / m, j = e_ % m;
@@ -1025,7 +1040,10 @@ __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
     A[e_] = Ms[a * ldm + b] - mu2 * Ws[a * ldm + b];
   }
   __syncthreads();
-  if (!tri_cholesky(A, m, flag)) {
+  // matrices in global memory (no LDS staging Gt): the Cholesky column goes through LDS (vv)
+  // and G's storage, free until G is formed, keeps R^-1 transposed for the substitution
+  const bool global = Gt == nullptr;
+  if (!tri_cholesky(A, m, flag, global ? vv : nullptr)) {
     if (t == 0) {
       info[0] = 1;
       info[1] = 0;
@@ -1033,7 +1051,7 @@ __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
     }
     return;
   }
-  tri_inverse(A, B, m);  // B = R^-1
+  tri_inverse(A, B, m, global ? G : nullptr);  // B = R^-1
   // Y = R^-1 Wsym into A (R is no longer needed), then G = Y R^-T
   for (int e_ = t; e_ < m * m; e_ += WG) {
     const int i = e_ / m, j = e_ % m;
