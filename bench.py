@@ -174,17 +174,16 @@ def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, pre
                      message=r["message"][:80])
                 for i, r in sorted(res.items()) if r["status"] != P.binding.OK]
     n_sigma = sum(r["report"]["n_sigma"] for r in ok)
-    # accuracy: the smallest served requests against the oracle
-    from oracle import pprpa_oracle as O
-    small = sorted(res, key=lambda i: reqs[i]["nvir"] + reqs[i]["nocc"])[:6]
+    # accuracy: the six smallest served requests against the oracle's stored roots (every request
+    # of the mix with at most 100 orbitals, tests/golden/serving_small.json)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "serving_small.json")))["roots"]
+    small = sorted((i for i in res if str(reqs[i]["rid"]) in gold),
+                   key=lambda i: reqs[i]["nvir"] + reqs[i]["nocc"])[:6]
     errs = []
     for i in small:
-        r = reqs[i]
         if res[i]["status"] != P.binding.OK:
             continue
-        ref = O.solve(gen.orbital_energies(r["seed"], r["nocc"], r["nvir"]),
-                      gen.lpq_full(r["seed"], r["nocc"] + r["nvir"], r["naux"]) * r["eig_scale"],
-                      r["nocc"], r["mult"], r["nroot"])
+        ref = np.array(gold[str(reqs[i]["rid"])])
         errs.append(float(np.max(np.abs(res[i]["omega"] - ref))))
     peak = PEAK_FP64 if prec == "fp64" else PEAK_FP32
     tf = st["sigma_flops"] / st["sigma_seconds"] if st["sigma_seconds"] > 0 else 0.0

@@ -8,6 +8,7 @@ paper prints no worked example for this path, so every stored value here is the 
     python tests/golden/make_golden.py hh         # the same, hh channel (minutes)
     python tests/golden/make_golden.py energy     # correlation energies, 5 x 20 x 100 (seconds)
     python tests/golden/make_golden.py unrestricted  # three spin sectors, nmo 60 (seconds)
+    python tests/golden/make_golden.py serving    # small requests of the serving mix (minutes)
 """
 import json
 import os
@@ -86,12 +87,33 @@ def run_unrestricted(name, nmo, nocc_a, nocc_b, naux, seed, nroot):
         json.dump(out, f, indent=1)
 
 
+def run_serving(name, count, max_nmo):
+    """Roots of every request of the serving mix (gen.serve_requests(0, count)) with at most
+    max_nmo orbitals, integrals scaled by the request's eig_scale."""
+    out = dict(source="oracle/pprpa_oracle.py, dense build + route D",
+               inputs=f"workloads/gen.py: serve_requests(0, {count}); request r: orbital_energies(r, nocc, "
+                      "nvir), lpq_full(r, nocc + nvir, naux) * eig_scale",
+               units="Hartree", count=count, max_nmo=max_nmo, roots={})
+    for r in gen.serve_requests(0, count):
+        if r["nocc"] + r["nvir"] > max_nmo:
+            continue
+        eps = gen.orbital_energies(r["seed"], r["nocc"], r["nvir"])
+        L = gen.lpq_full(r["seed"], r["nocc"] + r["nvir"], r["naux"]) * r["eig_scale"]
+        om = O.solve(eps, L, r["nocc"], r["mult"], r["nroot"])
+        out["roots"][str(r["rid"])] = [float(x) for x in om]
+    print(name, len(out["roots"]), "requests", flush=True)
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["small"]
     if "small" in which:
         run("small_direct", 5, 20, 100, (0, 1, 2, 3, 4), ("singlet", "triplet"), 5)
     if "davidson" in which:
         run("davidson_fp64", 20, 200, 700, (0,), ("singlet", "triplet"), 10)
+    if "serving" in which:
+        run_serving("serving_small", 512, 100)
     if "unrestricted" in which:
         run_unrestricted("unrestricted", 60, 10, 9, 200, 0, 8)
     if "energy" in which:
