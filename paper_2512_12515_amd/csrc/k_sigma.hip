@@ -31,8 +31,9 @@
 //     segment in HBM;
 //   * the aux index is split over workgroups; partial Q per split are summed in the epilogue in
 //     a fixed order (deterministic);
-//   * workgroup ids are remapped so the 8 XCDs each take a contiguous range of work units, which
-//     share P ranges and vectors in that XCD's L2.
+//   * workgroup ids are remapped so the 8 XCDs each take a contiguous range of work units; the
+//     vector index runs fastest within it, so the units of one (panel, P range) over all vectors
+//     run at the same time on one XCD and read its L^P tiles from that XCD's L2.
 #include "internal.h"
 #include "sigma_common.h"
 
@@ -238,8 +239,8 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   constexpr int GRP = 2;  // tiles per unrolled MFMA group
   static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
 
-  const int item = a.items[u % a.nitems];
-  const int kv = (u / a.nitems) % a.k;
+  const int item = a.items[(u / a.k) % a.nitems];
+  const int kv = u % a.k;
   const int sp = u / (a.nitems * a.k);
   const int pn = item >> 16;
   const int R0 = item & 0xFFFF;  // first row tile of the range (local to the block)

@@ -123,8 +123,8 @@ __device__ __forceinline__ void sandwich_bf16_cols(const u16* __restrict__ L, si
   constexpr int NPROD = 6, NPL = 3;
   using Cfg = Bf16ColsCfg;
   constexpr int CT = Cfg::CT, RH = Cfg::RH;
-  const int item = a.items[u % a.nitems];
-  const int kv = (u / a.nitems) % a.k;
+  const int item = a.items[(u / a.k) % a.nitems];
+  const int kv = u % a.k;
   const int sp = u / (a.nitems * a.k);
   const int pn = item >> 16;
   const int R0 = item & 0xFFFF;
@@ -277,8 +277,8 @@ __device__ __forceinline__ void sandwich_bf16_rows(const u16* __restrict__ L, si
                                                    int u, u16* __restrict__ buf) {
   constexpr int NPROD = 3, NPL = 2;  // planes used: hi, mid
   using Cfg = Bf16RowsCfg;
-  const int item = a.items[u % a.nitems];
-  const int kv = (u / a.nitems) % a.k;
+  const int item = a.items[(u / a.k) % a.nitems];
+  const int kv = u % a.k;
   const int sp = u / (a.nitems * a.k);
   const int pn = item >> 16;
   const int R0 = item & 0xFFFF;

@@ -6,7 +6,8 @@
 namespace pprpa {
 
 // One sigma product's decomposition into work units (one workgroup each): unit u ->
-// (work item u % nitems, vector (u / nitems) % k, aux split u / (nitems k)).
+// (vector u % k, work item (u / k) % nitems, aux split u / (nitems k)). The vector index runs
+// fastest, so the k units that stage the same L^P tiles are launched together.
 struct SandParams {
   int nvp, nop, nmop, nvt, nct, naux;
   int k, nsplit, nitems, nunits, per_xcd;
