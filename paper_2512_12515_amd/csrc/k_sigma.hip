@@ -238,6 +238,7 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   using Cfg = SandCfg<T, CT, RT>;
   constexpr int GRP = 2;  // tiles per unrolled MFMA group
   static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
+  static_assert(2 * CT * 4 * 64 <= Cfg::BUF, "T exchange of a two-column panel fits the buffer");
 
   const int item = a.items[(u / a.k) % a.nitems];
   const int kv = u % a.k;
@@ -254,12 +255,14 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   // scalar branches
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  // a panel of one or two column tiles gives the waves it has no column for a share of the rows
-  // instead (each wave of a column computes its own copy of T); a three-tile panel idles one wave
+  // a panel of one or two column tiles puts parts = 4 / npt waves on each column: in
+  // contraction 1 they share out the column's c groups (g % parts == rsel), exchange their T
+  // tiles through LDS, and in contraction 2 they share out its row groups the same way; a
+  // three-tile panel idles one wave
   const int parts = npt == 1 ? 4 : (npt == 2 ? 2 : 1);
   const bool active = w < npt * parts;
   const int wc = parts == 1 ? min(w, npt - 1) : w % npt;  // column tile (idle waves: the last)
-  const int rsel = parts == 1 ? 0 : w / npt;               // row groups g with g % parts == rsel
+  const int rsel = parts == 1 ? 0 : w / npt;               // c and row groups g with g % parts == rsel
   const int rend = min(bnt, R0 + RT);
   const int nrt = rend - R0;
   const int col0 = brow0 + t0 * TILE;
@@ -313,7 +316,7 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
               for (int grp = 0; grp < CT / GRP; ++grp) {
                 const int cg = cc0 + GRP * grp;
                 // groups that reach past d multiply exact zeros of U^T (c > d)
-                if (active && cg >= q0 && cg < q1) {
+                if (active && cg >= q0 && cg < q1 && grp % parts == rsel) {
                   // all four k steps of the group's A operands first: one LDS wait per group
                   T av[4][GRP];
 #pragma unroll
@@ -332,6 +335,24 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
             }
           }
         }
+      }
+      if (parts > 1) {
+        // narrow panel: every wave of a column takes the T tiles of the other waves' c groups
+        // (same values, same summation order as computing them itself); layout [col][tile][reg]
+        // [lane], conflict-free
+        T* const sT = buf;
+        __syncthreads();  // contraction-1 operands no longer read
+#pragma unroll
+        for (int i = 0; i < CT; ++i)
+          if ((i / GRP) % parts == rsel)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sT[((wc * CT + i) * 4 + j) * 64 + lane] = Tacc[i][j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CT; ++i)
+          if ((i / GRP) % parts != rsel)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Tacc[i][j] = sT[((wc * CT + i) * 4 + j) * 64 + lane];
       }
       // contraction 2: Q[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers, two c tiles
       // per stage
