@@ -111,26 +111,40 @@ __global__ __launch_bounds__(64 * DOT_WAVES) void k_dots(const double* __restric
   }
 }
 
-// C[i][j] = sum over chunks of part[c][i][j]: 64 elements per workgroup, four threads per
-// element, thread q summing chunks q, q + 4, ... in order; the four sums are added in a fixed
-// order (deterministic).
+// C[i][j] = sum over chunks of part[c][i][j]: 16 elements per workgroup, sixteen threads per
+// element (16 consecutive elements of one chunk are one 128-byte segment), thread q summing
+// chunks q, q + 16, ... in order; the sixteen sums are added in a fixed order (deterministic).
+constexpr int RED_T = 16;  // threads per element of k_dots_reduce
 __global__ __launch_bounds__(256) void k_dots_reduce(const double* __restrict__ part, int nchunk,
                                                      int ma, int mb, double* __restrict__ C,
                                                      int ldc) {
-  __shared__ double red[4][64];
-  const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int p = blockIdx.x * 64 + e;
-  const size_t stride = (size_t)ma * mb;
+  __shared__ double red[RED_T][17];
+  const int e = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int nel = ma * mb;
+  const int p = blockIdx.x * 16 + e;
+  const size_t stride = (size_t)nel;
+  const double* src = part + (p < nel ? p : nel - 1);
   double s = 0.0;
-  if (p < ma * mb) {
-    const double* src = part + p;
-#pragma unroll 4
-    for (int c = q; c < nchunk; c += 4) s += src[(size_t)c * stride];
+  // chunks q, q + 16, ... in order, four loads at a time (indices clamped, loads unguarded; the
+  // partial sums are finite, so the steps past the end add exact zeros)
+  for (int c0 = q; c0 < nchunk; c0 += 4 * RED_T) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * RED_T;
+      v[u] = src[(size_t)(c < nchunk ? c : nchunk - 1) * stride] * (c < nchunk ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u];
   }
   red[q][e] = s;
   __syncthreads();
-  if (q == 0 && p < ma * mb)
-    C[(p / mb) * ldc + (p % mb)] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+  if (q == 0 && p < nel) {
+    double t = red[0][e];
+#pragma unroll
+    for (int i = 1; i < RED_T; ++i) t += red[i][e];
+    C[(p / mb) * ldc + (p % mb)] = t;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -166,27 +180,51 @@ __global__ __launch_bounds__(64 * CMB_WAVES) void k_combine(const double* __rest
   for (int J = 0; J < NJ; ++J)
 #pragma unroll
     for (int c = 0; c < CMB_CT; ++c) acc[J][c] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int i0 = 0; i0 < m; i0 += 4) {
-    const int i = i0 + lk;
-    const bool iok = i < m;
-    const double* xr = X + (int64_t)(iok ? i : m - 1) * ldx;
-    const double* cr = Cm + (int64_t)(iok ? i : m - 1) * ldcm;
-    double xb[CMB_CT], ca[NJ];
+  // four k steps per iteration. Every address is clamped into its row and no load is guarded
+  // (so the loads of an iteration are issued together): steps past m get a zero coefficient
+  // (the clamped X row is finite data), and the products landing in columns past n or rows past
+  // r are never stored
+  constexpr int KU = 4;
+  for (int i0 = 0; i0 < m; i0 += 4 * KU) {
+    double xb[KU][CMB_CT], ca[KU][NJ];
 #pragma unroll
-    for (int c = 0; c < CMB_CT; ++c) xb[c] = (iok && tok[c]) ? xr[tc[c]] : 0.0;
+    for (int u = 0; u < KU; ++u) {
+      const int i = i0 + 4 * u + lk;
+      const bool iok = i < m;
+      const double keep = iok ? 1.0 : 0.0;
+      const double* xr = X + (int64_t)(iok ? i : m - 1) * ldx;
+      const double* cr = Cm + (int64_t)(iok ? i : m - 1) * ldcm;
 #pragma unroll
-    for (int J = 0; J < NJ; ++J) {
-      const int j = 16 * J + li;
-      ca[J] = (iok && j < r) ? cr[j] : 0.0;
+      for (int c = 0; c < CMB_CT; ++c) xb[u][c] = xr[tc[c]];
+#pragma unroll
+      for (int J = 0; J < NJ; ++J) {
+        const int j = 16 * J + li;
+        ca[u][J] = cr[j < r ? j : r - 1] * keep;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int J = 0; J < NJ; ++J)
+#pragma unroll
+        for (int c = 0; c < CMB_CT; ++c)
+          acc[J][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][J], xb[u][c], acc[J][c], 0, 0, 0);
+  }
+  // accumulator register q of lane (li, lk) holds row lk + 4 q, column li of the tile
+  // the old values of Y first, all at once (rows clamped below r, columns clamped into the
+  // row), then the stores
+  double yv[NJ][4][CMB_CT];
+  if (beta != 0.0) {
 #pragma unroll
     for (int J = 0; J < NJ; ++J)
 #pragma unroll
-      for (int c = 0; c < CMB_CT; ++c)
-        acc[J][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[J], xb[c], acc[J][c], 0, 0, 0);
+      for (int q = 0; q < 4; ++q) {
+        const int j = 16 * J + lk + 4 * q;
+        const double* y = Y + (int64_t)(j < r ? j : r - 1) * ldy;
+#pragma unroll
+        for (int c = 0; c < CMB_CT; ++c) yv[J][q][c] = y[tc[c]];
+      }
   }
-  // accumulator register q of lane (li, lk) holds row lk + 4 q, column li of the tile
 #pragma unroll
   for (int J = 0; J < NJ; ++J)
 #pragma unroll
@@ -198,7 +236,7 @@ __global__ __launch_bounds__(64 * CMB_WAVES) void k_combine(const double* __rest
       for (int c = 0; c < CMB_CT; ++c)
         if (tok[c]) {
           const double v = alpha * acc[J][c][q];
-          y[tc[c]] = beta == 0.0 ? v : beta * y[tc[c]] + v;
+          y[tc[c]] = beta == 0.0 ? v : beta * yv[J][q][c] + v;
         }
     }
 }
@@ -1250,7 +1288,7 @@ hipError_t launch_dots(const double* A, int64_t lda, int ma, const double* B, in
                      signed_w, chunk, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_reduce, dim3((ma * mb + 63) / 64), dim3(256), 0, s, part, nch, ma,
+  hipLaunchKernelGGL(k_dots_reduce, dim3((ma * mb + 15) / 16), dim3(256), 0, s, part, nch, ma,
                      mb, C, ldc);
   return hipGetLastError();
 }

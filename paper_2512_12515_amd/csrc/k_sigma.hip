@@ -476,12 +476,17 @@ __global__ __launch_bounds__(256) void k_epilogue(const double* __restrict__ z, 
   const T* Q = Sp + (int64_t)kv * nmop * nmop;
   const int64_t ia = (int64_t)(off + pa) * nmop + off + qa;
   const int64_t ib = (int64_t)(off + pb) * nmop + off + qb;
+  // both elements lie in the padded block, which every split writes in full: the loads are
+  // unconditional (so that the unrolled iterations issue them together), the padding is
+  // discarded afterwards
   double a = 0.0, b = 0.0;
 #pragma unroll 8
   for (int t = 0; t < nsplit; ++t) {
-    if (oka) a += (double)Q[t * split_stride + ia];
-    if (okb) b += (double)Q[t * split_stride + ib];
+    a += (double)Q[t * split_stride + ia];
+    b += (double)Q[t * split_stride + ib];
   }
+  if (!oka) a = 0.0;
+  if (!okb) b = 0.0;
   mirror[r][c] = b;
   __syncthreads();
   const int k = mult == 0 ? 0 : 1;
