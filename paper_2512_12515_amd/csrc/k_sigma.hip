@@ -218,8 +218,10 @@ struct SandCfg {
   static constexpr int SR1 = 3 * TILE;                            // contraction-1 rows (3 tiles)
   static constexpr int SR = 2 * TILE;                             // contraction-2 rows (2 tiles)
   static constexpr int S1 = SR1 * CT * TILE + SR1 * 4 * TILE;    // contraction-1 stage
-  static constexpr int S2 = SR * RT * TILE;                      // contraction-2 stage
-  static constexpr int BUF = S1 > S2 ? S1 : S2;                  // elements per LDS buffer
+  static constexpr int S2 = SR * RT * TILE;                      // contraction-2 stage, full rows
+  // elements per LDS buffer (two workgroups per CU leave room for small kernels beside them; a
+  // contraction-2 stage holds as many c tiles as fit at its row width)
+  static constexpr int BUF = S1 > S2 ? S1 : S2;
   static constexpr int VEC = 16 / sizeof(T);                     // elements per lane per load
   static constexpr int CHUNK = 1024 / sizeof(T);                 // elements per wave load
 };
@@ -239,6 +241,8 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   constexpr int GRP = 2;  // tiles per unrolled MFMA group
   static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
   static_assert(2 * CT * 4 * 64 <= Cfg::BUF, "T exchange of a two-column panel fits the buffer");
+  static_assert(2 * TILE * RT * TILE <= Cfg::BUF && 2 * TILE * (RT - 1) * TILE + TILE <= Cfg::BUF,
+                "two contraction-2 c tiles at any row count");
 
   const int item = a.items[(u / a.k) % a.nitems];
   const int kv = u % a.k;
@@ -269,6 +273,10 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
   const int ncol = npt * TILE;
   const int row0 = brow0 + R0 * TILE;
   const int wl = nrt * TILE;  // row stride of a staged L^P row tile (contraction 2)
+  // c tiles per contraction-2 stage: FP32 takes as many as the buffer holds at this row width
+  // (>= 2; with an odd row count TILE elements stay free past the last one for the unused second
+  // tile of the last row group), FP64 two (wider FP64 stages measured ~1 % slower in the solve)
+  const int nb2 = sizeof(T) == 8 ? 2 : min(CT, (Cfg::BUF - ((nrt & 1) ? TILE : 0)) / (TILE * wl));
   const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
   const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
   const T* __restrict__ Z = UT + (int64_t)kv * a.zstride;
@@ -354,41 +362,43 @@ __device__ __forceinline__ void sandwich_unit(const T* __restrict__ L, const T* 
 #pragma unroll
             for (int j = 0; j < 4; ++j) Tacc[i][j] = sT[((wc * CT + i) * 4 + j) * 64 + lane];
       }
-      // contraction 2: Q[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers, two c tiles
+      // contraction 2: Q[r][cols] += sum_c L^P[r][c] T[c][cols], T from registers, nb2 c tiles
       // per stage
+      // slot of c tile i in its stage: i % 2 for FP64 (known at compile time), a running count
+      // for FP32 (a run-time i % nb2 made the FP32 kernel ~15 % slower)
+      int run = 0;
 #pragma unroll
-      for (int i = 0; i < CT; i += 2) {
+      for (int i = 0; i < CT; ++i) {
         if (cc0 + i < cc1) {
-          const int nb = min(2, cc1 - cc0 - i);
-          __syncthreads();
-          dma_tile(Lp + (int64_t)((cc0 + i) * TILE) * a.nmop + row0, a.nmop, nb * TILE, wl, buf, w, lane);
-          __builtin_amdgcn_s_waitcnt(0);
-          __syncthreads();
+          const int slot = sizeof(T) == 8 ? i % 2 : run;
+          if (slot == 0) {
+            const int nb = min(nb2, cc1 - cc0 - i);
+            __syncthreads();
+            dma_tile(Lp + (int64_t)((cc0 + i) * TILE) * a.nmop + row0, a.nmop, nb * TILE, wl, buf, w, lane);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+          }
+          const T* sL = buf + slot * TILE * wl;
 #pragma unroll
-          for (int sub = 0; sub < 2; ++sub) {
-            if (sub < nb) {
-              const T* sL = buf + sub * TILE * wl;
+          for (int grp = 0; grp < RT / GRP; ++grp) {
+            // row tiles at or beyond nrt in the last group read other data of the buffer (in
+            // bounds); their results are never stored
+            if (active && GRP * grp < nrt && grp % parts == rsel) {
+              T av[4][GRP];
 #pragma unroll
-              for (int grp = 0; grp < RT / GRP; ++grp) {
-                // row tiles at or beyond nrt in the last group read other data of the buffer (in
-                // bounds); their results are never stored
-                if (active && GRP * grp < nrt && grp % parts == rsel) {
-                  T av[4][GRP];
+              for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-                  for (int ks = 0; ks < 4; ++ks)
+                for (int j = 0; j < GRP; ++j)
+                  av[ks][j] = sL[acc_row<T>(lk, ks) * wl + (GRP * grp + j) * TILE + li];
+              __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
 #pragma unroll
-                    for (int j = 0; j < GRP; ++j)
-                      av[ks][j] = sL[acc_row<T>(lk, ks) * wl + (GRP * grp + j) * TILE + li];
-                  __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+              for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-                  for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-                    for (int j = 0; j < GRP; ++j)
-                      S[GRP * grp + j] = mfma(av[ks][j], Tacc[i + sub][ks], S[GRP * grp + j]);
-                }
-              }
+                for (int j = 0; j < GRP; ++j)
+                  S[GRP * grp + j] = mfma(av[ks][j], Tacc[i][ks], S[GRP * grp + j]);
             }
           }
+          run = run + 1 == nb2 ? 0 : run + 1;
         }
       }
     }
