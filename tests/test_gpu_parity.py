@@ -59,6 +59,33 @@ def test_sigma_fp64(mult, case):
     assert np.array_equal(s1, s[2])  # a vector's result does not depend on the block around it
 
 
+# Virtual blocks of 5, 6 and 7 column tiles (a full four-tile panel, then a narrow one of 1, 2
+# or 3 tiles) and occupied blocks of 3, 4 and 5 tiles: every panel shape of the sigma kernels,
+# checked on sampled entries (the first and last pairs of each block and random ones) against the
+# oracle's row-by-row definition.
+PANEL_CASES = [(40, 70, 24), (50, 90, 20), (70, 110, 16)]
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("case", PANEL_CASES)
+def test_sigma_panel_mixes(case, mult, prec, rtol):
+    nocc, nvir, naux = case
+    note("sigma panel mix", prec, mult, case)
+    eps, L = problem(13, nocc, nvir, naux)
+    sp = O.active_space(eps, L, nocc)
+    with P.PpRPA(eps, L, nocc, mult=mult, prec=prec) as ctx:
+        nvv, n = ctx.n_pp, ctx.n
+        z = gen.random_vectors(6, 3, n)
+        s = ctx.matvec(z)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.r_[np.arange(4), nvv - 4 + np.arange(4), nvv + np.arange(4),
+                           n - 4 + np.arange(4), rng.integers(0, n, 24)])
+    for j in range(z.shape[0]):
+        ref = O.sigma_rows(sp, mult, rows, z[j])
+        assert np.max(np.abs(s[j, rows] - ref)) <= rtol * max(1.0, np.abs(ref).max())
+
+
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case", [(4, 9, 30), (5, 20, 100), (20, 35, 50), (17, 33, 23)])
 def test_sigma_fp32(mult, case):
