@@ -94,12 +94,19 @@ pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
  * that spin's eps, nocc and Lpq. The alpha-beta sector, pairs (a_alpha, b_beta) and
  * (i_alpha, j_beta) of every combination with the alpha index outer,
  *   A = d(e^a_a + e^b_b) + (ac|bd),  B = (ai|bj),  C = -d(e^a_i + e^b_j) + (ik|jl),
- * (pq|rs) = sum_P La^P_pq Lb^P_rs, no exchange term, is built here as a dense FP64 context:
- * pprpa_dims, pprpa_matvec (dense sigma = M z), pprpa_davidson (Davidson or direct, both
- * channels), pprpa_dense_matrix and pprpa_correlation_energy apply; pprpa_nto returns
- * EUNSUPPORTED. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO) / 2. Order n = nvir_a nvir_b
- * + nocc_a nocc_b <= 32768. Inputs (host, or device with on_device) are read during the call
- * only. Errors: EINVAL (arguments, non-finite input), ENOMEM, EDEVICE. */
+ * (pq|rs) = sum_P La^P_pq Lb^P_rs, no exchange term, is built here as an FP64 context, either
+ *  - dense (density_fitted = 0): M is built on the device and sigma = M z; pprpa_dims,
+ *    pprpa_matvec, pprpa_davidson (Davidson or direct, both channels), pprpa_dense_matrix and
+ *    pprpa_correlation_energy apply; order n = nvir_a nvir_b + nocc_a nocc_b <= 32768; or
+ *  - density fitted (density_fitted = 1): both spins' integrals are staged and sigma is
+ *    Q = sum_P La^P Z Lb^P with Z = blockdiag(X, Y) the rectangular amplitude blocks (alpha rows,
+ *    beta columns), sigma_x = (e^a_a + e^b_b) x + Q_vv, sigma_y = -(e^a_i + e^b_j) y + Q_oo; no
+ *    matrix is formed, so the order is limited by memory only (nvir, nocc < 65536);
+ *    pprpa_dims, pprpa_matvec and pprpa_davidson (Davidson, both channels) apply, the direct
+ *    solve, pprpa_dense_matrix and pprpa_correlation_energy return EUNSUPPORTED.
+ * pprpa_nto returns EUNSUPPORTED for both. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO)
+ * / 2. Inputs (host, or device with on_device) are read during the call only.
+ * Errors: EINVAL (arguments, non-finite input), ENOMEM, EDEVICE. */
 typedef struct {
   int32_t nmo;          /* orbitals per spin                                                 */
   int32_t nocc_a;       /* occupied alpha orbitals (< nmo)                                   */
@@ -112,6 +119,7 @@ typedef struct {
   int32_t on_device;
   int32_t max_block;    /* largest sigma block per call (<= 0: 32, at most 64)               */
   void* stream;         /* hipStream_t to run on, or NULL for a new non-blocking stream      */
+  int32_t density_fitted; /* 1: density-fitted sigma (no dense matrix); 0: dense context     */
 } pprpa_build_ab_args;
 pprpa_status pprpa_build_ab(const pprpa_build_ab_args* args, pprpa_ctx** out);
 

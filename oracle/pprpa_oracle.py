@@ -351,6 +351,36 @@ def ab_sector(eps_a, eps_b, La, Lb, nocc_a, nocc_b):
     return pprpa_matrix(A, B, C), nva * nvb
 
 
+def ab_sigma_rows(eps_a, eps_b, La, Lb, nocc_a, nocc_b, rows, z):
+    """Selected entries of sigma = M z in the alpha-beta sector, each from its row of M written
+    out (any size): for the pair (a, b),
+        sigma = (e^alpha_a + e^beta_b) x_ab + sum_cd (ac|bd) x_cd + sum_kl (ak|bl) y_kl,
+    for the pair (i, j),
+        sigma = sum_cd (ic|jd) x_cd + sum_kl (ik|jl) y_kl - (e^alpha_i + e^beta_j) y_ij,
+    with (pq|rs) = sum_P La^P_pq Lb^P_rs; X is nvir_a x nvir_b and Y nocc_a x nocc_b (the packed
+    order of ab_sector, alpha index outer)."""
+    nmo = eps_a.size
+    nva, nvb = nmo - nocc_a, nmo - nocc_b
+    nvv = nva * nvb
+    X = z[:nvv].reshape(nva, nvb)
+    Y = z[nvv:].reshape(nocc_a, nocc_b)
+    va, vb = np.arange(nocc_a, nmo), np.arange(nocc_b, nmo)
+    oa, ob = np.arange(nocc_a), np.arange(nocc_b)
+    out = np.empty(len(rows))
+    for t, r in enumerate(rows):
+        if r < nvv:
+            p, q = nocc_a + r // nvb, nocc_b + r % nvb
+            diag = (eps_a[p] + eps_b[q]) * z[r]
+        else:
+            p, q = (r - nvv) // nocc_b, (r - nvv) % nocc_b
+            diag = -(eps_a[p] + eps_b[q]) * z[r]
+        # sum_P [ La^P_{p,vir} X Lb^P_{vir,q} + La^P_{p,occ} Y Lb^P_{occ,q} ]
+        vv = np.einsum("Pc,cd,Pd->", La[:, p, va], X, Lb[:, q, vb])
+        oo = np.einsum("Pk,kl,Pl->", La[:, p, oa], Y, Lb[:, q, ob]) if Y.size else 0.0
+        out[t] = diag + vv + oo
+    return out
+
+
 def midgap_ab(eps_a, eps_b, nocc_a, nocc_b):
     """2 mu between the alpha-beta hh and pp pair energies: mu = (e^a_HOMO + e^b_HOMO +
     e^a_LUMO + e^b_LUMO) / 4 (the restricted mid-gap when alpha = beta)."""

@@ -48,7 +48,7 @@ class BuildAbArgs(C.Structure):
     _fields_ = [("nmo", C.c_int32), ("nocc_a", C.c_int32), ("nocc_b", C.c_int32),
                 ("naux", C.c_int32), ("eps_a", C.c_void_p), ("eps_b", C.c_void_p),
                 ("Lpq_a", C.c_void_p), ("Lpq_b", C.c_void_p), ("on_device", C.c_int32),
-                ("max_block", C.c_int32), ("stream", C.c_void_p)]
+                ("max_block", C.c_int32), ("stream", C.c_void_p), ("density_fitted", C.c_int32)]
 
 
 class DavidsonArgs(C.Structure):
@@ -228,8 +228,10 @@ class PpRPA:
         return self.nv, self.no
 
     @classmethod
-    def alpha_beta(cls, eps_a, eps_b, Lpq_a, Lpq_b, nocc_a, nocc_b, max_block=32, stream=None):
-        """The alpha-beta sector of spin-unrestricted ppRPA as a dense context (pprpa_build_ab);
+    def alpha_beta(cls, eps_a, eps_b, Lpq_a, Lpq_b, nocc_a, nocc_b, max_block=32, stream=None,
+                   density_fitted=False):
+        """The alpha-beta sector of spin-unrestricted ppRPA (pprpa_build_ab): a dense context, or
+        with density_fitted=True the density-fitted sigma of both spins' integrals (no matrix);
         the alpha-alpha and beta-beta sectors are PpRPA(eps_s, Lpq_s, nocc_s, mult="triplet")."""
         on_dev = _is_torch(Lpq_a) and Lpq_a.is_cuda
         if not on_dev:
@@ -241,6 +243,7 @@ class PpRPA:
         a.eps_a, a.eps_b = _ptr(eps_a, on_dev).value, _ptr(eps_b, on_dev).value
         a.Lpq_a, a.Lpq_b = _ptr(Lpq_a, on_dev).value, _ptr(Lpq_b, on_dev).value
         a.on_device, a.max_block, a.stream = int(on_dev), int(max_block), stream
+        a.density_fitted = int(bool(density_fitted))
         h = C.c_void_p()
         _check(lib().pprpa_build_ab(C.byref(a), C.byref(h)))
         self = cls.__new__(cls)

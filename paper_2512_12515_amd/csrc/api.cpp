@@ -108,8 +108,51 @@ constexpr int GATE_DEVICES = 64;
 SigmaGate g_gate[GATE_DEVICES];
 }  // namespace
 
+// Run one sandwich launch behind the device's sigma gate, with its timing events.
+template <typename F>
+static pprpa_status gated_launch(pprpa_ctx* c, pprpa_ctx::Timed& tm, F&& launch) {
+  if (c->device >= 0 && c->device < GATE_DEVICES) {
+    SigmaGate& gt = g_gate[c->device];
+    std::lock_guard<std::mutex> lk(gt.mu);
+    if (!gt.last) PPRPA_HIP(hipEventCreateWithFlags(&gt.last, hipEventDisableTiming));
+    PPRPA_HIP(hipStreamWaitEvent(c->stream, gt.last, 0));
+    PPRPA_HIP(hipEventRecord(tm.a, c->stream));
+    PPRPA_HIP(launch());
+    PPRPA_HIP(hipEventRecord(tm.b, c->stream));
+    PPRPA_HIP(hipEventRecord(gt.last, c->stream));
+  } else {
+    PPRPA_HIP(hipEventRecord(tm.a, c->stream));
+    PPRPA_HIP(launch());
+    PPRPA_HIP(hipEventRecord(tm.b, c->stream));
+  }
+  c->pend.push_back(tm);
+  return PPRPA_OK;
+}
+
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
   const int64_t n = c->g.n;
+  if (c->ab && c->ab_df) {  // density-fitted alpha-beta sector
+    const AbGeometry& ag = c->abg;
+    for (int k0 = 0; k0 < k; k0 += c->kcap) {
+      const int kk = std::min(c->kcap, k - k0);
+      const double* z = dz + (int64_t)k0 * n;
+      double* s = ds + (int64_t)k0 * n;
+      const int ns = nsplit_for(c, kk);
+      PPRPA_HIP(launch_unpack_ab(ag, z, kk, (double*)c->ZT, c->stream));
+      pprpa_ctx::Timed tm;
+      PPRPA_TRY(get_event(c, &tm.a));
+      PPRPA_TRY(get_event(c, &tm.b));
+      tm.flops = 2.0 * ag.naux * (double)n * ((ag.nva + ag.noa) + (ag.nvb + ag.nob)) * kk;
+      tm.bytes = (double)ag.naux * ((double)ag.nmopa * ag.nmopa + (double)ag.nmopb * ag.nmopb) * 8.0 +
+                 2.0 * kk * (double)n * 8.0;
+      PPRPA_TRY(gated_launch(c, tm, [&] {
+        return launch_sigma_ab(ag, c->plan, (const double*)c->L, c->Lb, (const double*)c->ZT,
+                               (double*)c->Sp, kk, ns, c->stream);
+      }));
+      PPRPA_HIP(launch_epilogue_ab(ag, z, kk, (const double*)c->Sp, ns, c->epair, s, c->stream));
+    }
+    return PPRPA_OK;
+  }
   if (c->ab) {  // dense context (alpha-beta sector): sigma = M z
     PPRPA_HIP(launch_dense_sigma(c->M, n, dz, k, ds, c->stream));
     return PPRPA_OK;
@@ -140,21 +183,7 @@ pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
     const double esz = c->st == Store::F64 ? 8.0 : (c->st == Store::F32 ? 4.0 : 2.0 * (c->nprod == 3 ? 2 : 3));
     tm.bytes = (double)g.naux * ((double)g.nv * g.nv + (double)g.nv * g.no + (double)g.no * g.no) * esz +
                2.0 * kk * (double)n * 8.0;
-    if (c->device >= 0 && c->device < GATE_DEVICES) {
-      SigmaGate& gt = g_gate[c->device];
-      std::lock_guard<std::mutex> lk(gt.mu);
-      if (!gt.last) PPRPA_HIP(hipEventCreateWithFlags(&gt.last, hipEventDisableTiming));
-      PPRPA_HIP(hipStreamWaitEvent(c->stream, gt.last, 0));
-      PPRPA_HIP(hipEventRecord(tm.a, c->stream));
-      PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
-      PPRPA_HIP(hipEventRecord(tm.b, c->stream));
-      PPRPA_HIP(hipEventRecord(gt.last, c->stream));
-    } else {
-      PPRPA_HIP(hipEventRecord(tm.a, c->stream));
-      PPRPA_HIP(launch_sigma(c->g, c->st, c->plan, la, c->stream));
-      PPRPA_HIP(hipEventRecord(tm.b, c->stream));
-    }
-    c->pend.push_back(tm);
+    PPRPA_TRY(gated_launch(c, tm, [&] { return launch_sigma(c->g, c->st, c->plan, la, c->stream); }));
     PPRPA_HIP(launch_epilogue(c->g, c->st, z, kk, c->Sp, ns, c->ptab, c->epair, s, c->stream));
   }
   return PPRPA_OK;
@@ -413,7 +442,8 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
 }
 
 // Alpha-beta sector of spin-unrestricted ppRPA: a dense context (the matrix built on the device,
-// sigma = M z by the dense product).
+// sigma = M z by the dense product) or a density-fitted one (both spins' integrals staged, sigma
+// by the alpha-beta sandwich kernel).
 pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
   const int nmo = a->nmo, noa = a->nocc_a, nob = a->nocc_b, naux = a->naux;
   const int nva = nmo - noa, nvb = nmo - nob;
@@ -425,8 +455,12 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
   g.nvv = (int64_t)nva * nvb;
   g.noo = (int64_t)noa * nob;
   g.n = g.nvv + g.noo;
-  if (g.n > 32768) return einval("alpha-beta sector of order %lld exceeds 32768", (long long)g.n);
+  if (!a->density_fitted && g.n > 32768)
+    return einval("dense alpha-beta sector of order %lld exceeds 32768", (long long)g.n);
+  if (nva >= 65536 || nvb >= 65536 || noa >= 65536 || nob >= 65536)
+    return einval("orbital counts must be below 65536");
   c->ab = true;
+  c->ab_df = a->density_fitted != 0;
   c->ab_nocc_b = nob;
   c->prec = PPRPA_FP64;
   c->st = Store::F64;
@@ -496,9 +530,68 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
   PPRPA_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
   PPRPA_HIP(launch_check_finite(La, per, d_bad, c->stream));
   PPRPA_HIP(launch_check_finite(Lb, per, d_bad, c->stream));
-  PPRPA_TRY(dalloc(c, (size_t)g.n * g.n * sizeof(double), (void**)&c->M));
-  PPRPA_HIP(launch_dense_build_ab(La, Lb, naux, nmo, noa, nob, g.n, g.nvv, c->ptab, c->epair, c->M,
-                                  c->stream));
+  if (c->ab_df) {
+    // both spins' integrals in the padded [virtual; occupied] layout of the sigma kernels
+    AbGeometry& ag = c->abg;
+    ag.nva = nva;
+    ag.noa = noa;
+    ag.nvb = nvb;
+    ag.nob = nob;
+    ag.naux = naux;
+    ag.nvpa = round_up(nva, TILE);
+    ag.nopa = round_up(noa, TILE);
+    ag.nmopa = ag.nvpa + ag.nopa;
+    ag.nvta = ag.nvpa / TILE;
+    ag.ncta = ag.nmopa / TILE;
+    ag.nvpb = round_up(nvb, TILE);
+    ag.nopb = round_up(nob, TILE);
+    ag.nmopb = ag.nvpb + ag.nopb;
+    ag.nvtb = ag.nvpb / TILE;
+    ag.nctb = ag.nmopb / TILE;
+    ag.nvv = g.nvv;
+    ag.noo = g.noo;
+    ag.n = g.n;
+    auto stage_spin = [&](const double* Lin, int nocc_s, int nv_s, int nvp_s, int nmop_s,
+                          double** out) -> pprpa_status {
+      std::vector<int> src(nmop_s, -1);
+      for (int r = 0; r < nv_s; ++r) src[r] = nocc_s + r;
+      for (int r = 0; r < nocc_s; ++r) src[nvp_s + r] = r;
+      int* d_src = nullptr;
+      PPRPA_TRY(dalloc(c, nmop_s * sizeof(int), (void**)&d_src));
+      PPRPA_HIP(hipMemcpyAsync(d_src, src.data(), nmop_s * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream));
+      PPRPA_TRY(dalloc(c, (size_t)naux * nmop_s * nmop_s * sizeof(double), (void**)out));
+      Geometry gs;
+      gs.nmop = nmop_s;
+      for (int p0 = 0; p0 < naux; p0 += 65535) {
+        const int np = std::min(65535, naux - p0);
+        PPRPA_HIP(launch_stage_L(gs, Store::F64, Lin + (size_t)p0 * nmo * nmo, nmo, p0, np, d_src,
+                                 *out, 0, d_bad, c->stream));
+      }
+      return PPRPA_OK;
+    };
+    double* la_p = nullptr;
+    PPRPA_TRY(stage_spin(La, noa, nva, ag.nvpa, ag.nmopa, &la_p));
+    PPRPA_TRY(stage_spin(Lb, nob, nvb, ag.nvpb, ag.nmopb, &c->Lb));
+    c->L = la_p;
+    const size_t zt = (size_t)c->kcap * ag.nmopb * ag.nmopa;
+    PPRPA_TRY(dalloc(c, zt * sizeof(double), &c->ZT));
+    PPRPA_HIP(hipMemsetAsync(c->ZT, 0, zt * sizeof(double), c->stream));
+    std::vector<int> items;
+    make_sigma_items_ab(ag, items, c->plan.npan_v);
+    c->plan.nitems = (int)items.size();
+    PPRPA_TRY(dalloc(c, items.size() * sizeof(int), (void**)&c->plan.d_items));
+    PPRPA_HIP(hipMemcpyAsync(c->plan.d_items, items.data(), items.size() * sizeof(int),
+                             hipMemcpyHostToDevice, c->stream));
+    size_t sp_max = 0;
+    for (int kk = 1; kk <= c->kcap; ++kk)
+      sp_max = std::max(sp_max, (size_t)nsplit_for(c, kk) * kk);
+    PPRPA_TRY(dalloc(c, sp_max * ag.nmopa * ag.nmopb * sizeof(double), &c->Sp));
+  } else {
+    PPRPA_TRY(dalloc(c, (size_t)g.n * g.n * sizeof(double), (void**)&c->M));
+    PPRPA_HIP(launch_dense_build_ab(La, Lb, naux, nmo, noa, nob, g.n, g.nvv, c->ptab, c->epair,
+                                    c->M, c->stream));
+  }
   PPRPA_TRY(dalloc(c, (size_t)c->kcap * g.n * sizeof(double), (void**)&c->zbuf));
   PPRPA_TRY(dalloc(c, (size_t)c->kcap * g.n * sizeof(double), (void**)&c->sbuf));
   int bad = 0;
@@ -627,6 +720,8 @@ pprpa_status pprpa_build_ab(const pprpa_build_ab_args* a, pprpa_ctx** out) {
   if (a->nocc_a < 0 || a->nocc_a >= a->nmo || a->nocc_b < 0 || a->nocc_b >= a->nmo)
     return einval("nocc_a=%d, nocc_b=%d outside [0, nmo=%d)", a->nocc_a, a->nocc_b, a->nmo);
   if (a->nmo > 65535) return einval("nmo=%d exceeds 65535", a->nmo);
+  if (a->density_fitted != 0 && a->density_fitted != 1)
+    return einval("density_fitted=%d must be 0 or 1", a->density_fitted);
   if (!a->eps_a || !a->eps_b || !a->Lpq_a || !a->Lpq_b)
     return einval("eps_a, eps_b, Lpq_a and Lpq_b must not be NULL");
   pprpa_ctx* c = new (std::nothrow) pprpa_ctx();

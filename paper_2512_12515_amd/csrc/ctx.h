@@ -32,8 +32,11 @@ struct pprpa_ctx {
 
   std::vector<double> ev_h, eo_h;  // active virtual / occupied energies (alpha for the ab sector)
   std::vector<double> epair_h;     // host copy of epair
-  bool ab = false;                 // alpha-beta sector of unrestricted ppRPA (dense only)
+  bool ab = false;                 // alpha-beta sector of unrestricted ppRPA
+  bool ab_df = false;              // ... with the density-fitted sigma (else dense: sigma = M z)
   int ab_nocc_b = 0;
+  pprpa::AbGeometry abg;           // density-fitted alpha-beta layout
+  double* Lb = nullptr;            // staged beta integrals [naux][nmopb][nmopb] (L holds alpha)
   std::vector<int> ptab_h;
   std::atomic<int> busy{0};
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -100,6 +100,33 @@ hipError_t launch_epilogue(const Geometry& g, Store st, const double* z, int k, 
                            hipStream_t s);
 hipError_t launch_check_finite(const double* x, size_t n, int* d_bad, hipStream_t s);
 
+// Alpha-beta sector of unrestricted ppRPA, density fitted: each spin's orbitals in the padded
+// [virtual; occupied] layout of the sigma kernels (alpha: rows and c; beta: d and columns).
+struct AbGeometry {
+  int nva = 0, noa = 0, nvb = 0, nob = 0, naux = 0;
+  int nvpa = 0, nopa = 0, nmopa = 0, nvta = 0, ncta = 0;
+  int nvpb = 0, nopb = 0, nmopb = 0, nvtb = 0, nctb = 0;
+  int64_t nvv = 0, noo = 0, n = 0;
+};
+// Kernel arguments of one alpha-beta sigma launch.
+struct AbParams {
+  int nvta, ncta, nvtb, nctb, nvpa, nvpb, nmopa, nmopb, naux;
+  int k, nsplit, nitems, nunits, per_xcd, npan_v;
+  const int* items;  // [nitems]: beta panel index << 16 | first alpha row tile of the range
+  int64_t la_stride, lb_stride, zt_stride, q_stride;
+};
+void make_sigma_items_ab(const AbGeometry& g, std::vector<int>& items, int& npan_v);
+// Z^T[kv][d][c] from packed alpha-beta vectors z [k][n] (device).
+hipError_t launch_unpack_ab(const AbGeometry& g, const double* z, int k, double* ZT,
+                            hipStream_t s);
+// Partial Q = sum_P La^P Z Lb^P per aux split: Qp [nsplit][k][nmopa][nmopb].
+hipError_t launch_sigma_ab(const AbGeometry& g, const SigmaPlan& plan, const double* La,
+                           const double* Lb, const double* ZT, double* Qp, int k, int nsplit,
+                           hipStream_t s);
+// sigma [k][n] = epair * z + the split sums of Qp (fixed order).
+hipError_t launch_epilogue_ab(const AbGeometry& g, const double* z, int k, const double* Qp,
+                              int nsplit, const double* epair, double* sigma, hipStream_t s);
+
 // --- dense (k_dense.hip) -------------------------------------------------------------------
 hipError_t launch_dense_build(const Geometry& g, const double* L64, const int* d_ptab,
                               const double* d_epair, double* M, hipStream_t s);

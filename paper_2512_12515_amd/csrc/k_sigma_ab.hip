@@ -1,0 +1,321 @@
+// Density-fitted sigma product of the alpha-beta sector of spin-unrestricted ppRPA on CDNA4
+// (gfx950), FP64 MFMA.
+//
+// Method (arXiv 2512.12515, section "Implementation Details": the unrestricted matrix splits into
+// three spin subspaces). In the alpha-beta sector a pair joins an alpha orbital with a beta one
+// and the exchange integral vanishes, so with (pq|rs) = sum_P La^P_pq Lb^P_rs
+//   A x (ab) = sum_cd (ac|bd) x_cd,  B y (ab) = sum_kl (ak|bl) y_kl,
+//   B^T x (ij) = sum_cd (ic|jd) x_cd,  C y (ij) = sum_kl (ik|jl) y_kl.
+// With Z = blockdiag(X, Y) (X: nv_a x nv_b, Y: no_a x no_b; every pair, alpha index outer) over
+// the orbitals ordered [virtual; occupied] of each spin,
+//   Q = sum_P La^P Z Lb^P   (nmo_a x nmo_b)
+// holds A x + B y in its virtual-virtual block and B^T x + C y in its occupied-occupied block:
+//   sigma_x(ab) = (e^a_a + e^b_b) x_ab + Q[a][b],   sigma_y(ij) = -(e^a_i + e^b_j) y_ij + Q[i][j].
+//
+// Kernel design: the two contractions of the restricted sandwich kernel, one workgroup of 4
+// waves per (vector, panel of up to 4 beta column tiles, range of up to RT alpha row tiles, aux
+// range), wave w owning column tile w: contraction 1, T[c][cols] = sum_d Z[c][d] Lb^P[d][cols]
+// with d over the whole beta block that pairs with c's alpha block (Z is rectangular: no
+// triangle), accumulates in registers; contraction 2, Q[r][cols] += sum_c La^P[r][c] T[c][cols],
+// takes T from those registers. Operands are staged in LDS by direct global->LDS loads; the aux
+// index is split over workgroups and the partial Q are summed in a fixed order by the epilogue.
+#include "internal.h"
+#include "sigma_common.h"
+
+namespace pprpa {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int AB_CT = 8;   // c tiles per chunk (T tiles held in registers)
+constexpr int AB_RT = 16;  // alpha row tiles per work unit
+constexpr int AB_ND = 3;   // d tiles per contraction-1 stage
+constexpr int AB_SR1 = AB_ND * TILE;
+constexpr int AB_BUF = AB_SR1 * AB_CT * TILE + AB_SR1 * 4 * TILE;  // 72 KiB of doubles
+static_assert(2 * TILE * AB_RT * TILE <= AB_BUF, "two contraction-2 c tiles fit the buffer");
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// c tiles of chunk [cc0, cc1) paired with beta d tile dt (all of the alpha block that matches d's
+// beta block), rounded out to pairs counted from cc0; tiles outside the block hold exact zeros of
+// Z^T.
+__device__ __forceinline__ void ab_c_range(int dt, int cc0, int cc1, int nvta, int ncta, int nvtb,
+                                           int* g0, int* g1, int* lo_out, int* hi_out) {
+  const bool virt = dt < nvtb;
+  const int lo = max(cc0, virt ? 0 : nvta);
+  const int hi = min(cc1, virt ? nvta : ncta);
+  *lo_out = lo;
+  *hi_out = hi;
+  *g0 = cc0 + ((lo - cc0) & ~1);
+  *g1 = min(cc1, cc0 + ((hi - cc0 + 1) & ~1));
+}
+
+// Unpack the packed alpha-beta vectors into Z^T[kv][d][c] (beta row d, alpha column c), the
+// layout contraction 1 stages. Positions outside the two blocks keep the zeros they were
+// cleared to at build.
+__global__ void k_unpack_ab(const double* __restrict__ z, int64_t n, int64_t nvv, int nva, int nvb,
+                            int noa, int nob, int nvpa, int nvpb, int nmopa, int nmopb,
+                            double* __restrict__ ZT) {
+  const int kv = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  int c, d;
+  if (e < nvv) {
+    c = (int)(e / nvb);
+    d = (int)(e % nvb);
+  } else {
+    const int64_t s = e - nvv;
+    c = nvpa + (int)(s / nob);
+    d = nvpb + (int)(s % nob);
+  }
+  ZT[((int64_t)kv * nmopb + d) * nmopa + c] = z[(int64_t)kv * n + e];
+  (void)nva;
+  (void)noa;
+}
+
+template <int CT, int RT>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
+                   const double* __restrict__ UT, double* __restrict__ Qp, AbParams a) {
+  __shared__ __attribute__((aligned(1024))) double buf[AB_BUF];
+  constexpr int GRP = 2;
+  static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
+  const int g = blockIdx.x;
+  const int u = (g & 7) * a.per_xcd + (g >> 3);
+  if (u >= a.nunits) return;
+
+  // unit u -> (vector u % k, work item (u / k) % nitems, aux split u / (nitems k))
+  const int item = a.items[(u / a.k) % a.nitems];
+  const int kv = u % a.k;
+  const int sp = u / (a.nitems * a.k);
+  const int pn = item >> 16;
+  const int R0 = item & 0xFFFF;  // first alpha row tile of the range (local to the block)
+  const bool vblk = pn < a.npan_v;
+  const int t0 = vblk ? 4 * pn : 4 * (pn - a.npan_v);            // first beta column tile
+  const int bntb = vblk ? a.nvtb : (a.nctb - a.nvtb);             // beta column tiles of block
+  const int bnta = vblk ? a.nvta : (a.ncta - a.nvta);             // alpha row tiles of block
+  const int col0 = (vblk ? 0 : a.nvpb) + t0 * TILE;
+  const int row0 = (vblk ? 0 : a.nvpa) + R0 * TILE;
+  const int npt = min(4, bntb - t0);
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const bool active = w < npt;
+  const int wc = min(w, npt - 1);
+  const int nrt = min(bnta, R0 + RT) - R0;
+  const int ncol = npt * TILE;
+  const int wl = nrt * TILE;
+  const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
+  const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
+  const double* __restrict__ Z = UT + (int64_t)kv * a.zt_stride;
+
+  d4 S[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) S[r] = d4{0, 0, 0, 0};
+
+  double* const sB = buf + AB_SR1 * CT * TILE;
+  for (int P = P0; P < P1; ++P) {
+    const double* __restrict__ Lap = La + (int64_t)P * a.la_stride;
+    const double* __restrict__ Lbp = Lb + (int64_t)P * a.lb_stride;
+    for (int cc0 = 0; cc0 < a.ncta; cc0 += CT) {
+      const int cc1 = min(cc0 + CT, a.ncta);
+      d4 Tacc[CT];
+#pragma unroll
+      for (int i = 0; i < CT; ++i) Tacc[i] = d4{0, 0, 0, 0};
+      // contraction 1: part 0 pairs the chunk's alpha virtual c tiles with every beta virtual d
+      // tile, part 1 its alpha occupied c tiles with every beta occupied d tile
+      for (int part = 0; part < 2; ++part) {
+        const bool has = part == 0 ? cc0 < a.nvta : cc1 > a.nvta;
+        const int lo = part == 0 ? 0 : a.nvtb;
+        const int hi = has ? (part == 0 ? a.nvtb : a.nctb) : lo;
+        for (int dt = lo; dt < hi; dt += AB_ND) {
+          const int nd = min(AB_ND, hi - dt);
+          int g0, g1, clo, chi;
+          ab_c_range(dt, cc0, cc1, a.nvta, a.ncta, a.nvtb, &g0, &g1, &clo, &chi);
+          const int wa = (g1 - g0) * TILE;
+          __syncthreads();
+          dma_tile(Z + (int64_t)(dt * TILE) * a.nmopa + g0 * TILE, a.nmopa, nd * TILE, wa, buf, w,
+                   lane);
+          dma_tile(Lbp + (int64_t)(dt * TILE) * a.nmopb + col0, a.nmopb, nd * TILE, ncol, sB, w,
+                   lane);
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+#pragma unroll
+          for (int sub = 0; sub < AB_ND; ++sub) {
+            if (sub < nd) {
+              const double* sA = buf + sub * TILE * wa;
+              const double* sBs = sB + sub * TILE * ncol;
+              double bv[4];
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) bv[ks] = sBs[(4 * ks + lk) * ncol + wc * TILE + li];
+#pragma unroll
+              for (int grp = 0; grp < CT / GRP; ++grp) {
+                const int cg = cc0 + GRP * grp;
+                if (active && cg >= g0 && cg < chi) {
+                  double av[4][GRP];
+#pragma unroll
+                  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      av[ks][j] = sA[(4 * ks + lk) * wa + (cg - g0 + j) * TILE + li];
+                  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      Tacc[GRP * grp + j] = mfma64(av[ks][j], bv[ks], Tacc[GRP * grp + j]);
+                }
+              }
+            }
+          }
+        }
+      }
+      // contraction 2: Q[r][cols] += sum_c La^P[r][c] T[c][cols] (La^P symmetric: the staged
+      // rows c of La^P give the A operand), two c tiles per stage
+#pragma unroll
+      for (int i = 0; i < CT; i += 2) {
+        if (cc0 + i < cc1) {
+          const int nb = min(2, cc1 - cc0 - i);
+          __syncthreads();
+          dma_tile(Lap + (int64_t)((cc0 + i) * TILE) * a.nmopa + row0, a.nmopa, nb * TILE, wl, buf, w,
+                   lane);
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+#pragma unroll
+          for (int sub = 0; sub < 2; ++sub) {
+            if (sub < nb) {
+              const double* sL = buf + sub * TILE * wl;
+#pragma unroll
+              for (int grp = 0; grp < RT / GRP; ++grp) {
+                // a row tile at nrt in the last group reads other staged data (in bounds); its
+                // result is never stored
+                if (active && GRP * grp < nrt) {
+                  double av[4][GRP];
+#pragma unroll
+                  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      av[ks][j] = sL[(lk + 4 * ks) * wl + (GRP * grp + j) * TILE + li];
+                  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = 0; j < GRP; ++j)
+                      S[GRP * grp + j] = mfma64(av[ks][j], Tacc[i + sub][ks], S[GRP * grp + j]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if (active) {
+    // accumulator register j of lane (li, lk) holds row lk + 4 j, column li of the tile
+    double* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.q_stride;
+    const int col = col0 + wc * TILE + li;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      if (rt < nrt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          out[(int64_t)(row0 + rt * TILE + lk + 4 * j) * a.nmopb + col] = S[rt][j];
+      }
+    }
+  }
+}
+
+// sigma[e] = epair[e] z[e] + sum over splits of Q[row][col] (fixed order), with epair the signed
+// pair energies (+ for vv, - for oo pairs).
+__global__ __launch_bounds__(256) void k_epilogue_ab(const double* __restrict__ z, int64_t n,
+                                                     int64_t nvv, int nvb, int nob, int nvpa,
+                                                     int nvpb, int nmopb, const double* __restrict__ Qp,
+                                                     int nsplit, int64_t split_stride,
+                                                     int64_t q_stride,
+                                                     const double* __restrict__ epair,
+                                                     double* __restrict__ sigma) {
+  const int kv = blockIdx.y;
+  const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = e0 < n ? e0 : n - 1;  // clamped: every thread's loads stay in bounds
+  int r, c;
+  if (e < nvv) {
+    r = (int)(e / nvb);
+    c = (int)(e % nvb);
+  } else {
+    const int64_t s = e - nvv;
+    r = nvpa + (int)(s / nob);
+    c = nvpb + (int)(s % nob);
+  }
+  const double* Q = Qp + (int64_t)kv * q_stride + (int64_t)r * nmopb + c;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int t = 0; t < nsplit; ++t) acc += Q[t * split_stride];
+  if (e0 < n) sigma[(int64_t)kv * n + e] = epair[e] * z[(int64_t)kv * n + e] + acc;
+}
+
+}  // namespace
+
+hipError_t launch_unpack_ab(const AbGeometry& g, const double* z, int k, double* ZT,
+                            hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
+  hipLaunchKernelGGL(k_unpack_ab, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nva, g.nvb, g.noa, g.nob,
+                     g.nvpa, g.nvpb, g.nmopa, g.nmopb, ZT);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_ab(const AbGeometry& g, const SigmaPlan& plan, const double* La,
+                           const double* Lb, const double* ZT, double* Qp, int k, int nsplit,
+                           hipStream_t s) {
+  AbParams p;
+  p.nvta = g.nvta;
+  p.ncta = g.ncta;
+  p.nvtb = g.nvtb;
+  p.nctb = g.nctb;
+  p.nvpa = g.nvpa;
+  p.nvpb = g.nvpb;
+  p.nmopa = g.nmopa;
+  p.nmopb = g.nmopb;
+  p.naux = g.naux;
+  p.k = k;
+  p.nsplit = nsplit;
+  p.nitems = plan.nitems;
+  p.nunits = p.nitems * k * nsplit;
+  p.per_xcd = (p.nunits + 7) / 8;
+  p.npan_v = plan.npan_v;
+  p.items = plan.d_items;
+  p.la_stride = (int64_t)g.nmopa * g.nmopa;
+  p.lb_stride = (int64_t)g.nmopb * g.nmopb;
+  p.zt_stride = (int64_t)g.nmopb * g.nmopa;
+  p.q_stride = (int64_t)g.nmopa * g.nmopb;
+  hipLaunchKernelGGL((k_sandwich_ab<AB_CT, AB_RT>), dim3(p.per_xcd * 8), dim3(256), 0, s, La, Lb,
+                     ZT, Qp, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue_ab(const AbGeometry& g, const double* z, int k, const double* Qp,
+                              int nsplit, const double* epair, double* sigma, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  const int64_t q_stride = (int64_t)g.nmopa * g.nmopb;
+  dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
+  hipLaunchKernelGGL(k_epilogue_ab, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob, g.nvpa,
+                     g.nvpb, g.nmopb, Qp, nsplit, (int64_t)k * q_stride, q_stride, epair, sigma);
+  return hipGetLastError();
+}
+
+// Work items of the alpha-beta sigma kernel: panels of up to 4 beta column tiles of each
+// diagonal block, with the alpha row tiles of the block in ranges of AB_RT.
+void make_sigma_items_ab(const AbGeometry& g, std::vector<int>& items, int& npan_v) {
+  items.clear();
+  npan_v = (g.nvtb + 3) / 4;
+  const int npan_o = (g.nctb - g.nvtb + 3) / 4;
+  const int rows_v = g.nvta, rows_o = g.ncta - g.nvta;
+  for (int pn = 0; pn < npan_v + npan_o; ++pn) {
+    const int rows = pn < npan_v ? rows_v : rows_o;
+    for (int R0 = 0; R0 < rows; R0 += AB_RT) items.push_back((pn << 16) | R0);
+  }
+}
+
+}  // namespace pprpa

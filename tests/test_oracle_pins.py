@@ -328,6 +328,17 @@ def test_unrestricted_sectors_equal_spin_orbital_matrix(nmo, nocc_a, nocc_b, nau
     assert np.array_equal(sgD, sg) and np.allclose(OmD, Om, atol=1e-11)
 
 
+@pytest.mark.parametrize("nmo,nocc_a,nocc_b,naux", [(7, 3, 2, 12), (9, 2, 4, 7), (6, 1, 0, 5)])
+def test_ab_sigma_rows_equal_dense_product(nmo, nocc_a, nocc_b, naux):
+    """The row-by-row alpha-beta sigma equals M z of the alpha-beta matrix, every row."""
+    ea, eb, La, Lb = unrestricted(10, nmo, nocc_a, nocc_b, naux)
+    M, nvv = O.ab_sector(ea, eb, La, Lb, nocc_a, nocc_b)
+    z = np.random.default_rng(3).standard_normal(M.shape[0])
+    rows = np.arange(M.shape[0])
+    assert np.allclose(O.ab_sigma_rows(ea, eb, La, Lb, nocc_a, nocc_b, rows, z), M @ z,
+                       atol=1e-13, rtol=0)
+
+
 def test_ab_sector_zero_interaction():
     nmo, nocc_a, nocc_b = 7, 3, 2
     ea, eb, La, Lb = unrestricted(9, nmo, nocc_a, nocc_b, 5)
