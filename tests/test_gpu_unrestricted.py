@@ -6,7 +6,11 @@
 * alpha != beta end to end: the lowest pp roots of the three GPU sectors (alpha-alpha and
   beta-beta as triplet contexts of one spin's data) equal the lowest pp roots of the oracle's
   general spin-orbital build;
-* argument checks.
+* argument checks;
+* the density-fitted alpha-beta sector (Q = sum_P La^P Z Lb^P on the rectangular amplitude
+  blocks): sigma against the oracle's M z at ragged shapes and against the dense context, the
+  Davidson roots of both channels against the oracle, a sector of order 33120 (beyond the dense
+  limit, which is refused) on sampled rows of the oracle, and the dense-only calls refused.
 Tolerances: matrices and sigma 1e-12 relative, eigenvalues 1e-9 Ha (FP64, tol 1e-10).
 """
 import sys
