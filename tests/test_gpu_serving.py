@@ -193,3 +193,20 @@ def test_failures_are_isolated(mix_inputs, served_mix):
     assert np.all(np.isfinite(r_cap["omega"]))
     assert r_big["status"] == P.binding.ENOMEM and "bytes" in r_big["message"]
     assert st["failed"] == 3 and st["completed"] == 4
+
+
+def test_largest_request_in_a_mix():
+    """The largest request of the serving workload (nocc 40, nvir 400, naux 1540, FP32 sigma)
+    served beside two small ones: each result equals its standalone context's, bit for bit."""
+    reqs = [(51, 40, 400, "singlet", 6, "fp32"), (52, 6, 40, "triplet", 4, "fp64"),
+            (53, 10, 90, "singlet", 5, "fp32")]
+    inputs = [device_inputs(s, no, nv, naux_of(no, nv), scale=0.7) for (s, no, nv, *_r) in reqs]
+    note("serving the largest request with two small ones")
+    res, stats = serve(reqs, budget=24 << 30, max_inflight=4, inputs=inputs)
+    assert stats["completed"] == 3 and stats["failed"] == 0
+    for i, (seed, nocc, nvir, mult, nroot, prec) in enumerate(reqs):
+        assert res[i]["status"] == P.binding.OK, res[i]["message"]
+        eps, L = inputs[i]
+        with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
+            r = ctx.davidson(nroot, tol=tol_of(prec))
+        assert np.array_equal(r["omega"], res[i]["omega"]), (r["omega"] - res[i]["omega"])
