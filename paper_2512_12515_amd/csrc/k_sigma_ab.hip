@@ -42,11 +42,10 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 // beta block), rounded out to pairs counted from cc0; tiles outside the block hold exact zeros of
 // Z^T.
 __device__ __forceinline__ void ab_c_range(int dt, int cc0, int cc1, int nvta, int ncta, int nvtb,
-                                           int* g0, int* g1, int* lo_out, int* hi_out) {
+                                           int* g0, int* g1, int* hi_out) {
   const bool virt = dt < nvtb;
   const int lo = max(cc0, virt ? 0 : nvta);
   const int hi = min(cc1, virt ? nvta : ncta);
-  *lo_out = lo;
   *hi_out = hi;
   *g0 = cc0 + ((lo - cc0) & ~1);
   *g1 = min(cc1, cc0 + ((hi - cc0 + 1) & ~1));
@@ -55,8 +54,8 @@ __device__ __forceinline__ void ab_c_range(int dt, int cc0, int cc1, int nvta, i
 // Unpack the packed alpha-beta vectors into Z^T[kv][d][c] (beta row d, alpha column c), the
 // layout contraction 1 stages. Positions outside the two blocks keep the zeros they were
 // cleared to at build.
-__global__ void k_unpack_ab(const double* __restrict__ z, int64_t n, int64_t nvv, int nva, int nvb,
-                            int noa, int nob, int nvpa, int nvpb, int nmopa, int nmopb,
+__global__ void k_unpack_ab(const double* __restrict__ z, int64_t n, int64_t nvv, int nvb,
+                            int nob, int nvpa, int nvpb, int nmopa, int nmopb,
                             double* __restrict__ ZT) {
   const int kv = blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -71,8 +70,6 @@ __global__ void k_unpack_ab(const double* __restrict__ z, int64_t n, int64_t nvv
     d = nvpb + (int)(s % nob);
   }
   ZT[((int64_t)kv * nmopb + d) * nmopa + c] = z[(int64_t)kv * n + e];
-  (void)nva;
-  (void)noa;
 }
 
 template <int CT, int RT>
@@ -131,8 +128,8 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
         const int hi = has ? (part == 0 ? a.nvtb : a.nctb) : lo;
         for (int dt = lo; dt < hi; dt += AB_ND) {
           const int nd = min(AB_ND, hi - dt);
-          int g0, g1, clo, chi;
-          ab_c_range(dt, cc0, cc1, a.nvta, a.ncta, a.nvtb, &g0, &g1, &clo, &chi);
+          int g0, g1, chi;
+          ab_c_range(dt, cc0, cc1, a.nvta, a.ncta, a.nvtb, &g0, &g1, &chi);
           const int wa = (g1 - g0) * TILE;
           __syncthreads();
           dma_tile(Z + (int64_t)(dt * TILE) * a.nmopa + g0 * TILE, a.nmopa, nd * TILE, wa, buf, w,
@@ -261,8 +258,8 @@ hipError_t launch_unpack_ab(const AbGeometry& g, const double* z, int k, double*
                             hipStream_t s) {
   if (k <= 0) return hipSuccess;
   dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
-  hipLaunchKernelGGL(k_unpack_ab, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nva, g.nvb, g.noa, g.nob,
-                     g.nvpa, g.nvpb, g.nmopa, g.nmopb, ZT);
+  hipLaunchKernelGGL(k_unpack_ab, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob, g.nvpa,
+                     g.nvpb, g.nmopa, g.nmopb, ZT);
   return hipGetLastError();
 }
 
