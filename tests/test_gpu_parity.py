@@ -66,7 +66,8 @@ def test_sigma_fp64(mult, case):
 PANEL_CASES = [(40, 70, 24), (50, 90, 20), (70, 110, 16)]
 
 
-@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16x6", 3e-5),
+                                       ("bf16x3", 3e-4)])
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case", PANEL_CASES)
 def test_sigma_panel_mixes(case, mult, prec, rtol):
