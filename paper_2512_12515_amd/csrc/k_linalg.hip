@@ -558,17 +558,33 @@ __device__ __forceinline__ void tri_inverse(const double* A, double* Ri, int m,
   const int t = threadIdx.x;
   for (int i = 0; i < m; ++i) {
     const double rii = A[i * m + i];
-    for (int c = t; c <= i; c += WG) {
-      double s = (c == i) ? 1.0 : 0.0;
-      if (RiT) {
-        const double* rc = RiT + (size_t)c * m;
-        for (int k = c; k < i; ++k) s -= A[i * m + k] * rc[k];
-      } else {
-        for (int k = c; k < i; ++k) s -= A[i * m + k] * Ri[k * m + c];
+    if (RiT) {
+      // global matrices: each element's dot product is split over tpe consecutive lanes (as
+      // many as the row's i + 1 elements leave room for), k = c + q, c + q + tpe, ..., and the
+      // lane partials are combined by a fixed butterfly: chains tpe times shorter
+      const int nc = i + 1;
+      const int tpe = nc * 8 <= WG ? 8 : (nc * 4 <= WG ? 4 : (nc * 2 <= WG ? 2 : 1));
+      for (int base = 0; base < nc * tpe; base += WG) {
+        const int id = base + t;
+        const int c = id / tpe, q = id % tpe;
+        double s = 0.0;
+        if (c < nc) {
+          const double* rc = RiT + (size_t)c * m;
+          for (int k = c + q; k < i; k += tpe) s += A[i * m + k] * rc[k];
+        }
+        for (int off = 1; off < tpe; off <<= 1) s += __shfl_xor(s, off, 64);
+        if (c < nc && q == 0) {
+          const double v = ((c == i ? 1.0 : 0.0) - s) / rii;
+          Ri[i * m + c] = v;
+          RiT[(size_t)c * m + i] = v;
+        }
       }
-      const double v = s / rii;
-      Ri[i * m + c] = v;
-      if (RiT) RiT[(size_t)c * m + i] = v;
+    } else {
+      for (int c = t; c <= i; c += WG) {
+        double s = (c == i) ? 1.0 : 0.0;
+        for (int k = c; k < i; ++k) s -= A[i * m + k] * Ri[k * m + c];
+        Ri[i * m + c] = s / rii;
+      }
     }
     for (int c = i + 1 + t; c < m; c += WG) Ri[i * m + c] = 0.0;
     __syncthreads();
