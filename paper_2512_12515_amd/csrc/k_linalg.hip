@@ -881,14 +881,29 @@ __device__ __forceinline__ bool dense_pencil_tridiag(const double* __restrict__ 
   __syncthreads();
   if (!tri_cholesky(A, m, flag, vv)) return false;
   tri_inverse(A, Ri, m, G);  // G holds the transposed copy until G itself is formed
-  // G = R^-1 W R^-T with W diagonal (both triangles)
-  for (int e_ = t; e_ < m * m; e_ += WG) {
-    const int i = e_ / m, j = e_ % m;
-    if (j < i) continue;
+  // G = R^-1 W R^-T with W diagonal (both triangles): element (i, j), i <= j, pair index
+  // pe = j (j + 1) / 2 + i, is reduced by 8 consecutive lanes (k = q, q + 8, ... <= i, so each load
+  // instruction reads 64-byte segments of rows i and j of R^-1), the lane partials combined by a
+  // fixed butterfly
+  const int npairs = m * (m + 1) / 2;
+  for (int base = 0; base < npairs * 8; base += WG) {
+    const int id = base + t, pe = id >> 3, q = id & 7;
     double s = 0.0;
-    for (int k = 0; k <= i; ++k) s += Ri[i * m + k] * (k < nvv ? 1.0 : -1.0) * Ri[j * m + k];
-    G[i * m + j] = s;
-    G[j * m + i] = s;
+    int i = 0, j = 0;
+    if (pe < npairs) {
+      j = (int)((sqrt(8.0 * pe + 1.0) - 1.0) * 0.5);
+      while ((j + 1) * (j + 2) / 2 <= pe) ++j;  // exact integer row of the pair index
+      while (j * (j + 1) / 2 > pe) --j;
+      i = pe - j * (j + 1) / 2;
+      const double* ri = Ri + (size_t)i * m;
+      const double* rj = Ri + (size_t)j * m;
+      for (int k = q; k <= i; k += 8) s += ri[k] * (k < nvv ? 1.0 : -1.0) * rj[k];
+    }
+    for (int off = 1; off < 8; off <<= 1) s += __shfl_xor(s, off, 64);
+    if (pe < npairs && q == 0) {
+      G[i * m + j] = s;
+      G[j * m + i] = s;
+    }
   }
   __syncthreads();
   tri_householder(G, m, d, e, beta, vv, pq, red);
