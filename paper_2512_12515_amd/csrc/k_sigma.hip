@@ -19,13 +19,14 @@
 //     the epilogue); the triangle halves contraction 1 and every work unit does the same work;
 //   * a workgroup owns one vector, a panel of up to 4 adjacent 16-column tiles of one diagonal
 //     block, a range of up to RT row tiles of that block, and a contiguous range of the aux
-//     index P; wave w owns column tile w of the panel (a panel of one or two tiles gives its
-//     other waves a share of the rows instead);
+//     index P; wave w owns column tile w of the panel (in a panel of one or two tiles the
+//     waves of a column share out its c groups in contraction 1, exchange their T tiles through
+//     LDS, and share out its rows in contraction 2);
 //   * per P: contraction 1, T[c][cols] = sum_{d >= c} U[c][d] L^P[d][cols], accumulates in
 //     registers (CT row tiles of T at a time); contraction 2, Q[r][cols] += sum_c L^P[r][c]
 //     T[c][cols], takes T straight from those registers as its B operand (the reduction index c
 //     is permuted to match the MFMA output layout, acc_row, and the A operand is read with the
-//     same permutation), so T never leaves the register file;
+//     same permutation), so T stays in the register file (narrow panels aside);
 //   * the A operands (rows of U^T and of L^P) are shared by the 4 waves and staged in LDS by
 //     direct global-to-LDS loads; L^P being symmetric, every staged tile is a contiguous row
 //     segment in HBM;
