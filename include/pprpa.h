@@ -68,7 +68,8 @@ typedef struct {
   int32_t naux;         /* auxiliary (density-fitting) count, > 0                           */
   int32_t nocc_act;     /* active occupied (<= 0: all)                                      */
   int32_t nvir_act;     /* active virtual  (<= 0: all)                                      */
-  const double* eps;    /* [nmo] orbital energies (host or device, see on_device)            */
+  const double* eps;    /* [nmo] orbital energies (host or device, see on_device), ascending
+                           within the occupied and the virtual block, HOMO below LUMO         */
   const double* Lpq;    /* [naux][nmo][nmo] row-major, symmetric in (p,q); or, when
                            lpq_is_active, [naux][nact][nact] over the active orbitals in
                            physical order (nact = no + nv). FP64. Host or device.           */
@@ -84,8 +85,9 @@ typedef struct {
 /* Stage the problem on the current device: slice the active window, reorder L into the
  * sigma kernels' padded layout in the chosen precision, tabulate pair energies, and (dense=1)
  * build M. Copies everything it needs: no caller pointer is retained after return.
- * Errors: EINVAL (sizes, window outside the spaces, non-finite eps/L, nv or no = 0 with no
- * pairs), ENOMEM, EDEVICE. On error *out is set to NULL. */
+ * Errors: EINVAL (sizes, window outside the spaces, non-finite eps/L, eps not ascending within
+ * the occupied or the virtual block or the highest occupied energy not below the lowest virtual
+ * one, nv or no = 0 with no pairs), ENOMEM, EDEVICE. On error *out is set to NULL. */
 pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
 
 /* Spin-unrestricted ppRPA (section "Implementation Details": the matrix is built and
@@ -106,7 +108,8 @@ pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
  *    solve, pprpa_dense_matrix and pprpa_correlation_energy return EUNSUPPORTED.
  * pprpa_nto returns EUNSUPPORTED for both. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO)
  * / 2. Inputs (host, or device with on_device) are read during the call only.
- * Errors: EINVAL (arguments, non-finite input), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (arguments, non-finite input, energies of a spin not ascending within its
+ * occupied or virtual block or its HOMO not below its LUMO), ENOMEM, EDEVICE. */
 typedef struct {
   int32_t nmo;          /* orbitals per spin                                                 */
   int32_t nocc_a;       /* occupied alpha orbitals (< nmo)                                   */
@@ -235,7 +238,10 @@ typedef struct {
   int32_t state;        /* 0 queued, 1 running (the caller's inputs are no longer read), 2 done */
   int32_t status;       /* pprpa_status of the solve (meaningful once done)                  */
   int32_t nroot;
-  int32_t reserved_;
+  int32_t max_overtaken; /* the most times the grouped sigma launches of another kernel
+                            variant (sigma precision) went ahead of one of this request's
+                            waiting sigma blocks; the variant of the longest-waiting block goes
+                            first, so this is at most 3 (one per other variant)               */
   double t_submit;      /* seconds on the server's steady clock (0 = creation)               */
   double t_admit;       /* reservation taken, build started                                  */
   double t_done;        /* roots copied out, memory released                                 */

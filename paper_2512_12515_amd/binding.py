@@ -85,7 +85,7 @@ class CorrEnergy(C.Structure):
 
 class RequestInfo(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("nroot", C.c_int32),
-                ("reserved_", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("max_overtaken", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
                 ("t_done", C.c_double), ("footprint", C.c_uint64), ("message", C.c_char * 256)]
 
 
@@ -411,6 +411,7 @@ class Server:
                                        resid.ctypes.data, C.byref(rep)))
         out = dict(state=info.state, status=info.status, t_submit=info.t_submit,
                    t_admit=info.t_admit, t_done=info.t_done, footprint=info.footprint,
+                   max_overtaken=info.max_overtaken,
                    message=info.message.decode(errors="replace"))
         if info.state >= self.RUNNING:
             self._held.pop(ticket, None)

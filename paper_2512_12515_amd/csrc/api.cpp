@@ -32,6 +32,24 @@ static pprpa_status einval(const char* fmt, ...) {
   return PPRPA_EINVAL;
 }
 
+// Orbital energies as the ABI requires them: finite, ascending within the occupied block
+// [0, nocc) and within the virtual block [nocc, nmo), and the highest occupied below the lowest
+// virtual. The definite shift 2 mu = e_HOMO + e_LUMO and the active window (the highest occupied,
+// the lowest virtual orbitals) both read the energies in this order.
+static pprpa_status check_energies(const std::vector<double>& e, int nocc, const char* name) {
+  const int nmo = (int)e.size();
+  for (int i = 0; i < nmo; ++i)
+    if (!std::isfinite(e[i])) return einval("%s[%d] is not finite", name, i);
+  for (int i = 1; i < nmo; ++i)
+    if (i != nocc && e[i] < e[i - 1])
+      return einval("%s is not ascending within its %s block (%s[%d] = %.17g < %s[%d] = %.17g)",
+                    name, i < nocc ? "occupied" : "virtual", name, i, e[i], name, i - 1, e[i - 1]);
+  if (nocc > 0 && nocc < nmo && !(e[nocc - 1] < e[nocc]))
+    return einval("highest occupied %s[%d] = %.17g is not below the lowest virtual %s[%d] = %.17g",
+                  name, nocc - 1, e[nocc - 1], name, nocc, e[nocc]);
+  return PPRPA_OK;
+}
+
 pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
@@ -301,8 +319,7 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
   } else {
     std::memcpy(eps.data(), a->eps, nmo * sizeof(double));
   }
-  for (int i = 0; i < nmo; ++i)
-    if (!std::isfinite(eps[i])) return einval("eps[%d] is not finite", i);
+  PPRPA_TRY(check_energies(eps, nocc, "eps"));
   c->eo_h.assign(eps.begin() + (nocc - no), eps.begin() + nocc);
   c->ev_h.assign(eps.begin() + nocc, eps.begin() + nocc + nv);
   c->mu2 = no > 0 ? c->eo_h.back() + c->ev_h.front() : 2.0 * (c->ev_h.front() - 1.0);
@@ -470,8 +487,8 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
   const hipMemcpyKind kind = a->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
   PPRPA_HIP(hipMemcpy(ea.data(), a->eps_a, nmo * sizeof(double), kind));
   PPRPA_HIP(hipMemcpy(eb.data(), a->eps_b, nmo * sizeof(double), kind));
-  for (int i = 0; i < nmo; ++i)
-    if (!std::isfinite(ea[i]) || !std::isfinite(eb[i])) return einval("eps[%d] is not finite", i);
+  PPRPA_TRY(check_energies(ea, noa, "eps_a"));
+  PPRPA_TRY(check_energies(eb, nob, "eps_b"));
   c->eo_h.assign(ea.begin(), ea.begin() + noa);
   c->ev_h.assign(ea.begin() + noa, ea.end());
   const double lumo = ea[noa] + eb[nob];

@@ -12,7 +12,10 @@
 //   together as one grouped grid on the group stream, ordered after each member's unpack by an
 //   event, with the epilogue back on each request's stream, ordered after the grid by an event.
 //   One grid is in flight at a time: the solves that become ready while it runs form the next
-//   group (continuous batching), so the groups grow with the load. A member's work units are
+//   group (continuous batching), so the groups grow with the load. Solves of different kernel
+//   variants (sigma precision) cannot share a grid; the variant whose waiting block has waited
+//   longest goes next, so no request is overtaken by more than one launch per other variant.
+//   A member's work units are
 //   those of a launch of its own (same decomposition, same partial-sum buffer), so its results do
 //   not depend on the mix it was served in.
 // * Finished solves copy out their roots, release their reservation and slot, and wake the
@@ -96,6 +99,9 @@ struct Request {
   pprpa_ctx* ctx = nullptr;
   std::unique_ptr<Solver> sv;
   bool unpacked = false;  // the pending sigma block is unpacked (ctx->e0 marks its end)
+  double t_wait = 0;      // when the pending sigma block started waiting for a grouped launch
+  int overtaken = 0;      // launch rounds of other variants while the pending block waited
+  int max_overtaken = 0;
   pprpa_status status = PPRPA_OK;
   std::string message;
   double omega[64] = {0}, resid[64] = {0};
@@ -354,6 +360,8 @@ void worker_loop(pprpa_server* S) {
               sv.message = "unpack launch failed";
             } else {
               r->unpacked = true;
+              r->t_wait = S->now();
+              r->overtaken = 0;
               progressed = true;
             }
           }
@@ -380,10 +388,26 @@ void worker_loop(pprpa_server* S) {
     }
     timed.erase(timed.begin(), timed.begin() + nt);
 
-    // one grouped grid in flight at a time: launch the waiting solves once the last one is done
-    for (auto& kv : need) {
-      if (!timed.empty()) break;
-      const std::vector<Request*>& list = kv.second;
+    // one grouped grid in flight at a time: once the last one is done, launch the waiting solves
+    // of the variant whose block has waited longest (all of them, in grids of GROUP_MAX)
+    if (timed.empty() && !need.empty()) {
+      auto oldest = [](const std::vector<Request*>& v) {
+        double t = v.front()->t_wait;
+        for (const Request* r : v) t = std::min(t, r->t_wait);
+        return t;
+      };
+      auto pick = need.begin();
+      for (auto it = need.begin(); it != need.end(); ++it)
+        if (oldest(it->second) < oldest(pick->second)) pick = it;
+      const std::vector<Request*>& list = pick->second;
+      for (auto& kv : need) {
+        if (kv.first == pick->first) continue;
+        for (Request* r : kv.second) r->overtaken += 1;
+      }
+      for (Request* r : list) {
+        r->max_overtaken = std::max(r->max_overtaken, r->overtaken);
+        r->overtaken = 0;
+      }
       for (size_t i0 = 0; i0 < list.size(); i0 += GROUP_MAX) {
         std::vector<Request*> grp(list.begin() + i0,
                                   list.begin() + std::min(list.size(), i0 + GROUP_MAX));
@@ -566,6 +590,7 @@ pprpa_status pprpa_server_poll(pprpa_server* S, uint64_t ticket, pprpa_request_i
   info->state = r->state;
   info->status = r->status;
   info->nroot = r->d.nroot;
+  info->max_overtaken = r->max_overtaken;
   info->t_submit = r->t_submit;
   info->t_admit = r->t_admit;
   info->t_done = r->t_done;

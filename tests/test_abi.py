@@ -75,6 +75,32 @@ def test_build_rejects_non_finite_energies():
     assert "not finite" in B.lib().pprpa_last_error().decode()
 
 
+@pytest.mark.parametrize("swap,msg", [
+    ((0, 1), "occupied block"),   # occupied energies out of order
+    ((3, 5), "virtual block"),    # virtual energies out of order
+    ((1, 2), "not below"),        # highest occupied above the lowest virtual
+])
+def test_build_rejects_unordered_energies(swap, msg):
+    """The definite shift 2 mu = e_HOMO + e_LUMO and the active window read the energies in
+    ascending order within each block: unordered energies are an argument error, not a silent
+    wrong shift or window."""
+    a, eps, L = _args()
+    i, j = swap
+    eps[i], eps[j] = eps[j], eps[i]
+    h = C.c_void_p(1234)
+    assert B.lib().pprpa_build(C.byref(a), C.byref(h)) == B.EINVAL
+    assert h.value is None
+    assert msg in B.lib().pprpa_last_error().decode()
+
+
+def test_build_rejects_degenerate_gap():
+    a, eps, L = _args()
+    eps[2] = eps[1]
+    h = C.c_void_p()
+    assert B.lib().pprpa_build(C.byref(a), C.byref(h)) == B.EINVAL
+    assert "not below" in B.lib().pprpa_last_error().decode()
+
+
 def test_null_arguments():
     L = B.lib()
     assert L.pprpa_build(None, None) == B.EINVAL

@@ -1,0 +1,116 @@
+"""GPU: boundary behaviour of the C ABI beyond the arithmetic.
+
+* EBUSY: a context is used by one thread at a time; a call from a second thread while the first
+  is inside pprpa_davidson returns EBUSY at once (and the first call is unaffected);
+* warm start: the converged vectors passed back as `guess` reach the same roots in at most two
+  iterations;
+* the per-iteration log callback: one JSON object per Davidson iteration, in order, whose last
+  line agrees with the report.
+"""
+import json
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+from oracle import pprpa_oracle as O
+from workloads import gen
+import paper_2512_12515_amd as P
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def problem(seed, nocc, nvir, naux):
+    return gen.orbital_energies(seed, nocc, nvir), gen.lpq_full(seed, nocc + nvir, naux)
+
+
+def test_second_thread_gets_ebusy():
+    note("EBUSY")
+    eps, L = problem(41, 6, 30, 60)
+    ref = O.solve(eps, L, 6, "singlet", 5)
+    inside, released = threading.Event(), threading.Event()
+    seen = {}
+
+    def on_iteration(line):
+        # called by the library from inside pprpa_davidson (the context is held): let the other
+        # thread try the context once, then continue
+        if not inside.is_set():
+            inside.set()
+            released.wait(timeout=60.0)
+
+    def other(ctx, z):
+        inside.wait(timeout=60.0)
+        try:
+            ctx.matvec(z)
+            seen["status"] = P.binding.OK
+        except P.PpRPAError as e:
+            seen["status"] = e.status
+            seen["message"] = str(e)
+        finally:
+            released.set()
+
+    with P.PpRPA(eps, L, 6) as ctx:
+        z = gen.random_vectors(3, 2, ctx.n)
+        th = threading.Thread(target=other, args=(ctx, z))
+        th.start()
+        r = ctx.davidson(5, block=5, tol=1e-8, log=on_iteration)
+        th.join(timeout=60.0)
+        assert not th.is_alive()
+        assert seen["status"] == P.binding.EBUSY, seen
+        # the context is free again once the first call returned
+        s = ctx.matvec(z)
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-8
+    M = O.pprpa_matrix(*O.build_matrices(O.active_space(eps, L, 6), "singlet"))
+    assert np.max(np.abs(s - (M @ z.T).T)) <= 1e-12 * np.abs(M @ z.T).max()
+
+
+@pytest.mark.parametrize("mult,channel", [("singlet", "pp"), ("triplet", "pp"), ("singlet", "hh")])
+def test_warm_start_from_converged_vectors(mult, channel):
+    note("warm start", mult, channel)
+    eps, L = problem(42, 8, 40, 90)
+    ref = O.solve(eps, L, 8, mult, 6, channel=channel)
+    with P.PpRPA(eps, L, 8, mult=mult) as ctx:
+        cold = ctx.davidson(6, block=6, tol=1e-8, vectors=True, channel=channel)
+        warm = ctx.davidson(6, block=6, tol=1e-8, guess=cold["vecs"], channel=channel)
+    note("cold", cold["report"]["iters"], "warm", warm["report"]["iters"])
+    assert cold["report"]["iters"] > 2
+    assert warm["report"]["iters"] <= 2
+    assert np.max(np.abs(warm["omega"] - ref)) <= 1e-8
+    assert np.max(np.abs(warm["omega"] - cold["omega"])) <= 1e-9
+    assert np.all(warm["resid"] <= 1e-8)
+
+
+def test_warm_start_guess_count_below_nroot_is_rejected():
+    eps, L = problem(42, 8, 40, 90)
+    with P.PpRPA(eps, L, 8) as ctx:
+        cold = ctx.davidson(6, block=6, tol=1e-8, vectors=True)
+        with pytest.raises(P.PpRPAError) as e:  # 3 directions cannot carry 6 roots
+            ctx.davidson(6, block=6, tol=1e-8, guess=cold["vecs"][:3])
+    assert e.value.status == P.binding.EINVAL
+
+
+def test_log_callback_one_json_line_per_iteration():
+    note("log callback")
+    eps, L = problem(43, 10, 50, 120)
+    got = []
+    with P.PpRPA(eps, L, 10, mult="triplet") as ctx:
+        r = ctx.davidson(8, block=8, tol=1e-7, log=got.append)
+    rep = r["report"]
+    assert rep["iters"] >= 3
+    assert len(got) == rep["iters"] == len(r["log"])
+    recs = [json.loads(s) for s in got]
+    assert [x["iter"] for x in recs] == list(range(1, rep["iters"] + 1))
+    for x in recs:
+        assert set(x) >= {"iter", "subspace", "n_conv", "max_resid", "omega0", "n_sigma"}
+        assert 0 <= x["n_conv"] <= 8 and x["max_resid"] >= 0.0
+    assert all(a["n_sigma"] <= b["n_sigma"] for a, b in zip(recs, recs[1:]))
+    last = recs[-1]
+    assert last["n_conv"] == 8 and last["n_sigma"] == rep["n_sigma"]
+    assert abs(last["max_resid"] - rep["max_resid"]) <= 1e-3 * rep["max_resid"]
+    assert abs(last["omega0"] - r["omega"][0]) <= 1e-11

@@ -80,7 +80,7 @@ def test_degenerate_orbitals_with_interactions(mult):
     assert np.max(np.abs(d["omega"] - ref)) <= 1e-8
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16x6", 3e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-7), ("bf16x6", 1e-7)])
 def test_no_occupied_orbitals(prec, tol):
     """nocc = 0: only the pp block (A); the shift falls back to e_LUMO - 1."""
     note("nocc = 0", prec)
@@ -128,8 +128,8 @@ def test_one_aux_function_and_widest_block():
     assert np.max(np.abs(s - ref)) <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16x6", 3e-5),
-                                      ("bf16x3", 3e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-7), ("bf16x6", 1e-7),
+                                      ("bf16x3", 3e-6)])
 def test_window_of_one_virtual(prec, tol):
     note("one-virtual window", prec)
     nocc, nvir, naux = 7, 15, 20

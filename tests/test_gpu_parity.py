@@ -3,7 +3,9 @@
 Tolerances:
 * FP64 sigma: |sigma_gpu - M z| <= 1e-12 * max(1, max|M z|) elementwise (only the summation
   order differs);
-* FP32 sigma: <= 3e-5 * max|M z| (operands rounded to 24 bits, sums over naux * nmo terms);
+* FP32 sigma: <= 1e-7 * max|M z| on the small shapes (3.5e-8 measured; operands rounded to 24
+  bits, sums over naux * nmo terms); on the panel shapes FP32 and BF16x6 <= 6e-7 and BF16x3
+  <= 1.5e-5 of the largest sampled entry (2.4e-7, 2.1e-7 and 5.4e-6 measured);
 * eigenvalues: <= 1e-6 Ha (the bar of the method's accuracy target); FP64 paths are asserted at
   1e-8 Ha, their measured level being ~1e-12.
 """
@@ -66,8 +68,8 @@ def test_sigma_fp64(mult, case):
 PANEL_CASES = [(40, 70, 24), (50, 90, 20), (70, 110, 16)]
 
 
-@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16x6", 3e-5),
-                                       ("bf16x3", 3e-4)])
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp32", 6e-7), ("bf16x6", 6e-7),
+                                       ("bf16x3", 1.5e-5)])
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case", PANEL_CASES)
 def test_sigma_panel_mixes(case, mult, prec, rtol):
@@ -98,8 +100,9 @@ def test_sigma_fp32(mult, case):
         z = gen.random_vectors(4, 7, ctx.n)
         s = ctx.matvec(z)
     ref = (M @ z.T).T
-    err = np.max(np.abs(s - ref))
-    assert err <= 3e-5 * np.abs(ref).max(), err
+    err = np.max(np.abs(s - ref)) / np.abs(ref).max()
+    note("relative error", err)
+    assert err <= 1e-7, err
 
 
 def test_sigma_block_sizes_and_repeat_bitwise():

@@ -6,6 +6,10 @@
 * small requests against the FP64 oracle within 1e-6 Ha;
 * the arena is never over-committed: peak reserved bytes <= budget, and a budget that holds one
   large request at a time serialises them;
+* fairness across sigma precisions (kernel variants, which cannot share a grid): the variant
+  whose waiting block has waited longest launches next, so a request's waiting sigma block is
+  overtaken by at most one launch round per other variant (max_overtaken <= 3), also in a stream
+  dominated by FP64 solves with a few reduced-precision ones;
 * failures stay with their request (EINVAL for non-finite integrals, found by the build;
   ENOCONV at the iteration cap; ENOMEM for a request larger than the arena) while the rest of the
   mix completes with the same roots.
@@ -104,6 +108,31 @@ def test_mix_completes(served_mix):
     # several solves shared launches: fewer grids than block products
     assert stats["grouped_products"] > stats["group_launches"]
     assert stats["peak_inflight"] >= 2
+    assert max(r["max_overtaken"] for r in res.values()) <= 3
+
+
+def test_mixed_precision_stream_is_fair():
+    """Six FP64 solves and two reduced-precision ones admitted together: with the FP64 solves
+    nearly always waiting for sigma somewhere, a policy that served the variants in a fixed order
+    would keep the others waiting; here each waiting block is overtaken at most once per other
+    variant, and every result equals its standalone solve bit for bit."""
+    reqs = [(61 + j, 10 + j, 100 + 10 * j, "singlet" if j % 2 else "triplet", 8, "fp64")
+            for j in range(6)]
+    reqs += [(71, 8, 90, "singlet", 6, "fp32"), (72, 9, 80, "triplet", 6, "bf16x6")]
+    inputs = [device_inputs(s, no, nv, naux_of(no, nv)) for (s, no, nv, *_r) in reqs]
+    note("mixed-precision stream")
+    res, stats = serve(reqs, max_inflight=8, inputs=inputs)
+    note("stats", stats, "overtaken", [r["max_overtaken"] for r in res.values()])
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for i, r in res.items():
+        assert r["status"] == P.binding.OK, r["message"]
+        assert r["max_overtaken"] <= 2  # three variants here: at most one round per other one
+    for i in (6, 7):
+        seed, nocc, nvir, mult, nroot, prec = reqs[i]
+        eps, L = inputs[i]
+        with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
+            r = ctx.davidson(nroot, tol=tol_of(prec))
+        assert np.array_equal(r["omega"], res[i]["omega"])
 
 
 @pytest.mark.parametrize("i", range(len(MIX)))
