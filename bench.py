@@ -1,13 +1,27 @@
 """Benchmark of the ppRPA hot path on one MI355X.
 
-Workload (default): the FP64 Davidson configuration, nocc = 20, nvir = 200, naux = 700,
-orbital energies and three-centre integrals from workloads/gen.py (seed 0), the lowest 10 pp
-roots of the singlet and of the triplet, block 20, residual tolerance 1e-6.
+Headline workload (default): nocc = 50, nvir = 500, naux = 1800 (the largest single-GPU
+configuration that the whole path runs on without an active window), orbital energies and
+three-centre integrals from workloads/gen.py (seed 0, integrals scaled by 0.7: unscaled, this
+size has no definite pencil and so no well-defined lowest roots), the lowest 20 singlet pp roots
+by block Davidson (block 20, residual tolerance 1e-6), sigma in FP64 on FP64 MFMA, subspace
+algebra in FP64.
 
-One step = the whole path for that workload with the inputs already resident in HBM:
-staging (pprpa_build, both spins) + the two Davidson solves (sigma products, FP64 subspace
-algebra, Rayleigh-Ritz, residuals). The metric is sigma products per second (single-vector
-products counted over both solves) at an eigenvalue error within 1e-6 Ha of the oracle's.
+One step = one Davidson iteration of that solve with the inputs already resident in HBM and the
+problem staged (pprpa_build, timed separately): the sigma product of the new block of trial
+vectors (unpack, the fused density-fitted contraction, the epilogue), the Rayleigh-Ritz step on
+the projected pencil, residuals, preconditioned corrections and their orthogonalisation, driven
+through pprpa_solve_iterate. After the K timed steps the solve runs on to convergence (untimed)
+and the line reports every root's residual norm. value = single-vector sigma products per second
+over the K steps.
+
+Extras on the same line: the 20/200/700 FP64 Davidson (singlet + triplet, 10 roots, both solves
+concurrently on two streams, eigenvalues against the oracle's), isolated sigma, the small direct
+workload, the correlation energy, unrestricted sectors, the hh channel, NTOs, the precision study
+at 50/500/1800 (FP32 / BF16x6 / BF16x3 sigma against the headline's FP64 roots), the active
+window (40 + 400 of 120/1500/4000) in every precision, a serving sample (the first 128 requests
+of the 512-request stream, which hold its largest, 37/399/1526 and 40/395/1523) and the oracle
+timed on the host cores.
 
 Serving stream (--serve-only): 512 seeded requests (workloads/gen.py serve_requests: nocc 4-40,
 nvir 30-400, naux = 3.5 nmo, singlet/triplet 50/50, 4-12 roots, integrals scaled by 0.7, tol
@@ -15,8 +29,7 @@ nvir 30-400, naux = 3.5 nmo, singlet/triplet 50/50, 4-12 roots, integrals scaled
 (--serve-prec fp64 for all-FP64). The saturated rate R_sat is measured first (the first 48
 requests submitted at once); then all 512 arrive as a Poisson process at 0.7 R_sat. Each
 request's integrals are generated on the device ahead of its arrival (not timed); latency =
-finish - submit on the server's clock. The default line carries a shorter sample of the same
-stream under "serving" (R_sat from 32 requests, then the first 64 requests at 0.7 R_sat).
+finish - submit on the server's clock.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-serve | --serve-only]
 """
@@ -35,39 +48,103 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6e12   # MI355X dense FP64 matrix, FLOP/s
 PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12     # B/s
-TRAFFIC_GB_PER_LAUNCH = 2.36  # measured for the FP64 sigma kernel as it stands (see roofline)
+# HBM traffic of one launch of the FP64 sigma kernel (GB), from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a plain 1 GiB device copy, keyed by (workload, precision); the profile
+# summaries under profiles/ name the command. A workload without an entry reports null.
+TRAFFIC_GB_PER_LAUNCH = {}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(nocc, nvir, naux, mult, nvec, budget_s=20.0):
-    """The oracle's density-fitted sigma (oracle/pprpa_oracle.py, sigma_factorised) on the
-    host cores, on a bounded sample of vectors of the same workload."""
-    from oracle import pprpa_oracle as O
-    from workloads import gen
+def host_info():
+    """Cores, CPU model and BLAS of the host the oracle runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cores"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count()])
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            b = blas[0]
+            info["blas"] = f"{b.get('internal_api')} {b.get('version')} ({b.get('architecture')})"
+            info["blas_threads"] = int(b.get("num_threads", 0))
     except Exception:
-        cores = os.cpu_count()
-    eps = gen.orbital_energies(0, nocc, nvir)
-    L = gen.lpq_full(0, nocc + nvir, naux)
-    sp = O.active_space(eps, L, nocc)
-    n = O.pairs(nvir, mult)[0].size + O.pairs(nocc, mult)[0].size
-    z = gen.random_vectors(1, nvec, n).T
-    done = 0
-    t0 = time.perf_counter()
-    for c in range(nvec):
-        O.sigma_factorised(sp, mult, z[:, c])
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "sigma/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{done} single-vector {mult} sigma products (oracle sigma_factorised, FP64 "
-                      f"NumPy) at nocc={nocc}, nvir={nvir}, naux={naux}"}
+        pass
+    info["omp_num_threads"] = os.environ.get("OMP_NUM_THREADS")
+    return info
+
+
+def _median_time(fn, reps=3):
+    fn()  # warm-up
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        t.append(time.perf_counter() - t0)
+    return float(np.median(t))
+
+
+def cpu_baseline(head_L=None, head_eps=None, head_cfg=None):
+    """The oracle (oracle/pprpa_oracle.py) on the host cores, on bounded samples:
+    * the headline workload's density-fitted sigma (sigma_factorised, FP64 NumPy/BLAS): single
+      vectors, median of 3 after a warm-up, all cores -> value (sigma/s);
+    * the 20/200/700 workload's sigma, all cores and 1 thread, medians of 3;
+    * the dense oracle end to end at 5/20/100 (build A, B, C + Cholesky-reduced eigh, 5 singlet
+      roots), all cores and 1 thread, medians of 3."""
+    from oracle import pprpa_oracle as O
+    from workloads import gen
+    from threadpoolctl import threadpool_limits
+    info = host_info()
+    out = {"kind": "oracle", "unit": "sigma/s", "host": info}
+    cores = info.get("blas_threads") or info.get("affinity_cores") or os.cpu_count()
+
+    def sigma_rate(sp, mult, n):
+        z = gen.random_vectors(1, 1, n)[0]
+        return 1.0 / _median_time(lambda: O.sigma_factorised(sp, mult, z))
+
+    # headline workload (the integrals come in from the caller's device copy)
+    if head_L is not None:
+        c = head_cfg
+        sp = O.active_space(head_eps, head_L, c["nocc"])
+        n = O.pairs(c["nvir"], c["mult"])[0].size + O.pairs(c["nocc"], c["mult"])[0].size
+        out["value"] = sigma_rate(sp, c["mult"], n)
+        out["sample"] = (f"median of 3 single-vector {c['mult']} sigma products (oracle "
+                         f"sigma_factorised, FP64) at nocc={c['nocc']}, nvir={c['nvir']}, "
+                         f"naux={c['naux']}, after one warm-up, {cores} BLAS threads")
+        del sp
+    # 20/200/700 sigma, all cores and 1 thread
+    eps = gen.orbital_energies(0, 20, 200)
+    L = gen.lpq_full(0, 220, 700)
+    sp = O.active_space(eps, L, 20)
+    n = O.pairs(200, "singlet")[0].size + O.pairs(20, "singlet")[0].size
+    out["sigma_20x200x700_all_cores"] = sigma_rate(sp, "singlet", n)
+    with threadpool_limits(1):
+        out["sigma_20x200x700_1_thread"] = sigma_rate(sp, "singlet", n)
+    del sp, L
+    # dense oracle end to end at 5/20/100
+    eps = gen.orbital_energies(0, 5, 20)
+    L = gen.lpq_full(0, 25, 100)
+    dense = lambda: O.solve(eps, L, 5, "singlet", 5)
+    out["dense_5x20x100_ms_all_cores"] = 1e3 * _median_time(dense)
+    with threadpool_limits(1):
+        out["dense_5x20x100_ms_1_thread"] = 1e3 * _median_time(dense)
+    out["cores"] = int(cores)
+    if "value" not in out:
+        out["value"] = out["sigma_20x200x700_all_cores"]
+        out["sample"] = "median of 3 single-vector singlet sigma products at 20/200/700"
+    return out
 
 
 def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, prec="fp64",
@@ -198,6 +275,7 @@ def serve_stream(P, gen, n_req=512, n_sat=48, budget_gb=96, max_inflight=16, pre
         "sigma_products_per_s": n_sigma / makespan,
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
         "latency_mean_s": float(np.mean(lat)), "latency_max_s": float(np.max(lat)),
+        "latency_p99_over_p50": float(np.percentile(lat, 99) / np.percentile(lat, 50)),
         "queue_wait_p50_s": float(np.percentile(qwait, 50)),
         "queue_wait_p99_s": float(np.percentile(qwait, 99)),
         "late_submits": len(late), "status": status, "failures": failures[:12],
@@ -408,8 +486,28 @@ def hh_channel(P, eps_d, L_d, nocc, nroot, block, tol, reps=2):
             "iters": iters, "max_eig_err_ha_vs_oracle": max(errs) if errs else None}
 
 
+def device_problem(gen, name, dev, scale=None):
+    """Orbital energies and the active block of the integrals of a large workload, generated on
+    the device (scaled by the workload's eig_scale unless scale is given), and the build
+    keywords that go with them."""
+    import torch
+    c = gen.CONFIGS[name]
+    nocc, nvir, naux = c["nocc"], c["nvir"], c["naux"]
+    no_act, nv_act = c.get("nocc_act"), c.get("nvir_act")
+    idx = gen.active_indices(nocc, nvir, no_act, nv_act)
+    scale = c.get("eig_scale", 1.0) if scale is None else scale
+    L = torch.empty((naux, idx.size, idx.size), dtype=torch.float64, device=dev)
+    for p0 in range(0, naux, 128):
+        aux = np.arange(p0, min(naux, p0 + 128))
+        L[p0:p0 + aux.size] = gen.lpq_block_torch(0, nocc + nvir, naux, idx, idx, aux, dev) * scale
+    eps = torch.from_numpy(gen.orbital_energies(0, nocc, nvir)).to(dev)
+    torch.cuda.synchronize()
+    kw = dict(nocc_act=no_act or 0, nvir_act=nv_act or 0, lpq_is_active=no_act is not None)
+    return eps, L, kw
+
+
 def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20, tol=1e-6,
-                    tol_reduced=1e-5, name="mixed"):
+                    tol_reduced=1e-5, name="mixed", problem=None, ref=None):
     """A large workload (default: the mixed-precision one, nocc 50, nvir 500, naux 1800, singlet,
     20 roots; name="active": the 40 + 400 window of 120 / 1500 / 4000, triplet, 16 roots, only
     the active block of L passed) solved by the same Davidson with sigma in each precision
@@ -424,15 +522,8 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
     nocc, nvir, naux, nroot = c["nocc"], c["nvir"], c["naux"], c["nroot"]
     mult = c["mult"] if isinstance(c["mult"], str) else c["mult"][0]
     no_act, nv_act = c.get("nocc_act"), c.get("nvir_act")
-    idx = gen.active_indices(nocc, nvir, no_act, nv_act)
-    L = torch.empty((naux, idx.size, idx.size), dtype=torch.float64, device=dev)
-    for p0 in range(0, naux, 128):
-        aux = np.arange(p0, min(naux, p0 + 128))
-        L[p0:p0 + aux.size] = gen.lpq_block_torch(0, nocc + nvir, naux, idx, idx, aux, dev) * c["eig_scale"]
-    eps = torch.from_numpy(gen.orbital_energies(0, nocc, nvir)).to(dev)
-    torch.cuda.synchronize()
-    kw = dict(nocc_act=no_act or 0, nvir_act=nv_act or 0, lpq_is_active=no_act is not None)
-    out, ref = {}, None
+    eps, L, kw = problem if problem is not None else device_problem(gen, name, dev)
+    out = {}
     for prec in precs:
         t0 = time.perf_counter()
         with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=block, **kw) as ctx:
@@ -452,7 +543,7 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
              "sigma_kernel_frac_of_peak": nprod * alg / peak,
              "sigma_kernel_share_of_solve": st["seconds"] / (t2 - t1),
              "max_resid": r["report"]["max_resid"]}
-        if prec == "fp64":
+        if prec == "fp64" and ref is None:
             ref = r["omega"]
         elif ref is not None:
             d = np.abs(r["omega"] - ref)
@@ -460,28 +551,138 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
             e["per_root_err_ha"] = [float(x) for x in d]
         out[prec] = e
         log(f"{name} {prec}: {e['status']} {e['solve_s']:.2f}s {e['sigma_kernel_tflops_algorithmic']:.1f} TF")
-    del L
+    del L, eps
     window = f" window {no_act} occ + {nv_act} vir," if no_act else ""
     return {"workload": f"nocc={nocc} nvir={nvir} naux={naux}{window} {mult}, {nroot} roots, "
                         f"block {block}, tol {tol:g} (FP64) / {tol_reduced:g} (reduced precisions), "
                         f"L x {c['eig_scale']}", "by_prec": out}
 
 
+def headline(P, gen, name, prec, block, tol, steps, warmup, problem):
+    """The headline: K Davidson iterations of the workload's solve, timed one by one through
+    pprpa_solve_iterate after W untimed ones; then the solve runs on to convergence. A solve
+    that converges inside the timed window is followed by a new one on the same context."""
+    import torch
+    c = gen.CONFIGS[name]
+    nocc, nroot = c["nocc"], c["nroot"]
+    mult = c["mult"] if isinstance(c["mult"], str) else c["mult"][0]
+    eps, L, kw = problem
+    t0 = time.perf_counter()
+    ctx = P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=block, **kw)
+    t_build = time.perf_counter() - t0
+    state = {"sv": None, "prev": 0, "solves": 0}
+
+    def begin():
+        state["sv"] = ctx.solve_begin(nroot, block=block, tol=tol, max_iter=300)
+        state["prev"] = 0
+        state["solves"] += 1
+
+    def step():
+        """One Davidson iteration; returns the sigma products it computed."""
+        if state["sv"] is None or state["sv"].done:
+            if state["sv"] is not None:
+                state["sv"].end()
+            begin()
+        sv = state["sv"]
+        if sv.iterate(1) != 1:
+            raise RuntimeError("no Davidson iteration ran")
+        ns = json.loads(sv.log[-1])["n_sigma"]
+        d, state["prev"] = ns - state["prev"], ns
+        return d
+
+    for w in range(warmup):
+        step()
+    log(f"headline: {warmup} warm-up iterations done")
+    torch.cuda.synchronize()
+    state["sv"].sigma_stats(reset=True)
+    n_sigma = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        n_sigma += step()
+        if (k + 1) % 5 == 0:
+            log(f"headline step {k + 1}/{steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = state["sv"].sigma_stats()
+    timed_solves = state["solves"]
+    # the solve runs on to convergence (untimed): residuals of every root
+    sv = state["sv"]
+    while not sv.done:
+        sv.iterate(8)
+    r = sv.end()
+    ctx.close()
+    return dict(elapsed=elapsed, n_sigma=n_sigma, stats=st, t_build=t_build, result=r,
+                solves_in_timed_window=timed_solves, mult=mult, nroot=nroot)
+
+
+def fp64_davidson_pair(P, gen, steps, warmup, nroot=10, block=20, tol=1e-6, concurrent=True):
+    """The 20/200/700 FP64 Davidson workload: one step = staging + the singlet and triplet solves
+    (concurrently on two streams), eigenvalues against the oracle's stored roots."""
+    import torch
+    dev = torch.device("cuda:0")
+    nocc, nvir, naux = 20, 200, 700
+    eps_d = torch.from_numpy(gen.orbital_energies(0, nocc, nvir)).to(dev)
+    L_d = torch.from_numpy(gen.lpq_full(0, nocc + nvir, naux)).to(dev)
+    torch.cuda.synchronize()
+    mults = ("singlet", "triplet")
+
+    def solve(mult):
+        t0 = time.perf_counter()
+        with P.PpRPA(eps_d, L_d, nocc, mult=mult, max_block=block) as ctx:
+            r = ctx.davidson(nroot, block=block, tol=tol)
+            st = ctx.sigma_stats()
+        return dict(omega=r["omega"], rep=r["report"], stats=st, latency=time.perf_counter() - t0)
+
+    pool = ThreadPoolExecutor(max_workers=2) if concurrent else None
+
+    def step():
+        if pool is None:
+            return {m: solve(m) for m in mults}
+        futs = {m: pool.submit(solve, m) for m in mults}
+        return {m: f.result() for m, f in futs.items()}
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_sigma = sum(r[m]["rep"]["n_sigma"] for r in results for m in mults)
+    k_sec = sum(r[m]["stats"]["seconds"] for r in results for m in mults)
+    k_flops = sum(r[m]["stats"]["flops"] for r in results for m in mults)
+    k_launch = sum(r[m]["stats"]["launches"] for r in results for m in mults)
+    lat = np.array([r[m]["latency"] for r in results for m in mults])
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "davidson_fp64.json")))
+    errs = [float(np.max(np.abs(r[m]["omega"] - np.array(g["roots"][f"0/{m}"][:nroot]))))
+            for r in results for m in mults]
+    out = {"workload": f"ppRPA Davidson nocc={nocc} nvir={nvir} naux={naux}, singlet+triplet, "
+                       f"{nroot} roots, block {block}, tol {tol:g}, FP64; one step = staging + both "
+                       f"solves ({'concurrent, 2 streams' if concurrent else 'serial'})",
+           "steps": steps, "sigma_per_s": n_sigma / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "sigma_kernel_tflops": k_flops / k_sec / 1e12, "sigma_kernel_frac": k_flops / k_sec / PEAK_FP64,
+           "avg_launch_ms": 1e3 * k_sec / max(k_launch, 1), "sigma_kernel_share": k_sec / elapsed,
+           "latency_p50_s": float(np.percentile(lat, 50)),
+           "max_eig_err_ha_vs_oracle": max(errs),
+           "iters": {m: results[-1][m]["rep"]["iters"] for m in mults}}
+    return out, (eps_d, L_d)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--nocc", type=int, default=20)
-    ap.add_argument("--nvir", type=int, default=200)
-    ap.add_argument("--naux", type=int, default=700)
-    ap.add_argument("--nroot", type=int, default=10)
+    ap.add_argument("--workload", default="mixed",
+                    help="headline workload (workloads/gen.py CONFIGS: mixed = 50/500/1800)")
     ap.add_argument("--block", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--prec", default="fp64")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline line")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
+    ap.add_argument("--no-active", action="store_true", help="skip the active-window study")
     ap.add_argument("--precision-only", action="store_true", help="run only the precision study")
     ap.add_argument("--precs", default="fp64,fp32,bf16x6,bf16x3",
                     help="sigma precisions of the precision / active-window study (comma list; "
@@ -490,16 +691,16 @@ def main():
                     help="run only the active-window workload in each precision")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving stream")
     ap.add_argument("--serve-requests", type=int, default=None,
-                    help="requests in the serving stream (default 512 with --serve-only, else 96)")
+                    help="requests in the serving stream (default 512 with --serve-only, else 128)")
     ap.add_argument("--serve-prec", default="fp32",
                     help="sigma precision of the served solves (subspace algebra is FP64)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the headline step (no isolated sigma, small direct, correlation energy, "
-                         "unrestricted, hh channel or NTO entries)")
+                    help="no isolated sigma, 20/200/700, small direct, correlation energy, "
+                         "unrestricted, hh channel or NTO entries")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--serial", dest="concurrent", action="store_false",
-                    help="run the singlet and triplet solves one after the other")
+                    help="20/200/700 extra: the singlet and triplet solves one after the other")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sigma product "
@@ -512,35 +713,19 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
-    if args.precision_only:
+    data = "synthetic (seeded counter-based generator, workloads/gen.py)"
+    if args.precision_only or args.active_only:
+        name = "active" if args.active_only else "mixed"
         line = {"metric": "sigma-products/sec and per-root eigenvalue error by sigma precision",
-                "n_gpus": 1, "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
-        line.update(precision_study(P, gen, precs=tuple(args.precs.split(","))))
-        print(json.dumps(line), flush=True)
-        return
-    if args.active_only:
-        line = {"metric": "sigma-products/sec and per-root eigenvalue error by sigma precision",
-                "n_gpus": 1, "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
-        line.update(precision_study(P, gen, precs=tuple(args.precs.split(",")), name="active"))
+                "n_gpus": 1, "data": data}
+        line.update(precision_study(P, gen, precs=tuple(args.precs.split(",")), name=name))
         print(json.dumps(line), flush=True)
         return
     if args.serve_only:
-        line = {"metric": "served ppRPA requests/s with p50/p99 latency", "n_gpus": 1,
-                "data": "synthetic (seeded counter-based generator, workloads/gen.py)"}
+        line = {"metric": "served ppRPA requests/s with p50/p99 latency", "n_gpus": 1, "data": data}
         line.update(serve_stream(P, gen, n_req=args.serve_requests or 512, prec=args.serve_prec))
         print(json.dumps(line), flush=True)
         return
-    nocc, nvir, naux = args.nocc, args.nvir, args.naux
-    t = time.perf_counter()
-    eps = gen.orbital_energies(0, nocc, nvir)
-    L = gen.lpq_full(0, nocc + nvir, naux)
-    eps_d = torch.from_numpy(eps).to(dev)
-    L_d = torch.from_numpy(L).to(dev)
-    torch.cuda.synchronize()
-    log(f"inputs generated and resident in HBM ({L.nbytes / 1e6:.0f} MB) in {time.perf_counter() - t:.1f}s")
-    del L
-
-    mults = ("singlet", "triplet")
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
@@ -548,116 +733,101 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def solve(mult):
-        t0 = time.perf_counter()
-        ctx = P.PpRPA(eps_d, L_d, nocc, mult=mult, prec=args.prec, max_block=args.block)
-        r = ctx.davidson(args.nroot, block=args.block, tol=args.tol)
-        st = ctx.sigma_stats()
-        ctx.close()
-        return dict(omega=r["omega"], resid=r["resid"], rep=r["report"], stats=st,
-                    latency=time.perf_counter() - t0)
-
-    # The singlet and triplet solves are independent: each runs on its own library stream from
-    # its own host thread, so one solve's small serial kernels overlap the other's sigma launches.
-    pool = ThreadPoolExecutor(max_workers=len(mults)) if args.concurrent else None
-
-    def step():
-        if pool is None:
-            return {m: solve(m) for m in mults}
-        futs = {m: pool.submit(solve, m) for m in mults}
-        return {m: f.result() for m, f in futs.items()}
-
-    for w in range(args.warmup):
-        step()
-        log(f"warmup {w + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for s in range(args.steps):
-        results.append(step())
-        log(f"step {s + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    n_sigma = sum(r[m]["rep"]["n_sigma"] for r in results for m in mults)
-    k_sec = sum(r[m]["stats"]["seconds"] for r in results for m in mults)
-    k_flops = sum(r[m]["stats"]["flops"] for r in results for m in mults)
-    k_bytes = sum(r[m]["stats"]["bytes"] for r in results for m in mults)
-    k_launch = sum(r[m]["stats"]["launches"] for r in results for m in mults)
-    lat = np.array([r[m]["latency"] for r in results for m in mults])
-
-    # accuracy against the oracle's stored eigenvalues for this workload
-    max_err = None
-    gold = os.path.join(ROOT, "tests", "golden", "davidson_fp64.json")
-    if os.path.exists(gold) and (nocc, nvir, naux) == (20, 200, 700):
-        g = json.load(open(gold))
-        errs = []
-        for m in mults:
-            ref = np.array(g["roots"][f"0/{m}"][:args.nroot])
-            errs += [float(np.max(np.abs(r[m]["omega"][:len(ref)] - ref))) for r in results]
-        max_err = max(errs)
-
-    peak = PEAK_FP64 if args.prec == "fp64" else PEAK_FP32
-    achieved = k_flops / k_sec if k_sec > 0 else 0.0
+    name = args.workload
+    c = gen.CONFIGS[name]
+    t = time.perf_counter()
+    problem = device_problem(gen, name, dev)
+    log(f"{name} inputs resident in HBM ({problem[1].numel() * 8 / 1e9:.2f} GB) in "
+        f"{time.perf_counter() - t:.1f}s")
+    h = headline(P, gen, name, args.prec, args.block, args.tol, args.steps, args.warmup, problem)
+    st, r = h["stats"], h["result"]
+    peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32}.get(args.prec, PEAK_BF16)
+    nprod = {"bf16x6": 6, "bf16x3": 3}.get(args.prec, 1)
+    achieved = st["flops"] / st["seconds"] if st["seconds"] > 0 else 0.0
+    window = (f", window {c['nocc_act']} occ + {c['nvir_act']} vir" if c.get("nocc_act") else "")
+    wl = (f"ppRPA Davidson nocc={c['nocc']} nvir={c['nvir']} naux={c['naux']}{window}, {h['mult']}, "
+          f"{h['nroot']} roots, block {args.block}, tol {args.tol:g}, sigma {args.prec}, subspace "
+          f"FP64, integrals x {c.get('eig_scale', 1.0)}; one step = one Davidson iteration")
     line = {
-        "metric": "sigma-products/sec (FP64 Davidson, eigenvalues within 1e-6 Ha of the oracle)",
-        "value": n_sigma / elapsed,
+        "metric": "sigma-products/sec (Davidson, every root converged to residual <= tol; "
+                  "eigenvalue error <= 1e-6 Ha)",
+        "value": h["n_sigma"] / h["elapsed"],
         "unit": "sigma/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * h["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else args.prec,
-        "data": "synthetic (seeded counter-based generator, workloads/gen.py)",
-        "config": {"workload": f"ppRPA Davidson nocc={nocc} nvir={nvir} naux={naux}, singlet+triplet, "
-                               f"{args.nroot} roots, block {args.block}, tol {args.tol:g}",
-                   "nocc": nocc, "nvir": nvir, "naux": naux, "nroot": args.nroot,
-                   "block": args.block, "tol": args.tol, "prec": args.prec,
-                   "solves": "concurrent (2 streams)" if args.concurrent else "serial"},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak,
-                     # HBM bytes per launch of this kernel (FP64, this workload), from
-                     # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy:
-                     # profiles/sigma_fp64_bench_20x200x700_hbm_traffic.md
-                     "traffic": TRAFFIC_GB_PER_LAUNCH if (args.prec == "fp64" and
-                                                          (nocc, nvir, naux) == (20, 200, 700)) else None,
+        "data": data,
+        "config": {"workload": wl, "nocc": c["nocc"], "nvir": c["nvir"], "naux": c["naux"],
+                   "nocc_act": c.get("nocc_act"), "nvir_act": c.get("nvir_act"),
+                   "mult": h["mult"], "nroot": h["nroot"], "block": args.block, "tol": args.tol,
+                   "prec": args.prec, "eig_scale": c.get("eig_scale", 1.0)},
+        "roofline": {"bound": "mfma", "achieved": nprod * achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": nprod * achieved / peak,
+                     "traffic": TRAFFIC_GB_PER_LAUNCH.get((name, args.prec)),
                      "traffic_unit": "GB/launch",
-                     "kernel": "k_sandwich (fused sigma contraction)",
-                     "launches": k_launch, "avg_launch_ms": 1e3 * k_sec / max(k_launch, 1),
-                     "algorithmic_gbytes_per_launch": k_bytes / max(k_launch, 1) / 1e9},
-        "sigma_mfma_tflops": achieved / 1e12,
-        "n_sigma_per_step": n_sigma / args.steps,
-        "sigma_kernel_share": k_sec / elapsed,
-        "latency_p50_s": float(np.percentile(lat, 50)),
-        "latency_p99_s": float(np.percentile(lat, 99)),
-        "max_eig_err_ha": max_err,
-        "iters": {m: results[-1][m]["rep"]["iters"] for m in mults},
+                     "kernel": "k_sandwich (fused density-fitted sigma contraction)",
+                     "launches": st["launches"], "avg_launch_ms": 1e3 * st["seconds"] / max(st["launches"], 1),
+                     "algorithmic_gflop_per_launch": st["flops"] / max(st["launches"], 1) / 1e9,
+                     "algorithmic_gbytes_per_launch": st["bytes"] / max(st["launches"], 1) / 1e9},
+        "sigma_mfma_tflops_algorithmic": achieved / 1e12,
+        "n_sigma_per_step": h["n_sigma"] / args.steps,
+        "sigma_kernel_share": st["seconds"] / h["elapsed"],
+        "staging_s": h["t_build"],
+        "solves_in_timed_window": h["solves_in_timed_window"],
+        "converged": {"status": P.binding.STATUS_NAMES[r["status"]], "iters": r["report"]["iters"],
+                      "n_sigma": r["report"]["n_sigma"], "solve_s": r["report"]["t_total_s"],
+                      "omega_ha": [float(x) for x in r["omega"]],
+                      "resid_per_root": [float(x) for x in r["resid"]],
+                      "max_resid": float(np.max(r["resid"]))},
     }
+    log(f"headline: {line['value']:.1f} sigma/s, kernel {line['roofline']['achieved']:.1f} TF "
+        f"({line['roofline']['frac']:.3f}), converged max resid {line['converged']['max_resid']:.2e}")
+    if args.headline_only:
+        print(json.dumps(line), flush=True)
+        return
+    ref_omega = r["omega"] if (args.prec == "fp64" and r["status"] == 0) else None
+    head_host = None
+    if not args.no_cpu:  # the headline's integrals, on the host, for the oracle's sigma rate
+        head_host = (problem[1].cpu().numpy(), problem[0].cpu().numpy())
+    if not args.no_precision and name == "mixed":
+        log("precision study ...")
+        precs = ("fp32", "bf16x6", "bf16x3") if ref_omega is not None else ("fp64", "fp32", "bf16x6", "bf16x3")
+        line["precision"] = precision_study(P, gen, precs=precs, name="mixed", problem=problem,
+                                            ref=ref_omega)
+    del problem
+    torch.cuda.empty_cache()
     if not args.no_extras:
+        log("20/200/700 FP64 Davidson ...")
+        line["fp64_davidson_20x200x700"], (eps_d, L_d) = fp64_davidson_pair(
+            P, gen, steps=5, warmup=2, concurrent=args.concurrent)
         log("isolated sigma ...")
-        line["isolated_sigma"] = isolated_sigma(P, gen, eps_d, L_d, nocc, args.block)
+        line["isolated_sigma"] = isolated_sigma(P, gen, eps_d, L_d, 20, 20)
+        log("hh channel ...")
+        line["hh_channel"] = hh_channel(P, eps_d, L_d, 20, 10, 20, 1e-6)
+        log("NTO analysis ...")
+        line["nto_analysis"] = nto_analysis(P, eps_d, L_d, 20, 10, 20, 1e-6)
+        del eps_d, L_d
         log("small direct workload ...")
         line["small_direct"] = small_direct(P, gen)
         line["correlation_energy"] = correlation_energy(P, gen)
         line["unrestricted"] = unrestricted(P, gen)
-    if (nocc, nvir, naux) == (20, 200, 700) and not args.no_extras:
-        log("hh channel ...")
-        line["hh_channel"] = hh_channel(P, eps_d, L_d, nocc, args.nroot, args.block, args.tol)
-        log("NTO analysis ...")
-        line["nto_analysis"] = nto_analysis(P, eps_d, L_d, nocc, args.nroot, args.block, args.tol)
-    if not args.no_precision:
-        log("precision study ...")
-        line["precision"] = precision_study(P, gen)
+    if not args.no_active:
+        log("active-window study ...")
+        line["active_window"] = precision_study(P, gen, precs=tuple(args.precs.split(",")),
+                                                name="active", block=20)
+    torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving stream ...")
-        line["serving"] = serve_stream(P, gen, n_req=args.serve_requests or 64, n_sat=32,
+        line["serving"] = serve_stream(P, gen, n_req=args.serve_requests or 128, n_sat=32,
                                        prec=args.serve_prec)
     if not args.no_cpu:
         log("timing the oracle on the host cores ...")
-        line["cpu_baseline"] = cpu_baseline(nocc, nvir, naux, "singlet", 64)
+        line["cpu_baseline"] = cpu_baseline(head_L=head_host[0], head_eps=head_host[1], head_cfg=c)
     print(json.dumps(line), flush=True)
 
 

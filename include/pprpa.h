@@ -218,6 +218,36 @@ typedef struct {
 } pprpa_kernel_stats;
 pprpa_status pprpa_sigma_stats(pprpa_ctx* ctx, pprpa_kernel_stats* out, int32_t reset);
 
+/* The Davidson solve of pprpa_davidson advanced by the caller, a few iterations at a time (for
+ * callers that interleave the solve with other work, time it per iteration, or stop it early).
+ * An iteration is the sigma product of the pending block of trial vectors (the density-fitted
+ * product of Eq. eigen_equation), the Rayleigh-Ritz step on the projected pencil, the residuals
+ * and the new correction vectors; iterations run exactly as in pprpa_davidson, so a solve driven
+ * to convergence here returns bitwise what pprpa_davidson returns for the same arguments.
+ *
+ * pprpa_solve_begin: validate args (as pprpa_davidson; direct = 1 is EUNSUPPORTED), take the
+ *   workspace and form the initial subspace. The solve holds the context until
+ *   pprpa_solve_end: other calls on the context return EBUSY, and the context must not be freed
+ *   before the solve is ended. Errors: EINVAL, EUNSUPPORTED, EBUSY, ENOMEM, EDEVICE (nothing
+ *   is held and *out is NULL).
+ * pprpa_solve_iterate: run up to n_iter (>= 0) iterations; *iters_done (may be NULL) receives
+ *   the number run and *done (may be NULL) 1 once the solve has finished (converged, failed,
+ *   or reached max_iter). Errors: EINVAL, EDEVICE (the solve is then finished).
+ * pprpa_solve_end: the outputs of pprpa_davidson (omega [nroot] host or NULL, vecs [nroot][n]
+ *   host or NULL, resid [nroot] host or NULL, rep or NULL) and its status: OK when converged, ENOCONV
+ *   when the solve was ended before convergence or reached max_iter (outputs from the last
+ *   iterate; omega and resid are left untouched if no iteration ran), ENONDEF and the other
+ *   failures as pprpa_davidson. Releases the solve and its hold on the context in every case. */
+typedef struct pprpa_solve pprpa_solve; /* opaque */
+pprpa_status pprpa_solve_begin(pprpa_ctx* ctx, const pprpa_davidson_args* args,
+                               pprpa_solve** out);
+pprpa_status pprpa_solve_iterate(pprpa_solve* solve, int32_t n_iter, int32_t* iters_done,
+                                 int32_t* done);
+pprpa_status pprpa_solve_end(pprpa_solve* solve, double* omega, double* vecs, double* resid,
+                             pprpa_report* rep);
+/* pprpa_sigma_stats of the solve's context while the solve holds it (same counters, same reset). */
+pprpa_status pprpa_solve_stats(pprpa_solve* solve, pprpa_kernel_stats* out, int32_t reset);
+
 /* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of many independent solves on the current device.
  *

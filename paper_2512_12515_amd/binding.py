@@ -104,7 +104,8 @@ _lib = None
 EXPORTS = ["pprpa_build", "pprpa_dims", "pprpa_matvec", "pprpa_dense_matrix", "pprpa_davidson",
            "pprpa_free", "pprpa_strerror", "pprpa_last_error", "pprpa_sigma_stats",
            "pprpa_server_create", "pprpa_server_submit", "pprpa_server_poll", "pprpa_server_wait",
-           "pprpa_server_stats", "pprpa_server_destroy"]
+           "pprpa_server_stats", "pprpa_server_destroy", "pprpa_solve_begin", "pprpa_solve_iterate",
+           "pprpa_solve_end", "pprpa_solve_stats"]
 
 
 def lib():
@@ -136,6 +137,16 @@ def lib():
     L.pprpa_davidson.argtypes = [C.c_void_p, C.POINTER(DavidsonArgs), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.POINTER(Report)]
     L.pprpa_davidson.restype = C.c_int
+    L.pprpa_solve_begin.argtypes = [C.c_void_p, C.POINTER(DavidsonArgs), C.POINTER(C.c_void_p)]
+    L.pprpa_solve_begin.restype = C.c_int
+    L.pprpa_solve_iterate.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
+    L.pprpa_solve_iterate.restype = C.c_int
+    L.pprpa_solve_end.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(Report)]
+    L.pprpa_solve_end.restype = C.c_int
+    L.pprpa_solve_stats.argtypes = [C.c_void_p, C.POINTER(KernelStats), C.c_int32]
+    L.pprpa_solve_stats.restype = C.c_int
     L.pprpa_nto.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p]
     L.pprpa_nto.restype = C.c_int
@@ -329,10 +340,10 @@ class PpRPA:
         return M
 
     # -- eigensolvers ------------------------------------------------------------------------
-    def davidson(self, nroot, block=0, tol=1e-6, max_iter=0, max_subspace=0, guess=None,
-                 direct=False, vectors=False, log=None, raise_noconv=True, channel="pp"):
-        """channel "pp": the lowest nroot two-electron addition roots, ascending; "hh": the nroot
-        two-electron removal roots nearest the gap, descending."""
+    @staticmethod
+    def _davidson_args(nroot, block, tol, max_iter, max_subspace, guess, direct, log, channel):
+        """pprpa_davidson_args plus the Python objects that must outlive the call (guess array,
+        log callback) and the list the log lines are collected in."""
         a = DavidsonArgs()
         a.nroot = int(nroot)
         a.channel = CHANNEL[channel]
@@ -347,8 +358,21 @@ class PpRPA:
             a.nguess = g.shape[0]
         a.direct = int(bool(direct))
         lines = []
-        cb = LOGFN((lambda u, s: (lines.append(s.decode()), log and log(s.decode()))) if True else 0)
+        cb = LOGFN(lambda u, s: (lines.append(s.decode()), log and log(s.decode())))
         a.log = cb
+        return a, (g, cb), lines
+
+    def solve_begin(self, nroot, block=0, tol=1e-6, max_iter=0, max_subspace=0, guess=None,
+                    log=None, channel="pp"):
+        """A Davidson solve advanced by the caller (pprpa_solve_begin); see Solve."""
+        return Solve(self, nroot, block, tol, max_iter, max_subspace, guess, log, channel)
+
+    def davidson(self, nroot, block=0, tol=1e-6, max_iter=0, max_subspace=0, guess=None,
+                 direct=False, vectors=False, log=None, raise_noconv=True, channel="pp"):
+        """channel "pp": the lowest nroot two-electron addition roots, ascending; "hh": the nroot
+        two-electron removal roots nearest the gap, descending."""
+        a, keep, lines = self._davidson_args(nroot, block, tol, max_iter, max_subspace, guess,
+                                             direct, log, channel)
         omega = np.empty(nroot)
         resid = np.empty(nroot)
         vecs = np.empty((nroot, self.n)) if vectors else None
@@ -361,6 +385,59 @@ class PpRPA:
             raise PpRPAError(st, msg)
         return dict(omega=omega, vecs=vecs, resid=resid, report=rep.as_dict(), status=st,
                     log=lines, message=msg)
+
+
+class Solve:
+    """pprpa_solve_begin / pprpa_solve_iterate / pprpa_solve_end: iterate(n) runs up to n
+    Davidson iterations and returns how many ran; done tells whether the solve has finished;
+    end() returns what PpRPA.davidson returns (and releases the context)."""
+
+    def __init__(self, ctx, nroot, block, tol, max_iter, max_subspace, guess, log, channel):
+        self._ctx = ctx
+        self._a, self._keep, self.log = ctx._davidson_args(nroot, block, tol, max_iter,
+                                                           max_subspace, guess, False, log,
+                                                           channel)
+        self.nroot = int(nroot)
+        self.done = False
+        self.iters = 0
+        h = C.c_void_p()
+        _check(lib().pprpa_solve_begin(ctx._h, C.byref(self._a), C.byref(h)))
+        self._h = h
+
+    def iterate(self, n=1):
+        it, dn = C.c_int32(), C.c_int32()
+        _check(lib().pprpa_solve_iterate(self._h, int(n), C.byref(it), C.byref(dn)))
+        self.iters += it.value
+        self.done = bool(dn.value)
+        return it.value
+
+    def sigma_stats(self, reset=False):
+        """PpRPA.sigma_stats of the context while this solve holds it."""
+        st = KernelStats()
+        _check(lib().pprpa_solve_stats(self._h, C.byref(st), int(bool(reset))))
+        return st.as_dict()
+
+    def end(self, vectors=False, raise_noconv=True):
+        omega = np.full(self.nroot, np.nan)
+        resid = np.full(self.nroot, np.nan)
+        vecs = np.empty((self.nroot, self._ctx.n)) if vectors else None
+        rep = Report()
+        st = lib().pprpa_solve_end(self._h, omega.ctypes.data,
+                                   vecs.ctypes.data if vectors else None, resid.ctypes.data,
+                                   C.byref(rep))
+        self._h = None
+        msg = lib().pprpa_last_error().decode()
+        if st not in (OK, ENOCONV) or (st == ENOCONV and raise_noconv):
+            raise PpRPAError(st, msg)
+        return dict(omega=omega, vecs=vecs, resid=resid, report=rep.as_dict(), status=st,
+                    log=self.log, message=msg)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            try:
+                lib().pprpa_solve_end(self._h, None, None, None, None)
+            except Exception:
+                pass
 
 
 class Server:

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <numeric>
 
@@ -965,6 +966,107 @@ pprpa_status pprpa_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* 
   PPRPA_HIP(hipSetDevice(c->device));
   pprpa_status st = run_davidson(c, a, omega, vecs, resid, rep);
   if (hipStreamSynchronize(c->stream) == hipSuccess) (void)harvest_timing(c);
+  return st;
+}
+
+// A Davidson solve advanced by the caller. It holds its context (other calls on the context
+// return EBUSY) from pprpa_solve_begin until pprpa_solve_end.
+struct pprpa_solve {
+  pprpa_ctx* c = nullptr;
+  std::unique_ptr<Solver> sv;
+};
+
+pprpa_status pprpa_solve_begin(pprpa_ctx* c, const pprpa_davidson_args* a, pprpa_solve** out) {
+  g_err.clear();
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (!c) return einval("ctx is NULL");
+  if (!a) return einval("args is NULL");
+  if (a->direct) {
+    set_error("pprpa_solve_begin runs the Davidson solver only (direct=0); use pprpa_davidson");
+    return PPRPA_EUNSUPPORTED;
+  }
+  int expect = 0;
+  if (!c->busy.compare_exchange_strong(expect, 1)) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  std::unique_ptr<pprpa_solve> s(new (std::nothrow) pprpa_solve());
+  if (!s) {
+    c->busy.store(0);
+    return einval("host allocation failed");
+  }
+  s->c = c;
+  pprpa_status rc = PPRPA_OK;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipSetDevice(%d) failed", c->device);
+    rc = PPRPA_EDEVICE;
+  } else {
+    s->sv.reset(new Solver(c, *a));
+    s->sv->start();
+    if (s->sv->phase == Solver::DONE && s->sv->status != PPRPA_OK) {
+      set_error("%s", s->sv->message.c_str());
+      rc = s->sv->status;
+    }
+  }
+  if (rc != PPRPA_OK) {
+    c->busy.store(0);
+    return rc;
+  }
+  *out = s.release();
+  return PPRPA_OK;
+}
+
+pprpa_status pprpa_solve_iterate(pprpa_solve* s, int32_t n_iter, int32_t* iters_done,
+                                 int32_t* done) {
+  g_err.clear();
+  if (!s) return einval("solve is NULL");
+  if (n_iter < 0) return einval("n_iter=%d must not be negative", n_iter);
+  PPRPA_HIP(hipSetDevice(s->c->device));
+  int it = 0;
+  pprpa_status rc = iterate_solver(s->c, *s->sv, n_iter, &it);
+  if (iters_done) *iters_done = it;
+  if (done) *done = s->sv->phase == Solver::DONE ? 1 : 0;
+  if (rc != PPRPA_OK) {
+    s->sv->phase = Solver::DONE;
+    s->sv->status = rc;
+    s->sv->message = pprpa_last_error();
+  }
+  return rc;
+}
+
+pprpa_status pprpa_solve_stats(pprpa_solve* s, pprpa_kernel_stats* out, int32_t reset) {
+  g_err.clear();
+  if (!s) return einval("solve is NULL");
+  pprpa_ctx* c = s->c;
+  PPRPA_HIP(hipSetDevice(c->device));
+  PPRPA_HIP(hipStreamSynchronize(c->stream));
+  PPRPA_TRY(harvest_timing(c));
+  if (out) *out = c->stats;
+  if (reset) c->stats = pprpa_kernel_stats{};
+  return PPRPA_OK;
+}
+
+pprpa_status pprpa_solve_end(pprpa_solve* s, double* omega, double* vecs, double* resid,
+                             pprpa_report* rep) {
+  g_err.clear();
+  if (!s) return einval("solve is NULL");
+  pprpa_ctx* c = s->c;
+  pprpa_status st = PPRPA_OK;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipSetDevice(%d) failed", c->device);
+    st = PPRPA_EDEVICE;
+  } else {
+    st = finish_solver(*s->sv, omega, vecs, resid, rep);
+    const std::string msg = pprpa_last_error();
+    if (hipStreamSynchronize(c->stream) == hipSuccess) (void)harvest_timing(c);
+    if (!msg.empty()) set_error("%s", msg.c_str());
+  }
+  s->sv.reset();
+  delete s;
+  c->busy.store(0);
   return st;
 }
 

@@ -81,4 +81,8 @@ void free_context(pprpa_ctx* c);
 constexpr size_t PINNED_ELEMS = 4096;
 pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
                           double* vecs, double* resid, pprpa_report* rep);
+class Solver;
+pprpa_status iterate_solver(pprpa_ctx* c, Solver& sv, int n_iter, int* done_iters);
+pprpa_status finish_solver(Solver& sv, double* omega, double* vecs, double* resid,
+                           pprpa_report* rep);
 }  // namespace pprpa

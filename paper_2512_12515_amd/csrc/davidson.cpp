@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <numeric>
 
@@ -534,12 +535,12 @@ pprpa_status Solver::run_direct() {
   return done(PPRPA_OK);
 }
 
-// One solve on one context, phases run back to back.
-pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega, double* vecs,
-                          double* resid, pprpa_report* rep) {
-  Solver sv(c, *a);
-  sv.start();
-  while (sv.phase != Solver::DONE) {
+// Up to n_iter iterations of a started solve, phases run back to back. An iteration starts with
+// the sigma product of the pending block and ends when the next block is requested or the solve
+// is done; *done_iters counts the iterations run.
+pprpa_status iterate_solver(pprpa_ctx* c, Solver& sv, int n_iter, int* done_iters) {
+  int it = 0;
+  while (sv.phase != Solver::DONE && it < n_iter) {
     if (sv.phase == Solver::NEED_SIGMA) {
       const int64_t n = c->g.n;
       PPRPA_HIP(hipEventRecord(c->e0, c->stream));
@@ -548,10 +549,25 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
       if (rc != PPRPA_OK) return rc;
       PPRPA_HIP(hipEventRecord(c->e1, c->stream));
       sv.sigma_done(true);
-      continue;
     }
-    if (sv.phase != Solver::RR_LAUNCH) PPRPA_HIP(hipStreamSynchronize(c->stream));
-    sv.advance();
+    while (sv.phase != Solver::DONE && sv.phase != Solver::NEED_SIGMA) {
+      if (sv.phase != Solver::RR_LAUNCH) PPRPA_HIP(hipStreamSynchronize(c->stream));
+      sv.advance();
+    }
+    ++it;
+  }
+  if (done_iters) *done_iters = it;
+  return PPRPA_OK;
+}
+
+// Outputs of a solve as pprpa_davidson returns them: its final status (ENOCONV if the caller
+// stopped it before convergence), with omega/resid/rep filled from the last iterate.
+pprpa_status finish_solver(Solver& sv, double* omega, double* vecs, double* resid,
+                           pprpa_report* rep) {
+  if (sv.phase != Solver::DONE) {
+    set_error("Davidson stopped by the caller after %d iterations (not converged)", sv.iters());
+    sv.status = PPRPA_ENOCONV;
+    sv.message = pprpa_last_error();
   }
   if (sv.status != PPRPA_OK && !sv.message.empty()) set_error("%s", sv.message.c_str());
   const pprpa_status st = sv.status;
@@ -562,6 +578,15 @@ pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* om
     if (!keep.empty()) set_error("%s", keep.c_str());
   }
   return st;
+}
+
+// One solve on one context, phases run back to back.
+pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega, double* vecs,
+                          double* resid, pprpa_report* rep) {
+  Solver sv(c, *a);
+  sv.start();
+  PPRPA_TRY(iterate_solver(c, sv, INT32_MAX, nullptr));
+  return finish_solver(sv, omega, vecs, resid, rep);
 }
 
 }  // namespace pprpa

@@ -5,7 +5,10 @@
 * warm start: the converged vectors passed back as `guess` reach the same roots in at most two
   iterations;
 * the per-iteration log callback: one JSON object per Davidson iteration, in order, whose last
-  line agrees with the report.
+  line agrees with the report;
+* the caller-driven solve (pprpa_solve_begin / _iterate / _end): driven to convergence one
+  iteration at a time it returns bitwise what pprpa_davidson returns; it holds the context
+  (EBUSY for other calls) until ended; ended early it reports ENOCONV with the last iterate.
 """
 import json
 import sys
@@ -114,3 +117,51 @@ def test_log_callback_one_json_line_per_iteration():
     assert last["n_conv"] == 8 and last["n_sigma"] == rep["n_sigma"]
     assert abs(last["max_resid"] - rep["max_resid"]) <= 1e-3 * rep["max_resid"]
     assert abs(last["omega0"] - r["omega"][0]) <= 1e-11
+
+
+@pytest.mark.parametrize("mult,prec,channel", [("singlet", "fp64", "pp"), ("triplet", "fp32", "pp"),
+                                               ("singlet", "fp64", "hh")])
+def test_solve_in_steps_equals_davidson(mult, prec, channel):
+    note("solve in steps", mult, prec, channel)
+    eps, L = problem(44, 9, 60, 110)
+    with P.PpRPA(eps, L, 9, mult=mult, prec=prec) as ctx:
+        ref = ctx.davidson(6, block=8, tol=1e-7, vectors=True, channel=channel)
+        sv = ctx.solve_begin(6, block=8, tol=1e-7, channel=channel)
+        steps = 0
+        while not sv.done:
+            assert sv.iterate(1) == 1
+            steps += 1
+        assert sv.iterate(3) == 0  # a finished solve runs no more iterations
+        r = sv.end(vectors=True)
+    assert steps == ref["report"]["iters"] == r["report"]["iters"]
+    assert r["report"]["n_sigma"] == ref["report"]["n_sigma"]
+    assert np.array_equal(r["omega"], ref["omega"])
+    assert np.array_equal(r["resid"], ref["resid"])
+    assert np.array_equal(r["vecs"], ref["vecs"])
+    assert len(r["log"]) == steps
+
+
+def test_open_solve_holds_the_context_and_ends_early():
+    note("open solve")
+    eps, L = problem(45, 8, 50, 100)
+    with P.PpRPA(eps, L, 8) as ctx:
+        z = gen.random_vectors(3, 1, ctx.n)
+        sv = ctx.solve_begin(5, block=5, tol=1e-9)
+        with pytest.raises(P.PpRPAError) as e:
+            ctx.matvec(z)
+        assert e.value.status == P.binding.EBUSY
+        with pytest.raises(P.PpRPAError) as e:
+            ctx.solve_begin(5)
+        assert e.value.status == P.binding.EBUSY
+        assert sv.iterate(0) == 0 and not sv.done
+        assert sv.iterate(2) == 2 and not sv.done
+        r = sv.end(raise_noconv=False)
+        assert r["status"] == P.binding.ENOCONV and r["report"]["iters"] == 2
+        assert np.all(np.isfinite(r["omega"])) and np.all(r["resid"] > 1e-9)
+        ctx.matvec(z)  # released
+        # the same solve run to the end converges to the oracle's roots
+        sv = ctx.solve_begin(5, block=5, tol=1e-9)
+        while not sv.done:
+            sv.iterate(4)
+        r = sv.end()
+    assert np.max(np.abs(r["omega"] - O.solve(eps, L, 8, "singlet", 5))) <= 1e-8
