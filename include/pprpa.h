@@ -192,6 +192,16 @@ typedef struct {
 } pprpa_corr_energy;
 pprpa_status pprpa_correlation_energy(pprpa_ctx* ctx, pprpa_corr_energy* out);
 
+/* pprpa_correlation_energy for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve and the same
+ * results, bit for bit, with its workspace in a static device array of the library (3 * 512^2 + 32
+ * doubles, about 6 MiB, held by each device the library runs on until the process ends) instead
+ * of a hipMalloc per call. Order n <= 512, as pprpa_correlation_energy (EUNSUPPORTED beyond).
+ * Every call on one device shares that array: calls that overlap on one device race and must be
+ * serialised by the caller. Errors as pprpa_correlation_energy, plus EDEVICE if the array's
+ * device address cannot be obtained. */
+pprpa_status pprpa_correlation_energy_noalloc(pprpa_ctx* ctx, pprpa_corr_energy* out);
+
 /* Natural transition orbital weights (section "Natural Transition Orbital", Eqs. nto_pp and
  * nto_hh) and the two-electron part of the one-particle density matrix (section "Density
  * Matrix") of k roots z ([k][n] packed FP64, host or device per on_device, e.g. the vectors of

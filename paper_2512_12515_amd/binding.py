@@ -105,7 +105,7 @@ EXPORTS = ["pprpa_build", "pprpa_dims", "pprpa_matvec", "pprpa_dense_matrix", "p
            "pprpa_free", "pprpa_strerror", "pprpa_last_error", "pprpa_sigma_stats",
            "pprpa_server_create", "pprpa_server_submit", "pprpa_server_poll", "pprpa_server_wait",
            "pprpa_server_stats", "pprpa_server_destroy", "pprpa_solve_begin", "pprpa_solve_iterate",
-           "pprpa_solve_end", "pprpa_solve_stats"]
+           "pprpa_solve_end", "pprpa_solve_stats", "pprpa_correlation_energy_noalloc"]
 
 
 def lib():
@@ -152,6 +152,8 @@ def lib():
     L.pprpa_nto.restype = C.c_int
     L.pprpa_correlation_energy.argtypes = [C.c_void_p, C.POINTER(CorrEnergy)]
     L.pprpa_correlation_energy.restype = C.c_int
+    L.pprpa_correlation_energy_noalloc.argtypes = [C.c_void_p, C.POINTER(CorrEnergy)]
+    L.pprpa_correlation_energy_noalloc.restype = C.c_int
     L.pprpa_sigma_stats.argtypes = [C.c_void_p, C.POINTER(KernelStats), C.c_int32]
     L.pprpa_sigma_stats.restype = C.c_int
     L.pprpa_free.argtypes = [C.c_void_p]
@@ -307,12 +309,15 @@ class PpRPA:
         _check(lib().pprpa_sigma_stats(self._h, C.byref(st), int(bool(reset))))
         return st.as_dict()
 
-    def correlation_energy(self):
+    def correlation_energy(self, noalloc=False):
         """ppRPA correlation energy of this spin block from the whole spectrum of the dense
         pencil (requires dense=True and n <= 512): both sides of the sum rule, ec_pp = sum of
-        the pp roots - Tr A and ec_hh = -(sum of the hh roots) - Tr C, and the root counts."""
+        the pp roots - Tr A and ec_hh = -(sum of the hh roots) - Tr C, and the root counts.
+        noalloc=True: pprpa_correlation_energy_noalloc (workspace in the library's static device
+        array, no device allocation)."""
         out = CorrEnergy()
-        _check(lib().pprpa_correlation_energy(self._h, C.byref(out)))
+        fn = lib().pprpa_correlation_energy_noalloc if noalloc else lib().pprpa_correlation_energy
+        _check(fn(self._h, C.byref(out)))
         return out.as_dict()
 
     def nto(self, z, density=True):

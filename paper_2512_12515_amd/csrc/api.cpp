@@ -704,6 +704,93 @@ void free_context(pprpa_ctx* c) { destroy(c); }
 
 }  // namespace pprpa
 
+namespace {
+
+// Checks shared by both correlation-energy entry points (max_n: the largest order accepted).
+pprpa_status corr_energy_checks(pprpa_ctx* c, pprpa_corr_energy* out, int64_t max_n) {
+  if (!c) return einval("ctx is NULL");
+  if (!out) return einval("out is NULL");
+  if (!c->M) {
+    set_error("the correlation energy needs a dense build (dense=1)");
+    return PPRPA_EUNSUPPORTED;
+  }
+  if (c->g.n > max_n) {
+    set_error("the whole-spectrum solve on the device is limited to n <= %lld (n=%lld)",
+              (long long)max_n, (long long)c->g.n);
+    return PPRPA_EUNSUPPORTED;
+  }
+  return PPRPA_OK;
+}
+
+// The whole-spectrum solve into the workspace `work` (3 n^2 doubles, then 4 doubles and 3 ints
+// of outputs), results copied out through the context's pinned buffer. No allocation.
+pprpa_status corr_energy_run(pprpa_ctx* c, double* work, pprpa_corr_energy* out) {
+  const int64_t n = c->g.n, nvv = c->g.nvv;
+  double* dout = work + 3 * (size_t)n * n;  // 4 doubles, then 3 ints
+  int* dinfo = (int*)(dout + 4);
+  double* hp = c->pinned;
+  hipError_t le = launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, work, dinfo, c->stream);
+  if (le == hipSuccess) le = hipMemcpyAsync(hp, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (le == hipSuccess) le = hipMemcpyAsync(hp + 4, dinfo, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (le == hipSuccess) le = hipStreamSynchronize(c->stream);
+  if (le != hipSuccess) {
+    set_error("correlation energy: %s", hipGetErrorString(le));
+    return PPRPA_EDEVICE;
+  }
+  const int* info = (const int*)(hp + 4);
+  if (info[0] == 1) {
+    set_error("M - 2 mu W is not positive definite");
+    return PPRPA_ENONDEF;
+  }
+  pprpa_corr_energy r{};
+  r.ec_pp = hp[0];
+  r.ec_hh = hp[1];
+  r.trace_a = hp[2];
+  r.trace_c = hp[3];
+  r.n_pp_roots = info[1];
+  r.n_hh_roots = info[2];
+  *out = r;
+  if (info[1] != nvv || info[2] != n - nvv) {
+    set_error("the spectrum splits into %d pp and %d hh roots, not %lld and %lld", info[1], info[2],
+              (long long)nvv, (long long)(n - nvv));
+    return PPRPA_ENONDEF;
+  }
+  return PPRPA_OK;
+}
+
+// Scratch of pprpa_correlation_energy_noalloc: the workspace of the whole-spectrum solve at the
+// largest order it accepts, plus its outputs. Each device the library runs on holds its own copy
+// for the life of the process; every call on a device shares it (calls that overlap on one
+// device race). Nothing in it needs clearing between calls: the solve writes every element it
+// reads.
+constexpr int64_t NOALLOC_MAX_N = 512;
+constexpr size_t NOALLOC_ELEMS = 3 * (size_t)NOALLOC_MAX_N * NOALLOC_MAX_N + 32;
+static __device__ __align__(256) double scratch[NOALLOC_ELEMS];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // per device: the device address of `scratch`
+
+// The device address of this device's copy of `scratch` (looked up once per device, with that
+// device current; the host-side name is not a device address).
+pprpa_status scratch_of(int device, double** ptr) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      set_error("device address of the static scratch: %s", hipGetErrorString(e));
+      return PPRPA_EDEVICE;
+    }
+    g_scratch_ptr[device] = (double*)p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return PPRPA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pprpa_strerror(pprpa_status s) {
@@ -831,23 +918,14 @@ pprpa_status pprpa_dense_matrix(pprpa_ctx* c, double* M, int32_t on_device) {
 
 pprpa_status pprpa_correlation_energy(pprpa_ctx* c, pprpa_corr_energy* out) {
   g_err.clear();
-  if (!c) return einval("ctx is NULL");
-  if (!out) return einval("out is NULL");
-  if (!c->M) {
-    set_error("the correlation energy needs a dense build (dense=1)");
-    return PPRPA_EUNSUPPORTED;
-  }
-  const int64_t n = c->g.n, nvv = c->g.nvv;
-  if (n > 512) {
-    set_error("the whole-spectrum solve on the device is limited to n <= 512 (n=%lld)", (long long)n);
-    return PPRPA_EUNSUPPORTED;
-  }
+  PPRPA_TRY(corr_energy_checks(c, out, 512));
   Busy busy(c->busy);
   if (!busy.ok) {
     set_error("context in use by another thread");
     return PPRPA_EBUSY;
   }
   PPRPA_HIP(hipSetDevice(c->device));
+  const int64_t n = c->g.n;
   const size_t work_bytes = 3 * (size_t)n * n * sizeof(double) + 256;
   void* work = nullptr;
   hipError_t e = hipMalloc(&work, work_bytes);
@@ -856,37 +934,23 @@ pprpa_status pprpa_correlation_energy(pprpa_ctx* c, pprpa_corr_energy* out) {
     set_error("correlation-energy workspace of %zu bytes: %s", work_bytes, hipGetErrorString(e));
     return PPRPA_ENOMEM;
   }
-  double* dout = (double*)work + 3 * (size_t)n * n;  // 4 doubles, then 3 ints
-  int* dinfo = (int*)(dout + 4);
-  double* hp = c->pinned;
-  hipError_t le = launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, (double*)work, dinfo, c->stream);
-  if (le == hipSuccess) le = hipMemcpyAsync(hp, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-  if (le == hipSuccess) le = hipMemcpyAsync(hp + 4, dinfo, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
-  if (le == hipSuccess) le = hipStreamSynchronize(c->stream);
+  const pprpa_status st = corr_energy_run(c, (double*)work, out);
   (void)hipFree(work);
-  if (le != hipSuccess) {
-    set_error("correlation energy: %s", hipGetErrorString(le));
-    return PPRPA_EDEVICE;
+  return st;
+}
+
+pprpa_status pprpa_correlation_energy_noalloc(pprpa_ctx* c, pprpa_corr_energy* out) {
+  g_err.clear();
+  PPRPA_TRY(corr_energy_checks(c, out, NOALLOC_MAX_N));
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
   }
-  const int* info = (const int*)(hp + 4);
-  if (info[0] == 1) {
-    set_error("M - 2 mu W is not positive definite");
-    return PPRPA_ENONDEF;
-  }
-  pprpa_corr_energy r{};
-  r.ec_pp = hp[0];
-  r.ec_hh = hp[1];
-  r.trace_a = hp[2];
-  r.trace_c = hp[3];
-  r.n_pp_roots = info[1];
-  r.n_hh_roots = info[2];
-  *out = r;
-  if (info[1] != nvv || info[2] != n - nvv) {
-    set_error("the spectrum splits into %d pp and %d hh roots, not %lld and %lld", info[1], info[2],
-              (long long)nvv, (long long)(n - nvv));
-    return PPRPA_ENONDEF;
-  }
-  return PPRPA_OK;
+  PPRPA_HIP(hipSetDevice(c->device));
+  double* work = nullptr;
+  PPRPA_TRY(scratch_of(c->device, &work));
+  return corr_energy_run(c, work, out);
 }
 
 pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_device, double* lam_p,
