@@ -78,15 +78,19 @@ pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p) {
 
 // Aux-index splits of a sigma launch: about 8192 workgroups (32 per CU), which measured best on
 // MI355X (shorter tails and better balance than 1.5k-4k; partial sums stay small).
-int nsplit_of(int nitems, int naux, int k) {
-  const int target = 8192;
+int nsplit_of(int variant, int nitems, int naux, int k) {
+  // work units per launch: the FP64 kernel runs one 8-wave workgroup per CU, the others two
+  // 4-wave workgroups
+  const int target = variant == 5 ? UNITS_F64 : 8192;
   const int per = std::max(1, nitems * k);
   int ns = (target + per - 1) / per;
   ns = std::min(ns, std::min(naux, 256));
   return std::max(1, ns);
 }
 
-int nsplit_for(const pprpa_ctx* c, int k) { return nsplit_of(c->plan.nitems, c->g.naux, k); }
+int nsplit_for(const pprpa_ctx* c, int k) {
+  return nsplit_of(c->plan.variant, c->plan.nitems, c->g.naux, k);
+}
 
 static pprpa_status get_event(pprpa_ctx* c, hipEvent_t* e) {
   if (!c->pool.empty()) {
@@ -661,14 +665,14 @@ size_t context_footprint(const pprpa_build_args* a, const pprpa_davidson_args* d
   }
   if (a->dense && st != Store::F64) b += al(plane * sizeof(double));
   int RT = 16, npan_v = 0;
-  (void)sigma_variant(g, st, &RT);
+  const int variant = sigma_variant(g, st, &RT);
   std::vector<int> items;
   make_sigma_items(g, RT, items, npan_v);
   b += al(items.size() * sizeof(int));
   b += al((size_t)kcap * zz * esz * nplanes);       // unpacked vectors
   size_t sp_max = 0;
   for (int kk = 1; kk <= kcap; ++kk)
-    sp_max = std::max(sp_max, (size_t)nsplit_of((int)items.size(), g.naux, kk) * kk);
+    sp_max = std::max(sp_max, (size_t)nsplit_of(variant, (int)items.size(), g.naux, kk) * kk);
   b += al(sp_max * zz * (st == Store::F64 ? 8 : 4));  // partial sums
   b += 2 * al((size_t)kcap * g.n * sizeof(double));   // host-vector staging
   if (a->dense) b += al((size_t)g.n * g.n * sizeof(double));

@@ -84,14 +84,15 @@ __device__ __forceinline__ void c_range(int dt, int cc0, int cc1, int nvt, int* 
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-// Issue this wave's share of the direct global->LDS loads of a rows x cols tile (packed in LDS at
-// dst, row stride cols). Each wave load moves 64 lanes x 16 bytes into 1 KiB of contiguous LDS.
-template <typename T>
+// Issue this wave's share (wave w of NWAVES) of the direct global->LDS loads of a rows x cols
+// tile (packed in LDS at dst, row stride cols). Each wave load moves 64 lanes x 16 bytes into
+// 1 KiB of contiguous LDS.
+template <typename T, int NWAVES = 4>
 __device__ __forceinline__ void dma_tile(const T* __restrict__ src, int64_t ld, int rows, int cols,
                                          T* dst, int w, int lane) {
   constexpr int VEC = 16 / sizeof(T), CHUNK = 1024 / sizeof(T);
   const int nchunk = rows * cols / CHUNK;
-  for (int j = w; j < nchunk; j += 4) {
+  for (int j = w; j < nchunk; j += NWAVES) {
     const int e = j * CHUNK + lane * VEC;
     const int row = e / cols, col = e - row * cols;
     __builtin_amdgcn_global_load_lds((const void*)(src + row * ld + col), (lds_ptr_t)(dst + j * CHUNK),
