@@ -279,9 +279,10 @@ typedef struct {
   int32_t status;       /* pprpa_status of the solve (meaningful once done)                  */
   int32_t nroot;
   int32_t max_overtaken; /* the most times the grouped sigma launches of another kernel
-                            variant (sigma precision) went ahead of one of this request's
+                            variant (the sigma precision, and for FP64 the kernel chosen by the
+                            size of the virtual block) went ahead of one of this request's
                             waiting sigma blocks; the variant of the longest-waiting block goes
-                            first, so this is at most 3 (one per other variant)               */
+                            first, so this is at most 4 (one per other variant)               */
   double t_submit;      /* seconds on the server's steady clock (0 = creation)               */
   double t_admit;       /* reservation taken, build started                                  */
   double t_done;        /* roots copied out, memory released                                 */

@@ -67,7 +67,7 @@ namespace pprpa {
 pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds);
 int nsplit_for(const pprpa_ctx* c, int k);
 int nsplit_of(int variant, int nitems, int naux, int k);
-constexpr int UNITS_F64 = 4096;  // work units per FP64 sigma launch (aux splits set to reach it)
+
 pprpa_status dalloc(pprpa_ctx* c, size_t bytes, void** p);
 // Fold completed launch timings into c->stats (call after synchronising the stream).
 pprpa_status harvest_timing(pprpa_ctx* c);

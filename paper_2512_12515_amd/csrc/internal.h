@@ -77,6 +77,8 @@ struct SigmaPlan {
   int* d_items = nullptr;
 };
 void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v);
+constexpr int UNITS_F64 = 8192;       // work units per launch of the pipelined FP64 kernel
+constexpr int F64_PIPE_MIN_NVT = 20;  // virtual 16-tiles from which FP64 sigma uses that kernel
 int sigma_variant(const Geometry& g, Store st, int* RT);
 
 // --- kernel launchers (k_sigma.hip) -------------------------------------------------------

@@ -592,10 +592,15 @@ void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& n
 }
 
 int sigma_variant(const Geometry& g, Store st, int* RT) {
-  (void)g;
-  if (st == Store::F64) {  // software-pipelined FP64 kernel (k_sigma_f64.hip)
-    *RT = 32;
-    return 5;
+  if (st == Store::F64) {
+    // the software-pipelined kernel (k_sigma_f64.hip) for large virtual blocks; below that its
+    // units are too short to keep the pipeline full and the two-workgroup kernel is faster
+    if (g.nvt >= F64_PIPE_MIN_NVT) {
+      *RT = 32;
+      return 5;
+    }
+    *RT = 16;
+    return 1;
   }
   if (st == Store::F32) { *RT = 32; return 4; }
   *RT = 32;
@@ -630,6 +635,7 @@ hipError_t launch_sigma_group(const GroupMember* m, int n, hipStream_t s) {
   for (int i = 1; i < n; ++i)
     if (m[i].plan->variant != variant || m[i].la.nprod != m[0].la.nprod) return hipErrorInvalidValue;
   switch (variant) {
+    case 1: return run_group<double, 8, 16, 2>(m, n, s);
     case 5: return launch_sigma_group_f64(m, n, s);
     case 4: return run_group<float, 16, 32, 2>(m, n, s);
     default: return launch_sigma_group_bf16(m, n, s);
@@ -642,6 +648,7 @@ hipError_t launch_sigma_bf16(const Geometry& g, const SigmaPlan& plan, const Sig
 hipError_t launch_sigma(const Geometry& g, Store st, const SigmaPlan& plan, const SigmaLaunch& la,
                         hipStream_t s) {
   switch (plan.variant) {
+    case 1: return run_sandwich<double, 8, 16, 2>(g, plan, la, s);
     case 5: return launch_sigma_f64(g, plan, la, s);
     case 4: return run_sandwich<float, 16, 32, 2>(g, plan, la, s);
     default: return launch_sigma_bf16(g, plan, la, s);

@@ -365,7 +365,7 @@ void worker_loop(pprpa_server* S) {
               progressed = true;
             }
           }
-          if (r->unpacked) need[(int)c->st * 8 + c->nprod].push_back(r);
+          if (r->unpacked) need[c->plan.variant * 8 + c->nprod].push_back(r);
         }
       }
       if (sv.phase == Solver::DONE) finished.push_back(r);
