@@ -51,7 +51,10 @@ PEAK_HBM = 8.0e12     # B/s
 # HBM traffic of one launch of the FP64 sigma kernel (GB), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a plain 1 GiB device copy, keyed by (workload, precision); the profile
 # summaries under profiles/ name the command. A workload without an entry reports null.
-TRAFFIC_GB_PER_LAUNCH = {}
+TRAFFIC_GB_PER_LAUNCH = {
+    # profiles/sigma_fp64_headline_50x500x1800_hbm_traffic.md (20 timed launches of 20 vectors)
+    ("mixed", "fp64"): 401.2,
+}
 
 
 def log(*a):
