@@ -11,11 +11,15 @@
 //   its block unpacked at once on its own stream; the solves waiting for sigma are then launched
 //   together as one grouped grid on the group stream, ordered after each member's unpack by an
 //   event, with the epilogue back on each request's stream, ordered after the grid by an event.
-//   One grid is in flight at a time: the solves that become ready while it runs form the next
-//   group (continuous batching), so the groups grow with the load. Solves of different kernel
-//   variants (sigma precision) cannot share a grid; the variant whose waiting block has waited
-//   longest goes next, so no request is overtaken by more than one launch per other variant.
-//   A member's work units are
+//   Solves come in two size classes by the cost of one sigma product (small and large), each
+//   with its own group stream and at most one grid in flight, so a small solve's sigma does not
+//   queue behind a large one's. Within a class the solves that become ready while its grid runs
+//   form the next group (continuous batching), so the groups grow with the load; a small-class
+//   launch is held for up to HOLD_US while other small solves of the same variant are still in
+//   their Davidson phases, so that solves running side by side fall into one grid. Solves of
+//   different kernel variants (sigma precision, FP64 kernel by size) cannot share a grid; the
+//   variant whose waiting block has waited longest goes next, so no request is overtaken by more
+//   than one launch per other variant of its class. A member's work units are
 //   those of a launch of its own (same decomposition, same partial-sum buffer), so its results do
 //   not depend on the mix it was served in.
 // * Finished solves copy out their roots, release their reservation and slot, and wake the
@@ -99,6 +103,7 @@ struct Request {
   pprpa_ctx* ctx = nullptr;
   std::unique_ptr<Solver> sv;
   bool unpacked = false;  // the pending sigma block is unpacked (ctx->e0 marks its end)
+  int cls = 0;            // size class: 0 small, 1 large (one sigma product >= LARGE_FLOPS)
   double t_wait = 0;      // when the pending sigma block started waiting for a grouped launch
   int overtaken = 0;      // launch rounds of other variants while the pending block waited
   int max_overtaken = 0;
@@ -112,7 +117,12 @@ struct TimedGroup {
   hipEvent_t a, b;
   double flops;
   int members;
+  int cls;
 };
+
+constexpr int NCLS = 2;
+constexpr double LARGE_FLOPS = 1e10;  // flops of one single-vector sigma from which a solve is large
+constexpr double HOLD_US = 300.0;     // longest hold of a small-class launch for more members
 
 }  // namespace
 }  // namespace pprpa
@@ -127,7 +137,7 @@ struct pprpa_server {
   char* base = nullptr;  // the arena's device memory
   Arena arena;
   std::vector<hipStream_t> streams;  // one per slot
-  hipStream_t gstream = nullptr;     // grouped sigma launches
+  hipStream_t gstream[2] = {nullptr, nullptr};  // grouped sigma launches, per size class
   double* pinned = nullptr;          // max_inflight * PINNED_ELEMS
   std::vector<int> free_slots;
 
@@ -229,6 +239,11 @@ void admission_loop(pprpa_server* S) {
       continue;
     }
     r->state = 1;
+    {
+      const Geometry& g = r->ctx->g;
+      const double f1 = 4.0 * g.naux * (double)(g.nv + g.no) * ((double)g.nv * g.nv + (double)g.no * g.no);
+      r->cls = f1 >= LARGE_FLOPS ? 1 : 0;
+    }
     S->admitted.push_back(r);
     S->st.inflight += 1;
     S->st.peak_inflight = std::max(S->st.peak_inflight, S->st.inflight);
@@ -241,8 +256,9 @@ void admission_loop(pprpa_server* S) {
 // Grouped sigma for the solves in `grp` (all in NEED_SIGMA with their block unpacked, one kernel
 // variant).
 // Returns false if the group launch failed (its members are then failed by the caller).
-bool launch_group(pprpa_server* S, std::vector<Request*>& grp, std::vector<TimedGroup>& timed,
-                  std::vector<hipEvent_t>& pool) {
+bool launch_group(pprpa_server* S, std::vector<Request*>& grp, int cls,
+                  std::vector<TimedGroup>& timed, std::vector<hipEvent_t>& pool) {
+  hipStream_t gs = S->gstream[cls];
   GroupMember m[GROUP_MAX];
   int ns[GROUP_MAX];
   double flops = 0.0;
@@ -253,7 +269,7 @@ bool launch_group(pprpa_server* S, std::vector<Request*>& grp, std::vector<Timed
     Solver& sv = *r->sv;
     const int k = sv.sig_k;
     ns[i] = nsplit_for(c, k);
-    if (hipStreamWaitEvent(S->gstream, c->e0, 0) != hipSuccess) return false;
+    if (hipStreamWaitEvent(gs, c->e0, 0) != hipSuccess) return false;
     SigmaLaunch la{};
     la.L = c->L;
     la.ZT = c->ZT;
@@ -280,9 +296,10 @@ bool launch_group(pprpa_server* S, std::vector<Request*>& grp, std::vector<Timed
   if (take(&tg.a) != hipSuccess || take(&tg.b) != hipSuccess) return false;
   tg.flops = flops;
   tg.members = cnt;
-  if (hipEventRecord(tg.a, S->gstream) != hipSuccess) return false;
-  if (launch_sigma_group(m, cnt, S->gstream) != hipSuccess) return false;
-  if (hipEventRecord(tg.b, S->gstream) != hipSuccess) return false;
+  tg.cls = cls;
+  if (hipEventRecord(tg.a, gs) != hipSuccess) return false;
+  if (launch_sigma_group(m, cnt, gs) != hipSuccess) return false;
+  if (hipEventRecord(tg.b, gs) != hipSuccess) return false;
   timed.push_back(tg);
   for (int i = 0; i < cnt; ++i) {
     Request* r = grp[i];
@@ -315,7 +332,8 @@ void worker_loop(pprpa_server* S) {
       S->admitted.clear();
     }
     bool progressed = false;
-    std::map<int, std::vector<Request*>> need;  // by kernel (storage type, products)
+    std::map<int, std::vector<Request*>> need[NCLS];  // per class, by kernel variant
+    std::map<int, int> busy_phases[NCLS];             // per class and variant: solves in phases
     std::vector<Request*> finished;
     for (Request* r : active) {
       Solver& sv = *r->sv;
@@ -365,42 +383,56 @@ void worker_loop(pprpa_server* S) {
               progressed = true;
             }
           }
-          if (r->unpacked) need[c->plan.variant * 8 + c->nprod].push_back(r);
+          if (r->unpacked) need[r->cls][c->plan.variant * 8 + c->nprod].push_back(r);
         }
+      } else if (sv.phase != Solver::DONE) {
+        busy_phases[r->cls][r->ctx->plan.variant * 8 + r->ctx->nprod] += 1;
       }
       if (sv.phase == Solver::DONE) finished.push_back(r);
     }
-    // fold finished group timings into the statistics
-    size_t nt = 0;
-    for (; nt < timed.size(); ++nt) {
-      if (hipEventQuery(timed[nt].b) != hipSuccess) break;
+    // fold finished group timings into the statistics (grids of the two classes finish in any
+    // order)
+    bool cls_busy[NCLS] = {false, false};
+    for (size_t i = 0; i < timed.size();) {
+      if (hipEventQuery(timed[i].b) != hipSuccess) {
+        cls_busy[timed[i].cls] = true;
+        ++i;
+        continue;
+      }
       float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, timed[nt].a, timed[nt].b);
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->st.group_launches += 1;
-      S->st.grouped_products += timed[nt].members;
-      S->st.sigma_seconds += ms * 1e-3;
-      S->st.sigma_flops += timed[nt].flops;
-    }
-    for (size_t i = 0; i < nt; ++i) {
+      (void)hipEventElapsedTime(&ms, timed[i].a, timed[i].b);
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.group_launches += 1;
+        S->st.grouped_products += timed[i].members;
+        S->st.sigma_seconds += ms * 1e-3;
+        S->st.sigma_flops += timed[i].flops;
+      }
       pool.push_back(timed[i].a);
       pool.push_back(timed[i].b);
+      timed.erase(timed.begin() + i);
     }
-    timed.erase(timed.begin(), timed.begin() + nt);
 
-    // one grouped grid in flight at a time: once the last one is done, launch the waiting solves
-    // of the variant whose block has waited longest (all of them, in grids of GROUP_MAX)
-    if (timed.empty() && !need.empty()) {
+    // per class, one grouped grid in flight at a time: once the last one is done, launch the
+    // waiting solves of the variant whose block has waited longest (all of them, in grids of
+    // GROUP_MAX); a small-class launch waits up to HOLD_US for solves of that variant still in
+    // their phases
+    const double now_s = S->now();
+    for (int cls = 0; cls < NCLS; ++cls) {
+      if (cls_busy[cls] || need[cls].empty()) continue;
       auto oldest = [](const std::vector<Request*>& v) {
         double t = v.front()->t_wait;
         for (const Request* r : v) t = std::min(t, r->t_wait);
         return t;
       };
-      auto pick = need.begin();
-      for (auto it = need.begin(); it != need.end(); ++it)
+      auto pick = need[cls].begin();
+      for (auto it = need[cls].begin(); it != need[cls].end(); ++it)
         if (oldest(it->second) < oldest(pick->second)) pick = it;
+      if (cls == 0 && busy_phases[cls][pick->first] > 0 &&
+          (now_s - oldest(pick->second)) * 1e6 < HOLD_US)
+        continue;  // hold: more members are on their way
       const std::vector<Request*>& list = pick->second;
-      for (auto& kv : need) {
+      for (auto& kv : need[cls]) {
         if (kv.first == pick->first) continue;
         for (Request* r : kv.second) r->overtaken += 1;
       }
@@ -411,7 +443,7 @@ void worker_loop(pprpa_server* S) {
       for (size_t i0 = 0; i0 < list.size(); i0 += GROUP_MAX) {
         std::vector<Request*> grp(list.begin() + i0,
                                   list.begin() + std::min(list.size(), i0 + GROUP_MAX));
-        if (!launch_group(S, grp, timed, pool)) {
+        if (!launch_group(S, grp, cls, timed, pool)) {
           (void)hipGetLastError();
           for (Request* r : grp) {
             r->sv->phase = Solver::DONE;
@@ -471,7 +503,8 @@ void destroy_server(pprpa_server* S) {
   if (S->worker.joinable()) S->worker.join();
   for (hipStream_t s : S->streams)
     if (s) (void)hipStreamDestroy(s);
-  if (S->gstream) (void)hipStreamDestroy(S->gstream);
+  for (hipStream_t g : S->gstream)
+    if (g) (void)hipStreamDestroy(g);
   if (S->pinned) (void)hipHostFree(S->pinned);
   if (S->base) (void)hipFree(S->base);
   delete S;
@@ -523,8 +556,10 @@ pprpa_status pprpa_server_create(size_t hbm_budget_bytes, int32_t max_inflight, 
     if (e != hipSuccess) return fail(PPRPA_EDEVICE, "stream creation", e);
     S->free_slots.push_back(max_inflight - 1 - i);
   }
-  e = hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking);
-  if (e != hipSuccess) return fail(PPRPA_EDEVICE, "stream creation", e);
+  for (hipStream_t& g : S->gstream) {
+    e = hipStreamCreateWithFlags(&g, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(PPRPA_EDEVICE, "stream creation", e);
+  }
   if (prepare_kernels() != hipSuccess) return fail(PPRPA_EDEVICE, "kernel set-up", hipGetLastError());
   S->st.budget = S->budget;
   S->admitter = std::thread(admission_loop, S);
