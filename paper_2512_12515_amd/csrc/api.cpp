@@ -433,10 +433,10 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
 
   // ---- sigma plan and workspaces ---------------------------------------------------------
   int RT = 16;
-  c->plan.variant = sigma_variant(g, c->st, &RT);
+  c->plan.variant = sigma_variant(g, c->st, c->nprod, &RT);
   c->plan.RT = RT;
   std::vector<int> items;
-  make_sigma_items(g, RT, items, c->plan.npan_v);
+  make_sigma_items(g, RT, items, c->plan.npan_v, panel_width(c->plan.variant));
   c->plan.nitems = (int)items.size();
   PPRPA_TRY(dalloc(c, items.size() * sizeof(int), (void**)&c->plan.d_items));
   PPRPA_HIP(hipMemcpyAsync(c->plan.d_items, items.data(), items.size() * sizeof(int),
@@ -665,9 +665,9 @@ size_t context_footprint(const pprpa_build_args* a, const pprpa_davidson_args* d
   }
   if (a->dense && st != Store::F64) b += al(plane * sizeof(double));
   int RT = 16, npan_v = 0;
-  const int variant = sigma_variant(g, st, &RT);
+  const int variant = sigma_variant(g, st, a->prec == PPRPA_BF16X3 ? 3 : 6, &RT);
   std::vector<int> items;
-  make_sigma_items(g, RT, items, npan_v);
+  make_sigma_items(g, RT, items, npan_v, panel_width(variant));
   b += al(items.size() * sizeof(int));
   b += al((size_t)kcap * zz * esz * nplanes);       // unpacked vectors
   size_t sp_max = 0;

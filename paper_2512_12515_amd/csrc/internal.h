@@ -76,10 +76,15 @@ struct SigmaPlan {
   int npan_v = 0;
   int* d_items = nullptr;
 };
-void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v);
+// Work items (panel index << 16 | first row tile): panels of pw adjacent column tiles of one
+// diagonal block, row ranges of RT tiles.
+void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v, int pw = 4);
+// Column tiles per panel of a sigma kernel variant.
+inline int panel_width(int variant) { return variant == 7 ? 8 : 4; }
 constexpr int UNITS_F64 = 8192;       // work units per launch of the pipelined FP64 kernel
 constexpr int F64_PIPE_MIN_NVT = 20;  // virtual 16-tiles from which FP64 sigma uses that kernel
-int sigma_variant(const Geometry& g, Store st, int* RT);
+constexpr int BF16_WIDE_MIN_NVT = 32;  // the same for the wide-panel BF16x6 kernel
+int sigma_variant(const Geometry& g, Store st, int nprod, int* RT);
 
 // --- kernel launchers (k_sigma.hip) -------------------------------------------------------
 hipError_t launch_stage_L(const Geometry& g, Store st, const double* Lin, int nin, int p0, int np,

@@ -577,21 +577,18 @@ hipError_t launch_epilogue(const Geometry& g, Store st, const double* z, int k, 
 }
 
 // Work items: (panel, first row tile) pairs; a panel spans up to 4 column tiles of one block.
-void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v) {
+void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v, int pw) {
   items.clear();
   const int not_ = g.nct - g.nvt;
-  npan_v = (g.nvt + 3) / 4;
-  const int npan_o = (not_ + 3) / 4;
+  npan_v = (g.nvt + pw - 1) / pw;
+  const int npan_o = (not_ + pw - 1) / pw;
   for (int pn = 0; pn < npan_v + npan_o; ++pn) {
-    const bool v = pn < npan_v;
-    const int t0 = v ? 4 * pn : 4 * (pn - npan_v);
-    const int bnt = v ? g.nvt : not_;
-    (void)t0;
+    const int bnt = pn < npan_v ? g.nvt : not_;
     for (int R0 = 0; R0 < bnt; R0 += RT) items.push_back((pn << 16) | R0);
   }
 }
 
-int sigma_variant(const Geometry& g, Store st, int* RT) {
+int sigma_variant(const Geometry& g, Store st, int nprod, int* RT) {
   if (st == Store::F64) {
     // the software-pipelined kernel (k_sigma_f64.hip) for large virtual blocks; below that its
     // units are too short to keep the pipeline full and the two-workgroup kernel is faster
@@ -604,7 +601,10 @@ int sigma_variant(const Geometry& g, Store st, int* RT) {
   }
   if (st == Store::F32) { *RT = 32; return 4; }
   *RT = 32;
-  return 3;
+  // BF16 split, six products: the double-buffered wide-panel kernel (k_sigma_bf16.hip) for
+  // large virtual blocks that it tiles with full 8-tile panels (a ragged last panel idles waves
+  // of its workgroup: at 26 tiles = 3 x 8 + 2 it measured no faster than the 4-tile kernel)
+  return nprod == 6 && g.nvt >= BF16_WIDE_MIN_NVT && g.nvt % 8 == 0 ? 7 : 3;
 }
 
 template <typename T, int CC, int RT, int OCC>

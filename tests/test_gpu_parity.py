@@ -89,6 +89,41 @@ def test_sigma_panel_mixes(case, mult, prec, rtol):
         assert np.max(np.abs(s[j, rows] - ref)) <= rtol * max(1.0, np.abs(ref).max())
 
 
+# Shapes for the software-pipelined FP64 kernel (from 20 virtual 16-tiles on) and the wide-panel
+# BF16x6 kernel (virtual blocks of 32 tiles and more in full 8-tile panels): a ragged last
+# virtual panel (FP64: 21 tiles = 5 x 4 + 1), a virtual block longer than one unit's 32 row
+# tiles (FP64 35 tiles: row ranges of 32 + 3 and a three-tile panel; BF16 at 630 virtual
+# orbitals: 40 tiles, 32 + 8), occupied blocks of 3 and 5 tiles (FP64) or 4 and 6 (BF16, padded
+# to 32 orbitals), and units that walk several aux indices (20 vectors at naux 120: dozens of
+# aux splits of 2-3 indices). The BF16x3 kernel and the BF16x6 kernel below 32 tiles run on
+# the same shapes. Sampled entries against the oracle's rows.
+PIPE_CASES = [((40, 330, 120), 20), ((70, 560, 12), 3), ((40, 500, 120), 20), ((70, 630, 12), 3)]
+
+
+# (BF16x6 is held to 1e-6 here, the full-size gate: these vectors are longer (nmo 370-630) than
+# the panel shapes' and FP32 accumulation sets the level, 6.6e-7 measured at 40/330/120.)
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("bf16x6", 1e-6), ("bf16x3", 1.5e-5)])
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("case,k", PIPE_CASES)
+def test_sigma_pipelined_shapes(case, k, mult, prec, rtol):
+    nocc, nvir, naux = case
+    note("sigma pipelined shapes", prec, mult, case, k)
+    eps, L = problem(14, nocc, nvir, naux)
+    sp = O.active_space(eps, L, nocc)
+    with P.PpRPA(eps, L, nocc, mult=mult, prec=prec) as ctx:
+        nvv, n = ctx.n_pp, ctx.n
+        z = gen.random_vectors(8, k, n)
+        s = ctx.matvec(z)
+    rng = np.random.default_rng(6)
+    rows = np.unique(np.r_[np.arange(3), nvv - 3 + np.arange(3), nvv + np.arange(3),
+                           n - 3 + np.arange(3), rng.integers(0, n, 16)])
+    for j in sorted({0, k - 1}):
+        ref = O.sigma_rows(sp, mult, rows, z[j])
+        err = np.max(np.abs(s[j, rows] - ref)) / max(1.0, np.abs(ref).max())
+        note("vector", j, "relative error", err)
+        assert err <= rtol
+
+
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case", [(4, 9, 30), (5, 20, 100), (20, 35, 50), (17, 33, 23)])
 def test_sigma_fp32(mult, case):
