@@ -922,7 +922,7 @@ pprpa_status pprpa_dense_matrix(pprpa_ctx* c, double* M, int32_t on_device) {
 
 pprpa_status pprpa_correlation_energy(pprpa_ctx* c, pprpa_corr_energy* out) {
   g_err.clear();
-  PPRPA_TRY(corr_energy_checks(c, out, 512));
+  PPRPA_TRY(corr_energy_checks(c, out, DENSE_SOLVE_MAX));
   Busy busy(c->busy);
   if (!busy.ok) {
     set_error("context in use by another thread");

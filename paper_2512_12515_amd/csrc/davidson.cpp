@@ -489,8 +489,9 @@ pprpa_status Solver::run_direct() {
     set_error("direct diagonalisation needs a dense build");
     return PPRPA_EUNSUPPORTED;
   }
-  if (n > 512) {
-    set_error("direct diagonalisation on the device is limited to n <= 512 (n=%lld)", (long long)n);
+  if (n > DENSE_SOLVE_MAX) {
+    set_error("direct diagonalisation on the device is limited to n <= %d (n=%lld)",
+              DENSE_SOLVE_MAX, (long long)n);
     return PPRPA_EUNSUPPORTED;
   }
   const int m = (int)n;

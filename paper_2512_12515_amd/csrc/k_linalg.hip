@@ -360,7 +360,8 @@ __global__ void k_fill(double* __restrict__ p, size_t n, double v) {
 // One-workgroup dense kernels (1024 threads). Matrices live in global memory (L2-resident).
 // ------------------------------------------------------------------------------------------
 constexpr int WG = 1024;
-constexpr int JMAX = 512;  // largest matrix order of the one-workgroup dense solvers
+constexpr int JMAX = 512;   // largest matrix order of the one-workgroup Davidson-side solvers
+constexpr int DMAX = DENSE_SOLVE_MAX;  // largest order of the dense pencil solves (direct, E_c)
 
 // Workgroup-wide sum / min / max (every thread calls it; every thread gets the result): a
 // butterfly within each wave, then the WG / 64 wave results in a fixed order (deterministic).
@@ -488,7 +489,7 @@ constexpr int PLDS = 96;
 // inverse iteration on T (vectors of nearly equal theta orthonormalised against each other),
 // back-transformed by the reflections; c = R^-T u / sqrt(theta), so that c^T W c = +1.
 // Two kernels use these steps: k_direct_pencil (the dense direct path, W = diag(+-1), matrices
-// in global memory, n up to 512) and k_pencil_tri (the Davidson pencils, m <= 96, matrices in
+// in global memory, n up to DMAX) and k_pencil_tri (the Davidson pencils, m <= 96, matrices in
 // LDS, W the projected metric).
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ int sturm_below(const double* d, const double* e2, int m, double x,
@@ -918,7 +919,7 @@ __global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__
                                                       double* __restrict__ work,
                                                       int* __restrict__ info) {
   __shared__ double red[WG];
-  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double d[DMAX], e[DMAX], e2[DMAX], beta[DMAX], vv[DMAX], pq[DMAX];
   __shared__ double theta[64];
   __shared__ int flag, npos_s;
   double* A = work;                        // K, then R (lower)
@@ -950,7 +951,7 @@ __global__ __launch_bounds__(WG) void k_pencil_energy(const double* __restrict__
                                                       double* __restrict__ work,
                                                       int* __restrict__ info) {
   __shared__ double red[WG];
-  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double d[DMAX], e[DMAX], e2[DMAX], beta[DMAX], vv[DMAX], pq[DMAX];
   __shared__ int flag;
   const int t = threadIdx.x;
   double* A = work;
@@ -1383,7 +1384,7 @@ hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, dou
 hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
                                 int channel, double* omega, double* Cout, int ldc, double* work,
                                 int* info, hipStream_t s) {
-  if (m > JMAX || nroot > 64 || nroot > m || (channel != 0 && channel != 1))
+  if (m > DMAX || nroot > 64 || nroot > m || (channel != 0 && channel != 1))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_direct_pencil, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, nroot, channel,
                      omega, Cout, ldc, work, info);
@@ -1392,7 +1393,7 @@ hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2,
 
 hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2, double* out,
                                 double* work, int* info, hipStream_t s) {
-  if (m < 1 || m > JMAX) return hipErrorInvalidValue;
+  if (m < 1 || m > DMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil_energy, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, out, work, info);
   return hipGetLastError();
 }

@@ -2,12 +2,13 @@
 whole spectrum of the dense pencil, through the C ABI, against the FP64 oracle.
 
 * both sides of the sum rule (sum of the pp roots - Tr A, -(sum of the hh roots) - Tr C) against
-  the oracle's full-spectrum values, both spins, shapes up to n = 456 (both pencil sizes of the
-  one-workgroup solver), and against each other;
+  the oracle's full-spectrum values, both spins, shapes up to n = 456 and at orders 1018 / 1071,
+  and against each other;
 * E_c = 0 when L = 0 and when the coupling block B vanishes (L_vo = 0), as the oracle's pin P2;
 * the closed-shell total E(singlet) + 3 E(triplet) against the oracle's;
-* argument checks: no dense build, n > 512.
-Tolerance: 1e-10 Ha absolute (the sums run over up to ~450 roots, each good to ~1e-13).
+* argument checks: no dense build, n > 2048.
+Tolerance: 1e-10 Ha absolute (the sums run over up to ~450 roots, each good to ~1e-13); 1e-9 Ha
+at order ~1000 (twice the roots, the reduction's rounding growing with the order).
 """
 import sys
 
@@ -53,6 +54,24 @@ def test_correlation_energy_vs_oracle(mult, case):
 
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
+def test_correlation_energy_order_above_1000(mult):
+    """8 occupied, 45 virtual orbitals: n = 1071 (singlet) and 1018 (triplet)."""
+    nocc, nvir, naux = 8, 45, 150
+    note("E_c order > 1000", mult)
+    eps = gen.orbital_energies(54, nocc, nvir)
+    L = gen.lpq_full(54, nocc + nvir, naux)
+    (ref_pp, ref_hh), npp, nhh = oracle_ec(eps, L, nocc, mult)
+    with P.PpRPA(eps, L, nocc, mult=mult, dense=True) as ctx:
+        assert ctx.n > 1000
+        r = ctx.correlation_energy()
+    note("ec_pp", r["ec_pp"], "oracle", ref_pp, "diff", r["ec_pp"] - ref_pp)
+    assert r["n_pp_roots"] == npp and r["n_hh_roots"] == nhh
+    assert abs(r["ec_pp"] - ref_pp) <= 1e-9
+    assert abs(r["ec_hh"] - ref_hh) <= 1e-9
+    assert abs(r["ec_pp"] - r["ec_hh"]) <= 1e-9
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
 def test_correlation_energy_vanishes_without_coupling(mult):
     note("E_c B = 0", mult)
     nocc, nvir, naux = 5, 14, 40
@@ -88,10 +107,10 @@ def test_correlation_energy_argument_checks():
         with pytest.raises(P.PpRPAError) as e:
             ctx.correlation_energy()
         assert e.value.status == P.binding.EUNSUPPORTED
-    eps = gen.orbital_energies(53, 4, 32)
-    L = gen.lpq_full(53, 36, 20)
+    eps = gen.orbital_energies(53, 4, 64)
+    L = gen.lpq_full(53, 68, 20)
     with P.PpRPA(eps, L, 4, dense=True) as ctx:
-        assert ctx.n > 512
+        assert ctx.n > 2048
         with pytest.raises(P.PpRPAError) as e:
             ctx.correlation_energy()
         assert e.value.status == P.binding.EUNSUPPORTED

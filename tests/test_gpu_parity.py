@@ -230,10 +230,11 @@ def test_direct_small(mult, seed):
 
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
-@pytest.mark.parametrize("case,nroot", [((8, 30, 60), 8), ((6, 14, 40), 5), ((2, 13, 30), 3)])
+@pytest.mark.parametrize("case,nroot", [((8, 30, 60), 8), ((6, 14, 40), 5), ((2, 13, 30), 3),
+                                        ((8, 45, 150), 6)])
 def test_direct_orders(mult, case, nroot):
-    """The direct dense path at orders up to the 512 limit (n = 501 / 463 for 8 x 30), above and
-    below the 96 of the LDS-resident solver: eigenvalues, residuals and normalisation."""
+    """The direct dense path at orders from below the 96 of the LDS-resident solver to above 1000
+    (n = 501 / 463 for 8 x 30, 1071 / 1018 for 8 x 45): eigenvalues, residuals, normalisation."""
     nocc, nvir, naux = case
     note("direct orders", mult, case)
     eps, L = problem(21, nocc, nvir, naux)
