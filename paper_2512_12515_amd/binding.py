@@ -48,7 +48,8 @@ class BuildAbArgs(C.Structure):
     _fields_ = [("nmo", C.c_int32), ("nocc_a", C.c_int32), ("nocc_b", C.c_int32),
                 ("naux", C.c_int32), ("eps_a", C.c_void_p), ("eps_b", C.c_void_p),
                 ("Lpq_a", C.c_void_p), ("Lpq_b", C.c_void_p), ("on_device", C.c_int32),
-                ("max_block", C.c_int32), ("stream", C.c_void_p), ("density_fitted", C.c_int32)]
+                ("max_block", C.c_int32), ("stream", C.c_void_p), ("density_fitted", C.c_int32),
+                ("prec", C.c_int32)]
 
 
 class DavidsonArgs(C.Structure):
@@ -242,10 +243,11 @@ class PpRPA:
 
     @classmethod
     def alpha_beta(cls, eps_a, eps_b, Lpq_a, Lpq_b, nocc_a, nocc_b, max_block=32, stream=None,
-                   density_fitted=False):
+                   density_fitted=False, prec="fp64"):
         """The alpha-beta sector of spin-unrestricted ppRPA (pprpa_build_ab): a dense context, or
-        with density_fitted=True the density-fitted sigma of both spins' integrals (no matrix);
-        the alpha-alpha and beta-beta sectors are PpRPA(eps_s, Lpq_s, nocc_s, mult="triplet")."""
+        with density_fitted=True the density-fitted sigma of both spins' integrals (no matrix;
+        prec "fp64" or "fp32"); the alpha-alpha and beta-beta sectors are
+        PpRPA(eps_s, Lpq_s, nocc_s, mult="triplet")."""
         on_dev = _is_torch(Lpq_a) and Lpq_a.is_cuda
         if not on_dev:
             eps_a, eps_b = (np.ascontiguousarray(x, dtype=np.float64) for x in (eps_a, eps_b))
@@ -257,6 +259,7 @@ class PpRPA:
         a.Lpq_a, a.Lpq_b = _ptr(Lpq_a, on_dev).value, _ptr(Lpq_b, on_dev).value
         a.on_device, a.max_block, a.stream = int(on_dev), int(max_block), stream
         a.density_fitted = int(bool(density_fitted))
+        a.prec = PREC[prec]
         h = C.c_void_p()
         _check(lib().pprpa_build_ab(C.byref(a), C.byref(h)))
         self = cls.__new__(cls)
@@ -265,7 +268,7 @@ class PpRPA:
         _check(lib().pprpa_dims(h, C.byref(npp), C.byref(nhh)))
         self.n_pp, self.n_hh = npp.value, nhh.value
         self.n = self.n_pp + self.n_hh
-        self.mult, self.prec = "alpha-beta", "fp64"
+        self.mult, self.prec = "alpha-beta", prec
         self.nv, self.no = a.nmo - a.nocc_a, a.nocc_a
         return self
 

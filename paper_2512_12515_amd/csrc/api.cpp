@@ -161,18 +161,18 @@ pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
       const double* z = dz + (int64_t)k0 * n;
       double* s = ds + (int64_t)k0 * n;
       const int ns = nsplit_for(c, kk);
-      PPRPA_HIP(launch_unpack_ab(ag, z, kk, (double*)c->ZT, c->stream));
+      PPRPA_HIP(launch_unpack_ab(ag, c->st, z, kk, c->ZT, c->stream));
       pprpa_ctx::Timed tm;
       PPRPA_TRY(get_event(c, &tm.a));
       PPRPA_TRY(get_event(c, &tm.b));
+      const double esz = c->st == Store::F32 ? 4.0 : 8.0;
       tm.flops = 2.0 * ag.naux * (double)n * ((ag.nva + ag.noa) + (ag.nvb + ag.nob)) * kk;
-      tm.bytes = (double)ag.naux * ((double)ag.nmopa * ag.nmopa + (double)ag.nmopb * ag.nmopb) * 8.0 +
+      tm.bytes = (double)ag.naux * ((double)ag.nmopa * ag.nmopa + (double)ag.nmopb * ag.nmopb) * esz +
                  2.0 * kk * (double)n * 8.0;
       PPRPA_TRY(gated_launch(c, tm, [&] {
-        return launch_sigma_ab(ag, c->plan, (const double*)c->L, c->Lb, (const double*)c->ZT,
-                               (double*)c->Sp, kk, ns, c->stream);
+        return launch_sigma_ab(ag, c->st, c->plan, c->L, c->Lb, c->ZT, c->Sp, kk, ns, c->stream);
       }));
-      PPRPA_HIP(launch_epilogue_ab(ag, z, kk, (const double*)c->Sp, ns, c->epair, s, c->stream));
+      PPRPA_HIP(launch_epilogue_ab(ag, c->st, z, kk, c->Sp, ns, c->epair, s, c->stream));
     }
     return PPRPA_OK;
   }
@@ -484,8 +484,8 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
   c->ab = true;
   c->ab_df = a->density_fitted != 0;
   c->ab_nocc_b = nob;
-  c->prec = PPRPA_FP64;
-  c->st = Store::F64;
+  c->prec = a->prec;
+  c->st = a->prec == PPRPA_FP32 ? Store::F32 : Store::F64;
   c->kcap = a->max_block > 0 ? std::min(a->max_block, 64) : 32;
 
   std::vector<double> ea(nmo), eb(nmo);
@@ -573,8 +573,9 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
     ag.nvv = g.nvv;
     ag.noo = g.noo;
     ag.n = g.n;
+    const size_t esz = c->st == Store::F32 ? 4 : 8;
     auto stage_spin = [&](const double* Lin, int nocc_s, int nv_s, int nvp_s, int nmop_s,
-                          double** out) -> pprpa_status {
+                          void** out) -> pprpa_status {
       std::vector<int> src(nmop_s, -1);
       for (int r = 0; r < nv_s; ++r) src[r] = nocc_s + r;
       for (int r = 0; r < nocc_s; ++r) src[nvp_s + r] = r;
@@ -582,23 +583,25 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
       PPRPA_TRY(dalloc(c, nmop_s * sizeof(int), (void**)&d_src));
       PPRPA_HIP(hipMemcpyAsync(d_src, src.data(), nmop_s * sizeof(int), hipMemcpyHostToDevice,
                                c->stream));
-      PPRPA_TRY(dalloc(c, (size_t)naux * nmop_s * nmop_s * sizeof(double), (void**)out));
+      PPRPA_TRY(dalloc(c, (size_t)naux * nmop_s * nmop_s * esz, out));
       Geometry gs;
       gs.nmop = nmop_s;
       for (int p0 = 0; p0 < naux; p0 += 65535) {
         const int np = std::min(65535, naux - p0);
-        PPRPA_HIP(launch_stage_L(gs, Store::F64, Lin + (size_t)p0 * nmo * nmo, nmo, p0, np, d_src,
+        PPRPA_HIP(launch_stage_L(gs, c->st, Lin + (size_t)p0 * nmo * nmo, nmo, p0, np, d_src,
                                  *out, 0, d_bad, c->stream));
       }
       return PPRPA_OK;
     };
-    double* la_p = nullptr;
+    void* la_p = nullptr;
+    void* lb_p = nullptr;
     PPRPA_TRY(stage_spin(La, noa, nva, ag.nvpa, ag.nmopa, &la_p));
-    PPRPA_TRY(stage_spin(Lb, nob, nvb, ag.nvpb, ag.nmopb, &c->Lb));
+    PPRPA_TRY(stage_spin(Lb, nob, nvb, ag.nvpb, ag.nmopb, &lb_p));
     c->L = la_p;
+    c->Lb = lb_p;
     const size_t zt = (size_t)c->kcap * ag.nmopb * ag.nmopa;
-    PPRPA_TRY(dalloc(c, zt * sizeof(double), &c->ZT));
-    PPRPA_HIP(hipMemsetAsync(c->ZT, 0, zt * sizeof(double), c->stream));
+    PPRPA_TRY(dalloc(c, zt * esz, &c->ZT));
+    PPRPA_HIP(hipMemsetAsync(c->ZT, 0, zt * esz, c->stream));
     std::vector<int> items;
     make_sigma_items_ab(ag, items, c->plan.npan_v);
     c->plan.nitems = (int)items.size();
@@ -608,7 +611,7 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
     size_t sp_max = 0;
     for (int kk = 1; kk <= c->kcap; ++kk)
       sp_max = std::max(sp_max, (size_t)nsplit_for(c, kk) * kk);
-    PPRPA_TRY(dalloc(c, sp_max * ag.nmopa * ag.nmopb * sizeof(double), &c->Sp));
+    PPRPA_TRY(dalloc(c, sp_max * ag.nmopa * ag.nmopb * esz, &c->Sp));
   } else {
     PPRPA_TRY(dalloc(c, (size_t)g.n * g.n * sizeof(double), (void**)&c->M));
     PPRPA_HIP(launch_dense_build_ab(La, Lb, naux, nmo, noa, nob, g.n, g.nvv, c->ptab, c->epair,
@@ -833,6 +836,12 @@ pprpa_status pprpa_build_ab(const pprpa_build_ab_args* a, pprpa_ctx** out) {
     return einval("density_fitted=%d must be 0 or 1", a->density_fitted);
   if (!a->eps_a || !a->eps_b || !a->Lpq_a || !a->Lpq_b)
     return einval("eps_a, eps_b, Lpq_a and Lpq_b must not be NULL");
+  if (a->prec < PPRPA_FP64 || a->prec > PPRPA_BF16X3) return einval("prec=%d", a->prec);
+  if (a->prec != PPRPA_FP64 && !(a->prec == PPRPA_FP32 && a->density_fitted)) {
+    set_error("the alpha-beta sector takes FP64, or FP32 sigma when density fitted (prec=%d)",
+              a->prec);
+    return PPRPA_EUNSUPPORTED;
+  }
   pprpa_ctx* c = new (std::nothrow) pprpa_ctx();
   if (!c) return einval("host allocation failed");
   pprpa_status s = build_ab_impl(a, c);

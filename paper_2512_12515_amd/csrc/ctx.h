@@ -36,7 +36,7 @@ struct pprpa_ctx {
   bool ab_df = false;              // ... with the density-fitted sigma (else dense: sigma = M z)
   int ab_nocc_b = 0;
   pprpa::AbGeometry abg;           // density-fitted alpha-beta layout
-  double* Lb = nullptr;            // staged beta integrals [naux][nmopb][nmopb] (L holds alpha)
+  void* Lb = nullptr;              // staged beta integrals [naux][nmopb][nmopb] (L holds alpha)
   std::vector<int> ptab_h;
   std::atomic<int> busy{0};
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -125,16 +125,18 @@ struct AbParams {
   int64_t la_stride, lb_stride, zt_stride, q_stride;
 };
 void make_sigma_items_ab(const AbGeometry& g, std::vector<int>& items, int& npan_v);
-// Z^T[kv][d][c] from packed alpha-beta vectors z [k][n] (device).
-hipError_t launch_unpack_ab(const AbGeometry& g, const double* z, int k, double* ZT,
+// Z^T[kv][d][c] from packed alpha-beta vectors z [k][n] (device), in the sigma precision st
+// (FP64 or FP32).
+hipError_t launch_unpack_ab(const AbGeometry& g, Store st, const double* z, int k, void* ZT,
                             hipStream_t s);
-// Partial Q = sum_P La^P Z Lb^P per aux split: Qp [nsplit][k][nmopa][nmopb].
-hipError_t launch_sigma_ab(const AbGeometry& g, const SigmaPlan& plan, const double* La,
-                           const double* Lb, const double* ZT, double* Qp, int k, int nsplit,
+// Partial Q = sum_P La^P Z Lb^P per aux split: Qp [nsplit][k][nmopa][nmopb], in precision st.
+hipError_t launch_sigma_ab(const AbGeometry& g, Store st, const SigmaPlan& plan, const void* La,
+                           const void* Lb, const void* ZT, void* Qp, int k, int nsplit,
                            hipStream_t s);
-// sigma [k][n] = epair * z + the split sums of Qp (fixed order).
-hipError_t launch_epilogue_ab(const AbGeometry& g, const double* z, int k, const double* Qp,
-                              int nsplit, const double* epair, double* sigma, hipStream_t s);
+// sigma [k][n] = epair * z + the split sums of Qp (fixed order, FP64).
+hipError_t launch_epilogue_ab(const AbGeometry& g, Store st, const double* z, int k,
+                              const void* Qp, int nsplit, const double* epair, double* sigma,
+                              hipStream_t s);
 
 // --- dense (k_dense.hip) -------------------------------------------------------------------
 hipError_t launch_dense_build(const Geometry& g, const double* L64, const int* d_ptab,

@@ -26,6 +26,7 @@ namespace pprpa {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int AB_CT = 8;   // c tiles per chunk (T tiles held in registers)
 constexpr int AB_RT = 16;  // alpha row tiles per work unit
@@ -54,9 +55,10 @@ __device__ __forceinline__ void ab_c_range(int dt, int cc0, int cc1, int nvta, i
 // Unpack the packed alpha-beta vectors into Z^T[kv][d][c] (beta row d, alpha column c), the
 // layout contraction 1 stages. Positions outside the two blocks keep the zeros they were
 // cleared to at build.
+template <typename T>
 __global__ void k_unpack_ab(const double* __restrict__ z, int64_t n, int64_t nvv, int nvb,
                             int nob, int nvpa, int nvpb, int nmopa, int nmopb,
-                            double* __restrict__ ZT) {
+                            T* __restrict__ ZT) {
   const int kv = blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
@@ -69,16 +71,30 @@ __global__ void k_unpack_ab(const double* __restrict__ z, int64_t n, int64_t nvv
     c = nvpa + (int)(s / nob);
     d = nvpb + (int)(s % nob);
   }
-  ZT[((int64_t)kv * nmopb + d) * nmopa + c] = z[(int64_t)kv * n + e];
+  ZT[((int64_t)kv * nmopb + d) * nmopa + c] = (T)z[(int64_t)kv * n + e];
 }
 
-template <int CT, int RT>
+template <typename T> struct AbAcc;
+template <> struct AbAcc<double> { using V = d4; };
+template <> struct AbAcc<float> { using V = f4; };
+__device__ __forceinline__ f4 mfma64(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// accumulator register j of lane group lk holds output row ab_acc_row(lk, j) of the tile
+// (FP64 16x16x4: lk + 4 j; FP32 16x16x4: 4 lk + j)
+template <typename T> __device__ __forceinline__ int ab_acc_row(int lk, int j);
+template <> __device__ __forceinline__ int ab_acc_row<double>(int lk, int j) { return lk + 4 * j; }
+template <> __device__ __forceinline__ int ab_acc_row<float>(int lk, int j) { return 4 * lk + j; }
+
+template <typename T, int CT, int RT>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
-                   const double* __restrict__ UT, double* __restrict__ Qp, AbParams a) {
-  __shared__ __attribute__((aligned(1024))) double buf[AB_BUF];
+void k_sandwich_ab(const T* __restrict__ La, const T* __restrict__ Lb,
+                   const T* __restrict__ UT, T* __restrict__ Qp, AbParams a) {
+  using V = typename AbAcc<T>::V;
+  __shared__ __attribute__((aligned(1024))) T buf[AB_BUF];
   constexpr int GRP = 2;
   static_assert(CT % GRP == 0 && RT % GRP == 0, "tile groups");
+  static_assert(2 * CT * 4 * 64 <= AB_BUF, "T exchange of a two-column panel fits the buffer");
   const int g = blockIdx.x;
   const int u = (g & 7) * a.per_xcd + (g >> 3);
   if (u >= a.nunits) return;
@@ -98,28 +114,34 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
   const int npt = min(4, bntb - t0);
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const bool active = w < npt;
-  const int wc = min(w, npt - 1);
+  // a panel of one or two column tiles puts parts = 4 / npt waves on each column: in
+  // contraction 1 they share out the column's c groups (g % parts == rsel), exchange their T
+  // tiles through LDS, and in contraction 2 they share out its row groups the same way; a
+  // three-tile panel idles one wave
+  const int parts = npt == 1 ? 4 : (npt == 2 ? 2 : 1);
+  const bool active = w < npt * parts;
+  const int wc = parts == 1 ? min(w, npt - 1) : w % npt;
+  const int rsel = parts == 1 ? 0 : w / npt;
   const int nrt = min(bnta, R0 + RT) - R0;
   const int ncol = npt * TILE;
   const int wl = nrt * TILE;
   const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
   const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
-  const double* __restrict__ Z = UT + (int64_t)kv * a.zt_stride;
+  const T* __restrict__ Z = UT + (int64_t)kv * a.zt_stride;
 
-  d4 S[RT];
+  V S[RT];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) S[r] = d4{0, 0, 0, 0};
+  for (int r = 0; r < RT; ++r) S[r] = V{0, 0, 0, 0};
 
-  double* const sB = buf + AB_SR1 * CT * TILE;
+  T* const sB = buf + AB_SR1 * CT * TILE;
   for (int P = P0; P < P1; ++P) {
-    const double* __restrict__ Lap = La + (int64_t)P * a.la_stride;
-    const double* __restrict__ Lbp = Lb + (int64_t)P * a.lb_stride;
+    const T* __restrict__ Lap = La + (int64_t)P * a.la_stride;
+    const T* __restrict__ Lbp = Lb + (int64_t)P * a.lb_stride;
     for (int cc0 = 0; cc0 < a.ncta; cc0 += CT) {
       const int cc1 = min(cc0 + CT, a.ncta);
-      d4 Tacc[CT];
+      V Tacc[CT];
 #pragma unroll
-      for (int i = 0; i < CT; ++i) Tacc[i] = d4{0, 0, 0, 0};
+      for (int i = 0; i < CT; ++i) Tacc[i] = V{0, 0, 0, 0};
       // contraction 1: part 0 pairs the chunk's alpha virtual c tiles with every beta virtual d
       // tile, part 1 its alpha occupied c tiles with every beta occupied d tile
       for (int part = 0; part < 2; ++part) {
@@ -141,16 +163,16 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
 #pragma unroll
           for (int sub = 0; sub < AB_ND; ++sub) {
             if (sub < nd) {
-              const double* sA = buf + sub * TILE * wa;
-              const double* sBs = sB + sub * TILE * ncol;
-              double bv[4];
+              const T* sA = buf + sub * TILE * wa;
+              const T* sBs = sB + sub * TILE * ncol;
+              T bv[4];
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) bv[ks] = sBs[(4 * ks + lk) * ncol + wc * TILE + li];
 #pragma unroll
               for (int grp = 0; grp < CT / GRP; ++grp) {
                 const int cg = cc0 + GRP * grp;
-                if (active && cg >= g0 && cg < chi) {
-                  double av[4][GRP];
+                if (active && cg >= g0 && cg < chi && grp % parts == rsel) {
+                  T av[4][GRP];
 #pragma unroll
                   for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
@@ -168,8 +190,27 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
           }
         }
       }
+      if (parts > 1) {
+        // narrow panel: every wave of a column takes the T tiles of the other waves' c groups
+        // (same values, same summation order as computing them itself); layout [col][tile][reg]
+        // [lane], conflict-free
+        T* const sT = buf;
+        __syncthreads();  // contraction-1 operands no longer read
+#pragma unroll
+        for (int i = 0; i < CT; ++i)
+          if ((i / GRP) % parts == rsel)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sT[((wc * CT + i) * 4 + j) * 64 + lane] = Tacc[i][j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CT; ++i)
+          if ((i / GRP) % parts != rsel)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Tacc[i][j] = sT[((wc * CT + i) * 4 + j) * 64 + lane];
+      }
       // contraction 2: Q[r][cols] += sum_c La^P[r][c] T[c][cols] (La^P symmetric: the staged
-      // rows c of La^P give the A operand), two c tiles per stage
+      // rows c of La^P give the A operand, read with the reduction index permuted to T's
+      // accumulator layout), two c tiles per stage
 #pragma unroll
       for (int i = 0; i < CT; i += 2) {
         if (cc0 + i < cc1) {
@@ -182,18 +223,18 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
 #pragma unroll
           for (int sub = 0; sub < 2; ++sub) {
             if (sub < nb) {
-              const double* sL = buf + sub * TILE * wl;
+              const T* sL = buf + sub * TILE * wl;
 #pragma unroll
               for (int grp = 0; grp < RT / GRP; ++grp) {
                 // a row tile at nrt in the last group reads other staged data (in bounds); its
                 // result is never stored
-                if (active && GRP * grp < nrt) {
-                  double av[4][GRP];
+                if (active && GRP * grp < nrt && grp % parts == rsel) {
+                  T av[4][GRP];
 #pragma unroll
                   for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
                     for (int j = 0; j < GRP; ++j)
-                      av[ks][j] = sL[(lk + 4 * ks) * wl + (GRP * grp + j) * TILE + li];
+                      av[ks][j] = sL[ab_acc_row<T>(lk, ks) * wl + (GRP * grp + j) * TILE + li];
                   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                   for (int ks = 0; ks < 4; ++ks)
@@ -210,15 +251,14 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
   }
 
   if (active) {
-    // accumulator register j of lane (li, lk) holds row lk + 4 j, column li of the tile
-    double* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.q_stride;
+    T* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.q_stride;
     const int col = col0 + wc * TILE + li;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      if (rt < nrt) {
+      if (rt < nrt && (rt / GRP) % parts == rsel) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          out[(int64_t)(row0 + rt * TILE + lk + 4 * j) * a.nmopb + col] = S[rt][j];
+          out[(int64_t)(row0 + rt * TILE + ab_acc_row<T>(lk, j)) * a.nmopb + col] = S[rt][j];
       }
     }
   }
@@ -226,9 +266,10 @@ void k_sandwich_ab(const double* __restrict__ La, const double* __restrict__ Lb,
 
 // sigma[e] = epair[e] z[e] + sum over splits of Q[row][col] (fixed order), with epair the signed
 // pair energies (+ for vv, - for oo pairs).
+template <typename T>
 __global__ __launch_bounds__(256) void k_epilogue_ab(const double* __restrict__ z, int64_t n,
                                                      int64_t nvv, int nvb, int nob, int nvpa,
-                                                     int nvpb, int nmopb, const double* __restrict__ Qp,
+                                                     int nvpb, int nmopb, const T* __restrict__ Qp,
                                                      int nsplit, int64_t split_stride,
                                                      int64_t q_stride,
                                                      const double* __restrict__ epair,
@@ -245,26 +286,32 @@ __global__ __launch_bounds__(256) void k_epilogue_ab(const double* __restrict__ 
     r = nvpa + (int)(s / nob);
     c = nvpb + (int)(s % nob);
   }
-  const double* Q = Qp + (int64_t)kv * q_stride + (int64_t)r * nmopb + c;
+  const T* Q = Qp + (int64_t)kv * q_stride + (int64_t)r * nmopb + c;
   double acc = 0.0;
 #pragma unroll 8
-  for (int t = 0; t < nsplit; ++t) acc += Q[t * split_stride];
+  for (int t = 0; t < nsplit; ++t) acc += (double)Q[t * split_stride];
   if (e0 < n) sigma[(int64_t)kv * n + e] = epair[e] * z[(int64_t)kv * n + e] + acc;
 }
 
 }  // namespace
 
-hipError_t launch_unpack_ab(const AbGeometry& g, const double* z, int k, double* ZT,
+hipError_t launch_unpack_ab(const AbGeometry& g, Store st, const double* z, int k, void* ZT,
                             hipStream_t s) {
   if (k <= 0) return hipSuccess;
   dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
-  hipLaunchKernelGGL(k_unpack_ab, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob, g.nvpa,
-                     g.nvpb, g.nmopa, g.nmopb, ZT);
+  if (st == Store::F64)
+    hipLaunchKernelGGL(k_unpack_ab<double>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
+                       g.nvpa, g.nvpb, g.nmopa, g.nmopb, (double*)ZT);
+  else if (st == Store::F32)
+    hipLaunchKernelGGL(k_unpack_ab<float>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
+                       g.nvpa, g.nvpb, g.nmopa, g.nmopb, (float*)ZT);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_sigma_ab(const AbGeometry& g, const SigmaPlan& plan, const double* La,
-                           const double* Lb, const double* ZT, double* Qp, int k, int nsplit,
+hipError_t launch_sigma_ab(const AbGeometry& g, Store st, const SigmaPlan& plan, const void* La,
+                           const void* Lb, const void* ZT, void* Qp, int k, int nsplit,
                            hipStream_t s) {
   AbParams p;
   p.nvta = g.nvta;
@@ -287,18 +334,33 @@ hipError_t launch_sigma_ab(const AbGeometry& g, const SigmaPlan& plan, const dou
   p.lb_stride = (int64_t)g.nmopb * g.nmopb;
   p.zt_stride = (int64_t)g.nmopb * g.nmopa;
   p.q_stride = (int64_t)g.nmopa * g.nmopb;
-  hipLaunchKernelGGL((k_sandwich_ab<AB_CT, AB_RT>), dim3(p.per_xcd * 8), dim3(256), 0, s, La, Lb,
-                     ZT, Qp, p);
+  if (st == Store::F64)
+    hipLaunchKernelGGL((k_sandwich_ab<double, AB_CT, AB_RT>), dim3(p.per_xcd * 8), dim3(256), 0, s,
+                       (const double*)La, (const double*)Lb, (const double*)ZT, (double*)Qp, p);
+  else if (st == Store::F32)
+    hipLaunchKernelGGL((k_sandwich_ab<float, AB_CT, AB_RT>), dim3(p.per_xcd * 8), dim3(256), 0, s,
+                       (const float*)La, (const float*)Lb, (const float*)ZT, (float*)Qp, p);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_epilogue_ab(const AbGeometry& g, const double* z, int k, const double* Qp,
-                              int nsplit, const double* epair, double* sigma, hipStream_t s) {
+hipError_t launch_epilogue_ab(const AbGeometry& g, Store st, const double* z, int k,
+                              const void* Qp, int nsplit, const double* epair, double* sigma,
+                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
   const int64_t q_stride = (int64_t)g.nmopa * g.nmopb;
   dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
-  hipLaunchKernelGGL(k_epilogue_ab, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob, g.nvpa,
-                     g.nvpb, g.nmopb, Qp, nsplit, (int64_t)k * q_stride, q_stride, epair, sigma);
+  if (st == Store::F64)
+    hipLaunchKernelGGL(k_epilogue_ab<double>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
+                       g.nvpa, g.nvpb, g.nmopb, (const double*)Qp, nsplit, (int64_t)k * q_stride,
+                       q_stride, epair, sigma);
+  else if (st == Store::F32)
+    hipLaunchKernelGGL(k_epilogue_ab<float>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
+                       g.nvpa, g.nvpb, g.nmopb, (const float*)Qp, nsplit, (int64_t)k * q_stride,
+                       q_stride, epair, sigma);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -10,8 +10,12 @@
 * the density-fitted alpha-beta sector (Q = sum_P La^P Z Lb^P on the rectangular amplitude
   blocks): sigma against the oracle's M z at ragged shapes and against the dense context, the
   Davidson roots of both channels against the oracle, a sector of order 33120 (beyond the dense
-  limit, which is refused) on sampled rows of the oracle, and the dense-only calls refused.
-Tolerances: matrices and sigma 1e-12 relative, eigenvalues 1e-9 Ha (FP64, tol 1e-10).
+  limit, which is refused) on sampled rows of the oracle, and the dense-only calls refused;
+* the density-fitted alpha-beta sector with FP32 sigma: sigma against the oracle's M z at the
+  same shapes and on sampled rows at order 33120, roots of both channels against the oracle.
+Tolerances: matrices and sigma 1e-12 relative, eigenvalues 1e-9 Ha (FP64, tol 1e-10); FP32
+sigma 2e-7 relative to max|M z| on the small shapes, 1e-6 at order 33120 (the level of FP32
+operands and accumulation, as for the restricted FP32 kernel), FP32 roots 1e-6 Ha.
 """
 import sys
 
@@ -157,6 +161,48 @@ def test_ab_df_sigma_vs_oracle(case):
     assert np.max(np.abs(s - sd)) <= 1e-12 * max(1.0, np.abs(sd).max())
 
 
+@pytest.mark.parametrize("case", AB_DF_CASES)
+def test_ab_df_sigma_fp32_vs_oracle(case):
+    """FP32 density-fitted alpha-beta sigma (integrals and amplitudes rounded to FP32, FP32 MFMA
+    accumulation, FP64 epilogue) against M z of the oracle's alpha-beta matrix."""
+    nmo, noa, nob, naux = case
+    note("ab df sigma fp32", case)
+    ea, eb, La, Lb = unrestricted(81, nmo, noa, nob, naux)
+    Mref, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec="fp32") as ctx:
+        z = gen.random_vectors(82, 6, ctx.n)
+        s = ctx.matvec(z)
+    sref = z @ Mref.T
+    err = np.max(np.abs(s - sref)) / np.abs(sref).max()
+    note("relative error", err)
+    assert err <= 2e-7
+
+
+@pytest.mark.parametrize("channel,nroot", [("pp", 6), ("hh", 4)])
+def test_ab_df_fp32_davidson_vs_oracle(channel, nroot):
+    """FP32 sigma, FP64 subspace algebra: every root within 1e-6 Ha of the oracle's."""
+    nmo, noa, nob, naux = 45, 10, 9, 60
+    note("ab df davidson fp32", channel)
+    ea, eb, La, Lb = unrestricted(83, nmo, noa, nob, naux)
+    ref = O.solve_ab(ea, eb, La, Lb, noa, nob, nroot, channel=channel)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec="fp32") as ctx:
+        r = ctx.davidson(nroot, block=nroot, tol=1e-5, channel=channel)
+    err = np.max(np.abs(r["omega"] - ref))
+    note("max root error", err)
+    assert r["status"] == 0
+    assert err <= 1e-6
+
+
+def test_ab_df_precision_refusals():
+    """The alpha-beta sector takes FP32 sigma only density fitted, and no BF16 split."""
+    ea, eb, La, Lb = unrestricted(88, 12, 3, 2, 20)
+    for kw in (dict(prec="fp32"), dict(prec="bf16x6", density_fitted=True),
+               dict(prec="bf16x3", density_fitted=True)):
+        with pytest.raises(P.PpRPAError) as e:
+            P.PpRPA.alpha_beta(ea, eb, La, Lb, 3, 2, **kw)
+        assert e.value.status == P.binding.EUNSUPPORTED
+
+
 @pytest.mark.parametrize("channel,nroot", [("pp", 6), ("hh", 4)])
 def test_ab_df_davidson_vs_oracle(channel, nroot):
     nmo, noa, nob, naux = 45, 10, 9, 60
@@ -185,6 +231,8 @@ def test_ab_df_beyond_the_dense_limit():
         z = gen.random_vectors(86, 4, ctx.n)
         s = ctx.matvec(z)
         r = ctx.davidson(5, block=10, tol=1e-7)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec="fp32") as c32:
+        s32 = c32.matvec(z)
     rng = np.random.default_rng(4)
     nvv = 180 * 182
     rows = np.unique(np.r_[np.arange(3), nvv - 3 + np.arange(6), ctx.n - 3 + np.arange(3),
@@ -192,6 +240,9 @@ def test_ab_df_beyond_the_dense_limit():
     for j in range(z.shape[0]):
         ref = O.ab_sigma_rows(ea, eb, La, Lb, noa, nob, rows, z[j])
         assert np.max(np.abs(s[j, rows] - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+        err32 = np.max(np.abs(s32[j, rows] - ref)) / np.abs(s32[j]).max()
+        note("fp32 relative error", err32)
+        assert err32 <= 1e-6
     assert r["status"] == 0 and np.all(r["resid"] <= 1e-7)
     assert np.all(np.diff(r["omega"]) >= 0)
 
