@@ -91,13 +91,14 @@ def test_sigma_panel_mixes(case, mult, prec, rtol):
 
 # Shapes for the software-pipelined FP64 kernel (from 20 virtual 16-tiles on) and the wide-panel
 # BF16x6 kernel (virtual blocks of 32 tiles and more in full 8-tile panels): a ragged last
-# virtual panel (FP64: 21 tiles = 5 x 4 + 1), a virtual block longer than one unit's 32 row
-# tiles (FP64 35 tiles: row ranges of 32 + 3 and a three-tile panel; BF16 at 630 virtual
-# orbitals: 40 tiles, 32 + 8), occupied blocks of 3 and 5 tiles (FP64) or 4 and 6 (BF16, padded
-# to 32 orbitals), and units that walk several aux indices (20 vectors at naux 120: dozens of
-# aux splits of 2-3 indices). The BF16x3 kernel and the BF16x6 kernel below 32 tiles run on
-# the same shapes. Sampled entries against the oracle's rows.
-PIPE_CASES = [((40, 330, 120), 20), ((70, 560, 12), 3), ((40, 500, 120), 20), ((70, 630, 12), 3)]
+# virtual panel (FP64: 21 tiles = 5 x 4 + 1, 25 = 6 x 4 + 1), a virtual block longer than one
+# unit's 32 row tiles (FP64 35 tiles: row ranges of 32 + 3 and a three-tile panel; BF16 at 630
+# virtual orbitals: 40 tiles, 32 + 8), occupied blocks of 3 and 5 tiles (FP64) or 4 and 6 (BF16,
+# padded to 32 orbitals), and units that walk several aux indices (20 vectors at naux 120:
+# dozens of aux splits of 2-3 indices). The BF16x3 kernel and the BF16x6 kernel elsewhere (22,
+# 26 and 36 tiles) run on the same shapes. Sampled entries against the oracle's rows.
+PIPE_CASES = [((40, 330, 120), 20), ((70, 560, 12), 3), ((40, 500, 120), 20), ((70, 630, 12), 3),
+              ((40, 400, 24), 3)]
 
 
 # (BF16x6 is held to 1e-6 here, the full-size gate: these vectors are longer (nmo 370-630) than
