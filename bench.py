@@ -52,8 +52,9 @@ PEAK_HBM = 8.0e12     # B/s
 # WRITE_SIZE scaled by a plain 1 GiB device copy, keyed by (workload, precision); the profile
 # summaries under profiles/ name the command. A workload without an entry reports null.
 TRAFFIC_GB_PER_LAUNCH = {
-    # profiles/sigma_fp64_headline_50x500x1800_hbm_traffic.md (20 timed launches of 20 vectors)
-    ("mixed", "fp64"): 401.2,
+    # profiles/sigma_fp64_headline_50x500x1800_hbm_traffic.md (20 timed launches of 20 vectors,
+    # 16384 work units each)
+    ("mixed", "fp64"): 452.8,
 }
 
 

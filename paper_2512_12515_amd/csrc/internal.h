@@ -81,7 +81,7 @@ struct SigmaPlan {
 void make_sigma_items(const Geometry& g, int RT, std::vector<int>& items, int& npan_v, int pw = 4);
 // Column tiles per panel of a sigma kernel variant.
 inline int panel_width(int variant) { return variant == 7 ? 8 : 4; }
-constexpr int UNITS_F64 = 8192;       // work units per launch of the pipelined FP64 kernel
+constexpr int UNITS_F64 = 16384;      // work units per launch of the pipelined FP64 kernel
 constexpr int F64_PIPE_MIN_NVT = 20;  // virtual 16-tiles from which FP64 sigma uses that kernel
 constexpr int BF16_WIDE_MIN_NVT = 32;  // the same for the wide-panel BF16x6 kernel
 // Largest order of the dense pencil solves on the device (direct diagonalisation, E_c).
