@@ -58,6 +58,22 @@ TRAFFIC_GB_PER_LAUNCH = {
 }
 
 
+def sigma_kernel_name(prec, nv):
+    """Name of the sigma kernel the library launches for this precision and virtual block (the
+    label of the roofline object; the choice itself is made in the library)."""
+    t16 = -(-nv // 16)
+    t32 = 2 * -(-nv // 32)
+    if prec == "fp64":
+        k = "k_sandwich_f64 (software-pipelined)" if t16 >= 20 else "k_sandwich<double> (two workgroups per CU)"
+    elif prec == "fp32":
+        k = "k_sandwich<float>"
+    elif prec == "bf16x6" and t32 >= 32 and t32 % 8 == 0:
+        k = "k_sandwich_bf16w (double-buffered, 8-column panels)"
+    else:
+        k = "k_sandwich_bf16<%d>" % (6 if prec == "bf16x6" else 3)
+    return k + ": fused density-fitted sigma contraction"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -774,7 +790,7 @@ def main():
                      "unit": "TFLOP/s", "frac": nprod * achieved / peak,
                      "traffic": TRAFFIC_GB_PER_LAUNCH.get((name, args.prec)),
                      "traffic_unit": "GB/launch",
-                     "kernel": "k_sandwich (fused density-fitted sigma contraction)",
+                     "kernel": sigma_kernel_name(args.prec, c.get("nvir_act") or c["nvir"]),
                      "launches": st["launches"], "avg_launch_ms": 1e3 * st["seconds"] / max(st["launches"], 1),
                      "algorithmic_gflop_per_launch": st["flops"] / max(st["launches"], 1) / 1e9,
                      "algorithmic_gbytes_per_launch": st["bytes"] / max(st["launches"], 1) / 1e9},
