@@ -186,7 +186,7 @@ pprpa_status pprpa_davidson(pprpa_ctx* ctx, const pprpa_davidson_args* args, dou
  * ec_pp = sum of the pp roots - Tr A and, from the same spectrum, ec_hh = -(sum of the hh
  * roots) - Tr C; the two agree by the sum rule of the method, their difference measures the
  * eigenvalue accuracy. For a closed shell the total is E(singlet) + 3 E(triplet).
- * Requires dense=1 at build and n <= 2048 (else EUNSUPPORTED). ENONDEF if M - 2 mu W is not
+ * Requires dense=1 at build and n <= 8192 (else EUNSUPPORTED). ENONDEF if M - 2 mu W is not
  * positive definite or the spectrum does not split into n_pp pp and n_hh hh roots (out is
  * still filled in the latter case). The call allocates 3 n^2 doubles of device scratch. */
 typedef struct {
@@ -202,7 +202,7 @@ pprpa_status pprpa_correlation_energy(pprpa_ctx* ctx, pprpa_corr_energy* out);
  * results, bit for bit, with its workspace in a static device array of the library (3 * 512^2 + 32
  * doubles, about 6 MiB, held by each device the library runs on until the process ends) instead
  * of a hipMalloc per call. Order n <= 512 (EUNSUPPORTED beyond; pprpa_correlation_energy goes
- * to 2048).
+ * to 8192).
  * Every call on one device shares that array: calls that overlap on one device race and must be
  * serialised by the caller. Errors as pprpa_correlation_energy, plus EDEVICE if the array's
  * device address cannot be obtained. */

@@ -314,7 +314,7 @@ class PpRPA:
 
     def correlation_energy(self, noalloc=False):
         """ppRPA correlation energy of this spin block from the whole spectrum of the dense
-        pencil (requires dense=True and n <= 2048): both sides of the sum rule, ec_pp = sum of
+        pencil (requires dense=True and n <= 8192): both sides of the sum rule, ec_pp = sum of
         the pp roots - Tr A and ec_hh = -(sum of the hh roots) - Tr C, and the root counts.
         noalloc=True: pprpa_correlation_energy_noalloc (workspace in the library's static device
         array, no device allocation)."""

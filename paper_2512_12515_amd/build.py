@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpprpa.so")
 SOURCES = ["api.cpp", "davidson.cpp", "server.cpp", "k_sigma.hip", "k_sigma_f64.hip", "k_sigma_ab.hip", "k_sigma_bf16.hip", "k_linalg.hip",
-           "k_dense.hip"]
+           "k_dense.hip", "k_dense_mw.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Wno-unused-function", "-Wno-unused-result",

@@ -736,7 +736,10 @@ pprpa_status corr_energy_run(pprpa_ctx* c, double* work, pprpa_corr_energy* out)
   double* dout = work + 3 * (size_t)n * n;  // 4 doubles, then 3 ints
   int* dinfo = (int*)(dout + 4);
   double* hp = c->pinned;
-  hipError_t le = launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, work, dinfo, c->stream);
+  // one workgroup up to order 512 (also the no-allocation entry point's limit), many above
+  hipError_t le = n <= 512 ? launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, work, dinfo, c->stream)
+                           : launch_pencil_energy_mw(c->M, (int)n, nvv, c->mu2, dout, work, dinfo,
+                                                     c->stream);
   if (le == hipSuccess) le = hipMemcpyAsync(hp, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (le == hipSuccess) le = hipMemcpyAsync(hp + 4, dinfo, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (le == hipSuccess) le = hipStreamSynchronize(c->stream);
@@ -931,7 +934,7 @@ pprpa_status pprpa_dense_matrix(pprpa_ctx* c, double* M, int32_t on_device) {
 
 pprpa_status pprpa_correlation_energy(pprpa_ctx* c, pprpa_corr_energy* out) {
   g_err.clear();
-  PPRPA_TRY(corr_energy_checks(c, out, DENSE_SOLVE_MAX));
+  PPRPA_TRY(corr_energy_checks(c, out, DENSE_ENERGY_MAX));
   Busy busy(c->busy);
   if (!busy.ok) {
     set_error("context in use by another thread");

@@ -84,8 +84,11 @@ inline int panel_width(int variant) { return variant == 7 ? 8 : 4; }
 constexpr int UNITS_F64 = 16384;      // work units per launch of the pipelined FP64 kernel
 constexpr int F64_PIPE_MIN_NVT = 20;  // virtual 16-tiles from which FP64 sigma uses that kernel
 constexpr int BF16_WIDE_MIN_NVT = 32;  // the same for the wide-panel BF16x6 kernel
-// Largest order of the dense pencil solves on the device (direct diagonalisation, E_c).
+// Largest order of the dense pencil solves on the device: the direct diagonalisation (one
+// workgroup) and the whole-spectrum solve of the correlation energy (one workgroup up to 512,
+// many above).
 constexpr int DENSE_SOLVE_MAX = 2048;
+constexpr int DENSE_ENERGY_MAX = 8192;
 int sigma_variant(const Geometry& g, Store st, int nprod, int* RT);
 
 // --- kernel launchers (k_sigma.hip) -------------------------------------------------------
@@ -200,6 +203,12 @@ hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2,
 // info: [0] 0 ok / 1 not definite, [1] pp roots, [2] hh roots. work: 3 m^2 doubles.
 hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2, double* out,
                                 double* work, int* info, hipStream_t s);
+// The same outputs as launch_pencil_energy for 2 <= m <= DENSE_ENERGY_MAX on many workgroups
+// (blocked Cholesky, S = L^T W L, Householder tridiagonal form, bisection; k_dense_mw.hip).
+// work: pencil_energy_mw_work(m) doubles.
+size_t pencil_energy_mw_work(int n);
+hipError_t launch_pencil_energy_mw(const double* M, int m, int64_t nvv, double mu2, double* out,
+                                   double* work, int* info, hipStream_t s);
 // NTO weights and two-electron density blocks of k packed roots Z [k][ldz] (nv, no <= 512):
 // X [k][nv][nv], Y [k][no][no] (triangular amplitude matrices), Gx, Gy (their T^T T, destroyed),
 // Dv = X X^T + X^T X, Do = -(Y Y^T + Y^T Y) (may be null), lam_p [k][nv], lam_h [k][no]

@@ -1,0 +1,415 @@
+// Whole spectrum of the dense definite pencil (M, W) on many workgroups: the correlation energy of
+// arXiv 2512.12515 (section "Total Energy", Eq. correlation_energy) at orders above the
+// one-workgroup solver's.
+//
+// With 2 mu inside the gap, K = M - 2 mu W is positive definite. K z = (Omega - 2 mu) W z, so the
+// eigenvalues lambda = Omega - 2 mu are those of W K = W L L^T (K = L L^T, Cholesky), which is
+// similar to the symmetric S = L^T W L; lambda > 0 exactly for the pp roots (z^T K z > 0 and
+// lambda z^T W z = z^T K z). The steps:
+//   1. K = M - 2 mu W;
+//   2. K = L L^T by the blocked right-looking Cholesky: a one-workgroup factorisation of each
+//      32 x 32 diagonal block, the panel below it by forward substitution (a row per thread),
+//      the trailing lower triangle updated in 32 x 32 tiles;
+//   3. S = L^T W L in 32 x 32 tiles (both triangles written);
+//   4. Householder reduction of S to tridiagonal form, one reflection per column: the reflection
+//      vector (one workgroup), p = beta S2 v (a wave per row), then S2 -= v w^T + w v^T with
+//      w = p - (beta p^T v / 2) v (every workgroup forms the dot product itself, in the same fixed
+//      order);
+//   5. every eigenvalue of the tridiagonal form by Sturm-count bisection (a thread per
+//      eigenvalue), and the sums of the sum rule in a fixed order.
+// Every reduction runs in a fixed order: the result is bitwise repeatable.
+#include "internal.h"
+
+namespace pprpa {
+namespace {
+
+constexpr int CB = 32;  // Cholesky block and tile edge
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// sum over the workgroup (every thread gets it); red: blockDim.x / 64 doubles of LDS
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double wg_max(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double wg_min(double v, double* red) {
+  return -wg_max(-v, red);
+}
+
+// (row, col) of pair index x in the lower triangle of a t x t tile grid (row >= col)
+__device__ __forceinline__ void tri_pair(int x, int* r, int* c) {
+  int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= x) ++i;
+  while (i * (i + 1) / 2 > x) --i;
+  *r = i;
+  *c = x - i * (i + 1) / 2;
+}
+
+__global__ void k_mw_init(int* flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+// K = M - mu2 W, mu2 = 2 mu, W = diag(+1 for i < nvv, -1)
+__global__ __launch_bounds__(256) void k_mw_shift(const double* __restrict__ M, int n, int64_t nvv,
+                                                  double mu2, double* __restrict__ K) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  K[e] = M[e] - (i == j ? mu2 * (i < nvv ? 1.0 : -1.0) : 0.0);
+}
+
+// Cholesky of the diagonal block at (j0, j0), b = min(CB, n - j0) rows, in place (lower); a
+// non-positive pivot sets flag.
+__global__ __launch_bounds__(256) void k_mw_chol_diag(double* __restrict__ K, int n, int j0,
+                                                      int* __restrict__ flag) {
+  __shared__ double a[CB][CB + 1];
+  const int b = min(CB, n - j0);
+  for (int e = threadIdx.x; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    a[r][c] = (r < b && c < b) ? K[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < b; ++c) {
+    if (threadIdx.x == 0) {
+      const double piv = a[c][c];
+      if (!(piv > 0.0)) flag[0] = 1;
+      a[c][c] = sqrt(fmax(piv, 0.0));
+    }
+    __syncthreads();
+    const double dc = a[c][c];
+    for (int r = c + 1 + threadIdx.x; r < b; r += 256) a[r][c] = dc > 0.0 ? a[r][c] / dc : 0.0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+      const int r = e / CB, t = e % CB;
+      if (r > c && r < b && t > c && t <= r) a[r][t] -= a[r][c] * a[t][c];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    if (r < b && c <= r) K[(int64_t)(j0 + r) * n + j0 + c] = a[r][c];
+  }
+}
+
+// Panel below the diagonal block: row i >= j0 + CB solves x L_jj^T = K[i][j0 .. j0 + CB) by
+// forward substitution (a thread per row).
+__global__ __launch_bounds__(256) void k_mw_chol_trsm(double* __restrict__ K, int n, int j0) {
+  __shared__ double l[CB][CB + 1];
+  for (int e = threadIdx.x; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    l[r][c] = c <= r ? K[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int i = j0 + CB + blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x[CB];
+  double* row = K + (int64_t)i * n + j0;
+#pragma unroll
+  for (int c = 0; c < CB; ++c) x[c] = row[c];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    double s = x[c];
+#pragma unroll
+    for (int t = 0; t < c; ++t) s -= x[t] * l[c][t];
+    x[c] = l[c][c] > 0.0 ? s / l[c][c] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) row[c] = x[c];
+}
+
+// Trailing update of the lower triangle right of the panel: K[i][k] -= sum_t L[i][j0+t] L[k][j0+t]
+// for j0 + CB <= k <= i, one 32 x 32 tile (I >= J) per workgroup, four elements per thread.
+__global__ __launch_bounds__(256) void k_mw_chol_update(double* __restrict__ K, int n, int j0) {
+  __shared__ double pi[CB][CB + 1], pk[CB][CB + 1];
+  int I, J;
+  tri_pair(blockIdx.x, &I, &J);
+  const int r0 = j0 + CB + I * CB, c0 = j0 + CB + J * CB;
+  for (int e = threadIdx.x; e < CB * CB; e += 256) {
+    const int r = e / CB, t = e % CB;
+    pi[r][t] = r0 + r < n ? K[(int64_t)(r0 + r) * n + j0 + t] : 0.0;
+    pk[r][t] = c0 + r < n ? K[(int64_t)(c0 + r) * n + j0 + t] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    const int i = r0 + r, k = c0 + c;
+    if (i < n && k < n && k <= i) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < CB; ++t) s += pi[r][t] * pk[c][t];
+      K[(int64_t)i * n + k] -= s;
+    }
+  }
+}
+
+// S = L^T W L (L: the lower triangle of K; the entries above its diagonal are ignored), tiles
+// (I, J) with I >= J, both triangles written: S[i][j] = sum over k >= max(i, j) of
+// L[k][i] w_k L[k][j].
+__global__ __launch_bounds__(256) void k_mw_sym(const double* __restrict__ K, int n, int64_t nvv,
+                                                double* __restrict__ S) {
+  __shared__ double a[CB][CB + 1], bb[CB][CB + 1];
+  int I, J;
+  tri_pair(blockIdx.x, &I, &J);
+  const int i0 = I * CB, j0 = J * CB;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = i0; k0 < n; k0 += CB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+      const int kk = e / CB, c = e % CB;
+      const int k = k0 + kk;
+      const double w = k < nvv ? 1.0 : -1.0;
+      const int ci = i0 + c, cj = j0 + c;
+      a[kk][c] = (k < n && ci < n && k >= ci) ? K[(int64_t)k * n + ci] * w : 0.0;
+      bb[kk][c] = (k < n && cj < n && k >= cj) ? K[(int64_t)k * n + cj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int r = e / CB, c = e % CB;
+      double s = acc[q];
+#pragma unroll 8
+      for (int kk = 0; kk < CB; ++kk) s += a[kk][r] * bb[kk][c];
+      acc[q] = s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int i = i0 + e / CB, j = j0 + e % CB;
+    if (i < n && j < n) {
+      S[(int64_t)i * n + j] = acc[q];
+      S[(int64_t)j * n + i] = acc[q];
+    }
+  }
+}
+
+// Householder step k: x = S[k][k+1 ..] (column k below the diagonal, read as row k), alpha =
+// -sign(x_0) |x|, v = x - alpha e_1, beta = 2 / v^T v (0 when x = 0); d[k] = S[k][k], e[k] = alpha.
+__global__ __launch_bounds__(1024) void k_mw_hh_vec(const double* __restrict__ S, int n, int k,
+                                                    double* __restrict__ v,
+                                                    double* __restrict__ scal,
+                                                    double* __restrict__ d,
+                                                    double* __restrict__ e) {
+  __shared__ double red[16];
+  const int m = n - k - 1;
+  const double* x = S + (int64_t)k * n + k + 1;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) s += x[i] * x[i];
+  const double nrm2 = wg_sum(s, red);
+  const double x0 = x[0];
+  const double nrm = sqrt(nrm2);
+  const double alpha = nrm > 0.0 ? (x0 > 0.0 ? -nrm : nrm) : 0.0;
+  const double v0 = x0 - alpha;
+  const double vtv = nrm2 - x0 * x0 + v0 * v0;
+  for (int i = threadIdx.x; i < m; i += 1024) v[i] = i == 0 ? v0 : x[i];
+  if (threadIdx.x == 0) {
+    scal[0] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    d[k] = S[(int64_t)k * n + k];
+    e[k] = alpha;
+  }
+}
+
+// p = beta S2 v, S2 = S[k+1 ..][k+1 ..]: a wave per row (lanes stride the row).
+__global__ __launch_bounds__(256) void k_mw_hh_matvec(const double* __restrict__ S, int n, int k,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ scal,
+                                                      double* __restrict__ p) {
+  const int m = n - k - 1;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= m) return;
+  const double* row = S + (int64_t)(k + 1 + r) * n + k + 1;
+  double s = 0.0;
+  for (int j = lane; j < m; j += 64) s += row[j] * v[j];
+  s = wave_sum(s);
+  if (lane == 0) p[r] = scal[0] * s;
+}
+
+// S2 -= v w^T + w v^T, w = p - (beta p^T v / 2) v: a wave per row; every workgroup forms p^T v
+// itself in the same fixed order.
+__global__ __launch_bounds__(256) void k_mw_hh_update(double* __restrict__ S, int n, int k,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ scal,
+                                                      const double* __restrict__ p) {
+  __shared__ double red[4];
+  const int m = n - k - 1;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) s += p[i] * v[i];
+  const double ptv = wg_sum(s, red);
+  const double kk = 0.5 * scal[0] * ptv;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= m) return;
+  const double vr = v[r], wr = p[r] - kk * vr;
+  double* row = S + (int64_t)(k + 1 + r) * n + k + 1;
+  for (int j = lane; j < m; j += 64) {
+    const double vj = v[j], wj = p[j] - kk * vj;
+    row[j] -= vr * wj + wr * vj;
+  }
+}
+
+__device__ __forceinline__ int mw_sturm_below(const double* __restrict__ d,
+                                              const double* __restrict__ e, int n, double x,
+                                              double tiny) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    if (fabs(q) < tiny) q = -tiny;
+    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// The last two diagonal and the last off-diagonal entry, then the Gershgorin interval of T:
+// bnd[0] = lower, bnd[1] = upper, bnd[2] = a norm of T (one workgroup).
+__global__ __launch_bounds__(1024) void k_mw_bounds(const double* __restrict__ S, int n,
+                                                    double* __restrict__ d, double* __restrict__ e,
+                                                    double* __restrict__ bnd) {
+  __shared__ double red[16];
+  if (threadIdx.x == 0) {
+    if (n >= 2) {
+      d[n - 2] = S[(int64_t)(n - 2) * n + n - 2];
+      e[n - 2] = S[(int64_t)(n - 1) * n + n - 2];
+    }
+    d[n - 1] = S[(int64_t)(n - 1) * n + n - 1];
+  }
+  __syncthreads();
+  double lo = 1e300, hi = -1e300, nr = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    nr = fmax(nr, fabs(d[i]) + r);
+  }
+  const double glo = wg_min(lo, red), ghi = wg_max(hi, red), gn = wg_max(nr, red);
+  if (threadIdx.x == 0) {
+    bnd[0] = glo;
+    bnd[1] = ghi;
+    bnd[2] = fmax(gn, 1e-300);
+  }
+}
+
+// Eigenvalue idx (ascending) of T by bisection on Sturm counts, a thread per eigenvalue.
+__global__ __launch_bounds__(256) void k_mw_bisect(const double* __restrict__ d,
+                                                   const double* __restrict__ e, int n,
+                                                   const double* __restrict__ bnd,
+                                                   double* __restrict__ lam) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const double tnorm = bnd[2];
+  const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
+  double lo = bnd[0] - 1e-12 * tnorm, hi = bnd[1] + 1e-12 * tnorm;
+  for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (mw_sturm_below(d, e, n, mid, tiny) <= idx)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  lam[idx] = 0.5 * (lo + hi);
+}
+
+// out[0] = sum over lambda > 0 of (mu2 + lambda) - Tr A, out[1] = -(sum over lambda < 0 of
+// (mu2 + lambda)) - Tr C, out[2] = Tr A, out[3] = Tr C; info: [0] 0 / 1 (K not positive definite),
+// [1] pp roots, [2] hh roots. Fixed-order sums (one workgroup).
+__global__ __launch_bounds__(1024) void k_mw_sums(const double* __restrict__ M, int n,
+                                                  int64_t nvv, double mu2,
+                                                  const double* __restrict__ lam,
+                                                  const int* __restrict__ flag,
+                                                  double* __restrict__ out,
+                                                  int* __restrict__ info) {
+  __shared__ double red[16];
+  double spp = 0.0, shh = 0.0, npp = 0.0, nhh = 0.0, tra = 0.0, trc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const double l = lam[i], om = mu2 + l;
+    if (l > 0.0) {
+      spp += om;
+      npp += 1.0;
+    } else {
+      shh += om;
+      nhh += 1.0;
+    }
+    if (i < nvv)
+      tra += M[(int64_t)i * n + i];
+    else
+      trc += M[(int64_t)i * n + i];
+  }
+  const double SPP = wg_sum(spp, red), SHH = wg_sum(shh, red);
+  const double NPP = wg_sum(npp, red), NHH = wg_sum(nhh, red);
+  const double TA = wg_sum(tra, red), TC = wg_sum(trc, red);
+  if (threadIdx.x == 0) {
+    out[0] = SPP - TA;
+    out[1] = -SHH - TC;
+    out[2] = TA;
+    out[3] = TC;
+    info[0] = flag[0] ? 1 : 0;
+    info[1] = (int)NPP;
+    info[2] = (int)NHH;
+  }
+}
+
+}  // namespace
+
+size_t pencil_energy_mw_work(int n) { return 2 * (size_t)n * n + 5 * (size_t)n + 8; }
+
+hipError_t launch_pencil_energy_mw(const double* M, int n, int64_t nvv, double mu2, double* out,
+                                   double* work, int* info, hipStream_t s) {
+  if (n < 2 || n > DENSE_ENERGY_MAX) return hipErrorInvalidValue;
+  const size_t nn = (size_t)n * n;
+  double* K = work;
+  double* S = K + nn;
+  double* v = S + nn;
+  double* p = v + n;
+  double* d = p + n;
+  double* e = d + n;
+  double* lam = e + n;
+  double* scal = lam + n;  // [0] beta, [1 .. 3] Gershgorin bounds and norm
+  int* flag = info;        // info[0] doubles as the not-definite flag until the last kernel
+  hipLaunchKernelGGL(k_mw_init, dim3(1), dim3(64), 0, s, flag);
+  hipLaunchKernelGGL(k_mw_shift, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, M, n, nvv,
+                     mu2, K);
+  for (int j0 = 0; j0 < n; j0 += CB) {
+    hipLaunchKernelGGL(k_mw_chol_diag, dim3(1), dim3(256), 0, s, K, n, j0, flag);
+    const int rest = n - j0 - CB;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_mw_chol_trsm, dim3((rest + 255) / 256), dim3(256), 0, s, K, n, j0);
+      const int nt = (rest + CB - 1) / CB;
+      hipLaunchKernelGGL(k_mw_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, K, n, j0);
+    }
+  }
+  const int ntile = (n + CB - 1) / CB;
+  hipLaunchKernelGGL(k_mw_sym, dim3(ntile * (ntile + 1) / 2), dim3(256), 0, s, K, n, nvv, S);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, k, v, scal, d, e);
+    hipLaunchKernelGGL(k_mw_hh_matvec, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
+    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
+  }
+  hipLaunchKernelGGL(k_mw_bounds, dim3(1), dim3(1024), 0, s, S, n, d, e, scal + 1);
+  hipLaunchKernelGGL(k_mw_bisect, dim3((n + 255) / 256), dim3(256), 0, s, d, e, n, scal + 1, lam);
+  hipLaunchKernelGGL(k_mw_sums, dim3(1), dim3(1024), 0, s, M, n, nvv, mu2, lam, flag, out, info);
+  return hipGetLastError();
+}
+
+}  // namespace pprpa

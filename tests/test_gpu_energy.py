@@ -2,11 +2,12 @@
 whole spectrum of the dense pencil, through the C ABI, against the FP64 oracle.
 
 * both sides of the sum rule (sum of the pp roots - Tr A, -(sum of the hh roots) - Tr C) against
-  the oracle's full-spectrum values, both spins, shapes up to n = 456 and at orders 1018 / 1071,
-  and against each other;
-* E_c = 0 when L = 0 and when the coupling block B vanishes (L_vo = 0), as the oracle's pin P2;
+  the oracle's full-spectrum values, both spins, shapes up to n = 456 (one-workgroup solver) and
+  at orders 1018, 1071 and 1989 (multi-workgroup solver), and against each other;
+* E_c = 0 when L = 0 and when the coupling block B vanishes (L_vo = 0), as the oracle's pin P2,
+  with both solvers;
 * the closed-shell total E(singlet) + 3 E(triplet) against the oracle's;
-* argument checks: no dense build, n > 2048.
+* argument checks: no dense build, n > 8192.
 Tolerance: 1e-10 Ha absolute (the sums run over up to ~450 roots, each good to ~1e-13); 1e-9 Ha
 at order ~1000 (twice the roots, the reduction's rounding growing with the order).
 """
@@ -53,11 +54,13 @@ def test_correlation_energy_vs_oracle(mult, case):
     assert r["ec_pp"] < 0.0
 
 
-@pytest.mark.parametrize("mult", ["singlet", "triplet"])
-def test_correlation_energy_order_above_1000(mult):
-    """8 occupied, 45 virtual orbitals: n = 1071 (singlet) and 1018 (triplet)."""
-    nocc, nvir, naux = 8, 45, 150
-    note("E_c order > 1000", mult)
+@pytest.mark.parametrize("mult,nvir", [("singlet", 45), ("triplet", 45), ("singlet", 62)])
+def test_correlation_energy_order_above_1000(mult, nvir):
+    """Orders above the one-workgroup solver's 512 (the multi-workgroup whole-spectrum solve):
+    8 occupied and 45 virtual orbitals, n = 1071 (singlet) and 1018 (triplet); 62 virtual,
+    n = 1989."""
+    nocc, naux = 8, 150
+    note("E_c order > 1000", mult, nvir)
     eps = gen.orbital_energies(54, nocc, nvir)
     L = gen.lpq_full(54, nocc + nvir, naux)
     (ref_pp, ref_hh), npp, nhh = oracle_ec(eps, L, nocc, mult)
@@ -71,10 +74,11 @@ def test_correlation_energy_order_above_1000(mult):
     assert abs(r["ec_pp"] - r["ec_hh"]) <= 1e-9
 
 
-@pytest.mark.parametrize("mult", ["singlet", "triplet"])
-def test_correlation_energy_vanishes_without_coupling(mult):
-    note("E_c B = 0", mult)
-    nocc, nvir, naux = 5, 14, 40
+@pytest.mark.parametrize("mult,nvir", [("singlet", 14), ("triplet", 14), ("singlet", 40)])
+def test_correlation_energy_vanishes_without_coupling(mult, nvir):
+    """nvir 40: n = 835, the multi-workgroup solve."""
+    note("E_c B = 0", mult, nvir)
+    nocc, naux = 5, 40
     eps = gen.orbital_energies(52, nocc, nvir)
     L = gen.lpq_full(52, nocc + nvir, naux)
     L[:, :nocc, nocc:] = 0.0
@@ -107,10 +111,10 @@ def test_correlation_energy_argument_checks():
         with pytest.raises(P.PpRPAError) as e:
             ctx.correlation_energy()
         assert e.value.status == P.binding.EUNSUPPORTED
-    eps = gen.orbital_energies(53, 4, 64)
-    L = gen.lpq_full(53, 68, 20)
+    eps = gen.orbital_energies(53, 4, 130)
+    L = gen.lpq_full(53, 134, 20)
     with P.PpRPA(eps, L, 4, dense=True) as ctx:
-        assert ctx.n > 2048
+        assert ctx.n > 8192
         with pytest.raises(P.PpRPAError) as e:
             ctx.correlation_energy()
         assert e.value.status == P.binding.EUNSUPPORTED
