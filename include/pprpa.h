@@ -176,7 +176,7 @@ typedef struct {
  * omega: [nroot] host. vecs: [nroot][n] host or NULL, normalised to z^T W z = +1 (pp) or -1
  * (hh). resid: [nroot] host or NULL. rep: host or NULL. Returns ENOCONV (outputs filled with
  * the last iterate) when max_iter is reached, ENONDEF if the projected pencil is not definite,
- * EUNSUPPORTED for direct without a dense build or above order 2048, EINVAL for nroot > n_pp
+ * EUNSUPPORTED for direct without a dense build or above order 8192, EINVAL for nroot > n_pp
  * (pp) or > n_hh (hh). */
 pprpa_status pprpa_davidson(pprpa_ctx* ctx, const pprpa_davidson_args* args, double* omega,
                             double* vecs, double* resid, pprpa_report* rep);

@@ -736,8 +736,8 @@ pprpa_status corr_energy_run(pprpa_ctx* c, double* work, pprpa_corr_energy* out)
   double* dout = work + 3 * (size_t)n * n;  // 4 doubles, then 3 ints
   int* dinfo = (int*)(dout + 4);
   double* hp = c->pinned;
-  // one workgroup up to order 512 (also the no-allocation entry point's limit), many above
-  hipError_t le = n <= 512 ? launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, work, dinfo, c->stream)
+  // one workgroup up to order 96, many above (the no-allocation entry point goes to 512)
+  hipError_t le = n <= DENSE_ONE_WG_MAX ? launch_pencil_energy(c->M, (int)n, nvv, c->mu2, dout, work, dinfo, c->stream)
                            : launch_pencil_energy_mw(c->M, (int)n, nvv, c->mu2, dout, work, dinfo,
                                                      c->stream);
   if (le == hipSuccess) le = hipMemcpyAsync(hp, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);

@@ -495,17 +495,18 @@ pprpa_status Solver::run_direct() {
     return PPRPA_EUNSUPPORTED;
   }
   const int m = (int)n;
-  PPRPA_TRY(get_ws(c_, m, nroot_, 1, std::max((size_t)4 * m * m, (size_t)3 * m * m + 4 * 64 * m),
+  PPRPA_TRY(get_ws(c_, m, nroot_, 1,
+                   std::max({(size_t)4 * m * m, (size_t)3 * m * m + 4 * 64 * m,
+                             direct_pencil_mw_work(m, nroot_)}),
                    (size_t)nroot_ * 64, &w));
   double* hp = c_->pinned;
   PPRPA_HIP(launch_metric_matrix(w.Ws_, n, nvv, s));
-  if (m <= 96)  // W as a dense matrix: the Davidson pencil solver on the whole problem
+  if (m <= DENSE_ONE_WG_MAX)  // W as a dense matrix: the Davidson pencil solver on the whole problem
     PPRPA_HIP(launch_pencil(c_->M, w.Ws_, m, m, c_->mu2, nroot_, nroot_, a_.channel, w.omega,
                             w.Cc, nroot_, w.pwork, w.info, s));
-  else  // W diagonal exploited
-
-    PPRPA_HIP(launch_direct_pencil(c_->M, m, nvv, c_->mu2, nroot_, a_.channel, w.omega, w.Cc,
-                                   nroot_, w.pwork, w.info, s));
+  else  // W diagonal, many workgroups
+    PPRPA_HIP(launch_direct_pencil_mw(c_->M, m, nvv, c_->mu2, nroot_, a_.channel, w.omega, w.Cc,
+                                      nroot_, w.pwork, w.info, s));
   PPRPA_HIP(launch_transpose(w.Cc, nroot_, m, nroot_, w.Z, n, s));
   PPRPA_HIP(launch_combine(c_->M, n, m, w.Cc, nroot_, nroot_, n, 1.0, 0.0, w.SZ, n, s));
   PPRPA_HIP(launch_residual(w.Z, w.SZ, n, nroot_, n, nvv, w.omega, w.R, w.part, 64, s));

@@ -84,11 +84,12 @@ inline int panel_width(int variant) { return variant == 7 ? 8 : 4; }
 constexpr int UNITS_F64 = 16384;      // work units per launch of the pipelined FP64 kernel
 constexpr int F64_PIPE_MIN_NVT = 20;  // virtual 16-tiles from which FP64 sigma uses that kernel
 constexpr int BF16_WIDE_MIN_NVT = 32;  // the same for the wide-panel BF16x6 kernel
-// Largest order of the dense pencil solves on the device: the direct diagonalisation (one
-// workgroup) and the whole-spectrum solve of the correlation energy (one workgroup up to 512,
-// many above).
-constexpr int DENSE_SOLVE_MAX = 2048;
+// Largest order of the dense pencil solves on the device (the direct diagonalisation and the
+// whole-spectrum solve of the correlation energy), and the largest order solved by one
+// workgroup (many workgroups above).
+constexpr int DENSE_SOLVE_MAX = 8192;
 constexpr int DENSE_ENERGY_MAX = 8192;
+constexpr int DENSE_ONE_WG_MAX = 96;
 int sigma_variant(const Geometry& g, Store st, int nprod, int* RT);
 
 // --- kernel launchers (k_sigma.hip) -------------------------------------------------------
@@ -191,15 +192,8 @@ hipError_t launch_precond(const double* R, int64_t ld, const int* h_sel, int nse
 hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, double mu2,
                          int nroot, int nret, int channel, double* omega, double* Cout, int ldc,
                          double* work, int* info, hipStream_t s);
-// Direct solve of the dense pencil (M, W), W = diag(+1 for i < nvv, -1), for 96 < m <=
-// DENSE_SOLVE_MAX:
-// the same outputs as launch_pencil (nret = nroot), W diagonal. work: 3 m^2 + 4 nroot m doubles.
-hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
-                                int channel, double* omega, double* Cout, int ldc, double* work,
-                                int* info, hipStream_t s);
-// Whole spectrum of the dense pencil (M, W) for m <= DENSE_SOLVE_MAX (eigenvalues only): out[0] =
-// sum of the
-// pp roots - Tr A, out[1] = -(sum of the hh roots) - Tr C, out[2] = Tr A, out[3] = Tr C;
+// Whole spectrum of the dense pencil (M, W) for m <= DENSE_ONE_WG_MAX (eigenvalues only): out[0] =
+// sum of the pp roots - Tr A, out[1] = -(sum of the hh roots) - Tr C, out[2] = Tr A, out[3] = Tr C;
 // info: [0] 0 ok / 1 not definite, [1] pp roots, [2] hh roots. work: 3 m^2 doubles.
 hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2, double* out,
                                 double* work, int* info, hipStream_t s);
@@ -208,6 +202,15 @@ hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2,
 // work: pencil_energy_mw_work(m) doubles.
 size_t pencil_energy_mw_work(int n);
 hipError_t launch_pencil_energy_mw(const double* M, int m, int64_t nvv, double mu2, double* out,
+                                   double* work, int* info, hipStream_t s);
+// Direct solve of the dense pencil (M, W), W = diag(+1 for i < nvv, -1), for 3 <= m <=
+// DENSE_SOLVE_MAX on many workgroups (the chain of launch_pencil_energy_mw keeping its
+// reflections, multisection for the wanted eigenvalues, inverse iteration, back-transformation,
+// L^T z = u): the outputs of launch_pencil (nret = nroot). work: direct_pencil_mw_work(m, nroot)
+// doubles.
+size_t direct_pencil_mw_work(int n, int nroot);
+hipError_t launch_direct_pencil_mw(const double* M, int m, int64_t nvv, double mu2, int nroot,
+                                   int channel, double* omega, double* Cout, int ldc,
                                    double* work, int* info, hipStream_t s);
 // NTO weights and two-electron density blocks of k packed roots Z [k][ldz] (nv, no <= 512):
 // X [k][nv][nv], Y [k][no][no] (triangular amplitude matrices), Gx, Gy (their T^T T, destroyed),

@@ -17,6 +17,16 @@
 //      order);
 //   5. every eigenvalue of the tridiagonal form by Sturm-count bisection (a thread per
 //      eigenvalue), and the sums of the sum rule in a fixed order.
+// The direct solve for the wanted roots (Eq. eigen_equation with the normalisation of Eq.
+// xy_norm) runs steps 1-4 keeping the reflection vectors, then
+//   5'. the wanted eigenvalues only: the Sturm count at 0 gives the number of hh roots, and
+//      multisection (a workgroup per root, 256 Sturm counts per round) the j-th eigenvalue above
+//      (pp) or below (hh) 0;
+//   6. their eigenvectors u of the tridiagonal form by inverse iteration (a thread per root),
+//      orthonormalised among nearly equal eigenvalues;
+//   7. per root (a workgroup each, the vector in LDS): the reflections applied to u, then
+//      L^T z = u by blocked back substitution and z scaled by sqrt|lambda|, so that
+//      z^T W z = |lambda| u^T S^-1 u = sign(lambda) (S^-1 = L^-1 W L^-T).
 // Every reduction runs in a fixed order: the result is bitwise repeatable.
 #include "internal.h"
 
@@ -209,7 +219,8 @@ __global__ __launch_bounds__(1024) void k_mw_hh_vec(const double* __restrict__ S
                                                     double* __restrict__ v,
                                                     double* __restrict__ scal,
                                                     double* __restrict__ d,
-                                                    double* __restrict__ e) {
+                                                    double* __restrict__ e,
+                                                    double* __restrict__ beta_keep) {
   __shared__ double red[16];
   const int m = n - k - 1;
   const double* x = S + (int64_t)k * n + k + 1;
@@ -223,7 +234,9 @@ __global__ __launch_bounds__(1024) void k_mw_hh_vec(const double* __restrict__ S
   const double vtv = nrm2 - x0 * x0 + v0 * v0;
   for (int i = threadIdx.x; i < m; i += 1024) v[i] = i == 0 ? v0 : x[i];
   if (threadIdx.x == 0) {
-    scal[0] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    scal[0] = beta;
+    if (beta_keep) beta_keep[k] = beta;
     d[k] = S[(int64_t)k * n + k];
     e[k] = alpha;
   }
@@ -245,12 +258,14 @@ __global__ __launch_bounds__(256) void k_mw_hh_matvec(const double* __restrict__
 }
 
 // S2 -= v w^T + w v^T, w = p - (beta p^T v / 2) v: a wave per row; every workgroup forms p^T v
-// itself in the same fixed order.
+// itself in the same fixed order. keep: row k right of the diagonal becomes the reflection vector
+// (only its first entry differs from x; no kernel of this step reads row k).
 __global__ __launch_bounds__(256) void k_mw_hh_update(double* __restrict__ S, int n, int k,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ scal,
-                                                      const double* __restrict__ p) {
+                                                      const double* __restrict__ p, int keep) {
   __shared__ double red[4];
+  if (keep && blockIdx.x == 0 && threadIdx.x == 0) S[(int64_t)k * n + k + 1] = v[0];
   const int m = n - k - 1;
   double s = 0.0;
   for (int i = threadIdx.x; i < m; i += 256) s += p[i] * v[i];
@@ -369,6 +384,250 @@ __global__ __launch_bounds__(1024) void k_mw_sums(const double* __restrict__ M, 
   }
 }
 
+// Number of eigenvalues of T below 0 (the hh roots) -> cnt[0].
+__global__ void k_mw_count(const double* __restrict__ d, const double* __restrict__ e, int n,
+                           const double* __restrict__ bnd, int* __restrict__ cnt) {
+  if (threadIdx.x != 0) return;
+  const double tiny = 1e-300 + 2.2e-16 * bnd[2] * 1e-8;
+  cnt[0] = mw_sturm_below(d, e, n, 0.0, tiny);
+}
+
+// Ascending index of wanted root j: pp (channel 0) the j-th eigenvalue above 0, hh the j-th below
+// 0; -1 when the channel has no such root.
+__device__ __forceinline__ int mw_wanted(int j, int nbelow, int n, int channel) {
+  const int idx = channel == 0 ? nbelow + j : nbelow - 1 - j;
+  return idx >= 0 && idx < n ? idx : -1;
+}
+
+// Wanted eigenvalue j of T (a workgroup each): per round the 256 threads take the Sturm count at
+// 256 evenly spaced interior points of the bracket, which shrinks to the two neighbouring points
+// that enclose the root's index, until its width is at the rounding level. lam[j] = 0 for a root
+// the channel does not have.
+__global__ __launch_bounds__(256) void k_mw_select(const double* __restrict__ d,
+                                                   const double* __restrict__ e, int n,
+                                                   const double* __restrict__ bnd,
+                                                   const int* __restrict__ cnt, int channel,
+                                                   const int* __restrict__ flag,
+                                                   double* __restrict__ lam) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int idx = mw_wanted(j, cnt[0], n, channel);
+  if (flag[0] || idx < 0) {
+    if (t == 0) lam[j] = 0.0;
+    return;
+  }
+  const double tnorm = bnd[2];
+  const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
+  double lo = bnd[0] - 1e-12 * tnorm, hi = bnd[1] + 1e-12 * tnorm;
+  for (int round = 0; round < 64; ++round) {
+    if (!(hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny)) break;
+    const double x = lo + (hi - lo) * ((double)(t + 1) / 257.0);
+    double xl = -1e300, xh = 1e300;
+    if (x > lo && x < hi) {
+      if (mw_sturm_below(d, e, n, x, tiny) <= idx)
+        xl = x;
+      else
+        xh = x;
+    }
+    const double nlo = fmax(lo, wg_max(xl, red));
+    const double nhi = fmin(hi, wg_min(xh, red));
+    if (nlo > nhi || (nlo == lo && nhi == hi)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (t == 0) lam[j] = 0.5 * (lo + hi);
+}
+
+// Eigenvector of T at lam[j] by inverse iteration (thread j): three solves of (T - lam I) y = b
+// by Gaussian elimination with partial pivoting (the fill-in on a second superdiagonal), y
+// normalised after each; the start vector a fixed pseudo-random sequence per root. Y [nsel][n]
+// (zero for a root the channel does not have); U [nsel][3][n] elimination scratch.
+__global__ __launch_bounds__(64) void k_mw_inviter(const double* __restrict__ d,
+                                                   const double* __restrict__ e, int n,
+                                                   const double* __restrict__ bnd,
+                                                   const int* __restrict__ cnt, int channel,
+                                                   const int* __restrict__ flag,
+                                                   const double* __restrict__ lam, int nsel,
+                                                   double* __restrict__ Y,
+                                                   double* __restrict__ U) {
+  const int j = threadIdx.x;
+  if (j >= nsel) return;
+  double* y = Y + (size_t)j * n;
+  if (flag[0] || mw_wanted(j, cnt[0], n, channel) < 0) {
+    for (int i = 0; i < n; ++i) y[i] = 0.0;
+    return;
+  }
+  double* U0 = U + (size_t)j * 3 * n;
+  double* U1 = U0 + n;
+  double* U2 = U1 + n;
+  const double th = lam[j];
+  const double pert = 2.2e-16 * bnd[2];
+  unsigned long long h = 0xD1B54A32D192ED03ull * (unsigned long long)(j + 1);
+  for (int i = 0; i < n; ++i) {
+    h ^= h >> 31;
+    h *= 0x9FB21C651E98DF25ull;
+    h ^= h >> 29;
+    y[i] = 0.5 + (double)(h >> 11) * (1.0 / 9007199254740992.0);
+  }
+  for (int pass = 0; pass < 3; ++pass) {
+    // forward elimination: row i holds (a_d, a_u, a_u2 | rhs) after the pivots above it
+    double a_d = d[0] - th, a_u = n > 1 ? e[0] : 0.0, a_u2 = 0.0, rhs = y[0];
+    for (int i = 0; i + 1 < n; ++i) {
+      const double b_l = e[i], b_d = d[i + 1] - th, b_u = i + 2 < n ? e[i + 1] : 0.0;
+      const double rb = y[i + 1];
+      if (fabs(a_d) >= fabs(b_l)) {
+        const double piv = fabs(a_d) < pert ? (a_d < 0.0 ? -pert : pert) : a_d;
+        const double l = b_l / piv;
+        U0[i] = piv;
+        U1[i] = a_u;
+        U2[i] = a_u2;
+        y[i] = rhs;
+        a_d = b_d - l * a_u;
+        a_u = b_u - l * a_u2;
+        a_u2 = 0.0;
+        rhs = rb - l * rhs;
+      } else {  // rows i and i + 1 exchanged
+        const double l = a_d / b_l;
+        U0[i] = b_l;
+        U1[i] = b_d;
+        U2[i] = b_u;
+        y[i] = rb;
+        a_d = a_u - l * b_d;
+        a_u = a_u2 - l * b_u;
+        a_u2 = 0.0;
+        rhs = rhs - l * rb;
+      }
+    }
+    if (fabs(a_d) < pert) a_d = a_d < 0.0 ? -pert : pert;
+    U0[n - 1] = a_d;
+    U1[n - 1] = 0.0;
+    U2[n - 1] = 0.0;
+    y[n - 1] = rhs;
+    double y1 = 0.0, y2 = 0.0, nrm2 = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double v = (y[i] - U1[i] * y1 - U2[i] * y2) / U0[i];
+      y[i] = v;
+      y2 = y1;
+      y1 = v;
+      nrm2 += v * v;
+    }
+    const double inv = 1.0 / sqrt(nrm2);
+    for (int i = 0; i < n; ++i) y[i] *= inv;
+  }
+}
+
+// Vectors of nearly equal eigenvalues (|lam_i - lam_j| <= 1e-7 |T|) orthonormalised in order
+// (modified Gram-Schmidt; one workgroup). Only roots the channel has take part.
+__global__ __launch_bounds__(1024) void k_mw_orth(int n, const double* __restrict__ bnd,
+                                                  const int* __restrict__ cnt, int channel,
+                                                  const int* __restrict__ flag,
+                                                  const double* __restrict__ lam, int nsel,
+                                                  double* __restrict__ Y) {
+  __shared__ double red[16];
+  if (flag[0]) return;
+  const double tol = 1e-7 * bnd[2];
+  for (int j = 1; j < nsel; ++j) {
+    if (mw_wanted(j, cnt[0], n, channel) < 0) break;
+    double* yj = Y + (size_t)j * n;
+    for (int i = 0; i < j; ++i) {
+      if (fabs(lam[i] - lam[j]) > tol) continue;
+      const double* yi = Y + (size_t)i * n;
+      double s = 0.0;
+      for (int r = threadIdx.x; r < n; r += 1024) s += yi[r] * yj[r];
+      const double dot = wg_sum(s, red);
+      double s2 = 0.0;
+      for (int r = threadIdx.x; r < n; r += 1024) {
+        const double v = yj[r] - dot * yi[r];
+        yj[r] = v;
+        s2 += v * v;
+      }
+      const double inv = 1.0 / sqrt(wg_sum(s2, red));
+      for (int r = threadIdx.x; r < n; r += 1024) yj[r] *= inv;
+      __syncthreads();
+    }
+  }
+}
+
+// Root j (a workgroup each; the vector in LDS, element r owned by thread r mod 256): u = H_0 H_1
+// ... H_{n-3} y (reflection k kept in row k of S right of the diagonal, beta[k]), then L^T z = u
+// by back substitution in 32-row blocks (the block's triangle within one wave, the rows above it
+// updated by all threads), z scaled by sqrt|lambda| into column j of Cout [n][ldc]. omega[j] =
+// mu2 + lambda_j; a root the channel does not have gets omega 0 and a zero column. info (block 0):
+// [0] 0 ok / 1 not definite / 2 fewer than nroot roots, [1] roots of the channel, [2] 0.
+__global__ __launch_bounds__(256) void k_mw_vectors(const double* __restrict__ K,
+                                                    const double* __restrict__ S,
+                                                    const double* __restrict__ beta, int n,
+                                                    const int* __restrict__ cnt, int channel,
+                                                    const int* __restrict__ flag,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ Y, double mu2,
+                                                    double* __restrict__ omega,
+                                                    double* __restrict__ Cout, int ldc,
+                                                    int* __restrict__ info) {
+  __shared__ double y[DENSE_SOLVE_MAX];
+  __shared__ double red[2][4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int bad = flag[0];
+  const int nb = cnt[0];
+  const int npos = bad ? 0 : (channel == 0 ? n - nb : nb);
+  if (j == 0 && t == 0) {
+    info[0] = bad ? 1 : (npos < (int)gridDim.x ? 2 : 0);
+    info[1] = npos;
+    info[2] = 0;
+  }
+  if (bad || j >= npos) {
+    if (t == 0) omega[j] = 0.0;
+    for (int r = t; r < n; r += 256) Cout[(size_t)r * ldc + j] = 0.0;
+    return;
+  }
+  const double lj = lam[j];
+  if (t == 0) omega[j] = mu2 + lj;
+  for (int r = t; r < n; r += 256) y[r] = Y[(size_t)j * n + r];
+  // reflections, last first; each thread updates only the elements it owns, so one barrier
+  // (inside the reduction, its partials alternating between two buffers) per reflection
+  int ph = 0;
+  for (int k = n - 3; k >= 0; --k) {
+    const double b = beta[k];
+    if (b == 0.0) continue;
+    const double* vk = S + (size_t)k * n;  // v_k[r - k - 1] = vk[r], r > k
+    const int r0 = k + 1 + ((t - (k + 1)) % 256 + 256) % 256;
+    double s = 0.0;
+    for (int r = r0; r < n; r += 256) s += vk[r] * y[r];
+    s = wave_sum(s);
+    double* rb = red[ph];
+    ph ^= 1;
+    if ((t & 63) == 0) rb[t >> 6] = s;
+    __syncthreads();
+    const double bs = b * (rb[0] + rb[1] + rb[2] + rb[3]);
+    for (int r = r0; r < n; r += 256) y[r] -= bs * vk[r];
+  }
+  __syncthreads();
+  // L^T z = u, blocks of 32 rows from the last
+  for (int j0 = ((n - 1) / CB) * CB; j0 >= 0; j0 -= CB) {
+    const int jb = min(CB, n - j0);
+    if (t < 64) {
+      const int l = t;
+      double r = l < jb ? y[j0 + l] : 0.0;
+      for (int jj = jb - 1; jj >= 0; --jj) {
+        const double z = l == jj ? r / K[(size_t)(j0 + jj) * n + j0 + jj] : 0.0;
+        const double zj = __shfl(z, jj, 64);
+        if (l == jj) r = zj;
+        if (l < jj) r -= K[(size_t)(j0 + jj) * n + j0 + l] * zj;
+      }
+      if (l < jb) y[j0 + l] = r;
+    }
+    __syncthreads();
+    for (int r = t; r < j0; r += 256) {
+      double acc = 0.0;
+      for (int jj = 0; jj < jb; ++jj) acc += K[(size_t)(j0 + jj) * n + r] * y[j0 + jj];
+      y[r] -= acc;
+    }
+    __syncthreads();
+  }
+  const double sc = sqrt(fabs(lj));
+  for (int r = t; r < n; r += 256) Cout[(size_t)r * ldc + j] = y[r] * sc;
+}
+
 }  // namespace
 
 size_t pencil_energy_mw_work(int n) { return 2 * (size_t)n * n + 5 * (size_t)n + 8; }
@@ -402,13 +661,73 @@ hipError_t launch_pencil_energy_mw(const double* M, int n, int64_t nvv, double m
   hipLaunchKernelGGL(k_mw_sym, dim3(ntile * (ntile + 1) / 2), dim3(256), 0, s, K, n, nvv, S);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
-    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, k, v, scal, d, e);
+    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, k, v, scal, d, e,
+                       (double*)nullptr);
     hipLaunchKernelGGL(k_mw_hh_matvec, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
-    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
+    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p,
+                       0);
   }
   hipLaunchKernelGGL(k_mw_bounds, dim3(1), dim3(1024), 0, s, S, n, d, e, scal + 1);
   hipLaunchKernelGGL(k_mw_bisect, dim3((n + 255) / 256), dim3(256), 0, s, d, e, n, scal + 1, lam);
   hipLaunchKernelGGL(k_mw_sums, dim3(1), dim3(1024), 0, s, M, n, nvv, mu2, lam, flag, out, info);
+  return hipGetLastError();
+}
+
+size_t direct_pencil_mw_work(int n, int nroot) {
+  return 2 * (size_t)n * n + 5 * (size_t)n + 4 * (size_t)nroot * n + 64 + 8 + 8;
+}
+
+hipError_t launch_direct_pencil_mw(const double* M, int n, int64_t nvv, double mu2, int nroot,
+                                   int channel, double* omega, double* Cout, int ldc,
+                                   double* work, int* info, hipStream_t s) {
+  if (n < 3 || n > DENSE_SOLVE_MAX || nroot < 1 || nroot > 64 || nroot > n || ldc < nroot ||
+      (channel != 0 && channel != 1))
+    return hipErrorInvalidValue;
+  const size_t nn = (size_t)n * n;
+  double* K = work;
+  double* S = K + nn;
+  double* v = S + nn;
+  double* p = v + n;
+  double* d = p + n;
+  double* e = d + n;
+  double* beta = e + n;
+  double* Y = beta + n;
+  double* U = Y + (size_t)nroot * n;
+  double* lam = U + 3 * (size_t)nroot * n;  // 64
+  double* scal = lam + 64;                  // [0] beta of the current step, [1 .. 3] bounds
+  int* cnt = (int*)(scal + 8);  // [0] eigenvalues below 0
+  int* flag = cnt + 1;          // K not positive definite
+  hipLaunchKernelGGL(k_mw_init, dim3(1), dim3(64), 0, s, flag);
+  hipLaunchKernelGGL(k_mw_shift, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, M, n, nvv,
+                     mu2, K);
+  for (int j0 = 0; j0 < n; j0 += CB) {
+    hipLaunchKernelGGL(k_mw_chol_diag, dim3(1), dim3(256), 0, s, K, n, j0, flag);
+    const int rest = n - j0 - CB;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_mw_chol_trsm, dim3((rest + 255) / 256), dim3(256), 0, s, K, n, j0);
+      const int nt = (rest + CB - 1) / CB;
+      hipLaunchKernelGGL(k_mw_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, K, n, j0);
+    }
+  }
+  const int ntile = (n + CB - 1) / CB;
+  hipLaunchKernelGGL(k_mw_sym, dim3(ntile * (ntile + 1) / 2), dim3(256), 0, s, K, n, nvv, S);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, k, v, scal, d, e, beta);
+    hipLaunchKernelGGL(k_mw_hh_matvec, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
+    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p,
+                       1);
+  }
+  hipLaunchKernelGGL(k_mw_bounds, dim3(1), dim3(1024), 0, s, S, n, d, e, scal + 1);
+  hipLaunchKernelGGL(k_mw_count, dim3(1), dim3(64), 0, s, d, e, n, scal + 1, cnt);
+  hipLaunchKernelGGL(k_mw_select, dim3(nroot), dim3(256), 0, s, d, e, n, scal + 1, cnt, channel,
+                     flag, lam);
+  hipLaunchKernelGGL(k_mw_inviter, dim3(1), dim3(64), 0, s, d, e, n, scal + 1, cnt, channel, flag,
+                     lam, nroot, Y, U);
+  hipLaunchKernelGGL(k_mw_orth, dim3(1), dim3(1024), 0, s, n, scal + 1, cnt, channel, flag, lam,
+                     nroot, Y);
+  hipLaunchKernelGGL(k_mw_vectors, dim3(nroot), dim3(256), 0, s, K, S, beta, n, cnt, channel, flag,
+                     lam, Y, mu2, omega, Cout, ldc, info);
   return hipGetLastError();
 }
 

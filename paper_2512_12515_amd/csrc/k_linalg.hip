@@ -361,7 +361,7 @@ __global__ void k_fill(double* __restrict__ p, size_t n, double v) {
 // ------------------------------------------------------------------------------------------
 constexpr int WG = 1024;
 constexpr int JMAX = 512;   // largest matrix order of the one-workgroup Davidson-side solvers
-constexpr int DMAX = DENSE_SOLVE_MAX;  // largest order of the dense pencil solves (direct, E_c)
+constexpr int DMAX = DENSE_ONE_WG_MAX;  // largest order of the one-workgroup dense pencil solves
 
 // Workgroup-wide sum / min / max (every thread calls it; every thread gets the result): a
 // butterfly within each wave, then the WG / 64 wave results in a fixed order (deterministic).
@@ -488,9 +488,10 @@ constexpr int PLDS = 96;
 // bisection on Sturm counts of T (the count at 0 gives the number of pp roots), their vectors by
 // inverse iteration on T (vectors of nearly equal theta orthonormalised against each other),
 // back-transformed by the reflections; c = R^-T u / sqrt(theta), so that c^T W c = +1.
-// Two kernels use these steps: k_direct_pencil (the dense direct path, W = diag(+-1), matrices
-// in global memory, n up to DMAX) and k_pencil_tri (the Davidson pencils, m <= 96, matrices in
-// LDS, W the projected metric).
+// Two kernels use these steps: k_pencil_energy (the whole spectrum of the small dense pencils,
+// W = diag(+-1), matrices in global memory, n up to DMAX; eigenvalues only) and k_pencil_tri
+// (the Davidson pencils and the direct path up to order 96, matrices in LDS, W the projected
+// metric).
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ int sturm_below(const double* d, const double* e2, int m, double x,
                                            double tiny) {
@@ -909,34 +910,6 @@ __device__ __forceinline__ bool dense_pencil_tridiag(const double* __restrict__ 
   __syncthreads();
   tri_householder(G, m, d, e, beta, vv, pq, red);
   return true;
-}
-
-// Direct path: M (n x n, full, ld m), W = diag(+1 for i < nvv, -1). work: 3 m^2 + 4 nroot m.
-__global__ __launch_bounds__(WG) void k_direct_pencil(const double* __restrict__ M, int m,
-                                                      int64_t nvv, double mu2, int nroot,
-                                                      int channel, double* __restrict__ omega,
-                                                      double* __restrict__ Cout, int ldc,
-                                                      double* __restrict__ work,
-                                                      int* __restrict__ info) {
-  __shared__ double red[WG];
-  __shared__ double d[DMAX], e[DMAX], e2[DMAX], beta[DMAX], vv[DMAX], pq[DMAX];
-  __shared__ double theta[64];
-  __shared__ int flag, npos_s;
-  double* A = work;                        // K, then R (lower)
-  double* Ri = work + (size_t)m * m;       // R^-1 (lower)
-  double* G = work + 2 * (size_t)m * m;    // G, then the reflection vectors
-  double* X = work + 3 * (size_t)m * m;    // vectors and inverse-iteration scratch
-  if (!dense_pencil_tridiag(M, m, nvv, mu2, A, Ri, G, d, e, beta, vv, pq, red, &flag)) {
-    if (threadIdx.x == 0) {
-      info[0] = 1;
-      info[1] = 0;
-      info[2] = 0;
-    }
-    return;
-  }
-  tri_eigen(d, e, e2, m, nroot, channel, theta, &npos_s, X, red, vv, pq, nullptr);
-  tri_back_transform(G, m, beta, X, nroot);
-  tri_outputs(Ri, X, theta, m, nroot, nroot, npos_s, mu2, omega, Cout, ldc, info);
 }
 
 // Correlation energy from the whole spectrum of the dense pencil (section "Total Energy", Eq.
@@ -1378,16 +1351,6 @@ hipError_t launch_pencil(const double* Ms, const double* Ws, int ldm, int m, dou
   else
     hipLaunchKernelGGL(k_pencil_tri_l2, dim3(1), dim3(WG), 0, s, Ms, Ws, ldm, m, mu2, nroot, nret,
                        channel, omega, Cout, ldc, work, info);
-  return hipGetLastError();
-}
-
-hipError_t launch_direct_pencil(const double* M, int m, int64_t nvv, double mu2, int nroot,
-                                int channel, double* omega, double* Cout, int ldc, double* work,
-                                int* info, hipStream_t s) {
-  if (m > DMAX || nroot > 64 || nroot > m || (channel != 0 && channel != 1))
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_direct_pencil, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, nroot, channel,
-                     omega, Cout, ldc, work, info);
   return hipGetLastError();
 }
 

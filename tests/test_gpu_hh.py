@@ -90,9 +90,10 @@ def test_hh_active_window(mult):
 
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
-@pytest.mark.parametrize("case", [(4, 9, 30), (9, 20, 60)])
+@pytest.mark.parametrize("case", [(4, 9, 30), (9, 20, 60), (8, 45, 150)])
 def test_hh_direct_vs_oracle(mult, case):
-    """(4, 9, 30): n <= 96 (pencil in LDS); (9, 20, 60): 96 < n <= 512 (dense direct pencil)."""
+    """(4, 9, 30): n <= 96 (pencil in LDS); (9, 20, 60) and (8, 45, 150): n = 255 / 226 and
+    1071 / 1018 (the dense direct pencil on many workgroups)."""
     nocc, nvir, naux = case
     note("hh direct", mult, case)
     eps, L = problem(45, nocc, nvir, naux)

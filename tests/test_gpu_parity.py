@@ -232,10 +232,11 @@ def test_direct_small(mult, seed):
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case,nroot", [((8, 30, 60), 8), ((6, 14, 40), 5), ((2, 13, 30), 3),
-                                        ((8, 45, 150), 6)])
+                                        ((8, 45, 150), 6), ((8, 62, 150), 6), ((8, 72, 120), 4)])
 def test_direct_orders(mult, case, nroot):
-    """The direct dense path at orders from below the 96 of the LDS-resident solver to above 1000
-    (n = 501 / 463 for 8 x 30, 1071 / 1018 for 8 x 45): eigenvalues, residuals, normalisation."""
+    """The direct dense path at orders from below the 96 of the LDS-resident solver (n = 94 / 79
+    for 2 x 13) to the many-workgroup one above it (501 / 463 for 8 x 30, 1071 / 1018 for 8 x 45,
+    1989 / 1919 for 8 x 62, 2664 / 2584 for 8 x 72): eigenvalues, residuals, normalisation."""
     nocc, nvir, naux = case
     note("direct orders", mult, case)
     eps, L = problem(21, nocc, nvir, naux)
@@ -315,12 +316,15 @@ def test_failure_paths():
     assert e.value.status == P.binding.EINVAL
 
 
-def test_non_definite_is_reported():
+@pytest.mark.parametrize("case", [(4, 10, 30), (8, 30, 60), (8, 45, 150)])
+def test_non_definite_is_reported(case):
     """Interactions scaled far beyond the orbital gap make M - 2 mu W indefinite: the dense
-    path must report ENONDEF, never return silently."""
-    note("non-definite")
-    eps, L = problem(19, 4, 10, 30)
-    with P.PpRPA(eps, L * 30.0, 4, dense=True) as ctx:
+    path must report ENONDEF, never return silently (order 65: the LDS-resident solver; 501
+    and 1071: the many-workgroup one)."""
+    nocc, nvir, naux = case
+    note("non-definite", case)
+    eps, L = problem(19, nocc, nvir, naux)
+    with P.PpRPA(eps, L * 30.0, nocc, dense=True) as ctx:
         with pytest.raises(P.PpRPAError) as e:
             ctx.davidson(3, direct=True)
     assert e.value.status == P.binding.ENONDEF
