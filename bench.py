@@ -369,6 +369,37 @@ def correlation_energy(P, gen, reps=10):
             "max_err_ha_vs_oracle": max(errs), "max_sum_rule_gap_ha": max(gaps)}
 
 
+def dense_large(P, gen, cases=((8, 45, 150), (8, 62, 150)), nroot=5, reps=3):
+    """The dense pencil solves on many workgroups: for each (nocc, nvir, naux), singlet (orders
+    1071 and 1989 by default), the direct solve of the nroot lowest pp roots with vectors and the
+    correlation energy from the whole spectrum, inputs resident on the device; median time of
+    reps calls after one untimed call, the largest residual |M z - Omega W z| of the roots and
+    the gap between the two sides of the energy's sum rule (both exact relations, so no stored
+    values are needed)."""
+    out = []
+    for nocc, nvir, naux in cases:
+        eps, L = gen.orbital_energies(54, nocc, nvir), gen.lpq_full(54, nocc + nvir, naux)
+        with P.PpRPA(eps, L, nocc, mult="singlet", dense=True) as ctx:
+            ctx.davidson(nroot, direct=True)
+            ctx.correlation_energy()
+            td, te = [], []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                r = ctx.davidson(nroot, direct=True, vectors=True)
+                td.append(time.perf_counter() - t0)
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                e = ctx.correlation_energy()
+                te.append(time.perf_counter() - t0)
+            out.append({"nocc": nocc, "nvir": nvir, "naux": naux, "n": ctx.n,
+                        "direct_ms_p50": 1e3 * float(np.median(td)),
+                        "direct_max_resid": float(np.max(r["resid"])),
+                        "energy_ms_p50": 1e3 * float(np.median(te)),
+                        "energy_sum_rule_gap_ha": abs(e["ec_pp"] - e["ec_hh"])})
+    return {"workload": f"singlet, {nroot} pp roots with vectors (direct) and the whole spectrum "
+                        "(correlation energy), many-workgroup dense solver", "orders": out}
+
+
 def nto_analysis(P, eps_d, L_d, nocc, nroot, block, tol, reps=5):
     """NTO weights and two-electron density blocks of the nroot singlet pp roots of the FP64
     Davidson workload (vectors handed over from the host, density blocks copied back): time per
@@ -710,13 +741,15 @@ def main():
     ap.add_argument("--active-only", action="store_true",
                     help="run only the active-window workload in each precision")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="run only the dense solves at orders 1071 and 1989 (many workgroups)")
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="requests in the serving stream (default 512 with --serve-only, else 128)")
     ap.add_argument("--serve-prec", default="fp32",
                     help="sigma precision of the served solves (subspace algebra is FP64)")
     ap.add_argument("--no-extras", action="store_true",
                     help="no isolated sigma, 20/200/700, small direct, correlation energy, "
-                         "unrestricted, hh channel or NTO entries")
+                         "large dense, unrestricted, hh channel or NTO entries")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--serial", dest="concurrent", action="store_false",
@@ -744,6 +777,12 @@ def main():
     if args.serve_only:
         line = {"metric": "served ppRPA requests/s with p50/p99 latency", "n_gpus": 1, "data": data}
         line.update(serve_stream(P, gen, n_req=args.serve_requests or 512, prec=args.serve_prec))
+        print(json.dumps(line), flush=True)
+        return
+    if args.dense_only:
+        line = {"metric": "dense pencil solve time (direct roots and correlation energy)",
+                "n_gpus": 1, "data": data}
+        line.update(dense_large(P, gen))
         print(json.dumps(line), flush=True)
         return
     if args.copy_probe:
@@ -835,6 +874,7 @@ def main():
         log("small direct workload ...")
         line["small_direct"] = small_direct(P, gen)
         line["correlation_energy"] = correlation_energy(P, gen)
+        line["dense_large"] = dense_large(P, gen)
         line["unrestricted"] = unrestricted(P, gen)
     if not args.no_active:
         log("active-window study ...")

@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_mw_sym(const double* __restrict__ K, in
 
 // Householder step k: x = S[k][k+1 ..] (column k below the diagonal, read as row k), alpha =
 // -sign(x_0) |x|, v = x - alpha e_1, beta = 2 / v^T v (0 when x = 0); d[k] = S[k][k], e[k] = alpha.
+// Launched for the first step; the update kernel of step k forms the vector of step k + 1.
 __global__ __launch_bounds__(1024) void k_mw_hh_vec(const double* __restrict__ S, int n, int k,
                                                     double* __restrict__ v,
                                                     double* __restrict__ scal,
@@ -259,25 +260,55 @@ __global__ __launch_bounds__(256) void k_mw_hh_matvec(const double* __restrict__
 
 // S2 -= v w^T + w v^T, w = p - (beta p^T v / 2) v: a wave per row; every workgroup forms p^T v
 // itself in the same fixed order. keep: row k right of the diagonal becomes the reflection vector
-// (only its first entry differs from x; no kernel of this step reads row k).
+// (only its first entry differs from x; no kernel of this step reads row k). The wave of row
+// k + 1, the first row of S2, then forms the reflection of step k + 1 from the row it has just
+// updated (as k_mw_hh_vec does; its norm summed over the wave's lanes in a fixed order) into the
+// other buffer of v and beta: v_next, beta_next[0], d[k + 1], e[k + 1] (and beta_keep[k + 1]).
 __global__ __launch_bounds__(256) void k_mw_hh_update(double* __restrict__ S, int n, int k,
                                                       const double* __restrict__ v,
-                                                      const double* __restrict__ scal,
-                                                      const double* __restrict__ p, int keep) {
+                                                      const double* __restrict__ bet,
+                                                      const double* __restrict__ p, int keep,
+                                                      double* __restrict__ v_next,
+                                                      double* __restrict__ beta_next,
+                                                      double* __restrict__ d,
+                                                      double* __restrict__ e,
+                                                      double* __restrict__ beta_keep) {
   __shared__ double red[4];
   if (keep && blockIdx.x == 0 && threadIdx.x == 0) S[(int64_t)k * n + k + 1] = v[0];
   const int m = n - k - 1;
   double s = 0.0;
   for (int i = threadIdx.x; i < m; i += 256) s += p[i] * v[i];
   const double ptv = wg_sum(s, red);
-  const double kk = 0.5 * scal[0] * ptv;
+  const double kk = 0.5 * bet[0] * ptv;
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (r >= m) return;
   const double vr = v[r], wr = p[r] - kk * vr;
   double* row = S + (int64_t)(k + 1 + r) * n + k + 1;
+  const bool next = r == 0 && k + 3 < n;  // uniform over the wave
+  double ss = 0.0, x0 = 0.0, dg = 0.0;
   for (int j = lane; j < m; j += 64) {
     const double vj = v[j], wj = p[j] - kk * vj;
-    row[j] -= vr * wj + wr * vj;
+    const double nv = row[j] - (vr * wj + wr * vj);
+    row[j] = nv;
+    if (j == 0) dg = nv;
+    if (j == 1) x0 = nv;
+    if (j >= 1) ss += nv * nv;
+  }
+  if (!next) return;
+  const double nrm2 = wave_sum(ss);
+  x0 = __shfl(x0, 1, 64);
+  dg = __shfl(dg, 0, 64);
+  const double nrm = sqrt(nrm2);
+  const double alpha = nrm > 0.0 ? (x0 > 0.0 ? -nrm : nrm) : 0.0;
+  const double v0 = x0 - alpha;
+  const double vtv = nrm2 - x0 * x0 + v0 * v0;
+  for (int j = lane + (lane == 0 ? 64 : 0); j < m; j += 64) v_next[j - 1] = j == 1 ? v0 : row[j];
+  if (lane == 0) {
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    beta_next[0] = beta;
+    if (beta_keep) beta_keep[k + 1] = beta;
+    d[k + 1] = dg;
+    e[k + 1] = alpha;
   }
 }
 
@@ -324,25 +355,46 @@ __global__ __launch_bounds__(1024) void k_mw_bounds(const double* __restrict__ S
   }
 }
 
-// Eigenvalue idx (ascending) of T by bisection on Sturm counts, a thread per eigenvalue.
+// Eigenvalue idx (ascending) of T, 16 lanes each: per round the lanes take the Sturm count at 16
+// evenly spaced interior points of the bracket, which shrinks to the two neighbouring points that
+// enclose the index (reduced over the 16 lanes by shuffles), until its width is at the rounding
+// level. A wave runs until its four brackets are done.
 __global__ __launch_bounds__(256) void k_mw_bisect(const double* __restrict__ d,
                                                    const double* __restrict__ e, int n,
                                                    const double* __restrict__ bnd,
                                                    double* __restrict__ lam) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= n) return;
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int idx = gid >> 4, g = gid & 15;
   const double tnorm = bnd[2];
   const double tiny = 1e-300 + 2.2e-16 * tnorm * 1e-8;
   double lo = bnd[0] - 1e-12 * tnorm, hi = bnd[1] + 1e-12 * tnorm;
-  for (int it = 0; it < 200 && hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (mw_sturm_below(d, e, n, mid, tiny) <= idx)
-      lo = mid;
-    else
-      hi = mid;
+  bool done = idx >= n;
+  for (int round = 0; round < 64; ++round) {
+    if (!done) done = !(hi - lo > 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny);
+    if (__all(done)) break;
+    const double x = lo + (hi - lo) * ((double)(g + 1) / 17.0);
+    double xl = -1e300, xh = 1e300;
+    if (!done && x > lo && x < hi) {
+      if (mw_sturm_below(d, e, n, x, tiny) <= idx)
+        xl = x;
+      else
+        xh = x;
+    }
+    for (int off = 8; off > 0; off >>= 1) {
+      xl = fmax(xl, __shfl_xor(xl, off, 64));
+      xh = fmin(xh, __shfl_xor(xh, off, 64));
+    }
+    if (!done) {
+      const double nlo = fmax(lo, xl), nhi = fmin(hi, xh);
+      if (nlo > nhi || (nlo == lo && nhi == hi)) {
+        done = true;
+      } else {
+        lo = nlo;
+        hi = nhi;
+      }
+    }
   }
-  lam[idx] = 0.5 * (lo + hi);
+  if (idx < n && g == 0) lam[idx] = 0.5 * (lo + hi);
 }
 
 // out[0] = sum over lambda > 0 of (mu2 + lambda) - Tr A, out[1] = -(sum over lambda < 0 of
@@ -583,36 +635,66 @@ __global__ __launch_bounds__(256) void k_mw_vectors(const double* __restrict__ K
   const double lj = lam[j];
   if (t == 0) omega[j] = mu2 + lj;
   for (int r = t; r < n; r += 256) y[r] = Y[(size_t)j * n + r];
-  // reflections, last first; each thread updates only the elements it owns, so one barrier
-  // (inside the reduction, its partials alternating between two buffers) per reflection
+  // reflections, last first; each thread updates only the elements it owns (r = t + 256 q), so
+  // one barrier (inside the reduction, its partials alternating between two buffers) per
+  // reflection; the next reflection's entries are loaded into registers a step ahead
+  constexpr int NQ = DENSE_SOLVE_MAX / 256;
+  double vc[NQ], vn[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int r = t + 256 * q;
+    vc[q] = n >= 3 && r > n - 3 && r < n ? S[(size_t)(n - 3) * n + r] : 0.0;
+  }
   int ph = 0;
   for (int k = n - 3; k >= 0; --k) {
     const double b = beta[k];
-    if (b == 0.0) continue;
-    const double* vk = S + (size_t)k * n;  // v_k[r - k - 1] = vk[r], r > k
-    const int r0 = k + 1 + ((t - (k + 1)) % 256 + 256) % 256;
-    double s = 0.0;
-    for (int r = r0; r < n; r += 256) s += vk[r] * y[r];
-    s = wave_sum(s);
-    double* rb = red[ph];
-    ph ^= 1;
-    if ((t & 63) == 0) rb[t >> 6] = s;
-    __syncthreads();
-    const double bs = b * (rb[0] + rb[1] + rb[2] + rb[3]);
-    for (int r = r0; r < n; r += 256) y[r] -= bs * vk[r];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = t + 256 * q;
+      vn[q] = k >= 1 && r > k - 1 && r < n ? S[(size_t)(k - 1) * n + r] : 0.0;
+    }
+    if (b != 0.0) {  // uniform
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int r = t + 256 * q;
+        if (r > k && r < n) s += vc[q] * y[r];
+      }
+      s = wave_sum(s);
+      double* rb = red[ph];
+      ph ^= 1;
+      if ((t & 63) == 0) rb[t >> 6] = s;
+      __syncthreads();
+      const double bs = b * (rb[0] + rb[1] + rb[2] + rb[3]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int r = t + 256 * q;
+        if (r > k && r < n) y[r] -= bs * vc[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) vc[q] = vn[q];
   }
   __syncthreads();
-  // L^T z = u, blocks of 32 rows from the last
+  // L^T z = u, blocks of 32 rows from the last; lane l of wave 0 holds column l of the block's
+  // triangle in registers before the block's chain of shuffles
   for (int j0 = ((n - 1) / CB) * CB; j0 >= 0; j0 -= CB) {
     const int jb = min(CB, n - j0);
     if (t < 64) {
       const int l = t;
+      double lc[CB];
+#pragma unroll
+      for (int jj = 0; jj < CB; ++jj)
+        lc[jj] = jj < jb && l <= jj ? K[(size_t)(j0 + jj) * n + j0 + l] : 0.0;
       double r = l < jb ? y[j0 + l] : 0.0;
-      for (int jj = jb - 1; jj >= 0; --jj) {
-        const double z = l == jj ? r / K[(size_t)(j0 + jj) * n + j0 + jj] : 0.0;
-        const double zj = __shfl(z, jj, 64);
-        if (l == jj) r = zj;
-        if (l < jj) r -= K[(size_t)(j0 + jj) * n + j0 + l] * zj;
+#pragma unroll
+      for (int jj = CB - 1; jj >= 0; --jj) {
+        if (jj < jb) {  // uniform
+          const double z = l == jj ? r / lc[jj] : 0.0;
+          const double zj = __shfl(z, jj, 64);
+          if (l == jj) r = zj;
+          if (l < jj) r -= lc[jj] * zj;
+        }
       }
       if (l < jb) y[j0 + l] = r;
     }
@@ -630,21 +712,14 @@ __global__ __launch_bounds__(256) void k_mw_vectors(const double* __restrict__ K
 
 }  // namespace
 
-size_t pencil_energy_mw_work(int n) { return 2 * (size_t)n * n + 5 * (size_t)n + 8; }
-
-hipError_t launch_pencil_energy_mw(const double* M, int n, int64_t nvv, double mu2, double* out,
-                                   double* work, int* info, hipStream_t s) {
-  if (n < 2 || n > DENSE_ENERGY_MAX) return hipErrorInvalidValue;
+// Steps 1-4 (K, its Cholesky factor, S = L^T W L, the tridiagonal form (d, e) with the bounds
+// of its spectrum) on stream s. v2: 2 n (the reflection vectors of two steps), bsc: 5 doubles
+// ([0], [1] beta of even and odd steps, [2 .. 4] the bounds); beta_keep: n doubles or null (keep
+// the reflections in the rows of S); flag: zeroed, then set when K is not positive definite.
+static void mw_reduce(const double* M, int n, int64_t nvv, double mu2, double* K, double* S,
+                      double* v2, double* p, double* d, double* e, double* bsc,
+                      double* beta_keep, int* flag, hipStream_t s) {
   const size_t nn = (size_t)n * n;
-  double* K = work;
-  double* S = K + nn;
-  double* v = S + nn;
-  double* p = v + n;
-  double* d = p + n;
-  double* e = d + n;
-  double* lam = e + n;
-  double* scal = lam + n;  // [0] beta, [1 .. 3] Gershgorin bounds and norm
-  int* flag = info;        // info[0] doubles as the not-definite flag until the last kernel
   hipLaunchKernelGGL(k_mw_init, dim3(1), dim3(64), 0, s, flag);
   hipLaunchKernelGGL(k_mw_shift, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, M, n, nvv,
                      mu2, K);
@@ -659,22 +734,43 @@ hipError_t launch_pencil_energy_mw(const double* M, int n, int64_t nvv, double m
   }
   const int ntile = (n + CB - 1) / CB;
   hipLaunchKernelGGL(k_mw_sym, dim3(ntile * (ntile + 1) / 2), dim3(256), 0, s, K, n, nvv, S);
+  if (n > 2)
+    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, 0, v2, bsc, d, e, beta_keep);
   for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, k, v, scal, d, e,
-                       (double*)nullptr);
-    hipLaunchKernelGGL(k_mw_hh_matvec, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
-    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p,
-                       0);
+    const int m = n - k - 1, c = k & 1;
+    double* vk = v2 + (size_t)c * n;
+    double* vn = v2 + (size_t)(1 - c) * n;
+    hipLaunchKernelGGL(k_mw_hh_matvec, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, vk, bsc + c, p);
+    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, vk, bsc + c, p,
+                       beta_keep ? 1 : 0, vn, bsc + (1 - c), d, e, beta_keep);
   }
-  hipLaunchKernelGGL(k_mw_bounds, dim3(1), dim3(1024), 0, s, S, n, d, e, scal + 1);
-  hipLaunchKernelGGL(k_mw_bisect, dim3((n + 255) / 256), dim3(256), 0, s, d, e, n, scal + 1, lam);
+  hipLaunchKernelGGL(k_mw_bounds, dim3(1), dim3(1024), 0, s, S, n, d, e, bsc + 2);
+}
+
+size_t pencil_energy_mw_work(int n) { return 2 * (size_t)n * n + 6 * (size_t)n + 8; }
+
+hipError_t launch_pencil_energy_mw(const double* M, int n, int64_t nvv, double mu2, double* out,
+                                   double* work, int* info, hipStream_t s) {
+  if (n < 2 || n > DENSE_ENERGY_MAX) return hipErrorInvalidValue;
+  const size_t nn = (size_t)n * n;
+  double* K = work;
+  double* S = K + nn;
+  double* v2 = S + nn;
+  double* p = v2 + 2 * (size_t)n;
+  double* d = p + n;
+  double* e = d + n;
+  double* lam = e + n;
+  double* bsc = lam + n;  // [0], [1] beta, [2 .. 4] Gershgorin bounds and norm
+  int* flag = info;       // info[0] doubles as the not-definite flag until the last kernel
+  mw_reduce(M, n, nvv, mu2, K, S, v2, p, d, e, bsc, nullptr, flag, s);
+  hipLaunchKernelGGL(k_mw_bisect, dim3((unsigned)((16 * (size_t)n + 255) / 256)), dim3(256), 0, s,
+                     d, e, n, bsc + 2, lam);
   hipLaunchKernelGGL(k_mw_sums, dim3(1), dim3(1024), 0, s, M, n, nvv, mu2, lam, flag, out, info);
   return hipGetLastError();
 }
 
 size_t direct_pencil_mw_work(int n, int nroot) {
-  return 2 * (size_t)n * n + 5 * (size_t)n + 4 * (size_t)nroot * n + 64 + 8 + 8;
+  return 2 * (size_t)n * n + 6 * (size_t)n + 4 * (size_t)nroot * n + 64 + 8 + 8;
 }
 
 hipError_t launch_direct_pencil_mw(const double* M, int n, int64_t nvv, double mu2, int nroot,
@@ -686,45 +782,24 @@ hipError_t launch_direct_pencil_mw(const double* M, int n, int64_t nvv, double m
   const size_t nn = (size_t)n * n;
   double* K = work;
   double* S = K + nn;
-  double* v = S + nn;
-  double* p = v + n;
+  double* v2 = S + nn;
+  double* p = v2 + 2 * (size_t)n;
   double* d = p + n;
   double* e = d + n;
   double* beta = e + n;
   double* Y = beta + n;
   double* U = Y + (size_t)nroot * n;
   double* lam = U + 3 * (size_t)nroot * n;  // 64
-  double* scal = lam + 64;                  // [0] beta of the current step, [1 .. 3] bounds
-  int* cnt = (int*)(scal + 8);  // [0] eigenvalues below 0
-  int* flag = cnt + 1;          // K not positive definite
-  hipLaunchKernelGGL(k_mw_init, dim3(1), dim3(64), 0, s, flag);
-  hipLaunchKernelGGL(k_mw_shift, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, M, n, nvv,
-                     mu2, K);
-  for (int j0 = 0; j0 < n; j0 += CB) {
-    hipLaunchKernelGGL(k_mw_chol_diag, dim3(1), dim3(256), 0, s, K, n, j0, flag);
-    const int rest = n - j0 - CB;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_mw_chol_trsm, dim3((rest + 255) / 256), dim3(256), 0, s, K, n, j0);
-      const int nt = (rest + CB - 1) / CB;
-      hipLaunchKernelGGL(k_mw_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, K, n, j0);
-    }
-  }
-  const int ntile = (n + CB - 1) / CB;
-  hipLaunchKernelGGL(k_mw_sym, dim3(ntile * (ntile + 1) / 2), dim3(256), 0, s, K, n, nvv, S);
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    hipLaunchKernelGGL(k_mw_hh_vec, dim3(1), dim3(1024), 0, s, S, n, k, v, scal, d, e, beta);
-    hipLaunchKernelGGL(k_mw_hh_matvec, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p);
-    hipLaunchKernelGGL(k_mw_hh_update, dim3((m + 3) / 4), dim3(256), 0, s, S, n, k, v, scal, p,
-                       1);
-  }
-  hipLaunchKernelGGL(k_mw_bounds, dim3(1), dim3(1024), 0, s, S, n, d, e, scal + 1);
-  hipLaunchKernelGGL(k_mw_count, dim3(1), dim3(64), 0, s, d, e, n, scal + 1, cnt);
-  hipLaunchKernelGGL(k_mw_select, dim3(nroot), dim3(256), 0, s, d, e, n, scal + 1, cnt, channel,
+  double* bsc = lam + 64;                   // [0], [1] beta, [2 .. 4] bounds
+  int* cnt = (int*)(bsc + 8);               // [0] eigenvalues below 0
+  int* flag = cnt + 1;                      // K not positive definite
+  mw_reduce(M, n, nvv, mu2, K, S, v2, p, d, e, bsc, beta, flag, s);
+  hipLaunchKernelGGL(k_mw_count, dim3(1), dim3(64), 0, s, d, e, n, bsc + 2, cnt);
+  hipLaunchKernelGGL(k_mw_select, dim3(nroot), dim3(256), 0, s, d, e, n, bsc + 2, cnt, channel,
                      flag, lam);
-  hipLaunchKernelGGL(k_mw_inviter, dim3(1), dim3(64), 0, s, d, e, n, scal + 1, cnt, channel, flag,
+  hipLaunchKernelGGL(k_mw_inviter, dim3(1), dim3(64), 0, s, d, e, n, bsc + 2, cnt, channel, flag,
                      lam, nroot, Y, U);
-  hipLaunchKernelGGL(k_mw_orth, dim3(1), dim3(1024), 0, s, n, scal + 1, cnt, channel, flag, lam,
+  hipLaunchKernelGGL(k_mw_orth, dim3(1), dim3(1024), 0, s, n, bsc + 2, cnt, channel, flag, lam,
                      nroot, Y);
   hipLaunchKernelGGL(k_mw_vectors, dim3(nroot), dim3(256), 0, s, K, S, beta, n, cnt, channel, flag,
                      lam, Y, mu2, omega, Cout, ldc, info);
