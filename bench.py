@@ -566,7 +566,8 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
     integrals are scaled by the workload's eig_scale (0.7), at which the pencil is definite.
     FP64 converges to residual tol; the reduced precisions to tol_reduced, since their sigma
     error puts a floor near 1e-6 under the residual (the eigenvalue error, quadratic in the
-    residual, stays far below 1e-6 Ha)."""
+    residual, stays far below 1e-6 Ha). sigma_rel_err_random_unit: |sigma_prec z - sigma_fp64 z|_2
+    / |sigma_fp64 z|_2 on four seeded random unit vectors, the size of that floor."""
     import torch
     dev = torch.device("cuda:0")
     c = gen.CONFIGS[name]
@@ -575,6 +576,10 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
     no_act, nv_act = c.get("nocc_act"), c.get("nvir_act")
     eps, L, kw = problem if problem is not None else device_problem(gen, name, dev)
     out = {}
+    with P.PpRPA(eps, L, nocc, mult=mult, prec="fp64", max_block=block, **kw) as ctx:
+        zr = gen.random_vectors(5, 4, ctx.n)
+        zr /= np.linalg.norm(zr, axis=1, keepdims=True)
+        s64 = ctx.matvec(zr)
     for prec in precs:
         t0 = time.perf_counter()
         with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=block, **kw) as ctx:
@@ -583,6 +588,7 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
                              max_iter=300, raise_noconv=False)
             t2 = time.perf_counter()
             st = ctx.sigma_stats()
+            rel = np.linalg.norm(ctx.matvec(zr) - s64, axis=1) / np.linalg.norm(s64, axis=1)
         nprod = {"bf16x6": 6, "bf16x3": 3}.get(prec, 1)
         peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32}.get(prec, PEAK_BF16)
         alg = st["flops"] / st["seconds"] if st["seconds"] > 0 else 0.0
@@ -593,7 +599,8 @@ def precision_study(P, gen, precs=("fp64", "fp32", "bf16x6", "bf16x3"), block=20
              "sigma_kernel_tflops_executed": nprod * alg / 1e12,
              "sigma_kernel_frac_of_peak": nprod * alg / peak,
              "sigma_kernel_share_of_solve": st["seconds"] / (t2 - t1),
-             "max_resid": r["report"]["max_resid"]}
+             "max_resid": r["report"]["max_resid"],
+             "sigma_rel_err_random_unit": float(rel.max())}
         if prec == "fp64" and ref is None:
             ref = r["omega"]
         elif ref is not None:
