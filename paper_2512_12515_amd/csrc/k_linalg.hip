@@ -493,14 +493,26 @@ constexpr int PLDS = 96;
 // (the Davidson pencils and the direct path up to order 96, matrices in LDS, W the projected
 // metric).
 // ------------------------------------------------------------------------------------------
+// 1 / b from the hardware reciprocal estimate and two Newton-Raphson steps r <- r (2 - b r)
+// (each squares the relative error), for b of moderate size (no scaling near the ends of the
+// exponent range): a shorter dependent chain than the IEEE division sequence, within an ulp or
+// two of it.
+__device__ __forceinline__ double recip_nr(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return r;
+}
+
 __device__ __forceinline__ int sturm_below(const double* d, const double* e2, int m, double x,
                                            double tiny) {
   int cnt = 0;
   double q = d[0] - x;
   if (q < 0.0) ++cnt;
+#pragma unroll 4
   for (int i = 1; i < m; ++i) {
     if (fabs(q) < tiny) q = -tiny;  // a zero pivot counts as negative (the usual convention)
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * recip_nr(q);
     if (q < 0.0) ++cnt;
   }
   return cnt;
@@ -526,6 +538,7 @@ __device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag, double
   const int t = threadIdx.x;
   if (t == 0) *flag = 0;
   __syncthreads();
+  const int lane = t & 63, w = t >> 6;
   for (int j = 0; j < m; ++j) {
     const double dj = A[j * m + j];
     if (!(dj > 0.0)) {
@@ -534,58 +547,54 @@ __device__ __forceinline__ bool tri_cholesky(double* A, int m, int* flag, double
       break;
     }
     const double rjj = sqrt(dj);
-    __syncthreads();
     for (int i = j + 1 + t; i < m; i += WG) {
       const double v = A[i * m + j] / rjj;
       A[i * m + j] = v;
       if (col) col[i] = v;
     }
-    if (t == 0) A[j * m + j] = rjj;
     __syncthreads();
-    const int nt = m - j - 1;
-    for (int e_ = t; e_ < nt * nt; e_ += WG) {
-      const int i = j + 1 + e_ / nt, k = j + 1 + e_ % nt;
-      if (k <= i) A[i * m + k] -= col ? col[i] * col[k] : A[i * m + j] * A[k * m + j];
+    if (t == 0) A[j * m + j] = rjj;  // no thread reads it in the update below
+    // trailing lower triangle: a wave per row, lanes along it
+    for (int i = j + 1 + w; i < m; i += WG / 64) {
+      const double li = col ? col[i] : A[i * m + j];
+      for (int k = j + 1 + lane; k <= i; k += 64)
+        A[i * m + k] -= li * (col ? col[k] : A[k * m + j]);
     }
     __syncthreads();
   }
   return *flag == 0;
 }
 
-// Ri = R^-1 (lower) by forward substitution, one row at a time, the row's columns in parallel.
-// RiT: scratch of m^2 doubles (global matrices) that keeps the transposed copy, so that thread c
-// reads its column c of R^-1 as a contiguous row, or null.
+// Ri = R^-1 (lower) by forward substitution, one row at a time, the row's columns in parallel;
+// each element's dot product is split over tpe consecutive lanes (as many as the row's i + 1
+// elements leave room for), k = c + q, c + q + tpe, ..., and the lane partials are combined by a
+// fixed butterfly: dependent chains tpe times shorter. RiT: scratch of m^2 doubles (global
+// matrices) that keeps the transposed copy, so that the lanes read column c of R^-1 as a
+// contiguous row, or null (matrices in LDS: column c read in place).
 __device__ __forceinline__ void tri_inverse(const double* A, double* Ri, int m,
                                             double* RiT = nullptr) {
   const int t = threadIdx.x;
   for (int i = 0; i < m; ++i) {
     const double rii = A[i * m + i];
-    if (RiT) {
-      // global matrices: each element's dot product is split over tpe consecutive lanes (as
-      // many as the row's i + 1 elements leave room for), k = c + q, c + q + tpe, ..., and the
-      // lane partials are combined by a fixed butterfly: chains tpe times shorter
-      const int nc = i + 1;
-      const int tpe = nc * 8 <= WG ? 8 : (nc * 4 <= WG ? 4 : (nc * 2 <= WG ? 2 : 1));
-      for (int base = 0; base < nc * tpe; base += WG) {
-        const int id = base + t;
-        const int c = id / tpe, q = id % tpe;
-        double s = 0.0;
-        if (c < nc) {
+    const int nc = i + 1;
+    const int tpe = nc * 8 <= WG ? 8 : (nc * 4 <= WG ? 4 : (nc * 2 <= WG ? 2 : 1));
+    for (int base = 0; base < nc * tpe; base += WG) {
+      const int id = base + t;
+      const int c = id / tpe, q = id % tpe;
+      double s = 0.0;
+      if (c < nc) {
+        if (RiT) {
           const double* rc = RiT + (size_t)c * m;
           for (int k = c + q; k < i; k += tpe) s += A[i * m + k] * rc[k];
-        }
-        for (int off = 1; off < tpe; off <<= 1) s += __shfl_xor(s, off, 64);
-        if (c < nc && q == 0) {
-          const double v = ((c == i ? 1.0 : 0.0) - s) / rii;
-          Ri[i * m + c] = v;
-          RiT[(size_t)c * m + i] = v;
+        } else {
+          for (int k = c + q; k < i; k += tpe) s += A[i * m + k] * Ri[k * m + c];
         }
       }
-    } else {
-      for (int c = t; c <= i; c += WG) {
-        double s = (c == i) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) s -= A[i * m + k] * Ri[k * m + c];
-        Ri[i * m + c] = s / rii;
+      for (int off = 1; off < tpe; off <<= 1) s += __shfl_xor(s, off, 64);
+      if (c < nc && q == 0) {
+        const double v = ((c == i ? 1.0 : 0.0) - s) / rii;
+        Ri[i * m + c] = v;
+        if (RiT) RiT[(size_t)c * m + i] = v;
       }
     }
     for (int c = i + 1 + t; c < m; c += WG) Ri[i * m + c] = 0.0;
@@ -595,63 +604,114 @@ __device__ __forceinline__ void tri_inverse(const double* A, double* Ri, int m,
 
 // Householder tridiagonalisation of the symmetric G (m x m, ld m) in place: diagonal d, off-
 // diagonal e, reflection k (H = I - beta[k] v v^T acting on rows/cols k+1..) kept in column k
-// below the diagonal. vv, pq: LDS scratch of m; red: WG doubles.
+// below the diagonal. vv, vw, pq: LDS scratch of m (vv and vw hold the reflection vectors of
+// alternate steps); red: WG doubles.
+//
+// Step k: p = beta G' v (eight lanes per row), K = beta p^T v / 2 from the waves' partial sums
+// (fixed order), G' -= v q^T + q v^T with q = p - K v (a wave per row); the wave that updates
+// row k + 1 (the first row of G') then forms the reflection of step k + 1 from that row (by
+// symmetry, column k + 1 below the diagonal) while the other waves finish their rows: two
+// barriers a step.
+__device__ __forceinline__ void tri_reflector(const double* G, int m, int k, double* v, double* d,
+                                              double* e, double* beta, int lane) {
+  // one wave: x = row k right of the diagonal, |x_1..|^2 by a butterfly, alpha = -sign(x_0) |x|,
+  // v = x - alpha e_1, beta = 2 / v^T v (0: already tridiagonal)
+  const int s0 = k + 1, ns = m - s0;
+  double part = 0.0;
+  for (int i = lane; i < ns; i += 64) {
+    const double x = G[k * m + s0 + i];
+    v[i] = x;
+    if (i > 0) part += x * x;
+  }
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if (lane == 0) {
+    const double x0 = v[0];
+    d[k] = G[k * m + k];
+    if (part == 0.0) {
+      e[k] = x0;
+      beta[k] = 0.0;
+    } else {
+      const double nrm = sqrt(x0 * x0 + part);
+      const double alpha = x0 >= 0.0 ? -nrm : nrm;
+      const double v0 = x0 - alpha;
+      v[0] = v0;
+      e[k] = alpha;
+      beta[k] = 2.0 / (v0 * v0 + part);  // H = I - beta v v^T
+    }
+  }
+}
+
 __device__ __forceinline__ void tri_householder(double* G, int m, double* d, double* e, double* beta, double* vv,
-                                double* pq, double* red) {
-  const int t = threadIdx.x;
+                                double* pq, double* red, double* vw) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double* vc = vv;
+  double* vn = vw;
+  if (m > 2 && w == 0) tri_reflector(G, m, 0, vc, d, e, beta, lane);
+  __syncthreads();
   for (int k = 0; k + 2 < m; ++k) {
     const int s0 = k + 1, ns = m - s0;
-    double part = 0.0;
-    for (int i = t; i < ns; i += WG) {
-      const double x = G[(s0 + i) * m + k];
-      vv[i] = x;
-      if (i > 0) part += x * x;
-    }
-    const double tail = block_sum(part, red);  // also orders the vv writes
-    const double x0 = vv[0];
-    if (t == 0) d[k] = G[k * m + k];
-    if (tail == 0.0) {  // already tridiagonal in this column
-      if (t == 0) {
-        e[k] = x0;
-        beta[k] = 0.0;
+    const double b = beta[k];
+    if (b != 0.0) {  // uniform; else column k is already in tridiagonal form
+      // p = b G' v: eight lanes per row, their partials combined by three shuffles; each wave's
+      // share of p^T v into red
+      double part = 0.0;
+      for (int r0 = 0; r0 < ns; r0 += WG / 8) {
+        const int i = r0 + (t >> 3), q = t & 7;
+        double sum = 0.0;
+        if (i < ns) {
+          const double* gi = G + (s0 + i) * m + s0;
+#pragma unroll 4
+          for (int j = q; j < ns; j += 8) sum += gi[j] * vc[j];
+        }
+        sum += __shfl_xor(sum, 1, 64);
+        sum += __shfl_xor(sum, 2, 64);
+        sum += __shfl_xor(sum, 4, 64);
+        if (q == 0 && i < ns) {
+          const double p_ = b * sum;
+          pq[i] = p_;
+          part += p_ * vc[i];
+        }
       }
+      part += __shfl_xor(part, 8, 64);
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (lane == 0) red[w] = part;
       __syncthreads();
-      continue;
+      double kp = 0.0;
+      for (int ww = 0; ww < WG / 64; ++ww) kp += red[ww];
+      const double K = 0.5 * b * kp;
+      // G' -= v q^T + q v^T: a wave per row, lanes along it
+      if (ns <= 128) {
+        const int j0 = lane, j1 = lane + 64;
+        const double vj0 = j0 < ns ? vc[j0] : 0.0, qj0 = j0 < ns ? pq[j0] - K * vj0 : 0.0;
+        const double vj1 = j1 < ns ? vc[j1] : 0.0, qj1 = j1 < ns ? pq[j1] - K * vj1 : 0.0;
+#pragma unroll 2
+        for (int i = w; i < ns; i += WG / 64) {
+          const double vi = vc[i], qi = pq[i] - K * vi;
+          double* Gi = G + (size_t)(s0 + i) * m + s0;
+          if (j0 < ns) Gi[j0] -= vi * qj0 + qi * vj0;
+          if (j1 < ns) Gi[j1] -= vi * qj1 + qi * vj1;
+        }
+      } else {
+        for (int i = w; i < ns; i += WG / 64) {
+          const double vi = vc[i], qi = pq[i] - K * vi;
+          double* Gi = G + (size_t)(s0 + i) * m + s0;
+          for (int j = lane; j < ns; j += 64) {
+            const double vj = vc[j];
+            Gi[j] -= vi * (pq[j] - K * vj) + qi * vj;
+          }
+        }
+      }
+      for (int i = t; i < ns; i += WG) G[(s0 + i) * m + k] = vc[i];
     }
-    const double nrm = sqrt(x0 * x0 + tail);
-    const double alpha = x0 >= 0.0 ? -nrm : nrm;
-    const double v0 = x0 - alpha;
-    const double b = 2.0 / (v0 * v0 + tail);  // H = I - b v v^T, v = (v0, x1, x2, ...)
-    __syncthreads();
-    if (t == 0) {
-      vv[0] = v0;
-      e[k] = alpha;
-      beta[k] = b;
+    if (w == 0 && k + 3 < m) {
+      __threadfence_block();  // row k + 1, just updated by this wave's lanes, read across lanes
+      tri_reflector(G, m, k + 1, vn, d, e, beta, lane);
     }
     __syncthreads();
-    // p = b G' v (4 threads per row)
-    for (int r0 = 0; r0 < ns; r0 += WG / 4) {
-      const int i = r0 + t / 4, q = t % 4;
-      double sum = 0.0;
-      if (i < ns)
-        for (int j = q; j < ns; j += 4) sum += G[(s0 + i) * m + s0 + j] * vv[j];
-      red[t] = sum;
-      __syncthreads();
-      if (q == 0 && i < ns) pq[i] = b * (red[t] + red[t + 1] + red[t + 2] + red[t + 3]);
-      __syncthreads();
-    }
-    double kp = 0.0;
-    for (int i = t; i < ns; i += WG) kp += pq[i] * vv[i];
-    const double K = 0.5 * b * block_sum(kp, red);
-    for (int i = t; i < ns; i += WG) pq[i] -= K * vv[i];  // q = p - K v
-    __syncthreads();
-    // G' -= v q^T + q v^T
-    for (int e_ = t; e_ < ns * ns; e_ += WG) {
-      const int i = e_ / ns, j = e_ % ns;
-      G[(s0 + i) * m + s0 + j] -= vv[i] * pq[j] + pq[i] * vv[j];
-    }
-    for (int i = t; i < ns; i += WG) G[(s0 + i) * m + k] = vv[i];
-    __syncthreads();
+    double* const tmp = vc;
+    vc = vn;
+    vn = tmp;
   }
   if (t == 0) {
     if (m >= 2) {
@@ -669,7 +729,8 @@ __device__ __forceinline__ void tri_householder(double* G, int m, double* d, dou
 // channel 1, hh: the smallest, theta[0] smallest), the count of roots of the channel's sign
 // (*npos: positive theta for pp, negative for hh), and their eigenvectors X[j][0..m) (global
 // scratch: 4 nsel m doubles from X). e2, lo_s, hi_s (nsel each): LDS scratch; xs: LDS scratch of
-// 4 nsel m doubles for the inverse iteration, or null (then it works in X). nsel <= WG.
+// 4 nsel (m | 1) doubles for the inverse iteration (X may be xs itself: the vectors then end in
+// its first nsel m doubles), or null (then it works in X). nsel <= WG.
 __device__ __forceinline__ void tri_eigen(const double* d, const double* e, double* e2, int m, int nsel,
                           int channel, double* theta, int* npos, double* X, double* red,
                           double* lo_s, double* hi_s, double* xs) {
@@ -692,8 +753,10 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
   }
   // multisection: root j (the j-th from the wanted end) gets G threads, which evaluate the
   // Sturm count at G interior points of its bracket per round; the bracket shrinks to the two
-  // neighbouring points that enclose the root's index, until its width is at the rounding level
-  const int G = max(1, min(32, WG / max(nsel, 1)));
+  // neighbouring points that enclose the root's index, until its width is at the rounding level.
+  // The counts are bound by the one CU's FP64 rate: 8 points per round measured faster than 16,
+  // 32 or 51 (fewer counts in all)
+  const int G = max(1, min(8, WG / max(nsel, 1)));
   for (int j = t; j < nsel; j += WG) {
     lo_s[j] = gmin - 1e-12 * tnorm;
     hi_s[j] = gmax + 1e-12 * tnorm;
@@ -736,12 +799,15 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
   __syncthreads();
   // inverse iteration (thread j): (T - theta I) y = b by Gaussian elimination with partial
   // pivoting on the tridiagonal (fill-in: a second superdiagonal), three solves
+  // rows of the LDS scratch at an odd stride ms (in doubles), so that the nsel threads' accesses
+  // fall in distinct banks; 4 nsel ms doubles
+  const int ms = xs ? (m | 1) : m;
   if (t < nsel) {
     double* const base = xs ? xs : X;
-    double* y = base + (size_t)t * m;
-    double* U0 = base + (size_t)nsel * m + (size_t)t * 3 * m;
-    double* U1 = U0 + m;
-    double* U2 = U1 + m;
+    double* y = base + (size_t)t * ms;
+    double* U0 = base + (size_t)nsel * ms + (size_t)t * 3 * ms;
+    double* U1 = U0 + ms;
+    double* U2 = U1 + ms;
     const double th = theta[t];
     const double pert = 2.2e-16 * tnorm;
     unsigned long long h = 0x9E3779B97F4A7C15ull * (unsigned long long)(t + 1);
@@ -759,7 +825,7 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
         if (fabs(a_d) >= fabs(b_l)) {
           double piv = a_d;
           if (fabs(piv) < pert) piv = piv < 0.0 ? -pert : pert;
-          const double l = b_l / piv;
+          const double l = b_l * recip_nr(piv);
           U0[i] = piv;
           U1[i] = a_u;
           U2[i] = a_u2;
@@ -769,7 +835,7 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
           a_u2 = 0.0;
           rhs = rb - l * rhs;
         } else {
-          const double l = a_d / b_l;  // rows i and i+1 swapped
+          const double l = a_d * recip_nr(b_l);  // rows i and i+1 swapped
           U0[i] = b_l;
           U1[i] = b_d;
           U2[i] = b_u;
@@ -788,7 +854,7 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
       y[m - 1] = rhs;
       double y1 = 0.0, y2 = 0.0, nrm2 = 0.0;
       for (int i = m - 1; i >= 0; --i) {
-        const double v = (y[i] - U1[i] * y1 - U2[i] * y2) / U0[i];
+        const double v = (y[i] - U1[i] * y1 - U2[i] * y2) * recip_nr(U0[i]);
         y[i] = v;
         y2 = y1;
         y1 = v;
@@ -797,10 +863,18 @@ __device__ __forceinline__ void tri_eigen(const double* d, const double* e, doub
       const double inv = 1.0 / sqrt(nrm2);
       for (int i = 0; i < m; ++i) y[i] *= inv;
     }
-    if (xs)  // the vector goes on to the orthonormalisation and back-transformation in X
+    if (xs && X != xs)  // the vector goes on to the orthonormalisation and back-transformation in X
       for (int i = 0; i < m; ++i) X[(size_t)t * m + i] = y[i];
   }
   __syncthreads();
+  if (xs && X == xs) {
+    // X is the scratch itself: rows of ms -> rows of m, through the free elimination rows
+    double* const tmp = xs + (size_t)nsel * ms;
+    for (int e_ = t; e_ < nsel * m; e_ += WG) tmp[e_] = xs[(size_t)(e_ / m) * ms + e_ % m];
+    __syncthreads();
+    for (int e_ = t; e_ < nsel * m; e_ += WG) X[e_] = tmp[e_];
+    __syncthreads();
+  }
   // vectors of nearly equal theta: orthonormalise in order (modified Gram-Schmidt)
   for (int j = 1; j < nsel; ++j) {
     for (int i = 0; i < j; ++i) {
@@ -874,7 +948,7 @@ __device__ __forceinline__ bool dense_pencil_tridiag(const double* __restrict__ 
                                                      int64_t nvv, double mu2, double* A,
                                                      double* Ri, double* G, double* d, double* e,
                                                      double* beta, double* vv, double* pq,
-                                                     double* red, int* flag) {
+                                                     double* red, int* flag, double* vw) {
   const int t = threadIdx.x;
   for (int e_ = t; e_ < m * m; e_ += WG) {
     const int i = e_ / m, j = e_ % m;
@@ -908,7 +982,7 @@ __device__ __forceinline__ bool dense_pencil_tridiag(const double* __restrict__ 
     }
   }
   __syncthreads();
-  tri_householder(G, m, d, e, beta, vv, pq, red);
+  tri_householder(G, m, d, e, beta, vv, pq, red, vw);
   return true;
 }
 
@@ -930,7 +1004,7 @@ __global__ __launch_bounds__(WG) void k_pencil_energy(const double* __restrict__
   double* A = work;
   double* Ri = work + (size_t)m * m;
   double* G = work + 2 * (size_t)m * m;
-  if (!dense_pencil_tridiag(M, m, nvv, mu2, A, Ri, G, d, e, beta, vv, pq, red, &flag)) {
+  if (!dense_pencil_tridiag(M, m, nvv, mu2, A, Ri, G, d, e, beta, vv, pq, red, &flag, e2)) {
     if (t == 0) {
       info[0] = 1;
       info[1] = 0;
@@ -1037,7 +1111,7 @@ __global__ __launch_bounds__(WG) void k_gram_eigenvalues(double* __restrict__ Ga
   __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
   const int t = threadIdx.x;
   double* G = Gall + (int64_t)blockIdx.x * m * m;
-  tri_householder(G, m, d, e, beta, vv, pq, red);
+  tri_householder(G, m, d, e, beta, vv, pq, red, e2);
   for (int i = t; i < m; i += WG) e2[i] = i + 1 < m ? e[i] * e[i] : 0.0;
   double lo_p = 1e300, hi_p = -1e300, nrm_p = 0.0;
   for (int i = t; i < m; i += WG) {
@@ -1120,21 +1194,24 @@ __device__ __forceinline__ void pencil_tri_body(const double* __restrict__ Ms,
     for (int e_ = t; e_ < m * m; e_ += WG) G[e_] = Gt[e_];
     __syncthreads();
   }
-  tri_householder(G, m, d, e, beta, vv, pq, red);
+  tri_householder(G, m, d, e, beta, vv, pq, red, e2);
   const int nsel = nret < m ? nret : m;
   // with the matrices in LDS (Gt given): R^-1 moves to the global staging area and its LDS
   // holds the inverse-iteration rows when they fit (B spans PLDS^2 doubles)
   double* Rinv = B;
   double* xs = nullptr;
-  if (Gt && (size_t)4 * nsel * m <= (size_t)PLDS * PLDS) {
+  if (Gt && (size_t)4 * nsel * (m | 1) <= (size_t)PLDS * PLDS) {
     for (int e_ = threadIdx.x; e_ < m * m; e_ += WG) Gt[e_] = B[e_];
     __syncthreads();
     Rinv = Gt;
     xs = B;
   }
-  tri_eigen(d, e, e2, m, nsel, channel, theta, npos_s, X, red, vv, pq, xs);
-  tri_back_transform(G, m, beta, X, nsel);
-  tri_outputs(Rinv, X, theta, m, nroot, nsel, *npos_s, mu2, omega, Cout, ldc, info);
+  // with the inverse-iteration rows in LDS the vectors stay there (the first nsel m doubles of
+  // xs) through the orthonormalisation, the back-transformation and the outputs
+  double* const Xv = xs ? xs : X;
+  tri_eigen(d, e, e2, m, nsel, channel, theta, npos_s, Xv, red, vv, pq, xs);
+  tri_back_transform(G, m, beta, Xv, nsel);
+  tri_outputs(Rinv, Xv, theta, m, nroot, nsel, *npos_s, mu2, omega, Cout, ldc, info);
 }
 
 // m <= PLDS: K, R, G in LDS (G over K); work: m^2 (G staging) + 4 nret m.
