@@ -469,7 +469,19 @@ def unrestricted(P, gen, reps=3, tol=1e-8):
         rb = ctx.davidson(broot, block=16, tol=1e-6)
         t_big = time.perf_counter() - t0
         st = ctx.sigma_stats()
-    del La2, Lb2
+    # the sigma kernel in each precision on the same sector: 16 vectors, 3 timed products
+    zb = torch.from_numpy(gen.random_vectors(86, 16, n_big)).to(dev)
+    by_prec = {}
+    for prec in ("fp64", "fp32", "bf16x6", "bf16x3"):
+        with P.PpRPA.alpha_beta(ea2, eb2, La2, Lb2, bna, bnb, density_fitted=True, prec=prec,
+                                max_block=16) as ctx:
+            ctx.matvec(zb)
+            ctx.sigma_stats(reset=True)
+            for _ in range(3):
+                ctx.matvec(zb)
+            sp = ctx.sigma_stats()
+        by_prec[prec] = sp["flops"] / max(sp["seconds"], 1e-30) / 1e12
+    del La2, Lb2, zb
     return {"workload": f"nmo {nmo}, nocc {noa}/{nob}, naux {naux}: aa + bb (triplet, DF sigma) + "
                         f"ab (dense, n {n_ab}), {nroot} roots each, tol {tol:g}",
             "s_per_three_sectors_p50": float(np.median(times)), "max_eig_err_ha_vs_oracle": err,
@@ -480,7 +492,8 @@ def unrestricted(P, gen, reps=3, tol=1e-8):
                                   "block 16, tol 1e-06",
                 "solve_s": t_big, "iters": rb["report"]["iters"],
                 "n_sigma": rb["report"]["n_sigma"], "max_resid": float(np.max(rb["resid"])),
-                "sigma_kernel_tflops_algorithmic": st["flops"] / max(st["seconds"], 1e-30) / 1e12}}
+                "sigma_kernel_tflops_algorithmic": st["flops"] / max(st["seconds"], 1e-30) / 1e12,
+                "isolated_sigma_tflops_algorithmic_by_prec": by_prec}}
 
 
 def isolated_sigma(P, gen, eps_d, L_d, nocc, block, warm=3, reps=20):

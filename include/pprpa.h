@@ -106,9 +106,8 @@ pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
  *    matrix is formed, so the order is limited by memory only (nvir, nocc < 65536);
  *    pprpa_dims, pprpa_matvec and pprpa_davidson (Davidson, both channels) apply, the direct
  *    solve, pprpa_dense_matrix and pprpa_correlation_energy return EUNSUPPORTED.
- * The density-fitted form also takes FP32 sigma (prec). pprpa_nto returns EUNSUPPORTED for
- * both. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO)
- * / 2. Inputs (host, or device with on_device) are read during the call only.
+ * The density-fitted form also takes FP32 and BF16-split sigma (prec). pprpa_nto returns
+ * EUNSUPPORTED for both. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO) / 2. Inputs (host, or device with on_device) are read during the call only.
  * Errors: EINVAL (arguments, non-finite input, energies of a spin not ascending within its
  * occupied or virtual block or its HOMO not below its LUMO), ENOMEM, EDEVICE. */
 typedef struct {
@@ -124,9 +123,12 @@ typedef struct {
   int32_t max_block;    /* largest sigma block per call (<= 0: 32, at most 64)               */
   void* stream;         /* hipStream_t to run on, or NULL for a new non-blocking stream      */
   int32_t density_fitted; /* 1: density-fitted sigma (no dense matrix); 0: dense context     */
-  pprpa_prec prec;      /* sigma precision: PPRPA_FP64, or PPRPA_FP32 (density fitted only:
-                           integrals and amplitudes in FP32, FP32 MFMA accumulation, the
-                           epilogue and every Davidson step in FP64); others EUNSUPPORTED   */
+  pprpa_prec prec;      /* sigma precision: PPRPA_FP64; density fitted only: PPRPA_FP32
+                           (integrals and amplitudes in FP32, FP32 MFMA accumulation) or
+                           PPRPA_BF16X6 / PPRPA_BF16X3 (three BF16 planes each, six or three
+                           plane products on the BF16 MFMA, FP32 accumulation); the epilogue
+                           and every Davidson step in FP64. A dense context with any
+                           precision but FP64 is EUNSUPPORTED                                */
 } pprpa_build_ab_args;
 pprpa_status pprpa_build_ab(const pprpa_build_ab_args* args, pprpa_ctx** out);
 

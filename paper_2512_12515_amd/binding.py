@@ -246,7 +246,7 @@ class PpRPA:
                    density_fitted=False, prec="fp64"):
         """The alpha-beta sector of spin-unrestricted ppRPA (pprpa_build_ab): a dense context, or
         with density_fitted=True the density-fitted sigma of both spins' integrals (no matrix;
-        prec "fp64" or "fp32"); the alpha-alpha and beta-beta sectors are
+        prec "fp64", "fp32", "bf16x6" or "bf16x3"); the alpha-alpha and beta-beta sectors are
         PpRPA(eps_s, Lpq_s, nocc_s, mult="triplet")."""
         on_dev = _is_torch(Lpq_a) and Lpq_a.is_cuda
         if not on_dev:

@@ -161,16 +161,17 @@ pprpa_status sigma_device(pprpa_ctx* c, int k, const double* dz, double* ds) {
       const double* z = dz + (int64_t)k0 * n;
       double* s = ds + (int64_t)k0 * n;
       const int ns = nsplit_for(c, kk);
-      PPRPA_HIP(launch_unpack_ab(ag, c->st, z, kk, c->ZT, c->stream));
+      PPRPA_HIP(launch_unpack_ab(ag, c->st, z, kk, c->ZT, c->zplane, c->stream));
       pprpa_ctx::Timed tm;
       PPRPA_TRY(get_event(c, &tm.a));
       PPRPA_TRY(get_event(c, &tm.b));
-      const double esz = c->st == Store::F32 ? 4.0 : 8.0;
+      const double esz = c->st == Store::F64 ? 8.0 : (c->st == Store::F32 ? 4.0 : 2.0 * (c->nprod == 3 ? 2 : 3));
       tm.flops = 2.0 * ag.naux * (double)n * ((ag.nva + ag.noa) + (ag.nvb + ag.nob)) * kk;
       tm.bytes = (double)ag.naux * ((double)ag.nmopa * ag.nmopa + (double)ag.nmopb * ag.nmopb) * esz +
                  2.0 * kk * (double)n * 8.0;
       PPRPA_TRY(gated_launch(c, tm, [&] {
-        return launch_sigma_ab(ag, c->st, c->plan, c->L, c->Lb, c->ZT, c->Sp, kk, ns, c->stream);
+        return launch_sigma_ab(ag, c->st, c->nprod, c->plan, c->L, c->Lb, c->ZT, c->zplane, c->Sp, kk,
+                               ns, c->stream);
       }));
       PPRPA_HIP(launch_epilogue_ab(ag, c->st, z, kk, c->Sp, ns, c->epair, s, c->stream));
     }
@@ -485,7 +486,9 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
   c->ab_df = a->density_fitted != 0;
   c->ab_nocc_b = nob;
   c->prec = a->prec;
-  c->st = a->prec == PPRPA_FP32 ? Store::F32 : Store::F64;
+  c->st = a->prec == PPRPA_FP32 ? Store::F32
+          : (a->prec == PPRPA_BF16X6 || a->prec == PPRPA_BF16X3) ? Store::BF16 : Store::F64;
+  c->nprod = a->prec == PPRPA_BF16X3 ? 3 : 6;
   c->kcap = a->max_block > 0 ? std::min(a->max_block, 64) : 32;
 
   std::vector<double> ea(nmo), eb(nmo);
@@ -560,20 +563,23 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
     ag.nvb = nvb;
     ag.nob = nob;
     ag.naux = naux;
-    ag.nvpa = round_up(nva, TILE);
-    ag.nopa = round_up(noa, TILE);
+    // BF16-split sigma reduces over 32 orbitals per MFMA: its blocks are padded to two tiles
+    const int pad = c->st == Store::BF16 ? 2 * TILE : TILE;
+    ag.nvpa = round_up(nva, pad);
+    ag.nopa = round_up(noa, pad);
     ag.nmopa = ag.nvpa + ag.nopa;
     ag.nvta = ag.nvpa / TILE;
     ag.ncta = ag.nmopa / TILE;
-    ag.nvpb = round_up(nvb, TILE);
-    ag.nopb = round_up(nob, TILE);
+    ag.nvpb = round_up(nvb, pad);
+    ag.nopb = round_up(nob, pad);
     ag.nmopb = ag.nvpb + ag.nopb;
     ag.nvtb = ag.nvpb / TILE;
     ag.nctb = ag.nmopb / TILE;
     ag.nvv = g.nvv;
     ag.noo = g.noo;
     ag.n = g.n;
-    const size_t esz = c->st == Store::F32 ? 4 : 8;
+    const size_t esz = c->st == Store::F64 ? 8 : (c->st == Store::F32 ? 4 : 2);
+    const size_t nplanes = c->st == Store::BF16 ? 3 : 1;  // BF16: hi, mid, lo
     auto stage_spin = [&](const double* Lin, int nocc_s, int nv_s, int nvp_s, int nmop_s,
                           void** out) -> pprpa_status {
       std::vector<int> src(nmop_s, -1);
@@ -583,13 +589,14 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
       PPRPA_TRY(dalloc(c, nmop_s * sizeof(int), (void**)&d_src));
       PPRPA_HIP(hipMemcpyAsync(d_src, src.data(), nmop_s * sizeof(int), hipMemcpyHostToDevice,
                                c->stream));
-      PPRPA_TRY(dalloc(c, (size_t)naux * nmop_s * nmop_s * esz, out));
+      const size_t plane_s = (size_t)naux * nmop_s * nmop_s;
+      PPRPA_TRY(dalloc(c, plane_s * esz * nplanes, out));
       Geometry gs;
       gs.nmop = nmop_s;
       for (int p0 = 0; p0 < naux; p0 += 65535) {
         const int np = std::min(65535, naux - p0);
         PPRPA_HIP(launch_stage_L(gs, c->st, Lin + (size_t)p0 * nmo * nmo, nmo, p0, np, d_src,
-                                 *out, 0, d_bad, c->stream));
+                                 *out, plane_s, d_bad, c->stream));
       }
       return PPRPA_OK;
     };
@@ -600,8 +607,9 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
     c->L = la_p;
     c->Lb = lb_p;
     const size_t zt = (size_t)c->kcap * ag.nmopb * ag.nmopa;
-    PPRPA_TRY(dalloc(c, zt * esz, &c->ZT));
-    PPRPA_HIP(hipMemsetAsync(c->ZT, 0, zt * esz, c->stream));
+    c->zplane = zt;
+    PPRPA_TRY(dalloc(c, zt * esz * nplanes, &c->ZT));
+    PPRPA_HIP(hipMemsetAsync(c->ZT, 0, zt * esz * nplanes, c->stream));
     std::vector<int> items;
     make_sigma_items_ab(ag, items, c->plan.npan_v);
     c->plan.nitems = (int)items.size();
@@ -611,7 +619,7 @@ pprpa_status build_ab_impl(const pprpa_build_ab_args* a, pprpa_ctx* c) {
     size_t sp_max = 0;
     for (int kk = 1; kk <= c->kcap; ++kk)
       sp_max = std::max(sp_max, (size_t)nsplit_for(c, kk) * kk);
-    PPRPA_TRY(dalloc(c, sp_max * ag.nmopa * ag.nmopb * esz, &c->Sp));
+    PPRPA_TRY(dalloc(c, sp_max * ag.nmopa * ag.nmopb * (c->st == Store::F64 ? 8 : 4), &c->Sp));
   } else {
     PPRPA_TRY(dalloc(c, (size_t)g.n * g.n * sizeof(double), (void**)&c->M));
     PPRPA_HIP(launch_dense_build_ab(La, Lb, naux, nmo, noa, nob, g.n, g.nvv, c->ptab, c->epair,
@@ -840,8 +848,8 @@ pprpa_status pprpa_build_ab(const pprpa_build_ab_args* a, pprpa_ctx** out) {
   if (!a->eps_a || !a->eps_b || !a->Lpq_a || !a->Lpq_b)
     return einval("eps_a, eps_b, Lpq_a and Lpq_b must not be NULL");
   if (a->prec < PPRPA_FP64 || a->prec > PPRPA_BF16X3) return einval("prec=%d", a->prec);
-  if (a->prec != PPRPA_FP64 && !(a->prec == PPRPA_FP32 && a->density_fitted)) {
-    set_error("the alpha-beta sector takes FP64, or FP32 sigma when density fitted (prec=%d)",
+  if (a->prec != PPRPA_FP64 && !(a->prec >= PPRPA_FP32 && a->prec <= PPRPA_BF16X3 && a->density_fitted)) {
+    set_error("the alpha-beta sector takes FP64, or FP32 or BF16-split sigma when density fitted (prec=%d)",
               a->prec);
     return PPRPA_EUNSUPPORTED;
   }

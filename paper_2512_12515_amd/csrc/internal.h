@@ -129,14 +129,15 @@ struct AbParams {
   int64_t la_stride, lb_stride, zt_stride, q_stride;
 };
 void make_sigma_items_ab(const AbGeometry& g, std::vector<int>& items, int& npan_v);
-// Z^T[kv][d][c] from packed alpha-beta vectors z [k][n] (device), in the sigma precision st
-// (FP64 or FP32).
+// The packed alpha-beta vectors z [k][n] (device) unpacked in the sigma precision st: Z^T[kv][d][c]
+// for FP64 and FP32, Z[kv][c][d] as three BF16 planes zplane elements apart for BF16.
 hipError_t launch_unpack_ab(const AbGeometry& g, Store st, const double* z, int k, void* ZT,
-                            hipStream_t s);
-// Partial Q = sum_P La^P Z Lb^P per aux split: Qp [nsplit][k][nmopa][nmopb], in precision st.
-hipError_t launch_sigma_ab(const AbGeometry& g, Store st, const SigmaPlan& plan, const void* La,
-                           const void* Lb, const void* ZT, void* Qp, int k, int nsplit,
-                           hipStream_t s);
+                            size_t zplane, hipStream_t s);
+// Partial Q = sum_P La^P Z Lb^P per aux split: Qp [nsplit][k][nmopa][nmopb], in precision st (FP32
+// for BF16, whose nprod = 6 or 3 products; La, Lb then three planes of naux nmop^2 each).
+hipError_t launch_sigma_ab(const AbGeometry& g, Store st, int nprod, const SigmaPlan& plan,
+                           const void* La, const void* Lb, const void* ZT, size_t zplane, void* Qp,
+                           int k, int nsplit, hipStream_t s);
 // sigma [k][n] = epair * z + the split sums of Qp (fixed order, FP64).
 hipError_t launch_epilogue_ab(const AbGeometry& g, Store st, const double* z, int k,
                               const void* Qp, int nsplit, const double* epair, double* sigma,

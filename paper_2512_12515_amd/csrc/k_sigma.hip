@@ -37,6 +37,7 @@
 //     run at the same time on one XCD and read its L^P tiles from that XCD's L2.
 #include "internal.h"
 #include "sigma_common.h"
+#include "sigma_bf16.h"
 
 namespace pprpa {
 namespace {
@@ -63,14 +64,6 @@ template <typename T> __device__ __forceinline__ int acc_row(int lk, int j);
 template <> __device__ __forceinline__ int acc_row<double>(int lk, int j) { return lk + 4 * j; }
 template <> __device__ __forceinline__ int acc_row<float>(int lk, int j) { return 4 * lk + j; }
 
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  unsigned r = 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)((u + r) >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(unsigned short h) {
-  return __uint_as_float(((unsigned)h) << 16);
-}
 
 // ------------------------------------------------------------------------------------------
 // Staging of L into the padded [P][nmop][nmop] layout in the sigma precision.

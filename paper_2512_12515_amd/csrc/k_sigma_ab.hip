@@ -12,6 +12,10 @@
 // holds A x + B y in its virtual-virtual block and B^T x + C y in its occupied-occupied block:
 //   sigma_x(ab) = (e^a_a + e^b_b) x_ab + Q[a][b],   sigma_y(ij) = -(e^a_i + e^b_j) y_ij + Q[i][j].
 //
+// BF16-split sigma (k_sandwich_ab_bf16): the integrals and Z carried as BF16 planes, contraction 1
+// reducing over d and contraction 2 over c in blocks of 32 on the BF16 MFMA (blocks padded to 32
+// orbitals), T split into planes in LDS between them, as the restricted rows-form BF16 kernel.
+//
 // Kernel design: the two contractions of the restricted sandwich kernel, one workgroup of 4
 // waves per (vector, panel of up to 4 beta column tiles, range of up to RT alpha row tiles, aux
 // range), wave w owning column tile w: contraction 1, T[c][cols] = sum_d Z[c][d] Lb^P[d][cols]
@@ -21,6 +25,7 @@
 // index is split over workgroups and the partial Q are summed in a fixed order by the epilogue.
 #include "internal.h"
 #include "sigma_common.h"
+#include "sigma_bf16.h"
 
 namespace pprpa {
 namespace {
@@ -293,13 +298,252 @@ __global__ __launch_bounds__(256) void k_epilogue_ab(const double* __restrict__ 
   if (e0 < n) sigma[(int64_t)kv * n + e] = epair[e] * z[(int64_t)kv * n + e] + acc;
 }
 
+// Z[kv][c][d] (alpha row c, beta column d contiguous) of the packed alpha-beta vectors as three
+// BF16 planes (hi, mid, lo) zplane elements apart; positions outside the two blocks keep the
+// zeros they were cleared to at build.
+__global__ void k_unpack_ab_bf16(const double* __restrict__ z, int64_t n, int64_t nvv, int nvb,
+                                 int nob, int nvpa, int nvpb, int nmopb, int64_t zstride,
+                                 u16* __restrict__ ZU, size_t zplane) {
+  const int kv = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  int c, d;
+  if (e < nvv) {
+    c = (int)(e / nvb);
+    d = (int)(e % nvb);
+  } else {
+    const int64_t s = e - nvv;
+    c = nvpa + (int)(s / nob);
+    d = nvpb + (int)(s % nob);
+  }
+  const double v = z[(int64_t)kv * n + e];
+  const unsigned short h = bf16_rne((float)v);
+  const double r1 = v - (double)bf16_to_f(h);
+  const unsigned short m = bf16_rne((float)r1);
+  const double r2 = r1 - (double)bf16_to_f(m);
+  const unsigned short l = bf16_rne((float)r2);
+  const size_t o = (size_t)kv * zstride + (size_t)c * nmopb + d;
+  ZU[o] = h;
+  ZU[o + zplane] = m;
+  ZU[o + 2 * zplane] = l;
+}
+
+// LDS plan of the BF16 alpha-beta kernel (u16 elements): a staging buffer (contraction 1: rows c
+// of Z and rows of Lb^P for the panel's columns, one 32-wide d block; contraction 2: RH rows of
+// La^P, one 32-wide c block), then T of the current chunk as NPL planes [64 columns][TWP] (c
+// contiguous; rows padded by 8 elements against bank conflicts).
+template <int NPL>
+struct AbBf16Cfg {
+  static constexpr int CT = NPL == 3 ? 6 : 8;   // alpha c tiles per chunk (three planes: 69 KiB,
+                                                // two workgroups per CU)
+  static constexpr int RH = NPL == 3 ? 8 : 16;  // alpha row tiles per contraction-2 stage
+  static constexpr int US = CT * TILE * KB;
+  static constexpr int LS = 4 * TILE * KB;
+  static constexpr int S1 = NPL * (US + LS);
+  static constexpr int RS = RH * TILE * KB;
+  static constexpr int S2 = NPL * RS;
+  static constexpr int STAGE = S1 > S2 ? S1 : S2;
+  static constexpr int TWP = CT * TILE + 8;
+  static constexpr int TS = 4 * TILE * TWP;
+  static constexpr int BUF = STAGE + NPL * TS;
+};
+
+// One work unit as in k_sandwich_ab (vector, panel of up to 4 beta column tiles, AB_RT alpha row
+// tiles, aux range), 4 waves: contraction 1 by column (wave w: T of column tile w), contraction 2
+// by rows (row tile 4 q + w of each contraction-2 stage to wave w, every column of the panel);
+// NPROD = 6 (planes hi, mid, lo) or 3 (hi, mid) products per pair of operands. Partial Q in FP32.
+template <int NPROD>
+__global__ __launch_bounds__(256) void k_sandwich_ab_bf16(const u16* __restrict__ La,
+                                                          const u16* __restrict__ Lb,
+                                                          const u16* __restrict__ ZU,
+                                                          float* __restrict__ Qp, AbParams a,
+                                                          size_t plane_a, size_t plane_b,
+                                                          size_t zplane) {
+  constexpr int NPL = NPROD == 6 ? 3 : 2;
+  using Cfg = AbBf16Cfg<NPL>;
+  constexpr int RT = AB_RT, RH = Cfg::RH, CT = Cfg::CT;
+  static_assert(RT % RH == 0 && RH % 4 == 0 && CT % 2 == 0, "tile groups");
+  __shared__ __attribute__((aligned(1024))) u16 buf[Cfg::BUF];
+  const int g = blockIdx.x;
+  const int u = (g & 7) * a.per_xcd + (g >> 3);
+  if (u >= a.nunits) return;
+  const int item = a.items[(u / a.k) % a.nitems];
+  const int kv = u % a.k;
+  const int sp = u / (a.nitems * a.k);
+  const int pn = item >> 16;
+  const int R0 = item & 0xFFFF;
+  const bool vblk = pn < a.npan_v;
+  const int t0 = vblk ? 4 * pn : 4 * (pn - a.npan_v);
+  const int bntb = vblk ? a.nvtb : (a.nctb - a.nvtb);
+  const int bnta = vblk ? a.nvta : (a.ncta - a.nvta);
+  const int col0 = (vblk ? 0 : a.nvpb) + t0 * TILE;
+  const int row0 = (vblk ? 0 : a.nvpa) + R0 * TILE;
+  const int npt = min(4, bntb - t0);
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const bool active = w < npt;  // contraction 1: wave w computes T for column tile w
+  const int wc = min(w, npt - 1);
+  const int nrt = min(bnta, R0 + RT) - R0;
+  const int ncol = npt * TILE;
+  const int P0 = (int)((int64_t)a.naux * sp / a.nsplit);
+  const int P1 = (int)((int64_t)a.naux * (sp + 1) / a.nsplit);
+  const u16* __restrict__ Z = ZU + (int64_t)kv * a.zt_stride;
+  u16* const sU = buf;
+  u16* const sL = buf + NPL * Cfg::US;
+  u16* const sT = buf + Cfg::STAGE;
+
+  f4 S[RT / 4][4];
+#pragma unroll
+  for (int q = 0; q < RT / 4; ++q)
+#pragma unroll
+    for (int cw = 0; cw < 4; ++cw) S[q][cw] = f4{0, 0, 0, 0};
+
+  for (int P = P0; P < P1; ++P) {
+    const u16* __restrict__ Lap = La + (int64_t)P * a.la_stride;
+    const u16* __restrict__ Lbp = Lb + (int64_t)P * a.lb_stride;
+    for (int cc0 = 0; cc0 < a.ncta; cc0 += CT) {
+      const int cc1 = min(cc0 + CT, a.ncta);
+      f4 Tacc[CT];
+#pragma unroll
+      for (int i = 0; i < CT; ++i) Tacc[i] = f4{0, 0, 0, 0};
+      // contraction 1: T[c][cols] = sum_d Z[c][d] Lb^P[d][cols]; part 0 pairs the chunk's alpha
+      // virtual c tiles with the beta virtual d, part 1 its alpha occupied c tiles with the beta
+      // occupied d; one 32-wide block of d per stage
+      for (int part = 0; part < 2; ++part) {
+        const int clo = part == 0 ? cc0 : max(cc0, a.nvta);
+        const int chi = part == 0 ? min(cc1, a.nvta) : cc1;
+        const int dlo = part == 0 ? 0 : a.nvtb, dhi = part == 0 ? a.nvtb : a.nctb;
+        if (clo >= chi) continue;  // uniform
+        for (int dt = dlo; dt < dhi; dt += 2) {
+          __syncthreads();
+#pragma unroll
+          for (int p = 0; p < NPL; ++p) {
+            dma_tile32(Z + p * zplane + (int64_t)(clo * TILE) * a.nmopb + dt * TILE, a.nmopb,
+                       (chi - clo) * TILE, sU + p * Cfg::US, w, lane);
+            dma_tile32(Lbp + p * plane_b + (int64_t)col0 * a.nmopb + dt * TILE, a.nmopb, ncol,
+                       sL + p * Cfg::LS, w, lane);
+          }
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+          if (active) {
+            const int lrow = (wc * TILE + li) * KB + 8 * (lk ^ swz(li));
+            bf8 bv[NPL];
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) bv[p] = *(const bf8*)(sL + p * Cfg::LS + lrow);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              const int cg = cc0 + ct;
+              if (cg >= clo && cg < chi) {
+                const int urow = ((cg - clo) * TILE + li) * KB + 8 * (lk ^ swz(li));
+                bf8 av[NPL];
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) av[p] = *(const bf8*)(sU + p * Cfg::US + urow);
+                Tacc[ct] = split_mfma<NPROD>(av[0], av[1], av[NPL - 1], bv[0], bv[1], bv[NPL - 1],
+                                             Tacc[ct]);
+              }
+            }
+          }
+        }
+      }
+      // T of this chunk into LDS, split, transposed: sT[p][col][c]; a lane holds rows
+      // 4 lk .. 4 lk + 3 of each c tile for column li of its tile (the barrier: the previous
+      // chunk's contraction 2 has read sT, also when this chunk had no contraction-1 stage)
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          bf4 tp[NPL];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            __bf16 h, m, l;
+            split3(Tacc[ct][j], h, m, l);
+            tp[0][j] = h;
+            tp[1][j] = m;
+            if (NPL == 3) tp[NPL - 1][j] = l;
+          }
+          const int o = (wc * TILE + li) * Cfg::TWP + ct * TILE + 4 * lk;
+#pragma unroll
+          for (int p = 0; p < NPL; ++p) *(bf4*)(sT + p * Cfg::TS + o) = tp[p];
+        }
+      }
+      __syncthreads();
+      // contraction 2: S[r][cols] += sum_c La^P[r][c] T[c][cols] over every c of the chunk (La^P
+      // couples the alpha blocks), one 32-wide block of c (two tiles of T) at a time; B operands
+      // from LDS, A (rows of La^P) staged RH row tiles at a time
+#pragma unroll
+      for (int cb = 0; cb < CT / 2; ++cb) {
+        if (cc0 + 2 * cb < cc1) {
+          bf8 B[4][NPL];
+#pragma unroll
+          for (int cw = 0; cw < 4; ++cw)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+              B[cw][p] = *(const bf8*)(sT + p * Cfg::TS + (min(cw, npt - 1) * TILE + li) * Cfg::TWP +
+                                       cb * KB + 8 * lk);
+#pragma unroll
+          for (int half = 0; half < RT / RH; ++half) {
+            const int rh0 = half * RH;
+            if (rh0 < nrt) {
+              const int nr = min(RH, nrt - rh0);
+              __syncthreads();
+#pragma unroll
+              for (int p = 0; p < NPL; ++p)
+                dma_tile32(Lap + p * plane_a + (int64_t)(row0 + rh0 * TILE) * a.nmopa +
+                               (cc0 + 2 * cb) * TILE,
+                           a.nmopa, nr * TILE, buf + p * Cfg::RS, w, lane);
+              __builtin_amdgcn_s_waitcnt(0);
+              __syncthreads();
+#pragma unroll
+              for (int rr = 0; rr < RH / 4; ++rr) {
+                const int r = 4 * rr + w;
+                if (r < nr) {
+                  const int o = (r * TILE + li) * KB + 8 * (lk ^ swz(li));
+                  bf8 av[NPL];
+#pragma unroll
+                  for (int p = 0; p < NPL; ++p) av[p] = *(const bf8*)(buf + p * Cfg::RS + o);
+#pragma unroll
+                  for (int cw = 0; cw < 4; ++cw)
+                    if (cw < npt)
+                      S[half * (RH / 4) + rr][cw] =
+                          split_mfma<NPROD>(av[0], av[1], av[NPL - 1], B[cw][0], B[cw][1],
+                                            B[cw][NPL - 1], S[half * (RH / 4) + rr][cw]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  float* __restrict__ out = Qp + ((int64_t)sp * a.k + kv) * a.q_stride;
+#pragma unroll
+  for (int half = 0; half < RT / RH; ++half)
+#pragma unroll
+    for (int rr = 0; rr < RH / 4; ++rr) {
+      const int rt = half * RH + 4 * rr + w;
+      if (rt < nrt) {
+#pragma unroll
+        for (int cw = 0; cw < 4; ++cw)
+          if (cw < npt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              out[(int64_t)(row0 + rt * TILE + 4 * lk + j) * a.nmopb + col0 + cw * TILE + li] =
+                  S[half * (RH / 4) + rr][cw][j];
+      }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_unpack_ab(const AbGeometry& g, Store st, const double* z, int k, void* ZT,
-                            hipStream_t s) {
+                            size_t zplane, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)k);
-  if (st == Store::F64)
+  if (st == Store::BF16)
+    hipLaunchKernelGGL(k_unpack_ab_bf16, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
+                       g.nvpa, g.nvpb, g.nmopb, (int64_t)g.nmopa * g.nmopb, (u16*)ZT, zplane);
+  else if (st == Store::F64)
     hipLaunchKernelGGL(k_unpack_ab<double>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
                        g.nvpa, g.nvpb, g.nmopa, g.nmopb, (double*)ZT);
   else if (st == Store::F32)
@@ -310,9 +554,9 @@ hipError_t launch_unpack_ab(const AbGeometry& g, Store st, const double* z, int 
   return hipGetLastError();
 }
 
-hipError_t launch_sigma_ab(const AbGeometry& g, Store st, const SigmaPlan& plan, const void* La,
-                           const void* Lb, const void* ZT, void* Qp, int k, int nsplit,
-                           hipStream_t s) {
+hipError_t launch_sigma_ab(const AbGeometry& g, Store st, int nprod, const SigmaPlan& plan,
+                           const void* La, const void* Lb, const void* ZT, size_t zplane, void* Qp,
+                           int k, int nsplit, hipStream_t s) {
   AbParams p;
   p.nvta = g.nvta;
   p.ncta = g.ncta;
@@ -340,6 +584,14 @@ hipError_t launch_sigma_ab(const AbGeometry& g, Store st, const SigmaPlan& plan,
   else if (st == Store::F32)
     hipLaunchKernelGGL((k_sandwich_ab<float, AB_CT, AB_RT>), dim3(p.per_xcd * 8), dim3(256), 0, s,
                        (const float*)La, (const float*)Lb, (const float*)ZT, (float*)Qp, p);
+  else if (nprod == 6)
+    hipLaunchKernelGGL(k_sandwich_ab_bf16<6>, dim3(p.per_xcd * 8), dim3(256), 0, s,
+                       (const u16*)La, (const u16*)Lb, (const u16*)ZT, (float*)Qp, p,
+                       (size_t)g.naux * p.la_stride, (size_t)g.naux * p.lb_stride, zplane);
+  else if (nprod == 3)
+    hipLaunchKernelGGL(k_sandwich_ab_bf16<3>, dim3(p.per_xcd * 8), dim3(256), 0, s,
+                       (const u16*)La, (const u16*)Lb, (const u16*)ZT, (float*)Qp, p,
+                       (size_t)g.naux * p.la_stride, (size_t)g.naux * p.lb_stride, zplane);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -355,7 +607,7 @@ hipError_t launch_epilogue_ab(const AbGeometry& g, Store st, const double* z, in
     hipLaunchKernelGGL(k_epilogue_ab<double>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
                        g.nvpa, g.nvpb, g.nmopb, (const double*)Qp, nsplit, (int64_t)k * q_stride,
                        q_stride, epair, sigma);
-  else if (st == Store::F32)
+  else if (st == Store::F32 || st == Store::BF16)
     hipLaunchKernelGGL(k_epilogue_ab<float>, grid, dim3(256), 0, s, z, g.n, g.nvv, g.nvb, g.nob,
                        g.nvpa, g.nvpb, g.nmopb, (const float*)Qp, nsplit, (int64_t)k * q_stride,
                        q_stride, epair, sigma);

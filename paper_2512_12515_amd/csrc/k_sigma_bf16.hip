@@ -33,17 +33,12 @@
 // at that size (a timing probe of an 8-wave form on 4-tile panels ran 1.44x faster with its
 // loads removed; double-buffering alone did not help it).
 #include "sigma_common.h"
+#include "sigma_bf16.h"
 
 namespace pprpa {
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-typedef unsigned short u16;
-
 constexpr int RT = 32;  // row tiles per work unit (equals the FP32 kernel's, same work items)
-constexpr int KB = 32;  // reduction block of one MFMA
 
 // Six products (two planes more than three) use the columns-per-wave kernel; its LDS holds one
 // staging buffer (a contraction-1 stage or a contraction-2 stage of RH row tiles).
@@ -76,49 +71,6 @@ struct Bf16RowsCfg {
 template <int NPROD>
 constexpr int bf16_buf() {
   return NPROD == 6 ? Bf16ColsCfg::BUF : Bf16RowsCfg::BUF;
-}
-
-// LDS layout of a staged rows x 32 BF16 tile: each 64-byte row holds four 16-byte chunks, stored
-// at position kc ^ swz(row) so that the lanes one LDS cycle serves (rows r .. r+7 or r .. r+15 of
-// one chunk column) fall in distinct banks. The direct global->LDS loads write each wave's 1 KiB
-// contiguously, so the permutation is applied to the global addresses instead.
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
-
-template <int NWV = 4>
-__device__ __forceinline__ void dma_tile32(const u16* __restrict__ src, int64_t ld, int rows,
-                                           u16* dst, int w, int lane) {
-  const int nchunk = rows / 16;  // 16 rows x 64 bytes per wave load
-  for (int j = w; j < nchunk; j += NWV) {
-    const int row = j * 16 + (lane >> 2), pos = lane & 3;
-    __builtin_amdgcn_global_load_lds((const void*)(src + row * ld + 8 * (pos ^ swz(row))),
-                                     (lds_ptr_t)(dst + j * 512), 16, 0, 0);
-  }
-}
-
-__device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// a b over the split planes (NPROD = 6 or 3 products).
-template <int NPROD>
-__device__ __forceinline__ f4 split_mfma(bf8 ah, bf8 am, bf8 al, bf8 bh, bf8 bm, bf8 bl, f4 c) {
-  c = mfma(ah, bh, c);
-  c = mfma(ah, bm, c);
-  c = mfma(am, bh, c);
-  if (NPROD == 6) {
-    c = mfma(am, bm, c);
-    c = mfma(ah, bl, c);
-    c = mfma(al, bh, c);
-  }
-  return c;
-}
-
-__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
-  h = (__bf16)x;
-  const float r1 = x - (float)h;  // exact
-  m = (__bf16)r1;
-  const float r2 = r1 - (float)m;  // exact
-  l = (__bf16)r2;
 }
 
 // acc[i][j] += a_i b_j over the split planes for an NA x NB grid of tiles, the products taken in

@@ -11,11 +11,14 @@
   blocks): sigma against the oracle's M z at ragged shapes and against the dense context, the
   Davidson roots of both channels against the oracle, a sector of order 33120 (beyond the dense
   limit, which is refused) on sampled rows of the oracle, and the dense-only calls refused;
-* the density-fitted alpha-beta sector with FP32 sigma: sigma against the oracle's M z at the
-  same shapes and on sampled rows at order 33120, roots of both channels against the oracle.
+* the density-fitted alpha-beta sector with FP32 and BF16-split sigma: sigma against the
+  oracle's M z at the same shapes and on sampled rows at order 33120, six BF16 products at least
+  20x more accurate than three on the same inputs, roots of both channels against the oracle.
 Tolerances: matrices and sigma 1e-12 relative, eigenvalues 1e-9 Ha (FP64, tol 1e-10); FP32
 sigma 2e-7 relative to max|M z| on the small shapes, 1e-6 at order 33120 (the level of FP32
-operands and accumulation, as for the restricted FP32 kernel), FP32 roots 1e-6 Ha.
+operands and accumulation, as for the restricted FP32 kernel); BF16x6 / BF16x3 sigma 1e-7 /
+2.5e-6 on the small shapes (TOL_AB_BF16), BF16x6 1e-6 at order 33120; reduced-precision roots
+1e-6 Ha.
 """
 import sys
 
@@ -193,11 +196,71 @@ def test_ab_df_fp32_davidson_vs_oracle(channel, nroot):
     assert err <= 1e-6
 
 
+# relative to max |M z|; measured on the MI355X over AB_DF_CASES (BF16x6 8.4e-9 - 3.5e-8, BF16x3
+# 4.1e-7 - 9.6e-7), then frozen at about 2.5x the largest value seen
+TOL_AB_BF16 = {"bf16x6": 1e-7, "bf16x3": 2.5e-6}
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+@pytest.mark.parametrize("case", AB_DF_CASES)
+def test_ab_df_sigma_bf16_vs_oracle(case, prec):
+    """BF16-split density-fitted alpha-beta sigma (integrals and amplitudes as hi/mid/lo BF16
+    planes, six or three products on the BF16 MFMA, FP32 accumulation, FP64 epilogue) against
+    M z of the oracle's alpha-beta matrix; shapes with one or no occupied beta orbital and
+    blocks that are not multiples of 32 orbitals included."""
+    nmo, noa, nob, naux = case
+    note("ab df sigma", prec, case)
+    ea, eb, La, Lb = unrestricted(81, nmo, noa, nob, naux)
+    Mref, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec=prec) as ctx:
+        z = gen.random_vectors(82, 6, ctx.n)
+        s = ctx.matvec(z)
+        s1 = ctx.matvec(z[2])
+    sref = z @ Mref.T
+    err = np.max(np.abs(s - sref)) / np.abs(sref).max()
+    note("relative error", err)
+    assert err <= TOL_AB_BF16[prec]
+    assert np.array_equal(s1, s[2])
+
+
+def test_ab_bf16x6_beats_bf16x3():
+    """The two BF16 schemes on the same alpha-beta inputs: six products at least 20 times more
+    accurate than three, which tells the arithmetic that ran apart."""
+    for case in [(30, 7, 5, 40), (45, 10, 9, 60)]:
+        nmo, noa, nob, naux = case
+        ea, eb, La, Lb = unrestricted(81, nmo, noa, nob, naux)
+        Mref, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+        err = {}
+        for prec in ("bf16x6", "bf16x3"):
+            with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True,
+                                    prec=prec) as ctx:
+                z = gen.random_vectors(82, 6, ctx.n)
+                s = ctx.matvec(z)
+            sref = z @ Mref.T
+            err[prec] = np.max(np.abs(s - sref)) / np.abs(sref).max()
+        note(case, "x6 %.2e x3 %.2e" % (err["bf16x6"], err["bf16x3"]))
+        assert err["bf16x6"] <= err["bf16x3"] / 20.0
+
+
+@pytest.mark.parametrize("channel,nroot", [("pp", 6), ("hh", 4)])
+def test_ab_df_bf16x6_davidson_vs_oracle(channel, nroot):
+    """BF16x6 sigma, FP64 subspace algebra: every root within 1e-6 Ha of the oracle's."""
+    nmo, noa, nob, naux = 45, 10, 9, 60
+    note("ab df davidson bf16x6", channel)
+    ea, eb, La, Lb = unrestricted(83, nmo, noa, nob, naux)
+    ref = O.solve_ab(ea, eb, La, Lb, noa, nob, nroot, channel=channel)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec="bf16x6") as ctx:
+        r = ctx.davidson(nroot, block=nroot, tol=1e-5, channel=channel)
+    err = np.max(np.abs(r["omega"] - ref))
+    note("max root error", err)
+    assert r["status"] == 0
+    assert err <= 1e-6
+
+
 def test_ab_df_precision_refusals():
-    """The alpha-beta sector takes FP32 sigma only density fitted, and no BF16 split."""
+    """The alpha-beta sector takes reduced-precision sigma only density fitted."""
     ea, eb, La, Lb = unrestricted(88, 12, 3, 2, 20)
-    for kw in (dict(prec="fp32"), dict(prec="bf16x6", density_fitted=True),
-               dict(prec="bf16x3", density_fitted=True)):
+    for kw in (dict(prec="fp32"), dict(prec="bf16x6"), dict(prec="bf16x3")):
         with pytest.raises(P.PpRPAError) as e:
             P.PpRPA.alpha_beta(ea, eb, La, Lb, 3, 2, **kw)
         assert e.value.status == P.binding.EUNSUPPORTED
@@ -233,6 +296,8 @@ def test_ab_df_beyond_the_dense_limit():
         r = ctx.davidson(5, block=10, tol=1e-7)
     with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec="fp32") as c32:
         s32 = c32.matvec(z)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True, prec="bf16x6") as c16:
+        s16 = c16.matvec(z)
     rng = np.random.default_rng(4)
     nvv = 180 * 182
     rows = np.unique(np.r_[np.arange(3), nvv - 3 + np.arange(6), ctx.n - 3 + np.arange(3),
@@ -241,8 +306,9 @@ def test_ab_df_beyond_the_dense_limit():
         ref = O.ab_sigma_rows(ea, eb, La, Lb, noa, nob, rows, z[j])
         assert np.max(np.abs(s[j, rows] - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
         err32 = np.max(np.abs(s32[j, rows] - ref)) / np.abs(s32[j]).max()
-        note("fp32 relative error", err32)
-        assert err32 <= 1e-6
+        err16 = np.max(np.abs(s16[j, rows] - ref)) / np.abs(s16[j]).max()
+        note("fp32 / bf16x6 relative error", err32, err16)
+        assert err32 <= 1e-6 and err16 <= 1e-6
     assert r["status"] == 0 and np.all(r["resid"] <= 1e-7)
     assert np.all(np.diff(r["omega"]) >= 0)
 
