@@ -390,6 +390,36 @@ def midgap_ab(eps_a, eps_b, nocc_a, nocc_b):
     return 0.5 * lumo - 1.0
 
 
+def nto_ab(z, nvir_a, nvir_b, nocc_a, nocc_b):
+    """NTOs of one alpha-beta root z = [x; y] (Eqs. nto_pp, nto_hh): the amplitude matrices are
+    rectangular here, X nvir_a x nvir_b and Y nocc_a x nocc_b (alpha index outer, the packed
+    order of ab_sector), and X = C^p1 sqrt(lam^p) C^p2^T with alpha NTOs C^p1 and beta NTOs C^p2
+    (likewise Y). Returns lam^p (nvir_a) and lam^h (nocc_a), descending, the squared singular
+    values followed by zeros when the alpha side is the longer one, and (C^p1, C^p2, C^h1, C^h2)."""
+    nvv = nvir_a * nvir_b
+    X = z[:nvv].reshape(nvir_a, nvir_b)
+    Y = z[nvv:].reshape(nocc_a, nocc_b)
+    lp, lh = np.zeros(nvir_a), np.zeros(nocc_a)
+    U, sx, Vt = np.linalg.svd(X)
+    lp[:sx.size] = sx ** 2
+    if Y.size:
+        Uh, sy, Vht = np.linalg.svd(Y)
+        lh[:sy.size] = sy ** 2
+    else:
+        Uh, Vht = np.eye(nocc_a), np.eye(nocc_b)
+    return lp, lh, (U, Vt.T, Uh, Vht.T)
+
+
+def density_2e_ab(z, nvir_a, nvir_b, nocc_a, nocc_b):
+    """Two-electron addition/removal part of the one-particle density of an alpha-beta root
+    (section "Density Matrix"), resolved by spin (the pair holds one electron of each):
+    D^alpha_vv = X X^T, D^beta_vv = X^T X, D^alpha_oo = -Y Y^T, D^beta_oo = -Y^T Y."""
+    nvv = nvir_a * nvir_b
+    X = z[:nvv].reshape(nvir_a, nvir_b)
+    Y = z[nvv:].reshape(nocc_a, nocc_b)
+    return X @ X.T, X.T @ X, -(Y @ Y.T), -(Y.T @ Y)
+
+
 def solve_ab(eps_a, eps_b, La, Lb, nocc_a, nocc_b, nroot, channel="pp", vectors=False):
     """Lowest nroot pp roots (or the nroot hh roots nearest the gap) of the alpha-beta sector."""
     M, nvv = ab_sector(eps_a, eps_b, La, Lb, nocc_a, nocc_b)

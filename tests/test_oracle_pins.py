@@ -287,6 +287,60 @@ def unrestricted(seed, nmo, nocc_a, nocc_b, naux):
             gen.lpq_full(seed, nmo, naux), gen.lpq_full(seed + 1000, nmo, naux))
 
 
+def test_nto_ab_zero_interaction_closed_form():
+    """L = 0 in the alpha-beta sector: every root is a unit vector on one pair (a_alpha, b_beta)
+    (or (i, j)): one NTO pair of weight 1 (alpha side padded with zeros), D^alpha = E_aa,
+    D^beta = E_bb (with the sign of the channel)."""
+    nmo, noa, nob, naux = 7, 3, 2, 4
+    ea, eb, La, Lb = unrestricted(31, nmo, noa, nob, naux)
+    La[:] = 0.0
+    Lb[:] = 0.0
+    nva, nvb = nmo - noa, nmo - nob
+    M, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    Om, Z, sg = O.solve_definite(M, nvv, O.midgap_ab(ea, eb, noa, nob))
+    for j in range(Z.shape[1]):
+        z = Z[:, j]
+        k = int(np.argmax(np.abs(z)))
+        lp, lh, _ = O.nto_ab(z, nva, nvb, noa, nob)
+        Dva, Dvb, Doa, Dob = O.density_2e_ab(z, nva, nvb, noa, nob)
+        if sg[j] > 0:
+            a, b = divmod(k, nvb)
+            assert np.allclose(lp, np.r_[1.0, np.zeros(nva - 1)], atol=1e-14) and np.allclose(lh, 0.0)
+            assert np.allclose(Dva, np.diag(np.eye(nva)[a]), atol=1e-14)
+            assert np.allclose(Dvb, np.diag(np.eye(nvb)[b]), atol=1e-14)
+            assert np.allclose(Doa, 0.0) and np.allclose(Dob, 0.0)
+        else:
+            i, jj = divmod(k - nvv, nob)
+            assert np.allclose(lh, np.r_[1.0, np.zeros(noa - 1)], atol=1e-14) and np.allclose(lp, 0.0)
+            assert np.allclose(Doa, -np.diag(np.eye(noa)[i]), atol=1e-14)
+            assert np.allclose(Dob, -np.diag(np.eye(nob)[jj]), atol=1e-14)
+
+
+@pytest.mark.parametrize("nmo,noa,nob", [(12, 4, 2), (10, 2, 5), (9, 3, 0)])
+def test_nto_ab_sum_rules(nmo, noa, nob):
+    """Every alpha-beta root: sum(lam^p) - sum(lam^h) = +1 (pp) / -1 (hh); the traces of the
+    spin-resolved density blocks: Tr D^alpha_vv = Tr D^beta_vv = x^T x, Tr D^alpha_oo =
+    Tr D^beta_oo = -y^T y, in all +2 / -2; the SVD factors reproduce X; the nonzero weights
+    number at most min(nvir_a, nvir_b) (alpha longer or shorter than beta; no beta occupied)."""
+    ea, eb, La, Lb = unrestricted(33, nmo, noa, nob, 16)
+    nva, nvb = nmo - noa, nmo - nob
+    M, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    Om, Z, sg = O.solve_definite(M, nvv, O.midgap_ab(ea, eb, noa, nob))
+    for j in range(Z.shape[1]):
+        z = Z[:, j]
+        lp, lh, (U, V, Uh, Vh) = O.nto_ab(z, nva, nvb, noa, nob)
+        assert abs(lp.sum() - lh.sum() - sg[j]) <= 1e-12
+        Dva, Dvb, Doa, Dob = O.density_2e_ab(z, nva, nvb, noa, nob)
+        x2, y2 = z[:nvv] @ z[:nvv], z[nvv:] @ z[nvv:]
+        assert abs(np.trace(Dva) - x2) <= 1e-12 and abs(np.trace(Dvb) - x2) <= 1e-12
+        assert abs(np.trace(Doa) + y2) <= 1e-12 and abs(np.trace(Dob) + y2) <= 1e-12
+        assert abs(np.trace(Dva) + np.trace(Dvb) + np.trace(Doa) + np.trace(Dob) - 2 * sg[j]) <= 1e-12
+        X = z[:nvv].reshape(nva, nvb)
+        r = min(nva, nvb)
+        assert np.allclose(U[:, :r] @ np.diag(np.sqrt(lp[:r])) @ V[:, :r].T, X, atol=1e-13)
+        assert np.all(lp[r:] == 0.0) and np.all(np.diff(lp) <= 1e-15) and np.all(lp >= 0.0)
+
+
 @pytest.mark.parametrize("nocc,nvir,naux", [(2, 3, 7), (3, 5, 11), (4, 6, 20)])
 def test_ab_sector_with_alpha_equal_beta_is_singlet_plus_triplet(nocc, nvir, naux):
     """alpha = beta: the alpha-beta pairs carry both spin couplings, so the sector's spectrum is
