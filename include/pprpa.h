@@ -106,8 +106,8 @@ pprpa_status pprpa_build(const pprpa_build_args* args, pprpa_ctx** out);
  *    matrix is formed, so the order is limited by memory only (nvir, nocc < 65536);
  *    pprpa_dims, pprpa_matvec and pprpa_davidson (Davidson, both channels) apply, the direct
  *    solve, pprpa_dense_matrix and pprpa_correlation_energy return EUNSUPPORTED.
- * The density-fitted form also takes FP32 and BF16-split sigma (prec). pprpa_nto returns
- * EUNSUPPORTED for both. 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO) / 2. Inputs (host, or device with on_device) are read during the call only.
+ * The density-fitted form also takes FP32 and BF16-split sigma (prec). pprpa_nto takes both
+ * forms (rectangular amplitude blocks, see there). 2 mu = (e^a_HOMO + e^b_HOMO + e^a_LUMO + e^b_LUMO) / 2. Inputs (host, or device with on_device) are read during the call only.
  * Errors: EINVAL (arguments, non-finite input, energies of a spin not ascending within its
  * occupied or virtual block or its HOMO not below its LUMO), ENOMEM, EDEVICE. */
 typedef struct {
@@ -219,7 +219,13 @@ pprpa_status pprpa_correlation_energy_noalloc(pprpa_ctx* ctx, pprpa_corr_energy*
  * descending (sum lam_p - sum lam_h = z^T W z = +1 for a pp root, -1 for an hh root);
  * d_vv [k][nv][nv] = X X^T + X^T X and d_oo [k][no][no] = -(Y Y^T + Y^T Y) (host, may be NULL;
  * trace of the pair = +-2). 1 <= k <= 64, nv, no <= 512 (else EINVAL / EUNSUPPORTED). The call
- * allocates its device scratch (about 3 k (nv^2 + no^2) doubles) and frees it before returning. */
+ * allocates its device scratch (about 3 k (nv^2 + no^2) doubles) and frees it before returning.
+ * On an alpha-beta context (dense or density fitted) the amplitude blocks are rectangular: X is
+ * nvir_a x nvir_b and Y nocc_a x nocc_b (the packed order, alpha index outer); lam_p [k][nvir_a]
+ * and lam_h [k][nocc_a] receive the eigenvalues of X X^T and Y Y^T (the squared singular values,
+ * then zeros where the alpha side is the longer), d_vv [k][nvir_a^2 + nvir_b^2] the alpha block
+ * X X^T followed by the beta block X^T X, and d_oo [k][nocc_a^2 + nocc_b^2] = -(Y Y^T, Y^T Y)
+ * (one electron of each spin: each spin's trace is x^T x, or -y^T y); every block <= 512. */
 pprpa_status pprpa_nto(pprpa_ctx* ctx, int32_t k, const double* z, int32_t on_device,
                        double* lam_p, double* lam_h, double* d_vv, double* d_oo);
 

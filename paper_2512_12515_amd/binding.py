@@ -270,6 +270,7 @@ class PpRPA:
         self.n = self.n_pp + self.n_hh
         self.mult, self.prec = "alpha-beta", prec
         self.nv, self.no = a.nmo - a.nocc_a, a.nocc_a
+        self.nvb, self.nob = a.nmo - a.nocc_b, a.nocc_b
         return self
 
     def close(self):
@@ -333,6 +334,8 @@ class PpRPA:
             z = np.ascontiguousarray(np.atleast_2d(z), dtype=np.float64)
         k = int(z.shape[0])
         nv, no = self._dims_active()
+        if self.mult == "alpha-beta":
+            return self._nto_ab(z, on_dev, k, nv, no, density)
         lam_p, lam_h = np.empty((k, nv)), np.empty((k, no))
         d_vv = np.empty((k, nv, nv)) if density else None
         d_oo = np.empty((k, no, no)) if density else None
@@ -341,6 +344,26 @@ class PpRPA:
                                d_vv.ctypes.data if density else None,
                                d_oo.ctypes.data if (density and no) else None))
         return dict(lam_p=lam_p, lam_h=lam_h, d_vv=d_vv, d_oo=d_oo)
+
+    def _nto_ab(self, z, on_dev, k, nva, noa, density):
+        """pprpa_nto on an alpha-beta context: lam_p [k][nvir_a], lam_h [k][nocc_a] and the
+        spin-resolved density blocks d_vv_a [k][nvir_a][nvir_a] = X X^T, d_vv_b = X^T X,
+        d_oo_a = -Y Y^T, d_oo_b = -Y^T Y."""
+        nvb, nob = self.nvb, self.nob
+        lam_p, lam_h = np.empty((k, nva)), np.empty((k, noa))
+        dv = np.empty((k, nva * nva + nvb * nvb)) if density else None
+        do = np.empty((k, noa * noa + nob * nob)) if density else None
+        _check(lib().pprpa_nto(self._h, k, _ptr(z, on_dev), int(on_dev), lam_p.ctypes.data,
+                               lam_h.ctypes.data if noa else None,
+                               dv.ctypes.data if density else None,
+                               do.ctypes.data if (density and do.size) else None))
+        out = dict(lam_p=lam_p, lam_h=lam_h)
+        if density:
+            out.update(d_vv_a=dv[:, :nva * nva].reshape(k, nva, nva),
+                       d_vv_b=dv[:, nva * nva:].reshape(k, nvb, nvb),
+                       d_oo_a=do[:, :noa * noa].reshape(k, noa, noa),
+                       d_oo_b=do[:, noa * noa:].reshape(k, nob, nob))
+        return out
 
     def dense_matrix(self):
         M = np.empty((self.n, self.n))

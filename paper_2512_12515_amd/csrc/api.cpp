@@ -977,16 +977,75 @@ pprpa_status pprpa_correlation_energy_noalloc(pprpa_ctx* c, pprpa_corr_energy* o
   return corr_energy_run(c, work, out);
 }
 
+// NTOs of alpha-beta roots (pprpa_nto on an alpha-beta context): the rectangular blocks are the
+// packed vectors themselves, so only the Gram products and their eigenvalues run.
+static pprpa_status nto_ab(pprpa_ctx* c, int k, const double* z, int on_device, double* lam_p,
+                           double* lam_h, double* d_vv, double* d_oo) {
+  const Geometry& g = c->g;
+  const int nmo = g.nv + g.no, nva = g.nv, noa = g.no, nob = c->ab_nocc_b, nvb = nmo - nob;
+  if (nva > 512 || nvb > 512 || noa > 512 || nob > 512) {
+    set_error("NTOs on the device are limited to orbital blocks <= 512 (nvir %d/%d, nocc %d/%d)",
+              nva, nvb, noa, nob);
+    return PPRPA_EUNSUPPORTED;
+  }
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  const size_t zv = (size_t)k * g.n;
+  const size_t gv = (size_t)k * nva * nva, go = (size_t)k * noa * noa;
+  const size_t dv = (size_t)k * ((size_t)nva * nva + (size_t)nvb * nvb);
+  const size_t dov = (size_t)k * ((size_t)noa * noa + (size_t)nob * nob);
+  const size_t lv = (size_t)k * nva, lo = (size_t)k * noa;
+  // z (when on the host), Gx, Gy, Dv, Do, lam_p, lam_h
+  const size_t total = (on_device ? 0 : zv) + gv + go + dv + dov + lv + lo;
+  double* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, std::max<size_t>(total, 1) * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("NTO workspace of %zu bytes: %s", total * sizeof(double), hipGetErrorString(e));
+    return PPRPA_ENOMEM;
+  }
+  double* p = buf;
+  const double* dz = z;
+  if (!on_device) {
+    dz = p;
+    p += zv;
+  }
+  double* Gx = p; p += gv;
+  double* Gy = p; p += go;
+  double* Dv = p; p += dv;
+  double* Do = p; p += dov;
+  double* lp = p; p += lv;
+  double* lh = p;
+  hipStream_t s = c->stream;
+  hipError_t le = hipSuccess;
+  if (!on_device) le = hipMemcpyAsync((void*)dz, z, zv * sizeof(double), hipMemcpyHostToDevice, s);
+  if (le == hipSuccess)
+    le = launch_nto_ab(dz, g.n, k, nva, nvb, noa, nob, Gx, Gy, Dv, Do, lp, lh, s);
+  if (le == hipSuccess) le = hipMemcpyAsync(lam_p, lp, lv * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && lo) le = hipMemcpyAsync(lam_h, lh, lo * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && d_vv) le = hipMemcpyAsync(d_vv, Dv, dv * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && d_oo && dov)
+    le = hipMemcpyAsync(d_oo, Do, dov * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess) le = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (le != hipSuccess) {
+    set_error("NTO analysis: %s", hipGetErrorString(le));
+    return PPRPA_EDEVICE;
+  }
+  return PPRPA_OK;
+}
+
 pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_device, double* lam_p,
                        double* lam_h, double* d_vv, double* d_oo) {
   g_err.clear();
   if (!c) return einval("ctx is NULL");
   if (!z || !lam_p || (!lam_h && c->g.no > 0)) return einval("z, lam_p and lam_h must not be NULL");
   if (k < 1 || k > 64) return einval("k=%d outside [1, 64]", k);
-  if (c->ab) {
-    set_error("NTOs of the alpha-beta sector (rectangular amplitude matrices) are not provided");
-    return PPRPA_EUNSUPPORTED;
-  }
+  if (c->ab) return nto_ab(c, k, z, on_device, lam_p, lam_h, d_vv, d_oo);
   const Geometry& g = c->g;
   if (g.nv > 512 || g.no > 512) {
     set_error("NTOs on the device are limited to nv, no <= 512 (nv=%d, no=%d)", g.nv, g.no);

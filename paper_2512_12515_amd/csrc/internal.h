@@ -220,6 +220,13 @@ hipError_t launch_direct_pencil_mw(const double* M, int m, int64_t nvv, double m
 hipError_t launch_nto(const double* Z, int64_t ldz, int k, const Geometry& g, const int* ptab,
                       double* X, double* Y, double* Gx, double* Gy, double* Dv, double* Do,
                       double* lam_p, double* lam_h, hipStream_t s);
+// The same for k packed alpha-beta roots: X = nva x nvb and Y = noa x nob read in place from Z
+// (alpha index outer); Gx = X X^T [k][nva][nva], Gy = Y Y^T (destroyed); Dv [k][nva^2 + nvb^2]
+// = (X X^T, X^T X), Do [k][noa^2 + nob^2] = -(Y Y^T, Y^T Y) (may be null); lam_p [k][nva],
+// lam_h [k][noa] (eigenvalues of X X^T and Y Y^T, descending, clamped at zero). All <= 512.
+hipError_t launch_nto_ab(const double* Z, int64_t ldz, int k, int nva, int nvb, int noa, int nob,
+                         double* Gx, double* Gy, double* Dv, double* Do, double* lam_p,
+                         double* lam_h, hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

@@ -1102,6 +1102,31 @@ __global__ void k_triangular_products(const double* __restrict__ T, int m, doubl
   if (D) D[(int64_t)r * m * m + e] = sgn * (tt + ttt);
 }
 
+// Gram matrices of the rectangular amplitude blocks of alpha-beta roots: A = rows x cols
+// (row-major, at offset off of root r's packed vector, ld ldz), element e of A A^T (rows^2,
+// into G and sgn times it into D) or, for e >= rows^2, of A^T A (cols^2, sgn times it into D
+// after the rows^2 block). One thread per element, sums in a fixed order.
+__global__ void k_rect_products(const double* __restrict__ Z, int64_t ldz, int64_t off, int rows,
+                                int cols, double sgn, double* __restrict__ G,
+                                double* __restrict__ D) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int r = blockIdx.y;
+  const int64_t m1 = (int64_t)rows * rows, m2 = (int64_t)cols * cols;
+  if (e >= m1 + m2) return;
+  const double* A = Z + (int64_t)r * ldz + off;
+  double s = 0.0;
+  if (e < m1) {
+    const int i = (int)(e / rows), j = (int)(e % rows);
+    for (int c = 0; c < cols; ++c) s += A[(int64_t)i * cols + c] * A[(int64_t)j * cols + c];
+    G[(int64_t)r * m1 + e] = s;
+  } else {
+    const int64_t f = e - m1;
+    const int i = (int)(f / cols), j = (int)(f % cols);
+    for (int c = 0; c < rows; ++c) s += A[(int64_t)c * cols + i] * A[(int64_t)c * cols + j];
+  }
+  if (D) D[(int64_t)r * (m1 + m2) + e] = sgn * s;
+}
+
 // Eigenvalues of the symmetric m x m matrices G (one workgroup per matrix, blockIdx.x; G is
 // overwritten by the Householder reflections), descending and clamped at zero (they are
 // squared singular values): lam [k][m].
@@ -1436,6 +1461,29 @@ hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2,
   if (m < 1 || m > DMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil_energy, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, out, work, info);
   return hipGetLastError();
+}
+
+hipError_t launch_nto_ab(const double* Z, int64_t ldz, int k, int nva, int nvb, int noa, int nob,
+                         double* Gx, double* Gy, double* Dv, double* Do, double* lam_p,
+                         double* lam_h, hipStream_t s) {
+  if (k < 1 || nva > JMAX || nvb > JMAX || noa > JMAX || nob > JMAX) return hipErrorInvalidValue;
+  const int64_t nvv = (int64_t)nva * nvb;
+  const int64_t ev = (int64_t)nva * nva + (int64_t)nvb * nvb;
+  hipLaunchKernelGGL(k_rect_products, dim3((unsigned)((ev + NT - 1) / NT), k), dim3(NT), 0, s, Z,
+                     ldz, (int64_t)0, nva, nvb, 1.0, Gx, Dv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_eigenvalues, dim3(k), dim3(WG), 0, s, Gx, nva, lam_p);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (noa > 0) {
+    const int64_t eo = (int64_t)noa * noa + (int64_t)nob * nob;
+    hipLaunchKernelGGL(k_rect_products, dim3((unsigned)((eo + NT - 1) / NT), k), dim3(NT), 0, s,
+                       Z, ldz, nvv, noa, nob, -1.0, Gy, Do);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_eigenvalues, dim3(k), dim3(WG), 0, s, Gy, noa, lam_h);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_nto(const double* Z, int64_t ldz, int k, const Geometry& g, const int* ptab,

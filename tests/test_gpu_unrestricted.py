@@ -11,6 +11,8 @@
   blocks): sigma against the oracle's M z at ragged shapes and against the dense context, the
   Davidson roots of both channels against the oracle, a sector of order 33120 (beyond the dense
   limit, which is refused) on sampled rows of the oracle, and the dense-only calls refused;
+* NTO weights and spin-resolved two-electron densities of alpha-beta roots (rectangular
+  amplitude blocks) against the oracle's, with their sum rules;
 * the density-fitted alpha-beta sector with FP32 and BF16-split sigma: sigma against the
   oracle's M z at the same shapes and on sampled rows at order 33120, six BF16 products at least
   20x more accurate than three on the same inputs, roots of both channels against the oracle.
@@ -127,8 +129,8 @@ def test_ab_argument_checks():
     ea, eb, La, Lb = unrestricted(77, 8, 3, 2, 10)
     with P.PpRPA.alpha_beta(ea, eb, La, Lb, 3, 2) as ctx:
         with pytest.raises(P.PpRPAError) as e:
-            ctx.nto(np.ones((1, ctx.n)))
-        assert e.value.status == P.binding.EUNSUPPORTED
+            ctx.nto(np.ones((65, ctx.n)))  # more than 64 roots per call
+        assert e.value.status == P.binding.EINVAL
     bad = Lb.copy()
     bad[1, 2, 3] = np.nan
     with pytest.raises(P.PpRPAError) as e:
@@ -322,3 +324,50 @@ def test_ab_df_dense_only_calls_are_refused():
             with pytest.raises(P.PpRPAError) as e:
                 call()
             assert e.value.status == P.binding.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("case", [(12, 4, 2, 20), (10, 2, 5, 18), (9, 3, 0, 14), (30, 7, 5, 40)])
+def test_ab_nto_vs_oracle(case):
+    """NTO weights and spin-resolved density blocks of alpha-beta roots (rectangular amplitude
+    blocks: alpha longer than beta, shorter, no beta occupied): pp and hh roots of the dense
+    context's direct solve and seeded random vectors against the oracle's, 1e-12 relative to the
+    vector's squared norm; on the roots, sum(lam^p) - sum(lam^h) = +1 / -1 and every spin's trace
+    x^T x (vv) or -y^T y (oo); the density-fitted context of the same system gives the same
+    values bit for bit."""
+    nmo, noa, nob, naux = case
+    note("ab nto", case)
+    ea, eb, La, Lb = unrestricted(91, nmo, noa, nob, naux)
+    nva, nvb = nmo - noa, nmo - nob
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob) as ctx:
+        zs = [ctx.davidson(3, direct=True, vectors=True)["vecs"]]
+        nh = min(2, ctx.n_hh)
+        if nh:
+            zs.append(ctx.davidson(nh, direct=True, vectors=True, channel="hh")["vecs"])
+        zs.append(gen.random_vectors(92, 3, ctx.n))
+        Z = np.vstack(zs)
+        out = ctx.nto(Z)
+        nvv = ctx.n_pp
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, density_fitted=True) as dfc:
+        out_df = dfc.nto(Z)
+    for key in ("lam_p", "lam_h", "d_vv_a", "d_vv_b", "d_oo_a", "d_oo_b"):
+        assert np.array_equal(out[key], out_df[key]), key
+    nroots = 3 + nh
+    for j, z in enumerate(Z):
+        lp, lh, _ = O.nto_ab(z, nva, nvb, noa, nob)
+        Dva, Dvb, Doa, Dob = O.density_2e_ab(z, nva, nvb, noa, nob)
+        tol = 1e-12 * max(1.0, z @ z)
+        assert np.max(np.abs(out["lam_p"][j] - lp)) <= tol
+        if noa:
+            assert np.max(np.abs(out["lam_h"][j] - lh)) <= tol
+        for got, ref in ((out["d_vv_a"][j], Dva), (out["d_vv_b"][j], Dvb),
+                         (out["d_oo_a"][j], Doa), (out["d_oo_b"][j], Dob)):
+            if ref.size:
+                assert np.max(np.abs(got - ref)) <= tol
+        if j < nroots:
+            sgn = 1.0 if j < 3 else -1.0
+            x2, y2 = z[:nvv] @ z[:nvv], z[nvv:] @ z[nvv:]
+            assert abs(out["lam_p"][j].sum() - out["lam_h"][j].sum() - sgn) <= 1e-10
+            assert abs(np.trace(out["d_vv_a"][j]) - x2) <= 1e-12
+            assert abs(np.trace(out["d_vv_b"][j]) - x2) <= 1e-12
+            if noa and nob:
+                assert abs(np.trace(out["d_oo_a"][j]) + y2) <= 1e-12
