@@ -494,10 +494,11 @@ constexpr int PLDS = 96;
 // metric).
 // ------------------------------------------------------------------------------------------
 // 1 / b from the hardware reciprocal estimate and two Newton-Raphson steps r <- r (2 - b r)
-// (each squares the relative error), for b of moderate size (no scaling near the ends of the
-// exponent range): a shorter dependent chain than the IEEE division sequence, within an ulp or
-// two of it.
+// (each squares the relative error): a shorter dependent chain than the IEEE division sequence,
+// within an ulp or two of it. Magnitudes below 1e-300 (near the denormal range, where the
+// estimate is not trusted) take the IEEE division.
 __device__ __forceinline__ double recip_nr(double b) {
+  if (!(fabs(b) >= 1e-300)) return 1.0 / b;
   double r = __builtin_amdgcn_rcp(b);
   r = fma(r, fma(-b, r, 1.0), r);
   r = fma(r, fma(-b, r, 1.0), r);
