@@ -229,6 +229,24 @@ pprpa_status pprpa_correlation_energy_noalloc(pprpa_ctx* ctx, pprpa_corr_energy*
 pprpa_status pprpa_nto(pprpa_ctx* ctx, int32_t k, const double* z, int32_t on_device,
                        double* lam_p, double* lam_h, double* d_vv, double* d_oo);
 
+/* The natural transition orbitals themselves (section "Natural Transition Orbital", Eqs. nto_pp
+ * and nto_hh): for each of k roots z (as pprpa_nto), the leading nvec singular-vector pairs of its
+ * amplitude matrices, X = C^p1 sqrt(lam^p) C^p2^T and Y = C^h1 sqrt(lam^h) C^h2^T, in the order
+ * of pprpa_nto's weights (descending). X and Y are those of pprpa_nto: the triangular nv x nv and
+ * no x no matrices of a restricted context, the rectangular nvir_a x nvir_b and nocc_a x nocc_b
+ * blocks of an alpha-beta one. Outputs (host, each may be NULL), one vector per row:
+ * c_p1 [k][nvec][rows of X], c_p2 [k][nvec][columns of X], c_h1 [k][nvec][rows of Y],
+ * c_h2 [k][nvec][columns of Y]. The right vectors are eigenvectors of X^T X (Householder
+ * tridiagonal form, bisection, inverse iteration), the left ones u = X v / |X v|; each pair's
+ * sign is fixed so that the largest |u_i| (lowest i among equals) is positive; rows beyond
+ * min(nvec, rows, columns), and u of a null direction (|X v| <= 1e-10 of the first), are zero.
+ * Vectors of equal weights are an orthonormal basis of their subspace, not unique. 1 <= k <= 64,
+ * 1 <= nvec <= 64, blocks <= 512 (else EINVAL / EUNSUPPORTED). Allocates and frees its device
+ * scratch. Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY. */
+pprpa_status pprpa_nto_vectors(pprpa_ctx* ctx, int32_t k, const double* z, int32_t on_device,
+                               int32_t nvec, double* c_p1, double* c_p2, double* c_h1,
+                               double* c_h2);
+
 /* Timing of the sigma contraction kernel (the fused sandwich kernel only, without the unpack
  * and epilogue kernels), measured with HIP events recorded on the context's stream around
  * every launch since the last reset. flops and bytes are algorithmic counts: per vector

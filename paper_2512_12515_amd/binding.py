@@ -151,6 +151,9 @@ def lib():
     L.pprpa_nto.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p]
     L.pprpa_nto.restype = C.c_int
+    L.pprpa_nto_vectors.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.pprpa_nto_vectors.restype = C.c_int
     L.pprpa_correlation_energy.argtypes = [C.c_void_p, C.POINTER(CorrEnergy)]
     L.pprpa_correlation_energy.restype = C.c_int
     L.pprpa_correlation_energy_noalloc.argtypes = [C.c_void_p, C.POINTER(CorrEnergy)]
@@ -344,6 +347,26 @@ class PpRPA:
                                d_vv.ctypes.data if density else None,
                                d_oo.ctypes.data if (density and no) else None))
         return dict(lam_p=lam_p, lam_h=lam_h, d_vv=d_vv, d_oo=d_oo)
+
+    def nto_vectors(self, z, nvec):
+        """The leading nvec NTO pairs of the packed roots z ([k][n]) (pprpa_nto_vectors): c_p1
+        [k][nvec][rows of X], c_p2 [k][nvec][columns of X], c_h1 / c_h2 likewise for Y, one vector
+        per row, in the order of the weights of nto()."""
+        on_dev = _is_torch(z) and z.is_cuda
+        if not on_dev:
+            z = np.ascontiguousarray(np.atleast_2d(z), dtype=np.float64)
+        k = int(z.shape[0])
+        rp, rh = self._dims_active()
+        if self.mult == "alpha-beta":
+            cp, ch = self.nvb, self.nob
+        else:
+            cp, ch = rp, rh
+        out = {name: np.zeros((k, int(nvec), m)) for name, m in
+               (("c_p1", rp), ("c_p2", cp), ("c_h1", rh), ("c_h2", ch))}
+        ptr = {name: (a.ctypes.data if a.size else None) for name, a in out.items()}
+        _check(lib().pprpa_nto_vectors(self._h, k, _ptr(z, on_dev), int(on_dev), int(nvec),
+                                       ptr["c_p1"], ptr["c_p2"], ptr["c_h1"], ptr["c_h2"]))
+        return out
 
     def _nto_ab(self, z, on_dev, k, nva, noa, density):
         """pprpa_nto on an alpha-beta context: lam_p [k][nvir_a], lam_h [k][nocc_a] and the

@@ -1100,6 +1100,95 @@ pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_devi
   return PPRPA_OK;
 }
 
+pprpa_status pprpa_nto_vectors(pprpa_ctx* c, int32_t k, const double* z, int32_t on_device,
+                               int32_t nvec, double* c_p1, double* c_p2, double* c_h1,
+                               double* c_h2) {
+  g_err.clear();
+  if (!c) return einval("ctx is NULL");
+  if (!z) return einval("z must not be NULL");
+  if (k < 1 || k > 64) return einval("k=%d outside [1, 64]", k);
+  if (nvec < 1 || nvec > 64) return einval("nvec=%d outside [1, 64]", nvec);
+  const Geometry& g = c->g;
+  // the amplitude blocks: rows x cols of the pp and hh parts
+  const int rp = g.nv, cp = c->ab ? (g.nv + g.no) - c->ab_nocc_b : g.nv;
+  const int rh = g.no, ch = c->ab ? c->ab_nocc_b : g.no;
+  if (rp > 512 || cp > 512 || rh > 512 || ch > 512) {
+    set_error("NTO vectors on the device are limited to orbital blocks <= 512");
+    return PPRPA_EUNSUPPORTED;
+  }
+  Busy busy(c->busy);
+  if (!busy.ok) {
+    set_error("context in use by another thread");
+    return PPRPA_EBUSY;
+  }
+  PPRPA_HIP(hipSetDevice(c->device));
+  const bool hh = rh > 0 && ch > 0;
+  const size_t zv = (size_t)k * g.n;
+  const size_t xs = c->ab ? 0 : (size_t)k * ((size_t)rp * rp + (size_t)rh * rh);  // unpacked X, Y
+  const size_t wp = svd_vectors_work(k, rp, cp, nvec), wh = hh ? svd_vectors_work(k, rh, ch, nvec) : 0;
+  const size_t op = (size_t)k * nvec * ((size_t)rp + cp), oh = hh ? (size_t)k * nvec * ((size_t)rh + ch) : 0;
+  const size_t total = (on_device ? 0 : zv) + xs + std::max(wp, wh) + op + oh;
+  double* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, std::max<size_t>(total, 1) * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("NTO workspace of %zu bytes: %s", total * sizeof(double), hipGetErrorString(e));
+    return PPRPA_ENOMEM;
+  }
+  double* p = buf;
+  const double* dz = z;
+  if (!on_device) {
+    dz = p;
+    p += zv;
+  }
+  const double *Ap, *Ah;
+  int64_t sp_, sh_;
+  hipStream_t s = c->stream;
+  hipError_t le = hipSuccess;
+  if (!on_device) le = hipMemcpyAsync((void*)dz, z, zv * sizeof(double), hipMemcpyHostToDevice, s);
+  if (c->ab) {  // the packed alpha-beta vector is X then Y, row-major (alpha index outer)
+    Ap = dz;
+    Ah = dz + g.nvv;
+    sp_ = sh_ = g.n;
+  } else {
+    double* X = p;
+    double* Y = p + (size_t)k * rp * rp;
+    p += xs;
+    if (le == hipSuccess) le = launch_unpack_triangular(dz, g.n, k, g, c->ptab, X, Y, s);
+    Ap = X;
+    Ah = Y;
+    sp_ = (int64_t)rp * rp;
+    sh_ = (int64_t)rh * rh;
+  }
+  double* work = p;
+  p += std::max(wp, wh);
+  double* U1 = p;
+  double* V1 = U1 + (size_t)k * nvec * rp;
+  double* U2 = V1 + (size_t)k * nvec * cp;
+  double* V2 = U2 + (size_t)k * nvec * rh;
+  if (le == hipSuccess) le = launch_svd_vectors(Ap, sp_, rp, cp, k, nvec, work, U1, V1, s);
+  if (le == hipSuccess && hh) le = launch_svd_vectors(Ah, sh_, rh, ch, k, nvec, work, U2, V2, s);
+  const size_t np1 = (size_t)k * nvec * rp, np2 = (size_t)k * nvec * cp;
+  const size_t nh1 = (size_t)k * nvec * rh, nh2 = (size_t)k * nvec * ch;
+  if (le == hipSuccess && c_p1) le = hipMemcpyAsync(c_p1, U1, np1 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && c_p2) le = hipMemcpyAsync(c_p2, V1, np2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess && c_h1 && nh1) {
+    if (hh) le = hipMemcpyAsync(c_h1, U2, nh1 * sizeof(double), hipMemcpyDeviceToHost, s);
+    else std::fill(c_h1, c_h1 + nh1, 0.0);
+  }
+  if (le == hipSuccess && c_h2 && nh2) {
+    if (hh) le = hipMemcpyAsync(c_h2, V2, nh2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    else std::fill(c_h2, c_h2 + nh2, 0.0);
+  }
+  if (le == hipSuccess) le = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (le != hipSuccess) {
+    set_error("NTO vectors: %s", hipGetErrorString(le));
+    return PPRPA_EDEVICE;
+  }
+  return PPRPA_OK;
+}
+
 pprpa_status pprpa_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega,
                             double* vecs, double* resid, pprpa_report* rep) {
   g_err.clear();

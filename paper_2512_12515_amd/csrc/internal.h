@@ -227,6 +227,17 @@ hipError_t launch_nto(const double* Z, int64_t ldz, int k, const Geometry& g, co
 hipError_t launch_nto_ab(const double* Z, int64_t ldz, int k, int nva, int nvb, int noa, int nob,
                          double* Gx, double* Gy, double* Dv, double* Do, double* lam_p,
                          double* lam_h, hipStream_t s);
+// The packed roots' triangular amplitude matrices X [k][nv][nv], Y [k][no][no] (zeros below).
+hipError_t launch_unpack_triangular(const double* Z, int64_t ldz, int k, const Geometry& g,
+                                    const int* ptab, double* X, double* Y, hipStream_t s);
+// Leading singular vectors of k matrices A (rows x cols, row-major, astride apart; rows, cols
+// <= 512): the nsel = min(nvec, rows, cols) right vectors from the largest eigenvalues of A^T A,
+// the left ones u = A v / |A v|, signs fixed (largest |u_i| positive); U [k][nvec][rows] and
+// V [k][nvec][cols] (rows beyond nsel, and u of a null direction, zero). 1 <= nvec <= 64.
+// work: svd_vectors_work(k, rows, cols, nvec) doubles.
+size_t svd_vectors_work(int k, int rows, int cols, int nvec);
+hipError_t launch_svd_vectors(const double* A, int64_t astride, int rows, int cols, int k,
+                              int nvec, double* work, double* U, double* V, hipStream_t s);
 hipError_t launch_normalize_rows(double* V, int64_t ld, int r, int64_t n, hipStream_t s);
 hipError_t prepare_kernels();
 // Small orthonormalisation in the m-dim subspace (one workgroup): Q = orth(C) by MGS.

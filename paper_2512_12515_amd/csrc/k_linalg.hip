@@ -376,6 +376,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
+// Sum over an NT-thread workgroup (every thread gets it), wave results in a fixed order.
+__device__ __forceinline__ double block_sum_nt(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < NT / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
 // Cyclic Jacobi on the symmetric m x m matrix G (ld), accumulating eigenvectors into U (ld).
 // Round-robin ordering: m (padded to even) - 1 rounds of m/2 disjoint rotations per sweep.
 // On return G's diagonal holds the eigenvalues and U's columns the eigenvectors.
@@ -1103,6 +1114,112 @@ __global__ void k_triangular_products(const double* __restrict__ T, int m, doubl
   if (D) D[(int64_t)r * m * m + e] = sgn * (tt + ttt);
 }
 
+// G = A^T A of k matrices A (rows x cols, row-major, astride doubles apart): G [k][cols][cols],
+// one thread per element, sums in a fixed order.
+__global__ void k_gram_ata(const double* __restrict__ Aall, int64_t astride, int rows, int cols,
+                           double* __restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= (int64_t)cols * cols) return;
+  const int i = (int)(e / cols), j = (int)(e % cols);
+  const double* A = Aall + (int64_t)r * astride;
+  double s = 0.0;
+  for (int c = 0; c < rows; ++c) s += A[(int64_t)c * cols + i] * A[(int64_t)c * cols + j];
+  G[(int64_t)r * cols * cols + e] = s;
+}
+
+// The nsel eigenvectors of the largest eigenvalues (descending) of the symmetric m x m matrices
+// G (one workgroup per matrix; G overwritten by the Householder reflections): tridiagonal form,
+// multisection, inverse iteration (vectors of nearly equal eigenvalues orthonormalised),
+// back-transformation. X: per matrix 4 nsel m doubles; the vectors end in its first nsel m
+// (row j = vector j). nsel <= 64.
+__global__ __launch_bounds__(WG) void k_gram_vectors(double* __restrict__ Gall, int m, int nsel,
+                                                     double* __restrict__ Xall) {
+  __shared__ double red[WG];
+  __shared__ double d[JMAX], e[JMAX], e2[JMAX], beta[JMAX], vv[JMAX], pq[JMAX];
+  __shared__ double theta[64];
+  __shared__ int npos;
+  double* G = Gall + (int64_t)blockIdx.x * m * m;
+  double* X = Xall + (int64_t)blockIdx.x * 4 * nsel * m;
+  tri_householder(G, m, d, e, beta, vv, pq, red, e2);
+  tri_eigen(d, e, e2, m, nsel, 0, theta, &npos, X, red, vv, pq, nullptr);
+  tri_back_transform(G, m, beta, X, nsel);
+}
+
+// Left singular vectors from the right ones: for root r and vector j, u = A v_j / |A v_j|
+// (zero when |A v_j| <= 1e-10 |A v_0|: no left vector for a null direction), the sign fixed so
+// that the largest |u_i| (lowest i among equals) is positive, v flipped with it. A: rows x cols at
+// astride per root; V: per root 4 nsel cols doubles, vectors in its first nsel cols; U [k][nvec]
+// [rows] and Vo [k][nvec][cols], rows nsel .. nvec zero. One workgroup per root.
+__global__ __launch_bounds__(NT) void k_svd_left(const double* __restrict__ Aall, int64_t astride,
+                                                int rows, int cols, const double* __restrict__ Vall,
+                                                int nsel, int nvec, double* __restrict__ Uall,
+                                                double* __restrict__ Voall) {
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  const int r = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double* A = Aall + (int64_t)r * astride;
+  const double* V = Vall + (int64_t)r * 4 * nsel * cols;
+  double* U = Uall + (int64_t)r * nvec * rows;
+  double* Vo = Voall + (int64_t)r * nvec * cols;
+  double s0 = 0.0;
+  for (int j = 0; j < nvec; ++j) {
+    if (j >= nsel) {  // uniform
+      for (int i = t; i < rows; i += NT) U[(int64_t)j * rows + i] = 0.0;
+      for (int i = t; i < cols; i += NT) Vo[(int64_t)j * cols + i] = 0.0;
+      continue;
+    }
+    const double* v = V + (int64_t)j * cols;
+    double part = 0.0;
+    for (int i = t; i < rows; i += NT) {
+      double u = 0.0;
+      for (int c = 0; c < cols; ++c) u += A[(int64_t)i * cols + c] * v[c];
+      U[(int64_t)j * rows + i] = u;
+      part += u * u;
+    }
+    const double nrm = sqrt(block_sum_nt(part, red));
+    if (j == 0) s0 = nrm;
+    const bool null_dir = !(nrm > 1e-10 * s0) || nrm == 0.0;
+    // the largest |u_i|, lowest i among equals (a fixed reduction order)
+    double best = -1.0;
+    int bi = 0;
+    for (int i = t; i < rows; i += NT) {
+      const double a = fabs(U[(int64_t)j * rows + i]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red[w] = best;
+      redi[w] = bi;
+    }
+    __syncthreads();
+    double gb = red[0];
+    int gi = redi[0];
+    for (int ww = 1; ww < NT / 64; ++ww)
+      if (red[ww] > gb || (red[ww] == gb && redi[ww] < gi)) {
+        gb = red[ww];
+        gi = redi[ww];
+      }
+    const double ug = U[(int64_t)j * rows + gi];
+    __syncthreads();
+    const double sgn = ug < 0.0 ? -1.0 : 1.0;
+    const double us = null_dir ? 0.0 : sgn / nrm;
+    for (int i = t; i < rows; i += NT) U[(int64_t)j * rows + i] *= us;
+    for (int i = t; i < cols; i += NT) Vo[(int64_t)j * cols + i] = (null_dir ? 1.0 : sgn) * v[i];
+    __syncthreads();
+  }
+}
+
 // Gram matrices of the rectangular amplitude blocks of alpha-beta roots: A = rows x cols
 // (row-major, at offset off of root r's packed vector, ld ldz), element e of A A^T (rows^2,
 // into G and sgn times it into D) or, for e >= rows^2, of A^T A (cols^2, sgn times it into D
@@ -1461,6 +1578,41 @@ hipError_t launch_pencil_energy(const double* M, int m, int64_t nvv, double mu2,
                                 double* work, int* info, hipStream_t s) {
   if (m < 1 || m > DMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pencil_energy, dim3(1), dim3(WG), 0, s, M, m, nvv, mu2, out, work, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_triangular(const double* Z, int64_t ldz, int k, const Geometry& g,
+                                    const int* ptab, double* X, double* Y, hipStream_t s) {
+  const size_t xv = (size_t)k * g.nv * g.nv, yo = (size_t)k * g.no * g.no;
+  hipError_t e = launch_fill(X, xv, 0.0, s);
+  if (e == hipSuccess && yo) e = launch_fill(Y, yo, 0.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpack_triangular, dim3((unsigned)((g.n + NT - 1) / NT), k), dim3(NT), 0, s,
+                     Z, ldz, g.n, g.nvv, g.nv, g.no, ptab, X, Y);
+  return hipGetLastError();
+}
+
+size_t svd_vectors_work(int k, int rows, int cols, int nvec) {
+  const int nsel = std::min(nvec, std::min(rows, cols));
+  return (size_t)k * cols * cols + (size_t)k * 4 * std::max(nsel, 1) * cols;
+}
+
+hipError_t launch_svd_vectors(const double* A, int64_t astride, int rows, int cols, int k,
+                              int nvec, double* work, double* U, double* V, hipStream_t s) {
+  if (k < 1 || rows < 1 || cols < 1 || rows > JMAX || cols > JMAX || nvec < 1 || nvec > 64)
+    return hipErrorInvalidValue;
+  const int nsel = std::min(nvec, std::min(rows, cols));
+  double* G = work;
+  double* X = work + (size_t)k * cols * cols;
+  const int64_t ev = (int64_t)cols * cols;
+  hipLaunchKernelGGL(k_gram_ata, dim3((unsigned)((ev + NT - 1) / NT), k), dim3(NT), 0, s, A,
+                     astride, rows, cols, G);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_vectors, dim3(k), dim3(WG), 0, s, G, cols, nsel, X);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_svd_left, dim3(k), dim3(NT), 0, s, A, astride, rows, cols, X, nsel, nvec, U,
+                     V);
   return hipGetLastError();
 }
 

@@ -7,7 +7,10 @@ against the FP64 oracle applied to the same vectors.
   spins, an active window, host and device vectors;
 * the sum rules: sum lam^p - sum lam^h = +1 (pp) / -1 (hh), Tr D = +2 / -2 (Eq. dm_constrain);
 * L = 0: one NTO pair of weight 1 per root;
-* argument checks.
+* argument checks;
+* the NTO pairs themselves (pprpa_nto_vectors): against the oracle's SVD (one sign convention
+  applied to both; pairs with nonzero, isolated weights, within 1e-9), the full set
+  reconstructing X and Y within 1e-10, for restricted and alpha-beta roots.
 """
 import sys
 
@@ -92,3 +95,72 @@ def test_nto_argument_checks():
         with pytest.raises(P.PpRPAError) as e:
             ctx.nto(np.zeros((0, ctx.n)))
         assert e.value.status == P.binding.EINVAL
+
+
+def _signed(u, v):
+    """The library's sign convention for a singular pair: the largest |u_i| (lowest i) positive."""
+    i = int(np.argmax(np.abs(u)))
+    return (u, v) if u[i] >= 0 else (-u, -v)
+
+
+def _check_vectors(out, j, lam, U, V, tol=1e-9, wkey=("c_p1", "c_p2")):
+    """Returned pairs against the oracle's where the weight is nonzero and isolated; every
+    returned pair orthonormal where nonzero."""
+    nvec = out[wkey[0]].shape[1]
+    for q in range(min(nvec, lam.size, U.shape[1], V.shape[1])):
+        gap = min([abs(lam[q] - lam[p]) for p in range(lam.size) if p != q] + [1.0])
+        if lam[q] < 1e-8 or gap < 1e-6 * max(lam[0], 1e-300):
+            continue
+        u, v = _signed(U[:, q], V[:, q])
+        assert np.max(np.abs(out[wkey[0]][j, q] - u)) <= tol
+        assert np.max(np.abs(out[wkey[1]][j, q] - v)) <= tol
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("case", [(4, 9, 30), (6, 14, 40)])
+def test_nto_vectors_vs_oracle(mult, case):
+    """pprpa_nto_vectors: the leading NTO pairs of pp and hh roots and of random vectors against
+    the oracle's SVD (sign convention applied to both, pairs with nonzero isolated weights), and
+    the full set reconstructing X and Y: X = sum_q sqrt(lam_q) c_p1[q] c_p2[q]^T (null directions
+    contribute zero); the leading three equal the first three of the full set."""
+    nocc, nvir, naux = case
+    note("nto vectors", mult, case)
+    eps, L = gen.orbital_energies(61, nocc, nvir), gen.lpq_full(61, nocc + nvir, naux)
+    with P.PpRPA(eps, L, nocc, mult=mult, dense=True) as ctx:
+        zs = [ctx.davidson(3, direct=True, vectors=True)["vecs"],
+              ctx.davidson(2, direct=True, vectors=True, channel="hh")["vecs"],
+              gen.random_vectors(62, 2, ctx.n)]
+        Z = np.vstack(zs)
+        full = ctx.nto_vectors(Z, max(nvir, nocc))
+        lead = ctx.nto_vectors(Z, 3)
+        w = ctx.nto(Z, density=False)
+    nvv = O.pairs(nvir, mult)[0].size
+    for j, z in enumerate(Z):
+        lp, lh, (U, V, Uh, Vh) = O.nto(z, nvir, nocc, mult)
+        _check_vectors(lead, j, lp, U, V)
+        _check_vectors(lead, j, lh, Uh, Vh, wkey=("c_h1", "c_h2"))
+        X = O.triangular(z[:nvv], nvir, mult)
+        Y = O.triangular(z[nvv:], nocc, mult)
+        Xr = (full["c_p1"][j].T * np.sqrt(w["lam_p"][j])) @ full["c_p2"][j][:nvir]
+        Yr = (full["c_h1"][j][:nocc].T * np.sqrt(w["lam_h"][j])) @ full["c_h2"][j][:nocc]
+        assert np.max(np.abs(Xr[:, :] - X)) <= 1e-10 * max(1.0, np.abs(X).max())
+        assert np.max(np.abs(Yr - Y)) <= 1e-10 * max(1.0, np.abs(Y).max())
+        assert np.allclose(lead["c_p1"][j], full["c_p1"][j][:3], atol=1e-9)
+
+
+def test_nto_vectors_alpha_beta_vs_oracle():
+    """The same for alpha-beta roots (rectangular blocks: alpha longer than beta, then shorter)."""
+    for nmo, noa, nob in ((12, 4, 2), (10, 2, 5)):
+        ea = gen.orbital_energies(63, noa, nmo - noa)
+        eb = gen.orbital_energies(1063, nob, nmo - nob)
+        La, Lb = gen.lpq_full(63, nmo, 16), gen.lpq_full(1063, nmo, 16)
+        nva, nvb = nmo - noa, nmo - nob
+        with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob) as ctx:
+            Z = np.vstack([ctx.davidson(2, direct=True, vectors=True)["vecs"],
+                           ctx.davidson(2, direct=True, vectors=True, channel="hh")["vecs"],
+                           gen.random_vectors(64, 2, ctx.n)])
+            out = ctx.nto_vectors(Z, 4)
+        for j, z in enumerate(Z):
+            lp, lh, (U, V, Uh, Vh) = O.nto_ab(z, nva, nvb, noa, nob)
+            _check_vectors(out, j, lp, U, V)
+            _check_vectors(out, j, lh, Uh, Vh, wkey=("c_h1", "c_h2"))
