@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpprpa.so")
-SOURCES = ["api.cpp", "davidson.cpp", "server.cpp", "k_sigma.hip", "k_sigma_f64.hip", "k_sigma_ab.hip", "k_sigma_bf16.hip", "k_linalg.hip",
+SOURCES = ["api.cpp", "davidson.cpp", "server.cpp", "trace.cpp", "k_sigma.hip", "k_sigma_f64.hip", "k_sigma_ab.hip", "k_sigma_bf16.hip", "k_linalg.hip",
            "k_dense.hip", "k_dense_mw.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
@@ -42,7 +42,7 @@ def build(verbose=False):
             if warn:
                 print(src, "\n".join(warn[:40]), file=sys.stderr)
     tmp = OUT + ".tmp"
-    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp] + objs,
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp] + objs + ["-ldl"],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

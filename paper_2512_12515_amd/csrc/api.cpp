@@ -740,6 +740,7 @@ pprpa_status corr_energy_checks(pprpa_ctx* c, pprpa_corr_energy* out, int64_t ma
 // The whole-spectrum solve into the workspace `work` (3 n^2 doubles, then 4 doubles and 3 ints
 // of outputs), results copied out through the context's pinned buffer. No allocation.
 pprpa_status corr_energy_run(pprpa_ctx* c, double* work, pprpa_corr_energy* out) {
+  TraceRange tr("pprpa_correlation_energy");
   const int64_t n = c->g.n, nvv = c->g.nvv;
   double* dout = work + 3 * (size_t)n * n;  // 4 doubles, then 3 ints
   int* dinfo = (int*)(dout + 4);
@@ -828,6 +829,7 @@ const char* pprpa_strerror(pprpa_status s) {
 const char* pprpa_last_error(void) { return pprpa::g_err.c_str(); }
 
 pprpa_status pprpa_build(const pprpa_build_args* a, pprpa_ctx** out) {
+  TraceRange tr("pprpa_build");
   g_err.clear();
   if (!out) return einval("out is NULL");
   *out = nullptr;
@@ -835,6 +837,7 @@ pprpa_status pprpa_build(const pprpa_build_args* a, pprpa_ctx** out) {
 }
 
 pprpa_status pprpa_build_ab(const pprpa_build_ab_args* a, pprpa_ctx** out) {
+  TraceRange tr("pprpa_build_ab");
   g_err.clear();
   if (!out) return einval("out is NULL");
   *out = nullptr;
@@ -875,6 +878,7 @@ pprpa_status pprpa_dims(const pprpa_ctx* c, int64_t* n_pp, int64_t* n_hh) {
 
 pprpa_status pprpa_matvec(pprpa_ctx* c, int32_t k, const double* z, double* sigma,
                           int32_t on_device) {
+  TraceRange tr("pprpa_matvec");
   g_err.clear();
   if (!c) return einval("ctx is NULL");
   if (k <= 0) return einval("k=%d must be positive", k);
@@ -1041,6 +1045,7 @@ static pprpa_status nto_ab(pprpa_ctx* c, int k, const double* z, int on_device, 
 
 pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_device, double* lam_p,
                        double* lam_h, double* d_vv, double* d_oo) {
+  TraceRange tr("pprpa_nto");
   g_err.clear();
   if (!c) return einval("ctx is NULL");
   if (!z || !lam_p || (!lam_h && c->g.no > 0)) return einval("z, lam_p and lam_h must not be NULL");
@@ -1103,6 +1108,7 @@ pprpa_status pprpa_nto(pprpa_ctx* c, int32_t k, const double* z, int32_t on_devi
 pprpa_status pprpa_nto_vectors(pprpa_ctx* c, int32_t k, const double* z, int32_t on_device,
                                int32_t nvec, double* c_p1, double* c_p2, double* c_h1,
                                double* c_h2) {
+  TraceRange tr("pprpa_nto_vectors");
   g_err.clear();
   if (!c) return einval("ctx is NULL");
   if (!z) return einval("z must not be NULL");

@@ -481,6 +481,7 @@ pprpa_status Solver::results(double* omega, double* vecs, double* resid, pprpa_r
 
 // Direct diagonalisation of the dense pencil (M, W) with the same device pencil solver.
 pprpa_status Solver::run_direct() {
+  TraceRange tr("davidson.direct");
   const Geometry& g = c_->g;
   const int64_t n = g.n, nvv = g.nvv;
   hipStream_t s = c_->stream;
@@ -537,6 +538,17 @@ pprpa_status Solver::run_direct() {
   return done(PPRPA_OK);
 }
 
+static const char* phase_name(Solver::Phase p) {
+  switch (p) {
+    case Solver::RR_LAUNCH: return "davidson.rayleigh_ritz";
+    case Solver::RR_READ: return "davidson.ritz_read";
+    case Solver::RESTART_READ: return "davidson.restart";
+    case Solver::ORTH1_READ: return "davidson.orth1";
+    case Solver::ORTH2_READ: return "davidson.orth2";
+    default: return "davidson.phase";
+  }
+}
+
 // Up to n_iter iterations of a started solve, phases run back to back. An iteration starts with
 // the sigma product of the pending block and ends when the next block is requested or the solve
 // is done; *done_iters counts the iterations run.
@@ -544,6 +556,7 @@ pprpa_status iterate_solver(pprpa_ctx* c, Solver& sv, int n_iter, int* done_iter
   int it = 0;
   while (sv.phase != Solver::DONE && it < n_iter) {
     if (sv.phase == Solver::NEED_SIGMA) {
+      TraceRange tr("davidson.sigma");
       const int64_t n = c->g.n;
       PPRPA_HIP(hipEventRecord(c->e0, c->stream));
       pprpa_status rc = sigma_device(c, sv.sig_k, sv.w.V + (size_t)sv.sig_m0 * n,
@@ -553,7 +566,11 @@ pprpa_status iterate_solver(pprpa_ctx* c, Solver& sv, int n_iter, int* done_iter
       sv.sigma_done(true);
     }
     while (sv.phase != Solver::DONE && sv.phase != Solver::NEED_SIGMA) {
-      if (sv.phase != Solver::RR_LAUNCH) PPRPA_HIP(hipStreamSynchronize(c->stream));
+      if (sv.phase != Solver::RR_LAUNCH) {
+        TraceRange tw("davidson.wait");
+        PPRPA_HIP(hipStreamSynchronize(c->stream));
+      }
+      TraceRange tp(phase_name(sv.phase));
       sv.advance();
     }
     ++it;
@@ -585,6 +602,7 @@ pprpa_status finish_solver(Solver& sv, double* omega, double* vecs, double* resi
 // One solve on one context, phases run back to back.
 pprpa_status run_davidson(pprpa_ctx* c, const pprpa_davidson_args* a, double* omega, double* vecs,
                           double* resid, pprpa_report* rep) {
+  TraceRange tr("pprpa_davidson");
   Solver sv(c, *a);
   sv.start();
   PPRPA_TRY(iterate_solver(c, sv, INT32_MAX, nullptr));

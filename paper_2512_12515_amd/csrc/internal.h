@@ -24,6 +24,20 @@ void set_error(const char* fmt, ...);
     }                                                                                        \
   } while (0)
 
+// Named roctx range for the lifetime of the object (host-side phase markers for rocprofv3
+// --marker-trace); a no-op unless PPRPA_ROCTX=1 is set and the roctx library opens.
+class TraceRange {
+ public:
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+
+ private:
+  bool on_;
+};
+bool trace_enabled();
+
 #define PPRPA_TRY(expr)                   \
   do {                                    \
     pprpa_status s_ = (expr);             \

@@ -110,6 +110,22 @@ def test_null_arguments():
     assert L.pprpa_davidson(None, C.byref(d), None, None, None, None) == B.EINVAL
 
 
+def test_roctx_ranges_open_when_enabled():
+    """PPRPA_ROCTX=1 opens the profiler SDK's roctx library on the first traced entry point;
+    with no profiler attached its ranges are no-ops and the call behaves as without them."""
+    import subprocess
+    import sys
+    code = ("import ctypes as C; from paper_2512_12515_amd import binding as B; "
+            "L = B.lib(); assert L.pprpa_build(None, None) == B.EINVAL; "
+            "assert L.pprpa_matvec(None, 1, None, None, 0) == B.EINVAL; print('ok')")
+    env = dict(os.environ, PPRPA_ROCTX="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       cwd=ROOT, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().endswith("ok")
+    assert "could not be opened" not in r.stderr and "lacks" not in r.stderr, r.stderr
+
+
 def test_server_argument_checks():
     L = B.lib()
     h = C.c_void_p(1234)
