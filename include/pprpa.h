@@ -123,7 +123,7 @@ typedef struct {
   int32_t max_block;    /* largest sigma block per call (<= 0: 32, at most 64)               */
   void* stream;         /* hipStream_t to run on, or NULL for a new non-blocking stream      */
   int32_t density_fitted; /* 1: density-fitted sigma (no dense matrix); 0: dense context     */
-  pprpa_prec prec;      /* sigma precision: PPRPA_FP64; density fitted only: PPRPA_FP32
+  int32_t prec;         /* pprpa_prec, the sigma precision: PPRPA_FP64; density fitted only: PPRPA_FP32
                            (integrals and amplitudes in FP32, FP32 MFMA accumulation) or
                            PPRPA_BF16X6 / PPRPA_BF16X3 (three BF16 planes each, six or three
                            plane products on the BF16 MFMA, FP32 accumulation); the epilogue

@@ -282,9 +282,11 @@ pprpa_status geometry_of(const pprpa_build_args* a, Geometry* out) {
   return PPRPA_OK;
 }
 
-// Aux slices per host-to-device staging copy (about 256 MB of FP64 input at a time).
-int staging_chunk(size_t per) {
-  return (int)std::max<size_t>(1, std::min<size_t>(65535, (size_t(256) << 20) / (per * 8)));
+// Aux slices per host-to-device staging copy: all naux of them, or about 256 MB of FP64 input
+// at a time when L is larger (the staging buffer holds one chunk).
+int staging_chunk(size_t per, int naux) {
+  const size_t cap = std::min<size_t>(65535, (size_t(256) << 20) / (per * 8));
+  return (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(naux, 1), cap));
 }
 
 // Stream (the caller's or a new non-blocking one), timing events and the pinned status buffer of
@@ -390,7 +392,7 @@ pprpa_status build_impl(const pprpa_build_args* a, pprpa_ctx* c) {
       return PPRPA_OK;
     }
     const size_t per = (size_t)nin * nin;
-    const int chunk = staging_chunk(per);
+    const int chunk = staging_chunk(per, naux);
     if (!tmp) {
       if (c->slab) {
         PPRPA_TRY(dalloc(c, (size_t)chunk * per * sizeof(double), (void**)&tmp));
@@ -672,7 +674,7 @@ size_t context_footprint(const pprpa_build_args* a, const pprpa_davidson_args* d
   if (!a->on_device) {
     const int nin = a->lpq_is_active ? g.no + g.nv : a->nmo;
     const size_t per = (size_t)nin * nin;
-    b += al((size_t)staging_chunk(per) * per * sizeof(double));
+    b += al((size_t)staging_chunk(per, g.naux) * per * sizeof(double));
   }
   if (a->dense && st != Store::F64) b += al(plane * sizeof(double));
   int RT = 16, npan_v = 0;
@@ -813,7 +815,12 @@ pprpa_status scratch_of(int device, double** ptr) {
 extern "C" {
 
 const char* pprpa_strerror(pprpa_status s) {
-  switch (s) {
+  // A C caller may pass any int; reading it as the enum type would be undefined outside the
+  // enum's range of values, so the bytes are compared as an int.
+  static_assert(sizeof(pprpa_status) == sizeof(int), "pprpa_status is an int on this ABI");
+  int v;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case PPRPA_OK: return "ok";
     case PPRPA_EINVAL: return "invalid argument";
     case PPRPA_ENOMEM: return "out of device memory";

@@ -1,0 +1,36 @@
+"""Small solves on every path of the C ABI (restricted singlet and triplet in each sigma
+precision with Davidson, warm start, log callback, caller-driven iterations, hh channel, direct
+solve, correlation energy, NTOs; the alpha-beta sector dense and density fitted; the serving
+queue) with AddressSanitizer, LeakSanitizer and UndefinedBehaviorSanitizer on the library's host
+code: tests/abi_sanitized.c run as `abi_sanitized gpu` against the sanitized build that
+__graft_entry__.build() makes in paper_2512_12515_amd/_build/. Leaks reported inside the GPU
+runtime's own libraries are suppressed; the library's are not."""
+import os
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EXE = os.path.join(os.path.dirname(HERE), "paper_2512_12515_amd", "_build", "abi_sanitized")
+
+SUPPRESS = ["leak:libamdhip64.so", "leak:libhsa-runtime64.so", "leak:librocprofiler-register.so",
+            "leak:libdrm", "leak:libnuma", "leak:libelf", "leak:libcomgr", "leak:libamd_comgr.so"]
+
+
+@pytest.mark.gpu
+def test_every_path_clean_under_host_sanitizers(tmp_path):
+    if not os.path.exists(EXE):
+        raise RuntimeError(f"{EXE} is missing: run __graft_entry__.build() before the GPU tests")
+    sup = tmp_path / "lsan.supp"
+    sup.write_text("\n".join(SUPPRESS) + "\n")
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+               LSAN_OPTIONS=f"suppressions={sup}",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    print("abi_sanitized gpu", flush=True)
+    r = subprocess.run([EXE, "gpu"], env=env, capture_output=True, text=True, timeout=600)
+    out = r.stdout + r.stderr
+    print(r.stdout[-2000:], flush=True)
+    assert r.returncode == 0, out[-6000:]
+    assert "ALL OK" in r.stdout, out[-6000:]
+    assert "runtime error" not in out and "ERROR: AddressSanitizer" not in out, out[-6000:]
