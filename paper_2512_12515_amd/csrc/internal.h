@@ -182,7 +182,7 @@ hipError_t launch_dots(const double* A, int64_t lda, int ma, const double* B, in
                        int64_t n, int64_t nsign, int signed_w, double* C, int ldc, double* part,
                        int nchunk, hipStream_t s);
 // Y[j][t] (ldy) = beta * Y[j][t] + alpha * sum_i Cm[i][j] X[i][t], i < m, j < r.
-// Cm: [m][ldcm] device.
+// Cm: [m][ldcm] device, r <= ldcm (any r: one launch per 64 rows of Y).
 hipError_t launch_combine(const double* X, int64_t ldx, int m, const double* Cm, int ldcm, int r,
                           int64_t n, double alpha, double beta, double* Y, int64_t ldy,
                           hipStream_t s);

@@ -1522,16 +1522,25 @@ hipError_t launch_combine(const double* X, int64_t ldx, int m, const double* Cm,
                           int64_t n, double alpha, double beta, double* Y, int64_t ldy,
                           hipStream_t s) {
   if (r <= 0 || n <= 0) return hipSuccess;
-  if (r > 64) return hipErrorInvalidValue;
+  if (r > ldcm) return hipErrorInvalidValue;
   const int64_t per_block = (int64_t)16 * CMB_CT * CMB_WAVES;
   dim3 grid((unsigned)((n + per_block - 1) / per_block)), block(64 * CMB_WAVES);
-  switch ((r + 15) / 16) {
-    case 1: hipLaunchKernelGGL(k_combine<1>, grid, block, 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy); break;
-    case 2: hipLaunchKernelGGL(k_combine<2>, grid, block, 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy); break;
-    case 3: hipLaunchKernelGGL(k_combine<3>, grid, block, 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy); break;
-    default: hipLaunchKernelGGL(k_combine<4>, grid, block, 0, s, X, ldx, m, Cm, ldcm, r, n, alpha, beta, Y, ldy); break;
+  // one launch per 64 output rows (a restart keeps up to 2 nroot = 128 vectors): rows j0.. of Y
+  // from columns j0.. of Cm, each row's sum in the same order as in a single launch
+  for (int j0 = 0; j0 < r; j0 += 64) {
+    const int rj = r - j0 < 64 ? r - j0 : 64;
+    const double* Cj = Cm + j0;
+    double* Yj = Y + (int64_t)j0 * ldy;
+    switch ((rj + 15) / 16) {
+      case 1: hipLaunchKernelGGL(k_combine<1>, grid, block, 0, s, X, ldx, m, Cj, ldcm, rj, n, alpha, beta, Yj, ldy); break;
+      case 2: hipLaunchKernelGGL(k_combine<2>, grid, block, 0, s, X, ldx, m, Cj, ldcm, rj, n, alpha, beta, Yj, ldy); break;
+      case 3: hipLaunchKernelGGL(k_combine<3>, grid, block, 0, s, X, ldx, m, Cj, ldcm, rj, n, alpha, beta, Yj, ldy); break;
+      default: hipLaunchKernelGGL(k_combine<4>, grid, block, 0, s, X, ldx, m, Cj, ldcm, rj, n, alpha, beta, Yj, ldy); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_residual(const double* Z, const double* SZ, int64_t ld, int r, int64_t n,

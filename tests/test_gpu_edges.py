@@ -4,6 +4,7 @@
   are exactly the lowest pair energies, degenerate ones included (Davidson and direct);
 * degenerate orbital energies with interactions: eigenvalues with multiplicity;
 * no occupied orbitals (pp block only), a single pair (nroot = n_pp = 1), one aux function;
+* every root of a channel (nroot = n_pp or n_hh), the subspace reaching the whole space;
 * the widest block (64 vectors) and a window of one virtual orbital;
 * every sigma precision on the smallest and most ragged shapes.
 Tolerances as in the parity tests: FP64 sigma 1e-12 relative, eigenvalues 1e-8 Ha (FP64).
@@ -113,6 +114,23 @@ def test_single_pair(mult, nvir):
         d = ctx.davidson(1, direct=True)
     assert abs(r["omega"][0] - ref[0]) <= 1e-10
     assert abs(d["omega"][0] - ref[0]) <= 1e-10
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("channel", ["pp", "hh"])
+def test_every_root_of_a_channel(mult, channel):
+    """nroot = the whole channel (n_pp or n_hh) on a tiny problem, where the Davidson subspace
+    can reach the whole space: every root of the channel, against the oracle."""
+    note("every root of the channel", mult, channel)
+    nocc, nvir, naux = 4, 3, 6
+    eps = gen.orbital_energies(37, nocc, nvir)
+    L = gen.lpq_full(37, nocc + nvir, naux)
+    with P.PpRPA(eps, L, nocc, mult=mult) as ctx:
+        nroot = ctx.n_pp if channel == "pp" else ctx.n - ctx.n_pp
+        ref = O.solve(eps, L, nocc, mult, nroot, channel=channel)
+        r = ctx.davidson(nroot, tol=1e-9, channel=channel)
+    assert r["status"] == 0
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-9
 
 
 def test_one_aux_function_and_widest_block():

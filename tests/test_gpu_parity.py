@@ -267,6 +267,25 @@ def test_davidson_small(mult, case, nroot):
 
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
+def test_davidson_most_roots_widest_block(mult):
+    """The largest solve the interface takes: 64 roots in blocks of 64, so the subspace grows to
+    its cap of 256 and the projected pencil runs on its L2-resident path (order > 96)."""
+    nocc, nvir, naux = 6, 30, 60
+    note("davidson 64 roots, block 64", mult)
+    eps, L = problem(23, nocc, nvir, naux)
+    ref = O.solve(eps, L, nocc, mult, 64)
+    M, nvv, _ = oracle_M(eps, L, nocc, mult)
+    with P.PpRPA(eps, L, nocc, mult=mult, max_block=64) as ctx:
+        r = ctx.davidson(64, block=64, tol=1e-8, vectors=True)
+    assert r["status"] == 0 and r["report"]["iters"] >= 2
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-8
+    Z = r["vecs"]
+    w = np.r_[np.ones(nvv), -np.ones(M.shape[0] - nvv)]
+    assert np.allclose(np.einsum("ij,j,ij->i", Z, w, Z), 1.0, atol=1e-9)
+    assert np.max(np.abs(M @ Z.T - (w[:, None] * Z.T) * r["omega"][None, :])) < 1e-7
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("seed", [0, 3])
 def test_davidson_vs_direct_small_config(mult, seed):
     gd = _golden("small_direct.json")
