@@ -5,7 +5,8 @@
 * degenerate orbital energies with interactions: eigenvalues with multiplicity;
 * no occupied orbitals (pp block only), a single pair (nroot = n_pp = 1), one aux function;
 * every root of a channel (nroot = n_pp or n_hh), the subspace reaching the whole space;
-* the widest block (64 vectors) and a window of one virtual orbital;
+* the widest block (64 vectors; FP64 with one aux function, every reduced precision on a
+  ragged shape) and a window of one virtual orbital;
 * every sigma precision on the smallest and most ragged shapes.
 Tolerances as in the parity tests: FP64 sigma 1e-12 relative, eigenvalues 1e-8 Ha (FP64).
 """
@@ -144,6 +145,26 @@ def test_one_aux_function_and_widest_block():
         s = ctx.matvec(z)
     ref = (M @ z.T).T
     assert np.max(np.abs(s - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-7), ("bf16x6", 1e-7), ("bf16x3", 3e-6)])
+def test_widest_block_every_precision(mult, prec, tol):
+    """64 vectors in one block in each reduced sigma precision on a ragged shape, against the
+    oracle's M z; the last vector alone gives the same product to the same tolerance."""
+    note("k = 64", mult, prec)
+    nocc, nvir, naux = 5, 21, 30
+    eps = gen.orbital_energies(38, nocc, nvir)
+    L = gen.lpq_full(38, nocc + nvir, naux)
+    M, _ = dense(eps, L, nocc, mult)
+    with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
+        z = gen.random_vectors(11, 64, ctx.n)
+        s = ctx.matvec(z)
+        s1 = ctx.matvec(z[63])
+    ref = (M @ z.T).T
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(s - ref)) <= tol * scale
+    assert np.max(np.abs(s1 - ref[63])) <= tol * scale
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-7), ("bf16x6", 1e-7),

@@ -123,6 +123,21 @@ def test_hh_full_size_fp64(mult):
     assert np.all(r["resid"] <= 1e-6)
 
 
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+def test_hh_most_roots_widest_block(mult):
+    """64 hh roots in blocks of 64 (the largest solve the interface takes; n below the subspace
+    cap of 256, so the subspace can span the whole space), against the oracle."""
+    nocc, nvir, naux = 12, 14, 50
+    note("hh 64 roots, block 64", mult)
+    eps = gen.orbital_energies(29, nocc, nvir)
+    L = gen.lpq_full(29, nocc + nvir, naux)
+    ref = O.solve(eps, L, nocc, mult, 64, channel="hh")
+    with P.PpRPA(eps, L, nocc, mult=mult, max_block=64) as ctx:
+        r = ctx.davidson(64, block=64, tol=1e-8, channel="hh")
+    assert r["status"] == 0
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-8
+
+
 def test_hh_served_equals_standalone():
     note("hh served")
     reqs = [(46, 8, 40, "singlet", 5, "hh"), (47, 10, 50, "triplet", 6, "pp"),

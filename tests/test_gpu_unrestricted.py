@@ -225,6 +225,29 @@ def test_ab_df_sigma_bf16_vs_oracle(case, prec):
     assert np.array_equal(s1, s[2])
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-7),
+                                      ("bf16x6", TOL_AB_BF16["bf16x6"]),
+                                      ("bf16x3", TOL_AB_BF16["bf16x3"])])
+def test_ab_df_sigma_widest_block(prec, tol):
+    """64 vectors in one block (the largest block the interface takes) in each precision,
+    against M z of the oracle's alpha-beta matrix; the last vector alone to the same tolerance."""
+    nmo, noa, nob, naux = 30, 7, 5, 40
+    note("ab df sigma k = 64", prec)
+    ea, eb, La, Lb = unrestricted(81, nmo, noa, nob, naux)
+    Mref, nvv = O.ab_sector(ea, eb, La, Lb, noa, nob)
+    with P.PpRPA.alpha_beta(ea, eb, La, Lb, noa, nob, max_block=64, density_fitted=True,
+                            prec=prec) as ctx:
+        z = gen.random_vectors(83, 64, ctx.n)
+        s = ctx.matvec(z)
+        s1 = ctx.matvec(z[63])
+    sref = z @ Mref.T
+    scale = max(1.0, np.abs(sref).max()) if prec == "fp64" else np.abs(sref).max()
+    err = np.max(np.abs(s - sref)) / scale
+    note("relative error", err)
+    assert err <= tol
+    assert np.max(np.abs(s1 - sref[63])) / scale <= tol
+
+
 def test_ab_bf16x6_beats_bf16x3():
     """The two BF16 schemes on the same alpha-beta inputs: six products at least 20 times more
     accurate than three, which tells the arithmetic that ran apart."""
