@@ -3,6 +3,8 @@
 * every request's roots in a mix equal the same request served alone, and the same problem
   solved by pprpa_build + pprpa_davidson, bit for bit (a grouped launch runs each member's work
   units exactly as its own launch would: same decomposition, same reduction order);
+* requests at the interface's limit (64 roots) served beside a small one, bit for bit as solved
+  standalone;
 * small requests against the FP64 oracle within 1e-6 Ha;
 * the arena is never over-committed: peak reserved bytes <= budget, and a budget that holds one
   large request at a time serialises them;
@@ -133,6 +135,25 @@ def test_mixed_precision_stream_is_fair():
         with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
             r = ctx.davidson(nroot, tol=tol_of(prec))
         assert np.array_equal(r["omega"], res[i]["omega"])
+
+
+def test_most_roots_served_equals_standalone():
+    """Requests at the interface's limit (64 roots: blocks of 64, restarts keeping 128 vectors)
+    served beside a small one: every result equals its standalone solve bit for bit."""
+    reqs = [(81, 12, 40, "singlet", 64, "fp64"), (82, 12, 40, "triplet", 64, "fp64"),
+            (83, 6, 30, "singlet", 4, "fp64")]
+    inputs = [device_inputs(s, no, nv, naux_of(no, nv)) for (s, no, nv, *_r) in reqs]
+    note("64-root requests served")
+    res, stats = serve(reqs, max_inflight=4, inputs=inputs)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for i, r in res.items():
+        assert r["status"] == P.binding.OK, r["message"]
+        seed, nocc, nvir, mult, nroot, prec = reqs[i]
+        eps, L = inputs[i]
+        with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
+            ref = ctx.davidson(nroot, tol=tol_of(prec))
+        assert np.array_equal(ref["omega"], r["omega"]), (ref["omega"] - r["omega"])
+        assert ref["report"]["iters"] == r["report"]["iters"]
 
 
 @pytest.mark.parametrize("i", range(len(MIX)))
