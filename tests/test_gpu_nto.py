@@ -148,6 +148,29 @@ def test_nto_vectors_vs_oracle(mult, case):
         assert np.allclose(lead["c_p1"][j], full["c_p1"][j][:3], atol=1e-9)
 
 
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
+def test_nto_largest_block(mult):
+    """Both NTO entry points at their block limit (nv = 512) on random vectors: weights and
+    density blocks against the oracle's SVD and densities, the leading pairs against the oracle's
+    singular vectors."""
+    nocc, nvir, naux = 3, 512, 8
+    note("nto at nv = 512", mult)
+    eps, L = gen.orbital_energies(65, nocc, nvir), gen.lpq_full(65, nocc + nvir, naux)
+    with P.PpRPA(eps, L, nocc, mult=mult) as ctx:
+        Z = gen.random_vectors(66, 2, ctx.n)
+        res = ctx.nto(Z)
+        out = ctx.nto_vectors(Z, 4)
+    for j, z in enumerate(Z):
+        lp, lh, (U, V, Uh, Vh) = O.nto(z, nvir, nocc, mult)
+        Dv, Do = O.density_2e(z, nvir, nocc, mult)
+        assert np.max(np.abs(res["lam_p"][j] - lp)) <= 1e-12 * lp.max()
+        assert np.max(np.abs(res["lam_h"][j] - lh)) <= 1e-12 * max(lh.max(), 1e-300)
+        assert np.max(np.abs(res["d_vv"][j] - Dv)) <= 1e-12 * np.abs(Dv).max()
+        assert np.max(np.abs(res["d_oo"][j] - Do)) <= 1e-12 * max(np.abs(Do).max(), 1e-300)
+        _check_vectors(out, j, lp, U, V)
+        _check_vectors(out, j, lh, Uh, Vh, wkey=("c_h1", "c_h2"))
+
+
 def test_nto_vectors_alpha_beta_vs_oracle():
     """The same for alpha-beta roots (rectangular blocks: alpha longer than beta, then shorter)."""
     for nmo, noa, nob in ((12, 4, 2), (10, 2, 5)):
