@@ -251,6 +251,36 @@ def test_direct_orders(mult, case, nroot):
     assert np.max(np.abs(M @ Z.T - (w[:, None] * Z.T) * r["omega"][None, :])) < 1e-9
 
 
+def test_direct_at_the_order_limit():
+    """The direct dense solve near its order limit (n = 8183 of 8192), where an oracle
+    eigensolve is too slow for a test: the dense matrix on sampled rows against the oracle's
+    elements (its sigma rows of the returned vectors), then what holds at any size: residual and
+    normalisation of every returned vector, and the same roots from a Davidson solve of the
+    density-fitted product on the same context; the correlation energy's two sum-rule sides at
+    the same order."""
+    nocc, nvir, naux = 10, 127, 400
+    note("direct near the order limit")
+    eps, L = problem(67, nocc, nvir, naux)
+    sp = O.active_space(eps, L, nocc)
+    with P.PpRPA(eps, L, nocc, dense=True, max_block=16) as ctx:
+        assert 8100 < ctx.n <= 8192
+        r = ctx.davidson(5, direct=True, vectors=True)
+        dv = ctx.davidson(5, block=10, tol=1e-8)
+        ec = ctx.correlation_energy()
+        M = ctx.dense_matrix()
+    # the whole-spectrum energy at the same order: both sides of the sum rule agree
+    assert abs(ec["ec_pp"] - ec["ec_hh"]) <= 1e-9 * max(1.0, abs(ec["ec_pp"]))
+    Z = r["vecs"]
+    rows = np.linspace(0, ctx.n - 1, 24).astype(int)
+    for j in range(5):
+        ref = O.sigma_rows(sp, "singlet", rows, Z[j])
+        assert np.max(np.abs(M[rows] @ Z[j] - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+    w = np.r_[np.ones(ctx.n_pp), -np.ones(ctx.n_hh)]
+    assert np.allclose(np.einsum("ij,j,ij->i", Z, w, Z), 1.0, atol=1e-10)
+    assert np.max(np.abs(M @ Z.T - (w[:, None] * Z.T) * r["omega"][None, :])) < 1e-8
+    assert np.max(np.abs(r["omega"] - dv["omega"])) <= 1e-8
+
+
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("case,nroot", [((4, 9, 30), 3), ((3, 17, 40), 6), ((0, 8, 20), 4),
                                         ((12, 25, 60), 8)])
