@@ -3,7 +3,8 @@
 * every request's roots in a mix equal the same request served alone, and the same problem
   solved by pprpa_build + pprpa_davidson, bit for bit (a grouped launch runs each member's work
   units exactly as its own launch would: same decomposition, same reduction order);
-* requests at the interface's limit (64 roots) served beside a small one, bit for bit as solved
+* requests at the interface's limit (64 roots) served beside a small one, and twenty requests
+  of one kernel variant filling grouped launches to their 16-member limit, bit for bit as solved
   standalone;
 * small requests against the FP64 oracle within 1e-6 Ha;
 * the arena is never over-committed: peak reserved bytes <= budget, and a budget that holds one
@@ -154,6 +155,27 @@ def test_most_roots_served_equals_standalone():
             ref = ctx.davidson(nroot, tol=tol_of(prec))
         assert np.array_equal(ref["omega"], r["omega"]), (ref["omega"] - r["omega"])
         assert ref["report"]["iters"] == r["report"]["iters"]
+
+
+def test_full_groups_equal_standalone():
+    """Twenty small FP64 requests of one kernel variant admitted together with 20 slots, so
+    grouped launches fill up to their limit of 16 members: every result equals its standalone
+    solve bit for bit."""
+    reqs = [(90 + j, 6 + j % 3, 40 + 5 * (j % 4), "singlet" if j % 2 else "triplet", 4, "fp64")
+            for j in range(20)]
+    inputs = [device_inputs(s, no, nv, naux_of(no, nv)) for (s, no, nv, *_r) in reqs]
+    note("twenty requests, 20 slots")
+    res, stats = serve(reqs, max_inflight=20, inputs=inputs)
+    note("stats", stats)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["peak_inflight"] > 16
+    assert stats["grouped_products"] > 2 * stats["group_launches"]
+    for i, r in res.items():
+        seed, nocc, nvir, mult, nroot, prec = reqs[i]
+        eps, L = inputs[i]
+        with P.PpRPA(eps, L, nocc, mult=mult, prec=prec, max_block=64) as ctx:
+            ref = ctx.davidson(nroot, tol=tol_of(prec))
+        assert np.array_equal(ref["omega"], r["omega"]), (i, ref["omega"] - r["omega"])
 
 
 @pytest.mark.parametrize("i", range(len(MIX)))
