@@ -4,6 +4,7 @@
   is inside pprpa_davidson returns EBUSY at once (and the first call is unaffected);
 * warm start: the converged vectors passed back as `guess` reach the same roots in at most two
   iterations;
+* a start block of 128 and of 256 guesses (wider than any correction block): the oracle's roots;
 * the per-iteration log callback: one JSON object per Davidson iteration, in order, whose last
   line agrees with the report;
 * the caller-driven solve (pprpa_solve_begin / _iterate / _end): driven to convergence one
@@ -86,6 +87,23 @@ def test_warm_start_from_converged_vectors(mult, channel):
     assert warm["report"]["iters"] <= 2
     assert np.max(np.abs(warm["omega"] - ref)) <= 1e-8
     assert np.max(np.abs(warm["omega"] - cold["omega"])) <= 1e-9
+    assert np.all(warm["resid"] <= 1e-8)
+
+
+@pytest.mark.parametrize("nguess", [128, 256])
+def test_warm_start_with_many_guesses(nguess):
+    """A start block wider than a correction block: the converged vectors followed by random
+    ones, 128 and 256 (the subspace cap) guesses in all; the same roots as the oracle's."""
+    note("warm start with", nguess, "guesses")
+    eps, L = problem(42, 8, 40, 90)
+    ref = O.solve(eps, L, 8, "singlet", 6)
+    with P.PpRPA(eps, L, 8) as ctx:
+        cold = ctx.davidson(6, block=6, tol=1e-8, vectors=True)
+        guess = np.vstack([cold["vecs"], gen.random_vectors(44, nguess - 6, ctx.n)])
+        warm = ctx.davidson(6, block=6, tol=1e-8, guess=guess, max_subspace=256)
+    note("warm iters", warm["report"]["iters"])
+    assert warm["status"] == 0
+    assert np.max(np.abs(warm["omega"] - ref)) <= 1e-8
     assert np.all(warm["resid"] <= 1e-8)
 
 
