@@ -739,6 +739,16 @@ def fp64_davidson_pair(P, gen, steps, warmup, nroot=10, block=20, tol=1e-6, conc
     return out, (eps_d, L_d)
 
 
+def copy_probe(torch, dev):
+    """One plain 1 GiB device-to-device copy: a kernel of known traffic (1 GiB read, 1 GiB
+    written) that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -772,6 +782,9 @@ def main():
                          "large dense, unrestricted, hh channel or NTO entries")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--pair-only", action="store_true",
+                    help="run only the 20/200/700 FP64 singlet + triplet Davidson workload "
+                         "(--steps / --warmup steps of it; with --copy-probe, the calibration copy)")
     ap.add_argument("--serial", dest="concurrent", action="store_false",
                     help="20/200/700 extra: the singlet and triplet solves one after the other")
     args = ap.parse_args()
@@ -805,12 +818,19 @@ def main():
         line.update(dense_large(P, gen))
         print(json.dumps(line), flush=True)
         return
+    if args.pair_only:
+        if args.copy_probe:
+            copy_probe(torch, dev)
+        line = {"metric": "sigma-products/sec (20/200/700 FP64 Davidson, singlet + triplet)",
+                "n_gpus": 1, "data": data}
+        line.update(fp64_davidson_pair(P, gen, steps=args.steps, warmup=args.warmup,
+                                       concurrent=args.concurrent)[0])
+        print(json.dumps(line), flush=True)
+        return
     if args.copy_probe:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe(torch, dev)
+
+    name = args.workload
 
     name = args.workload
     c = gen.CONFIGS[name]

@@ -402,15 +402,13 @@ __device__ __forceinline__ double block_sum_nt(double v, double* red) {
 
 // Cyclic Jacobi on the symmetric m x m matrix G (ld), accumulating eigenvectors into U (ld).
 // Round-robin ordering: m (padded to even) - 1 rounds of m/2 disjoint rotations per sweep.
-// NTH threads (the workgroup); red holds the round's index pairs (at least m + 1 doubles).
 // On return G's diagonal holds the eigenvalues and U's columns the eigenvectors.
-template <int NTH>
 __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, double* cs,
                            double* sn, bool init_u = true) {
   const int me = m + (m & 1);
   const int half = me / 2;
   if (init_u)
-    for (int e = threadIdx.x; e < m * m; e += NTH) U[(e / m) * ld + (e % m)] = (e / m == e % m);
+    for (int e = threadIdx.x; e < m * m; e += WG) U[(e / m) * ld + (e % m)] = (e / m == e % m);
   __syncthreads();
   if (m < 2) return 0;
   __shared__ int nrot;
@@ -420,7 +418,7 @@ __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, dou
     __syncthreads();
     for (int rnd = 0; rnd < me - 1; ++rnd) {
       // rotation parameters for each pair of this round
-      for (int pi = threadIdx.x; pi < half; pi += NTH) {
+      for (int pi = threadIdx.x; pi < half; pi += WG) {
         int p, q;
         if (pi == 0) {
           p = 0;
@@ -455,7 +453,7 @@ __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, dou
       }
       __syncthreads();
       // G <- J^T G J on all 2x2 blocks (pair a, pair b)
-      for (int e = threadIdx.x; e < half * half; e += NTH) {
+      for (int e = threadIdx.x; e < half * half; e += WG) {
         const int pa = e / half, pb = e % half;
         const int p = (int)red[2 * pa], q = (int)red[2 * pa + 1];
         const int r = (int)red[2 * pb], s = (int)red[2 * pb + 1];
@@ -487,7 +485,7 @@ __device__ int jacobi_eigh(double* G, int ld, int m, double* U, double* red, dou
         G[q * ld + s] = s2 * x1r + c2 * x1s;
       }
       // U <- U J
-      for (int e = threadIdx.x; e < m * half; e += NTH) {
+      for (int e = threadIdx.x; e < m * half; e += WG) {
         const int i = e / half, pb = e % half;
         const int r = (int)red[2 * pb], s = (int)red[2 * pb + 1];
         if (s >= m) continue;
@@ -1467,34 +1465,25 @@ __global__ __launch_bounds__(WG) void k_congruence(const double* __restrict__ A,
 }
 
 // Symmetric orthonormalisation of a block from its Gram matrix G (b x b): G = U diag(l) U^T;
-// keep l_j > cut * l_max (descending order); Tm[i][jj] = U[i][j] / sqrt(l_j). G and U live in
-// LDS for b <= GRAM_LDS_MAX (a correction block), in the work buffer above (a wide start block):
-// the same operations in the same order either way; in LDS a Jacobi round's dependent reads
-// and writes do not go through L2.
-// A correction block runs on one wave (NTH = 64): each Jacobi round has two barriers, and on a
-// one-wave workgroup they cost next to nothing.
-constexpr int GRAM_LDS_MAX = 64;
-template <int NTH, bool IN_LDS>
-__global__ __launch_bounds__(NTH) void k_gram_orth(const double* __restrict__ Gin, int ldg, int b,
-                                                   double cut, double* __restrict__ Tm, int ldt,
-                                                   int* __restrict__ kept,
-                                                   double* __restrict__ work) {
-  constexpr int LG = IN_LDS ? GRAM_LDS_MAX * GRAM_LDS_MAX : 1;
-  __shared__ double red[NTH];
+// keep l_j > cut * l_max (descending order); Tm[i][jj] = U[i][j] / sqrt(l_j).
+__global__ __launch_bounds__(WG) void k_gram_orth(const double* __restrict__ Gin, int ldg, int b,
+                                                  double cut, double* __restrict__ Tm, int ldt,
+                                                  int* __restrict__ kept,
+                                                  double* __restrict__ work) {
+  __shared__ double red[WG];
   __shared__ double cs[JMAX / 2 + 1], sn[JMAX / 2 + 1];
   __shared__ int rank_of[JMAX];
-  __shared__ double lds_g[LG], lds_u[LG];
-  double* G = IN_LDS ? lds_g : work;
-  double* U = IN_LDS ? lds_u : work + (size_t)b * b;
-  for (int e = threadIdx.x; e < b * b; e += NTH) {
+  double* G = work;
+  double* U = work + (size_t)b * b;
+  for (int e = threadIdx.x; e < b * b; e += WG) {
     const int i = e / b, j = e % b;
     G[e] = 0.5 * (Gin[i * ldg + j] + Gin[j * ldg + i]);
   }
   __syncthreads();
-  jacobi_eigh<NTH>(G, b, b, U, red, cs, sn);
+  jacobi_eigh(G, b, b, U, red, cs, sn);
   double lmax = 0.0;
   for (int i = 0; i < b; ++i) lmax = fmax(lmax, G[i * b + i]);
-  for (int i = threadIdx.x; i < b; i += NTH) {
+  for (int i = threadIdx.x; i < b; i += WG) {
     const double li = G[i * b + i];
     int rk = -1;
     if (li > cut * lmax && li > 1e-280) {
@@ -1509,7 +1498,7 @@ __global__ __launch_bounds__(NTH) void k_gram_orth(const double* __restrict__ Gi
   __syncthreads();
   int nk = 0;
   for (int i = 0; i < b; ++i) nk += rank_of[i] >= 0;
-  for (int e = threadIdx.x; e < b * b; e += NTH) {
+  for (int e = threadIdx.x; e < b * b; e += WG) {
     const int row = e / b, i = e % b;
     const int rk = rank_of[i];
     if (rk >= 0) Tm[row * ldt + rk] = U[row * b + i] / sqrt(G[i * b + i]);
@@ -1714,12 +1703,7 @@ hipError_t launch_small_congruence(const double* Ms, int ldm, int m, const doubl
 hipError_t launch_gram_orth(const double* G, int ldg, int b, double cut, double* Tm, int ldt,
                             int* kept, double* work, hipStream_t s) {
   if (b > JMAX) return hipErrorInvalidValue;
-  if (b <= GRAM_LDS_MAX)
-    hipLaunchKernelGGL((k_gram_orth<64, true>), dim3(1), dim3(64), 0, s, G, ldg, b, cut, Tm, ldt,
-                       kept, work);
-  else
-    hipLaunchKernelGGL((k_gram_orth<WG, false>), dim3(1), dim3(WG), 0, s, G, ldg, b, cut, Tm, ldt,
-                       kept, work);
+  hipLaunchKernelGGL(k_gram_orth, dim3(1), dim3(WG), 0, s, G, ldg, b, cut, Tm, ldt, kept, work);
   return hipGetLastError();
 }
 
