@@ -5,6 +5,7 @@
 * degenerate orbital energies with interactions: eigenvalues with multiplicity;
 * no occupied orbitals (pp block only), a single pair (nroot = n_pp = 1), one aux function;
 * every root of a channel (nroot = n_pp or n_hh), the subspace reaching the whole space;
+* more aux functions (70001) than one staging pass takes, from host and device inputs;
 * the widest block (64 vectors; FP64 with one aux function, every reduced precision on a
   ragged shape) and a window of one virtual orbital;
 * every sigma precision on the smallest and most ragged shapes.
@@ -165,6 +166,34 @@ def test_widest_block_every_precision(mult, prec, tol):
     scale = np.abs(ref).max()
     assert np.max(np.abs(s - ref)) <= tol * scale
     assert np.max(np.abs(s1 - ref[63])) <= tol * scale
+
+
+_NAUX_CACHE = {}
+
+
+@pytest.mark.parametrize("inputs", ["host", "device"])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-7)])
+def test_aux_count_above_65535(inputs, prec, tol):
+    """naux = 70001: more aux slices than one staging pass takes (65535), from host and from
+    device inputs, against the oracle's M z."""
+    note("naux 70001", inputs, prec)
+    nocc, nvir, naux = 3, 7, 70001
+    eps = gen.orbital_energies(39, nocc, nvir)
+    L = gen.lpq_full(39, nocc + nvir, naux) * (1.0 / 16.0)
+    if "M" not in _NAUX_CACHE:  # the oracle's matrix once for the four cases (8 s)
+        _NAUX_CACHE["M"] = dense(eps, L, nocc, "singlet")[0]
+    M = _NAUX_CACHE["M"]
+    if inputs == "device":
+        import torch
+        dev = torch.device("cuda:0")
+        e_in, L_in = torch.from_numpy(eps).to(dev), torch.from_numpy(L).to(dev)
+    else:
+        e_in, L_in = eps, L
+    with P.PpRPA(e_in, L_in, nocc, prec=prec) as ctx:
+        z = gen.random_vectors(12, 5, ctx.n)
+        s = ctx.matvec(z)
+    ref = (M @ z.T).T
+    assert np.max(np.abs(s - ref)) <= tol * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-7), ("bf16x6", 1e-7),
