@@ -831,8 +831,6 @@ def main():
         copy_probe(torch, dev)
 
     name = args.workload
-
-    name = args.workload
     c = gen.CONFIGS[name]
     t = time.perf_counter()
     problem = device_problem(gen, name, dev)
