@@ -7,6 +7,7 @@
 * a start block of 128 and of 256 guesses (wider than any correction block): the oracle's roots;
 * the per-iteration log callback: one JSON object per Davidson iteration, in order, whose last
   line agrees with the report;
+* a solve with the roctx ranges switched on (PPRPA_ROCTX=1, no profiler attached);
 * the caller-driven solve (pprpa_solve_begin / _iterate / _end): driven to convergence one
   iteration at a time it returns bitwise what pprpa_davidson returns; it holds the context
   (EBUSY for other calls) until ended; ended early it reports ENOCONV with the last iterate.
@@ -183,3 +184,25 @@ def test_open_solve_holds_the_context_and_ends_early():
             sv.iterate(4)
         r = sv.end()
     assert np.max(np.abs(r["omega"] - O.solve(eps, L, 8, "singlet", 5))) <= 1e-8
+
+
+def test_solve_with_roctx_ranges_enabled():
+    """PPRPA_ROCTX=1 (roctx ranges around the entry points and Davidson phases, no profiler
+    attached): a solve in a child process gives the oracle's roots, as without the ranges."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import numpy as np, paper_2512_12515_amd as P; from workloads import gen; "
+            "eps, L = gen.orbital_energies(42, 8, 40), gen.lpq_full(42, 48, 90); "
+            "ctx = P.PpRPA(eps, L, 8); r = ctx.davidson(6, block=6, tol=1e-8); ctx.close(); "
+            "print(' '.join(repr(float(x)) for x in r['omega']))")
+    note("solve with PPRPA_ROCTX=1")
+    out = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, PPRPA_ROCTX="1"),
+                         cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-3000:]
+    assert "could not be opened" not in out.stderr
+    omega = np.array([float(x) for x in out.stdout.strip().splitlines()[-1].split()])
+    eps, L = problem(42, 8, 40, 90)
+    assert np.max(np.abs(omega - O.solve(eps, L, 8, "singlet", 6))) <= 1e-8
+
