@@ -29,6 +29,10 @@
  *    pprpa_last_error() gives a message for the calling thread.
  *  - "host or device" pointers: the on_device flag says which; device pointers must be
  *    memory of the context's device (e.g. a torch tensor's data_ptr()).
+ *  - Environment: PPRPA_ROCTX=1 makes the library open the ROCm profiler SDK's roctx library
+ *    (by dlopen, on first use) and push a named range around each entry point and each host-side
+ *    Davidson phase, for rocprofv3 --marker-trace; unset, or when that library cannot be opened,
+ *    nothing is traced and nothing else changes.
  */
 #ifndef PPRPA_H
 #define PPRPA_H
