@@ -316,6 +316,37 @@ def test_davidson_most_roots_widest_block(mult):
 
 
 @pytest.mark.parametrize("mult", ["singlet", "triplet"])
+@pytest.mark.parametrize("block,max_subspace", [(1, 0), (1, 20), (2, 20), (3, 15), (5, 15)])
+def test_davidson_small_blocks_and_restarts(mult, block, max_subspace):
+    """Fewer corrections per iteration than roots, and subspace caps that force restarts every
+    few iterations: the oracle's roots all the same."""
+    nocc, nvir, naux = 6, 20, 60
+    note("davidson block", block, "max_subspace", max_subspace, mult)
+    eps, L = problem(19, nocc, nvir, naux)
+    ref = O.solve(eps, L, nocc, mult, 5)
+    with P.PpRPA(eps, L, nocc, mult=mult) as ctx:
+        r = ctx.davidson(5, block=block, tol=1e-8, max_iter=600, max_subspace=max_subspace)
+    note("iterations", r["report"]["iters"], "final subspace", r["report"]["subspace"])
+    assert r["status"] == 0
+    assert max_subspace == 0 or r["report"]["subspace"] <= max_subspace
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-8
+
+
+def test_davidson_stalled_by_a_tight_cap_reports_enoconv():
+    """A subspace cap barely above nroot with one correction per iteration stalls on this singlet
+    problem (each restart to the five Ritz vectors discards what the corrections added): the
+    solve reports ENOCONV with its last iterate, finite and not claimed converged."""
+    eps, L = problem(19, 6, 20, 60)
+    with P.PpRPA(eps, L, 6) as ctx:
+        r = ctx.davidson(5, block=1, tol=1e-8, max_iter=60, max_subspace=7, raise_noconv=False)
+        with pytest.raises(P.PpRPAError) as e:
+            ctx.davidson(5, block=1, tol=1e-8, max_iter=60, max_subspace=7)
+    assert r["status"] == P.binding.ENOCONV and e.value.status == P.binding.ENOCONV
+    assert np.all(np.isfinite(r["omega"])) and np.all(np.isfinite(r["resid"]))
+    assert r["report"]["max_resid"] > 1e-8 and r["report"]["n_conv"] < 5
+
+
+@pytest.mark.parametrize("mult", ["singlet", "triplet"])
 @pytest.mark.parametrize("seed", [0, 3])
 def test_davidson_vs_direct_small_config(mult, seed):
     gd = _golden("small_direct.json")
