@@ -154,7 +154,10 @@ typedef struct {
   int32_t nroot;        /* number of roots wanted (>= 1)                                    */
   int32_t block;        /* max correction vectors added per iteration (<= 0: nroot)         */
   int32_t max_iter;     /* iteration cap (<= 0: 100)                                        */
-  int32_t max_subspace; /* subspace size that triggers a restart (<= 0: automatic)          */
+  int32_t max_subspace; /* subspace size that triggers a restart (<= 0: automatic,
+                           max(8 nroot, nroot + 4 block); at most 256). A restart keeps the
+                           wanted Ritz vectors only, so a cap close to nroot + block can stall
+                           (reported as ENOCONV with the last iterate)                        */
   double tol;           /* converged when ||M z - Omega W z||_2 <= tol for every root       */
   const double* guess;  /* optional [nguess][n] FP64 host start vectors, or NULL             */
   int32_t nguess;
