@@ -1406,12 +1406,16 @@ __global__ __launch_bounds__(WG) void k_pencil_tri_l2(const double* __restrict__
                   &flag, &npos_s);
 }
 
-// Q = orth(C[:, :r]) by modified Gram-Schmidt, twice; columns with relative norm below 1e-10
-// are dropped. Q: [m][ldq]; rank written to rank[0].
+// Q = orth(C[:, :r]) by classical Gram-Schmidt applied twice per column (CGS2): in each pass
+// the projections on the kept columns come from one set of dot products, each computed by one
+// wave over the rows in a fixed order, and are subtracted in column order; columns with relative
+// norm below 1e-10 are dropped. Q: [m][ldq], r <= JMAX; rank written to rank[0].
 __global__ __launch_bounds__(WG) void k_small_orth(const double* __restrict__ C, int ldc, int m,
                                                    int r, double* __restrict__ Q, int ldq,
                                                    int* __restrict__ rank) {
   __shared__ double red[WG];
+  __shared__ double dk[JMAX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int kept = 0;
   for (int j = 0; j < r; ++j) {
     // copy column j into column kept
@@ -1420,14 +1424,20 @@ __global__ __launch_bounds__(WG) void k_small_orth(const double* __restrict__ C,
     double n0 = 0.0;
     for (int i = threadIdx.x; i < m; i += WG) n0 += Q[i * ldq + kept] * Q[i * ldq + kept];
     n0 = sqrt(block_sum(n0, red));
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int k = 0; k < kept; ++k) {
+    for (int pass = 0; pass < 2 && kept > 0; ++pass) {
+      for (int k = wv; k < kept; k += WG / 64) {
         double d = 0.0;
-        for (int i = threadIdx.x; i < m; i += WG) d += Q[i * ldq + k] * Q[i * ldq + kept];
-        d = block_sum(d, red);
-        for (int i = threadIdx.x; i < m; i += WG) Q[i * ldq + kept] -= d * Q[i * ldq + k];
-        __syncthreads();
+        for (int i = lane; i < m; i += 64) d += Q[i * ldq + k] * Q[i * ldq + kept];
+        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+        if (lane == 0) dk[k] = d;
       }
+      __syncthreads();
+      for (int i = threadIdx.x; i < m; i += WG) {
+        double p = 0.0;
+        for (int k = 0; k < kept; ++k) p += dk[k] * Q[i * ldq + k];
+        Q[i * ldq + kept] -= p;
+      }
+      __syncthreads();
     }
     double nn = 0.0;
     for (int i = threadIdx.x; i < m; i += WG) nn += Q[i * ldq + kept] * Q[i * ldq + kept];
@@ -1690,6 +1700,7 @@ hipError_t launch_nto(const double* Z, int64_t ldz, int k, const Geometry& g, co
 
 hipError_t launch_small_orth(const double* C, int ldc, int m, int r, double* Q, int ldq,
                              int* rank, hipStream_t s) {
+  if (r > JMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_small_orth, dim3(1), dim3(WG), 0, s, C, ldc, m, r, Q, ldq, rank);
   return hipGetLastError();
 }
