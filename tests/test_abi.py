@@ -110,6 +110,22 @@ def test_null_arguments():
     assert L.pprpa_davidson(None, C.byref(d), None, None, None, None) == B.EINVAL
 
 
+def test_binding_constants_match_header_enums():
+    """The binding's status, multiplicity and precision constants equal the header's enum values
+    (parsed from include/pprpa.h, so that a renumbering on either side fails here)."""
+    text = open(os.path.join(ROOT, "include", "pprpa.h")).read()
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(PPRPA_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    for name in ("OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOCONV", "ENONDEF", "EUNSUPPORTED", "EBUSY"):
+        assert getattr(B, name) == vals["PPRPA_" + name], name
+    assert B.MULT == {"singlet": vals["PPRPA_SINGLET"], "triplet": vals["PPRPA_TRIPLET"]}
+    assert B.PREC == {"fp64": vals["PPRPA_FP64"], "fp32": vals["PPRPA_FP32"],
+                      "bf16x6": vals["PPRPA_BF16X6"], "bf16x3": vals["PPRPA_BF16X3"]}
+    for code in range(8):  # every status has its own message; an unknown code is reported as such
+        assert B.lib().pprpa_strerror(code).decode() != "unknown status"
+    assert B.lib().pprpa_strerror(8).decode() == "unknown status"
+    assert B.lib().pprpa_strerror(-1).decode() == "unknown status"
+
+
 def test_roctx_ranges_open_when_enabled():
     """PPRPA_ROCTX=1 opens the profiler SDK's roctx library on the first traced entry point;
     with no profiler attached its ranges are no-ops and the call behaves as without them."""
